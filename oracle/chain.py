@@ -1,0 +1,106 @@
+"""TNMCMC-1 slice update, Metropolis-Hastings decision and sweeps.
+
+Oracle code (test infrastructure only).
+
+* Slice update = SM Alg. 2 (SampleLayer + acceptance): build the layer's network
+  from the held layers, draw a new layer s' with q(s'), evaluate q of the
+  current layer s, and accept with the Metropolis-Hastings probability.
+* Acceptance (main text Eq. 1; SM S1.C; SM S2.A):
+      A(s -> s') = min{1, q(s) exp(-beta E(s')) / (q(s') exp(-beta E(s)))}
+  with s the current and s' the proposed layer.  (The printed Alg. 2 writes
+  the inverse ratio; Eq. 1 and the two SM equations agree with the form above,
+  which is the one that leaves the Boltzmann distribution invariant.)
+* Schedule (SM S2.A, last paragraph; SM S3.D): all even layers are updated
+  with the odd ones held, then all odd layers; one sweep visits every layer once.
+* A proposal whose sampling or forced path reported a numeric fault is
+  rejected.  Faults are a deterministic function of (held layers, layer
+  configuration), so rejecting when either path faults keeps detailed balance.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import bmps, model, sampler
+from .philox import PURPOSE_MH, uniform
+
+
+def mh_accept(logq_old: float, logq_new: float, beta: float, dE: float, u: float) -> bool:
+    """Accept iff u < exp(min(0, log q(old) - log q(new) - beta * (E(new) - E(old))))."""
+    lr = logq_old - logq_new - beta * dE
+    return bool(u < math.exp(min(0.0, lr)))
+
+
+def propose(J, spins, z: int, beta: float, chi: int, d: int, *, seed: int = 0,
+            chain: int = 0, sweep: int = 0):
+    """One proposal for layer z without changing the state.
+
+    Returns a dict with the new layer (int8 spins [y, x]), log q(new), log q(old),
+    dE = E(new) - E(old), the layer's approximate log Z and the fault flag."""
+    F = model.slice_field(J, spins, z, d)
+    envs, logscale = bmps.environments(J, F, z, beta, chi, d)
+    new, lq_new, f_new = sampler.sample_layer(envs, J, F, z, beta, d, seed=seed,
+                                              chain=chain, sweep=sweep)
+    old = model.to_states(spins[z], d)
+    _, lq_old, f_old = sampler.sample_layer(envs, J, F, z, beta, d, forced=old)
+    dE = model.slice_energy(J, F, new, z, d) - model.slice_energy(J, F, old, z, d)
+    return {
+        "new": model.from_states(new, d),
+        "logq_new": lq_new,
+        "logq_old": lq_old,
+        "dE": dE,
+        "fault": bool(f_new or f_old),
+        "envs": envs,
+        "logscale": logscale,
+        "F": F,
+    }
+
+
+def slice_logq(J, spins, z: int, layer_spins, beta: float, chi: int, d: int) -> float:
+    """log q of an arbitrary configuration of layer z given the held layers."""
+    F = model.slice_field(J, spins, z, d)
+    envs, _ = bmps.environments(J, F, z, beta, chi, d)
+    _, lq, _ = sampler.sample_layer(envs, J, F, z, beta, d,
+                                    forced=model.to_states(layer_spins, d))
+    return lq
+
+
+def slice_update(J, spins, z: int, beta: float, chi: int, d: int, *, seed: int,
+                 chain: int, sweep: int):
+    """Propose for layer z and apply the MH decision in place.  Returns the proposal
+    record extended with the uniform and the decision."""
+    rec = propose(J, spins, z, beta, chi, d, seed=seed, chain=chain, sweep=sweep)
+    u = uniform(seed, chain, sweep, z, PURPOSE_MH, 0)
+    acc = (not rec["fault"]) and mh_accept(rec["logq_old"], rec["logq_new"], beta, rec["dE"], u)
+    if acc:
+        spins[z] = rec["new"]
+    rec["u_acc"] = u
+    rec["accepted"] = acc
+    return rec
+
+
+def sweep(J, spins, beta: float, chi: int, d: int, *, seed: int, chain: int, sweep_index: int):
+    """Even layers, then odd layers (in place).  Returns the number of accepted updates."""
+    Lz = spins.shape[0]
+    n_acc = 0
+    for parity in (0, 1):
+        for z in range(parity, Lz, 2):
+            rec = slice_update(J, spins, z, beta, chi, d, seed=seed, chain=chain,
+                               sweep=sweep_index)
+            n_acc += int(rec["accepted"])
+    return n_acc
+
+
+def run_chain(J, spins, beta: float, chi: int, d: int, n_sweeps: int, *, seed: int,
+              chain: int = 0, sweep_offset: int = 0):
+    """Run n_sweeps sweeps in place; returns per-sweep energies, magnetisations and
+    the acceptance count."""
+    E = np.zeros(n_sweeps)
+    M = np.zeros(n_sweeps)
+    acc = 0
+    for t in range(n_sweeps):
+        acc += sweep(J, spins, beta, chi, d, seed=seed, chain=chain, sweep_index=sweep_offset + t)
+        E[t] = model.energy(J, spins, d)
+        M[t] = model.magnetisation(spins, d)
+    return E, M, acc
