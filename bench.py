@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Throughput of the TNMCMC-1 slice proposal on one MI355X.
+
+A step is one sweep: every layer of every chain is resampled once (even layers,
+then odd layers), each by boundary-MPS contraction, ancestral sampling with
+exact log q, teacher-forced log q of the current layer and a Metropolis-Hastings
+decision.  Default workload: 3D Edwards-Anderson +-J, 32^3, open boundaries,
+beta = 1.0, chi = 32, 16 disorder instances x 2 replicas = 32 chains, FP64,
+synthetic couplings and spins from fixed seeds.
+
+Prints one JSON line with slice updates/s, the roofline of the contraction
+kernel (HIP events on the launch stream) and the FP64 oracle timed on the host
+cores over a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+
+WORKLOADS = {
+    # name: L, chi, beta, instances, replicas
+    "ea32": dict(L=32, chi=32, beta=1.0, n_inst=16, n_rep=2),
+    "ea16": dict(L=16, chi=32, beta=1.0, n_inst=64, n_rep=2),
+    "ea8": dict(L=8, chi=16, beta=0.5, n_inst=1, n_rep=1),
+}
+PHILOX_SEED = 20250928
+
+
+def build_inputs(name: str):
+    cfg = WORKLOADS[name]
+    L, n_inst, n_rep = cfg["L"], cfg["n_inst"], cfg["n_rep"]
+    J = np.stack([synth.couplings_pm_j(L, L, L, i) for i in range(n_inst)])
+    spins = np.stack([synth.spins_random(L, L, L, 1000 * i + j) for i in range(n_inst) for j in range(n_rep)])
+    inst = np.array([i for i in range(n_inst) for _ in range(n_rep)], dtype=np.int32)
+    pairs = np.array([[n_rep * i, n_rep * i + 1] for i in range(n_inst)], dtype=np.int32) if n_rep == 2 else None
+    betas = np.full(n_inst * n_rep, cfg["beta"])
+    return cfg, J, spins, inst, pairs, betas
+
+
+def make_lattice(name: str, record_capacity: int = 0):
+    import paper_2509_23945_amd as tn
+    cfg, J, spins, inst, pairs, betas = build_inputs(name)
+    L = cfg["L"]
+    lat = tn.tnmc_lattice_init(Lx=L, Ly=L, Lz=L, d=2, chi=cfg["chi"], J=J, beta=betas, spins=spins,
+                               chain_instance=inst, seed=PHILOX_SEED, pairs=pairs,
+                               record_capacity=record_capacity)
+    return lat, cfg, J, spins, inst, betas
+
+
+def _oracle_task(args):
+    """One slice update of the workload by the FP64 oracle (cpu_baseline leg)."""
+    name, chain, z = args
+    from threadpoolctl import threadpool_limits
+    from oracle import chain as ochain
+    cfg, J, spins, inst, _, betas = build_inputs(name)
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        ochain.propose(J[inst[chain]], spins[chain], z, betas[chain], cfg["chi"], 2, seed=PHILOX_SEED,
+                       chain=chain, sweep=0)
+        return time.perf_counter() - t
+
+
+def cpu_baseline(name: str, per_worker: int = 1):
+    import multiprocessing as mp
+    cfg = WORKLOADS[name]
+    cores = max(1, min(16, os.cpu_count() or 1))
+    n_chains = cfg["n_inst"] * cfg["n_rep"]
+    tasks = [(name, k % n_chains, (2 * k) % cfg["L"]) for k in range(cores * per_worker)]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        per = pool.map(_oracle_task, tasks)
+    wall = time.perf_counter() - t0
+    return {"value": len(tasks) / wall, "unit": "slice updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(tasks)} slice updates of the {name} workload (L={cfg['L']}, chi={cfg['chi']}), "
+                      f"one per worker process, numpy single-threaded; wall {wall:.1f} s, "
+                      f"mean {np.mean(per):.2f} s per update per core"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ea32", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
+              "design only, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2509_23945_amd as tn
+    from paper_2509_23945_amd import analysis
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    lat, cfg, J, spins, inst, betas = make_lattice(args.workload, record_capacity=args.steps)
+    L = cfg["L"]
+    n_chains = cfg["n_inst"] * cfg["n_rep"]
+    print(f"[bench] workload {args.workload}: {n_chains} chains of {L}^3, chi={cfg['chi']}, "
+          f"warmup {args.warmup}", file=sys.stderr, flush=True)
+    if args.warmup:
+        tn.tnmc_sweep([lat], args.warmup, sweep_offset=0, stream=stream)
+    tn.tnmc_timeseries_reset(lat)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} sweeps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    st = tn.tnmc_sweep([lat], args.steps, sweep_offset=args.warmup, record=True, time_kernels=True,
+                       stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    updates = args.steps * n_chains * L
+    value = updates / secs
+
+    flops_task, flops_sample = tn.tnmc_flop_model(L, L, 2, cfg["chi"])
+    tasks_per_launch = n_chains * (L // 2)
+    avg_launch_s = st["contract_ms"] / 1e3 / max(1, st["contract_launches"])
+    achieved = flops_task * tasks_per_launch / avg_launch_s / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                "kernel": "contract_kernel<2,32>", "avg_launch_ms": avg_launch_s * 1e3,
+                "flops_per_task": flops_task, "tasks_per_launch": tasks_per_launch}
+
+    _, _, q = tn.tnmc_timeseries(lat)
+    indep = None
+    tau = None
+    if q.shape[0] >= 100 and q.shape[1] > 0:
+        indep, tau, _ = analysis.independent_samples_per_second(q, secs / args.steps)
+
+    out = {
+        "metric": "slice updates/s (TNMCMC-1 slice proposal, FP64 plain)",
+        "value": value,
+        "unit": "slice updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded +-J couplings, random initial spins)",
+        "config": {"workload": f"3D EA +-J {L}^3 open BC, beta={cfg['beta']}, chi={cfg['chi']}, "
+                               f"{cfg['n_inst']} instances x {cfg['n_rep']} replicas",
+                   "chains": n_chains, "slice_updates_per_step": n_chains * L, "parallelism": "none (1 GPU)"},
+        "acceptance": st["accepted"] / max(1, st["proposed"]),
+        "numeric_faults": st["numeric_faults"],
+        "contract_ms_per_step": st["contract_ms"] / args.steps,
+        "sample_ms_per_step": st["sample_ms"] / args.steps,
+        "tau_int_q": tau,
+        "indep_samples_per_s": indep,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

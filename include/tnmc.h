@@ -1,0 +1,153 @@
+/*
+ * tnmc.h - C ABI of the MI355X TNMCMC-1 slice-proposal library (libtnmc.so).
+ *
+ * Method: Tensor Network Markov Chain Monte Carlo, arXiv 2509.23945.  A layer
+ * (z-slice) of a 3D lattice with quenched couplings is resampled given its two
+ * neighbouring layers (SM S2.A, TNMCMC-1): the layer's 2D tensor network, with
+ * the neighbours acting as an external field, is contracted by boundary MPS with
+ * truncation to bond dimension chi (SM S1.B), a new layer is drawn site by site
+ * with its exact log-probability log q (main text "TNMCMC"; SM S1.C), q of the
+ * current layer is evaluated by teacher forcing (SM Alg. 2), and the move is
+ * accepted by Metropolis-Hastings (main text Eq. 1).
+ *
+ * Conventions shared by every call:
+ *  - Lattices have free boundaries.  Couplings are float32 J[3][Lz][Ly][Lx]:
+ *    component 0 couples (x,y,z)-(x+1,y,z), 1 couples (x,y,z)-(x,y+1,z),
+ *    2 couples (x,y,z)-(x,y,z+1); bonds leaving the lattice must be 0.
+ *  - Ising (d=2): spins int8 +1/-1, energy -sum J s s'.  Potts (d=3): states
+ *    int8 0/1/2, energy -sum J delta(s,s').  Spins are [Lz][Ly][Lx] per chain.
+ *  - Random numbers: Philox4x64-10 with key (seed, chain_key) and counter
+ *    (draw, z, sweep, purpose); purpose 0 = site draws (draw = y*Lx+x),
+ *    purpose 1 = the MH uniform; U = ((w0 >> 11) + 0.5) * 2^-53.
+ *  - All device work is stream-ordered on the hip_stream argument (a
+ *    hipStream_t, NULL = default stream).  Calls that return host data
+ *    synchronise that stream.  A handle is used by one host thread at a time.
+ *  - Every call returns a tnmc_status; on TNMC_ERR_ARG nothing is changed.
+ */
+#ifndef TNMC_H
+#define TNMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TNMC_OK = 0,
+  TNMC_ERR_ARG = -1,         /* invalid shape, pointer or parameter */
+  TNMC_ERR_OOM = -2,         /* device allocation failed */
+  TNMC_ERR_DEVICE = -3,      /* a HIP call failed (message: tnmc_last_error) */
+  TNMC_ERR_NUMERIC = -4,     /* non-finite result in a proposal */
+  TNMC_ERR_UNSUPPORTED = -5  /* (d, chi, precision) combination not built */
+} tnmc_status;
+
+enum { TNMC_FP64 = 0, TNMC_FP32 = 1 };   /* contraction precision */
+
+typedef struct tnmc_lattice tnmc_lattice;  /* opaque; owns the device state it allocates */
+
+/* A batch of chains on lattices of one shape (Lx, Ly, Lz, d) and bond
+ * dimension chi.  Chains may have different couplings (instances) and
+ * different inverse temperatures.  All pointers are HOST pointers, copied at
+ * init and not retained. */
+typedef struct {
+  int32_t Lx, Ly, Lz;           /* 1 <= Lx, Ly; 1 <= Lz */
+  int32_t d;                    /* 2 (Ising / EA) or 3 (Potts) */
+  int32_t chi;                  /* boundary-MPS bond dimension, >= 1 */
+  int32_t precision;            /* TNMC_FP64 */
+  int32_t n_chains;             /* >= 1 */
+  int32_t n_instances;          /* >= 1, number of coupling sets */
+  const float* J;               /* [n_instances][3][Lz][Ly][Lx] */
+  const int32_t* chain_instance;/* [n_chains] in [0, n_instances); NULL: chain c -> c % n_instances */
+  const double* beta;           /* [n_chains], >= 0 */
+  const int8_t* spins;          /* [n_chains][Lz][Ly][Lx] initial configuration */
+  uint64_t seed;                /* Philox key word 0 */
+  const uint64_t* chain_key;    /* [n_chains] Philox key word 1; NULL: chain index */
+  int32_t n_pairs;              /* replica pairs for the overlap q, >= 0 */
+  const int32_t* pairs;         /* [n_pairs][2] chain indices (same instance) */
+  int32_t record_capacity;      /* sweeps of observables kept on the device */
+} tnmc_lattice_desc;
+
+/* Allocate the device state of a batch of chains (SM Alg. 2 inputs: L, {J},
+ * chi, beta, initial configuration).  *out receives the handle. */
+tnmc_status tnmc_lattice_init(const tnmc_lattice_desc* desc, tnmc_lattice** out);
+tnmc_status tnmc_lattice_free(tnmc_lattice* lat);
+
+/* One TNMCMC-1 proposal for layer z of chain `chain` (SM Alg. 2, SampleLayer):
+ * builds the layer network from the held layers z-1, z+1, contracts it by
+ * boundary MPS to chi, draws a new layer with the site uniforms of counter
+ * (., z, sweep, 0), and evaluates q of the current layer by teacher forcing.
+ * The state is not changed.  Outputs are HOST pointers: s_new [Ly][Lx] int8,
+ * and natural-log q of the new and current layer and dE = E(new) - E(current).
+ * Returns TNMC_ERR_NUMERIC if either path hit a non-positive or non-finite
+ * total site weight (the outputs are still written). */
+tnmc_status tnmc_slice_propose(tnmc_lattice* lat, int32_t chain, int32_t z, uint64_t sweep,
+                               int8_t* s_new, double* logq_new, double* logq_old, double* dE,
+                               void* hip_stream);
+
+/* log q of an arbitrary configuration s [Ly][Lx] (HOST) of layer z given the
+ * current held layers (SM S1.C: product of the conditionals along the
+ * sampling order, with the spins projected on their states). */
+tnmc_status tnmc_slice_logq(tnmc_lattice* lat, int32_t chain, int32_t z, const int8_t* s,
+                            double* logq, void* hip_stream);
+
+/* Metropolis-Hastings decision of main text Eq. 1 for an independence
+ * proposal: *accepted = u < exp(min(0, logq_old - logq_new - beta*dE)),
+ * with 0 < u < 1.  Pure host function. */
+tnmc_status tnmc_mh_accept(double logq_old, double logq_new, double beta, double dE, double u,
+                           int32_t* accepted);
+
+typedef struct {
+  int64_t proposed, accepted, numeric_faults;
+  double contract_ms;           /* summed duration of the contraction launches (HIP events) */
+  double sample_ms;             /* summed duration of the sampling/MH launches */
+  int64_t contract_launches, sample_launches;
+} tnmc_stats;
+
+/* n_sweeps sweeps of every chain of every lattice in lats[0..n_lats-1]
+ * (SM S2.A: all even layers with the odd ones held, then all odd layers; one
+ * sweep updates every layer once).  Sweep t uses Philox sweep counter
+ * sweep_offset + t.  With record != 0 the energy, magnetisation and pair
+ * overlaps after each sweep are appended to each lattice's device record.
+ * stats (may be NULL) accumulates counts; with time_kernels != 0 it also
+ * receives the summed kernel durations measured with HIP events on
+ * hip_stream (the call then synchronises). */
+tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps,
+                       uint64_t sweep_offset, int32_t record, int32_t time_kernels,
+                       tnmc_stats* stats, void* hip_stream);
+
+/* One half-sweep (parity 0: even layers, 1: odd layers) of every chain in
+ * lats, as inside tnmc_sweep.  trace (DEVICE pointer or NULL) receives, for
+ * task t in the order lattice-major, chain, layer z = parity, parity+2, ...:
+ * trace[5t..5t+4] = {log q(new), log q(current), dE, accepted, fault}. */
+tnmc_status tnmc_half_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t parity,
+                            uint64_t sweep, double* trace, tnmc_stats* stats, void* hip_stream);
+
+/* State access (HOST buffers, synchronous). */
+tnmc_status tnmc_get_spins(tnmc_lattice* lat, int32_t chain, int8_t* out);     /* [Lz][Ly][Lx] */
+tnmc_status tnmc_set_spins(tnmc_lattice* lat, int32_t chain, const int8_t* in);
+/* Full-lattice energy of a chain, computed on the device in FP64. */
+tnmc_status tnmc_energy(tnmc_lattice* lat, int32_t chain, double* E);
+/* Recorded observables: E[n][n_chains], M[n][n_chains], q[n][n_pairs] (HOST,
+ * each may be NULL); *n receives the number of recorded sweeps (capped at
+ * record_capacity; later sweeps are dropped). */
+tnmc_status tnmc_timeseries(tnmc_lattice* lat, double* E, double* M, double* q, int64_t* n);
+/* Drop the recorded observables. */
+tnmc_status tnmc_timeseries_reset(tnmc_lattice* lat);
+
+/* Algorithmic FP64 flop count of one slice update of an Lx x Ly layer with
+ * bond dimension chi, split into the boundary-MPS contraction (textbook
+ * counts of the Householder QR, Golub-Reinsch SVD and GEMM steps at the bond
+ * dimensions the method uses) and the two sampling passes.  Used for
+ * roofline reporting; either output may be NULL. */
+tnmc_status tnmc_flop_model(int32_t Lx, int32_t Ly, int32_t d, int32_t chi, double* contract_flops,
+                            double* sample_flops);
+
+const char* tnmc_status_string(tnmc_status s);
+/* Text of the last failed HIP call (thread-local). */
+const char* tnmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNMC_H */

@@ -33,7 +33,7 @@ def mh_accept(logq_old: float, logq_new: float, beta: float, dE: float, u: float
 
 
 def propose(J, spins, z: int, beta: float, chi: int, d: int, *, seed: int = 0,
-            chain: int = 0, sweep: int = 0):
+            chain: int = 0, sweep: int = 0, margins=None):
     """One proposal for layer z without changing the state.
 
     Returns a dict with the new layer (int8 spins [y, x]), log q(new), log q(old),
@@ -41,7 +41,7 @@ def propose(J, spins, z: int, beta: float, chi: int, d: int, *, seed: int = 0,
     F = model.slice_field(J, spins, z, d)
     envs, logscale = bmps.environments(J, F, z, beta, chi, d)
     new, lq_new, f_new = sampler.sample_layer(envs, J, F, z, beta, d, seed=seed,
-                                              chain=chain, sweep=sweep)
+                                              chain=chain, sweep=sweep, margins=margins)
     old = model.to_states(spins[z], d)
     _, lq_old, f_old = sampler.sample_layer(envs, J, F, z, beta, d, forced=old)
     dE = model.slice_energy(J, F, new, z, d) - model.slice_energy(J, F, old, z, d)

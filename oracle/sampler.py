@@ -57,11 +57,13 @@ def draw(p: np.ndarray, U: float) -> int:
 
 
 def sample_layer(envs, J, F, z: int, beta: float, d: int, *, forced=None,
-                 seed: int = 0, chain: int = 0, sweep: int = 0):
+                 seed: int = 0, chain: int = 0, sweep: int = 0, margins=None):
     """Draw a layer configuration (state indices [y, x]) and its log q.
 
     With ``forced`` given, the draws are replaced by the given states
-    (teacher forcing) and the result is log q(forced).
+    (teacher forcing) and the result is log q(forced).  If ``margins`` is a
+    list, the distance of every draw's uniform to the nearest cumulative
+    threshold is appended to it (to recognise near-ties).
     Returns (states, logq, fault)."""
     Ly, Lx, _ = F.shape
     sig = sig_table(d)
@@ -100,7 +102,10 @@ def sample_layer(envs, J, F, z: int, beta: float, d: int, *, forced=None,
             if forced is not None:
                 u = int(forced[y, x])
             else:
-                u = draw(p, uniform(seed, chain, sweep, z, PURPOSE_SITE, y * Lx + x))
+                U = uniform(seed, chain, sweep, z, PURPOSE_SITE, y * Lx + x)
+                u = draw(p, U)
+                if margins is not None:
+                    margins.append(float(np.min(np.abs(U - np.cumsum(p)[:-1]))))
             logq += float(np.log(p[u]))
             a[y, x] = u
             lvec = mvec[u]

@@ -1,0 +1,273 @@
+"""ctypes binding of libtnmc (include/tnmc.h): argument marshalling only.
+
+Every function has the name of the C entry point it calls.  Host arrays are
+numpy arrays; device buffers (``trace``) and streams are passed as integer
+addresses (for instance ``tensor.data_ptr()`` and
+``torch.cuda.current_stream().cuda_stream``).  Nothing here computes any part
+of the method: when the library is missing the first call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtnmc.so")
+HEADER_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "tnmc.h")
+
+TNMC_OK = 0
+TNMC_ERR_ARG = -1
+TNMC_ERR_OOM = -2
+TNMC_ERR_DEVICE = -3
+TNMC_ERR_NUMERIC = -4
+TNMC_ERR_UNSUPPORTED = -5
+TNMC_FP64 = 0
+TNMC_FP32 = 1
+
+__all__ = [
+    "TnmcError", "load", "declared_symbols", "tnmc_lattice_init", "tnmc_lattice_free", "tnmc_slice_propose",
+    "tnmc_slice_logq", "tnmc_mh_accept", "tnmc_sweep", "tnmc_half_sweep", "tnmc_get_spins", "tnmc_set_spins",
+    "tnmc_energy", "tnmc_timeseries", "tnmc_timeseries_reset", "tnmc_flop_model", "tnmc_status_string",
+    "tnmc_last_error", "Lattice",
+]
+
+
+class TnmcError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = f"{where}: {tnmc_status_string(status)} ({status})"
+        detail = tnmc_last_error()
+        if detail:
+            msg += f" [{detail}]"
+        super().__init__(msg)
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [
+        ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32),
+        ("d", ctypes.c_int32), ("chi", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("n_chains", ctypes.c_int32), ("n_instances", ctypes.c_int32),
+        ("J", ctypes.POINTER(ctypes.c_float)),
+        ("chain_instance", ctypes.POINTER(ctypes.c_int32)),
+        ("beta", ctypes.POINTER(ctypes.c_double)),
+        ("spins", ctypes.POINTER(ctypes.c_int8)),
+        ("seed", ctypes.c_uint64),
+        ("chain_key", ctypes.POINTER(ctypes.c_uint64)),
+        ("n_pairs", ctypes.c_int32),
+        ("pairs", ctypes.POINTER(ctypes.c_int32)),
+        ("record_capacity", ctypes.c_int32),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("proposed", ctypes.c_int64), ("accepted", ctypes.c_int64), ("numeric_faults", ctypes.c_int64),
+        ("contract_ms", ctypes.c_double), ("sample_ms", ctypes.c_double),
+        ("contract_launches", ctypes.c_int64), ("sample_launches", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libtnmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.tnmc_lattice_init.argtypes = [P(_Desc), P(vp)]
+    lib.tnmc_lattice_free.argtypes = [vp]
+    lib.tnmc_slice_propose.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, P(ctypes.c_int8),
+                                       P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double), vp]
+    lib.tnmc_slice_logq.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int8), P(ctypes.c_double), vp]
+    lib.tnmc_mh_accept.argtypes = [ctypes.c_double] * 5 + [P(ctypes.c_int32)]
+    lib.tnmc_sweep.argtypes = [P(vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
+                               ctypes.c_int32, P(_Stats), vp]
+    lib.tnmc_half_sweep.argtypes = [P(vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, vp, P(_Stats), vp]
+    lib.tnmc_get_spins.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int8)]
+    lib.tnmc_set_spins.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int8)]
+    lib.tnmc_energy.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double)]
+    lib.tnmc_timeseries.argtypes = [vp, P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
+                                    P(ctypes.c_int64)]
+    lib.tnmc_timeseries_reset.argtypes = [vp]
+    lib.tnmc_flop_model.argtypes = [ctypes.c_int32] * 4 + [P(ctypes.c_double), P(ctypes.c_double)]
+    lib.tnmc_status_string.argtypes = [ctypes.c_int]
+    lib.tnmc_status_string.restype = ctypes.c_char_p
+    lib.tnmc_last_error.argtypes = []
+    lib.tnmc_last_error.restype = ctypes.c_char_p
+    for name in ("tnmc_lattice_init", "tnmc_lattice_free", "tnmc_slice_propose", "tnmc_slice_logq",
+                 "tnmc_mh_accept", "tnmc_sweep", "tnmc_half_sweep", "tnmc_get_spins", "tnmc_set_spins",
+                 "tnmc_energy", "tnmc_timeseries", "tnmc_timeseries_reset", "tnmc_flop_model"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def declared_symbols(header: str = HEADER_PATH):
+    """Names of the functions declared in include/tnmc.h."""
+    text = open(header).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tnmc_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(status: int, where: str, allow=()):
+    if status != TNMC_OK and status not in allow:
+        raise TnmcError(status, where)
+    return status
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
+
+
+def tnmc_status_string(status: int) -> str:
+    return load().tnmc_status_string(status).decode()
+
+
+def tnmc_last_error() -> str:
+    return load().tnmc_last_error().decode()
+
+
+class Lattice:
+    """Handle of a tnmc_lattice plus its shape (host-side bookkeeping only)."""
+
+    def __init__(self, handle, Lx, Ly, Lz, d, chi, n_chains, n_pairs, record_capacity):
+        self.handle = handle
+        self.Lx, self.Ly, self.Lz, self.d, self.chi = Lx, Ly, Lz, d, chi
+        self.n_chains, self.n_pairs, self.record_capacity = n_chains, n_pairs, record_capacity
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.tnmc_lattice_free(self.handle)
+            self.handle = None
+
+
+def tnmc_lattice_init(*, Lx, Ly, Lz, d, chi, J, beta, spins, chain_instance=None, seed=0, chain_key=None,
+                      pairs=None, record_capacity=0, precision=TNMC_FP64) -> Lattice:
+    lib = load()
+    J = np.ascontiguousarray(J, dtype=np.float32)
+    spins = np.ascontiguousarray(spins, dtype=np.int8)
+    n_chains = spins.shape[0] if spins.ndim == 4 else 1
+    sites = Lx * Ly * Lz
+    if sites > 0:   # shapes are checked here; values and limits by the library
+        if spins.size != n_chains * sites or J.size % (3 * sites) != 0:
+            raise ValueError("spins / J do not match (Lx, Ly, Lz)")
+    n_inst = J.size // (3 * sites) if sites > 0 else 1
+    beta = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, dtype=np.float64), (n_chains,)))
+    ci = None if chain_instance is None else np.ascontiguousarray(chain_instance, dtype=np.int32)
+    ck = None if chain_key is None else np.ascontiguousarray(chain_key, dtype=np.uint64)
+    pr = np.zeros((0, 2), dtype=np.int32) if pairs is None else np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    if (ci is not None and ci.size != n_chains) or (ck is not None and ck.size != n_chains):
+        raise ValueError("chain_instance / chain_key need one entry per chain")
+    desc = _Desc(Lx, Ly, Lz, d, chi, precision, n_chains, n_inst, _ptr(J, ctypes.c_float),
+                 _ptr(ci, ctypes.c_int32), _ptr(beta, ctypes.c_double), _ptr(spins, ctypes.c_int8),
+                 ctypes.c_uint64(seed), _ptr(ck, ctypes.c_uint64), pr.shape[0],
+                 _ptr(pr, ctypes.c_int32) if pr.shape[0] else None, record_capacity)
+    h = ctypes.c_void_p()
+    _check(lib.tnmc_lattice_init(ctypes.byref(desc), ctypes.byref(h)), "tnmc_lattice_init")
+    return Lattice(h, Lx, Ly, Lz, d, chi, n_chains, pr.shape[0], record_capacity)
+
+
+def tnmc_lattice_free(lat: Lattice):
+    if lat.handle:
+        _check(load().tnmc_lattice_free(lat.handle), "tnmc_lattice_free")
+        lat.handle = None
+
+
+def tnmc_slice_propose(lat: Lattice, chain: int, z: int, sweep: int = 0, stream=None):
+    """Returns (s_new [Ly, Lx] int8, logq_new, logq_old, dE, status)."""
+    lib = load()
+    s_new = np.zeros((lat.Ly, lat.Lx), dtype=np.int8)
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st = lib.tnmc_slice_propose(lat.handle, chain, z, ctypes.c_uint64(sweep), _ptr(s_new, ctypes.c_int8),
+                                ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), stream)
+    _check(st, "tnmc_slice_propose", allow=(TNMC_ERR_NUMERIC,))
+    return s_new, a.value, b.value, c.value, st
+
+
+def tnmc_slice_logq(lat: Lattice, chain: int, z: int, s, stream=None) -> float:
+    s = np.ascontiguousarray(s, dtype=np.int8).reshape(lat.Ly, lat.Lx)
+    out = ctypes.c_double()
+    _check(load().tnmc_slice_logq(lat.handle, chain, z, _ptr(s, ctypes.c_int8), ctypes.byref(out), stream),
+           "tnmc_slice_logq")
+    return out.value
+
+
+def tnmc_mh_accept(logq_old: float, logq_new: float, beta: float, dE: float, u: float) -> bool:
+    acc = ctypes.c_int32()
+    _check(load().tnmc_mh_accept(logq_old, logq_new, beta, dE, u, ctypes.byref(acc)), "tnmc_mh_accept")
+    return bool(acc.value)
+
+
+def _handles(lats):
+    lats = list(lats) if isinstance(lats, (list, tuple)) else [lats]
+    arr = (ctypes.c_void_p * len(lats))(*[l.handle for l in lats])
+    return arr, len(lats)
+
+
+def tnmc_sweep(lats, n_sweeps: int, sweep_offset: int = 0, record: bool = False, time_kernels: bool = False,
+               stream=None) -> dict:
+    arr, n = _handles(lats)
+    st = _Stats()
+    _check(load().tnmc_sweep(arr, n, n_sweeps, ctypes.c_uint64(sweep_offset), int(record), int(time_kernels),
+                             ctypes.byref(st), stream), "tnmc_sweep")
+    return st.as_dict()
+
+
+def tnmc_half_sweep(lats, parity: int, sweep: int, trace_ptr=None, stream=None) -> dict:
+    arr, n = _handles(lats)
+    st = _Stats()
+    _check(load().tnmc_half_sweep(arr, n, parity, ctypes.c_uint64(sweep), trace_ptr, ctypes.byref(st), stream),
+           "tnmc_half_sweep")
+    return st.as_dict()
+
+
+def tnmc_get_spins(lat: Lattice, chain: int) -> np.ndarray:
+    out = np.zeros((lat.Lz, lat.Ly, lat.Lx), dtype=np.int8)
+    _check(load().tnmc_get_spins(lat.handle, chain, _ptr(out, ctypes.c_int8)), "tnmc_get_spins")
+    return out
+
+
+def tnmc_set_spins(lat: Lattice, chain: int, spins) -> None:
+    s = np.ascontiguousarray(spins, dtype=np.int8).reshape(lat.Lz, lat.Ly, lat.Lx)
+    _check(load().tnmc_set_spins(lat.handle, chain, _ptr(s, ctypes.c_int8)), "tnmc_set_spins")
+
+
+def tnmc_energy(lat: Lattice, chain: int) -> float:
+    e = ctypes.c_double()
+    _check(load().tnmc_energy(lat.handle, chain, ctypes.byref(e)), "tnmc_energy")
+    return e.value
+
+
+def tnmc_timeseries(lat: Lattice):
+    """Returns (E [n, n_chains], M [n, n_chains], q [n, n_pairs])."""
+    cap = max(lat.record_capacity, 1)
+    E = np.zeros((cap, lat.n_chains))
+    M = np.zeros((cap, lat.n_chains))
+    q = np.zeros((cap, max(lat.n_pairs, 1)))
+    n = ctypes.c_int64()
+    _check(load().tnmc_timeseries(lat.handle, _ptr(E, ctypes.c_double), _ptr(M, ctypes.c_double),
+                                  _ptr(q, ctypes.c_double), ctypes.byref(n)), "tnmc_timeseries")
+    k = n.value
+    return E[:k], M[:k], q[:k, : lat.n_pairs]
+
+
+def tnmc_timeseries_reset(lat: Lattice) -> None:
+    _check(load().tnmc_timeseries_reset(lat.handle), "tnmc_timeseries_reset")
+
+
+def tnmc_flop_model(Lx: int, Ly: int, d: int, chi: int):
+    """Returns (contraction flops, sampling flops) of one slice update."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(load().tnmc_flop_model(Lx, Ly, d, chi, ctypes.byref(a), ctypes.byref(b)), "tnmc_flop_model")
+    return a.value, b.value

@@ -1,0 +1,657 @@
+// Host side of libtnmc: the C ABI of include/tnmc.h.  Owns the lattice state
+// on the device, the per-task workspace (environments and R factors of every
+// slice task of a half-sweep), builds the task lists of the even/odd
+// half-sweeps and launches the contraction and sampling kernels on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tnmc.h"
+#include "tnmc_internal.h"
+
+using tnmc::TaskDesc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+#define HIP_TRY(expr)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      g_last_error = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+      return (e_ == hipErrorOutOfMemory) ? TNMC_ERR_OOM : TNMC_ERR_DEVICE;            \
+    }                                                                                 \
+  } while (0)
+
+constexpr int kLxMax = 64;
+constexpr int kLyMax = 64;
+
+}  // namespace
+
+struct tnmc_lattice {
+  int Lx = 0, Ly = 0, Lz = 0, d = 2, chi = 1, chi_max = 4, precision = TNMC_FP64;
+  int n_chains = 0, n_instances = 0, n_pairs = 0, record_capacity = 0;
+  int64_t n_recorded = 0;
+  uint64_t seed = 0;
+  std::vector<int> chain_instance;
+  std::vector<double> beta;
+  std::vector<uint64_t> chain_key;
+  std::vector<int> pairs;
+  float* dJ = nullptr;
+  int8_t* dspins = nullptr;
+  int* dpa = nullptr;
+  int* dpb = nullptr;
+  const float** dJc = nullptr;
+  int8_t** dSc = nullptr;
+  double* dErec = nullptr;
+  double* dMrec = nullptr;
+  double* dqrec = nullptr;
+  double* dscal = nullptr;
+  size_t sites() const { return (size_t)Lx * Ly * Lz; }
+  const float* J_of(int c) const { return dJ + (size_t)chain_instance[c] * 3 * sites(); }
+  int8_t* spins_of(int c) const { return dspins + (size_t)c * sites(); }
+};
+
+namespace {
+
+// Grow-only device buffers shared by all lattices of the process.
+struct Workspace {
+  std::mutex mu;
+  double* env = nullptr;
+  size_t env_cap = 0;
+  double* rscr = nullptr;
+  size_t rscr_cap = 0;
+  int* ints = nullptr;
+  size_t ints_cap = 0;
+  double* dbl = nullptr;
+  size_t dbl_cap = 0;
+  long long* counters = nullptr;
+  size_t counters_cap = 0;
+  TaskDesc* tasks = nullptr;
+  size_t tasks_cap = 0;
+  int8_t* bytes = nullptr;
+  size_t bytes_cap = 0;
+};
+Workspace g_ws;
+
+template <typename T>
+tnmc_status grow(T*& p, size_t& cap, size_t need) {
+  if (need <= cap) return TNMC_OK;
+  if (p) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(p));
+    p = nullptr;
+    cap = 0;
+  }
+  size_t n = std::max(need, (size_t)1);
+  HIP_TRY(hipMalloc((void**)&p, n * sizeof(T)));
+  cap = n;
+  return TNMC_OK;
+}
+
+struct Task {
+  tnmc_lattice* lat;
+  int chain;
+  int z;
+};
+
+// Builds the device descriptors of `tasks` at descriptor slot `slot0`, laid out
+// in the shared workspace, grouped by kernel instantiation.
+struct Plan {
+  std::vector<TaskDesc> desc;
+  struct Group {
+    int d, chi_max, first, count, lx_max;
+  };
+  std::vector<Group> groups;
+};
+
+tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
+  // order by instantiation so that each group is a contiguous launch
+  std::vector<int> order(tasks.size());
+  for (size_t i = 0; i < tasks.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const auto* la = tasks[a].lat;
+    const auto* lb = tasks[b].lat;
+    if (la->d != lb->d) return la->d < lb->d;
+    return la->chi_max < lb->chi_max;
+  });
+  size_t env_need = 0, rscr_need = 0, int_need = 0, dbl_need = 0;
+  for (int i : order) {
+    const auto* L = tasks[i].lat;
+    env_need += tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max);
+    rscr_need += tnmc::rscr_doubles(L->Lx, L->d, L->chi_max);
+    int_need += (size_t)L->Ly * L->Lx + L->Lx + 1;
+    dbl_need += (size_t)L->Ly;
+  }
+  if (grow(g_ws.env, g_ws.env_cap, env_need) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.rscr, g_ws.rscr_cap, rscr_need) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.ints, g_ws.ints_cap, int_need) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.dbl, g_ws.dbl_cap, dbl_need) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.counters, g_ws.counters_cap, 3 * tasks.size()) != TNMC_OK) return TNMC_ERR_OOM;
+  plan.desc.clear();
+  plan.groups.clear();
+  size_t eo = 0, ro = 0, io = 0, dof = 0;
+  for (size_t k = 0; k < order.size(); ++k) {
+    const Task& tk = tasks[order[k]];
+    const auto* L = tk.lat;
+    TaskDesc t;
+    std::memset(&t, 0, sizeof(t));
+    t.J = L->J_of(tk.chain);
+    t.spins = L->spins_of(tk.chain);
+    t.env = g_ws.env + eo;
+    t.rscr = g_ws.rscr + ro;
+    t.bond = g_ws.ints + io;
+    t.rrows = g_ws.ints + io + (size_t)L->Ly * L->Lx;
+    t.status = g_ws.ints + io + (size_t)L->Ly * L->Lx + L->Lx;
+    t.logscale = g_ws.dbl + dof;
+    t.counters = g_ws.counters + 3 * k;
+    t.beta = L->beta[tk.chain];
+    t.key0 = L->seed;
+    t.key1 = L->chain_key[tk.chain];
+    t.Lx = L->Lx;
+    t.Ly = L->Ly;
+    t.Lz = L->Lz;
+    t.z = tk.z;
+    t.chi = L->chi;
+    t.d = L->d;
+    t.chi_max = L->chi_max;
+    t.write_back = 1;
+    eo += tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max);
+    ro += tnmc::rscr_doubles(L->Lx, L->d, L->chi_max);
+    io += (size_t)L->Ly * L->Lx + L->Lx + 1;
+    dof += (size_t)L->Ly;
+    if (plan.groups.empty() || plan.groups.back().d != L->d || plan.groups.back().chi_max != L->chi_max) {
+      plan.groups.push_back({L->d, L->chi_max, (int)k, 0, 0});
+    }
+    plan.groups.back().count += 1;
+    plan.groups.back().lx_max = std::max(plan.groups.back().lx_max, L->Lx);
+    plan.desc.push_back(t);
+  }
+  return TNMC_OK;
+}
+
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> c_ev, s_ev;   // start/stop pairs
+  ~Timer() {
+    for (auto e : c_ev) (void)hipEventDestroy(e);
+    for (auto e : s_ev) (void)hipEventDestroy(e);
+  }
+  tnmc_status mark(std::vector<hipEvent_t>& v, hipStream_t s) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    v.push_back(e);
+    HIP_TRY(hipEventRecord(e, s));
+    return TNMC_OK;
+  }
+};
+
+// Launch the contraction and sampling kernels of a plan whose descriptors are at dtasks.
+tnmc_status launch_plan(const Plan& plan, const TaskDesc* dtasks, uint64_t sweep, hipStream_t s, Timer* tm,
+                        tnmc_stats* st) {
+  for (const auto& g : plan.groups) {
+    if (tm && tm->on && tm->mark(tm->c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+    HIP_TRY(tnmc::launch_contract(dtasks + g.first, g.count, g.d, g.chi_max, s));
+    if (tm && tm->on && tm->mark(tm->c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+    if (st) st->contract_launches += 1;
+  }
+  for (const auto& g : plan.groups) {
+    if (tm && tm->on && tm->mark(tm->s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+    HIP_TRY(tnmc::launch_sample(dtasks + g.first, g.count, g.d, g.chi_max, g.lx_max, sweep, s));
+    if (tm && tm->on && tm->mark(tm->s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+    if (st) st->sample_launches += 1;
+  }
+  return TNMC_OK;
+}
+
+std::vector<Task> half_sweep_tasks(tnmc_lattice* const* lats, int n_lats, int parity) {
+  std::vector<Task> v;
+  for (int l = 0; l < n_lats; ++l)
+    for (int c = 0; c < lats[l]->n_chains; ++c)
+      for (int z = parity; z < lats[l]->Lz; z += 2) v.push_back({lats[l], c, z});
+  return v;
+}
+
+tnmc_status check_lats(tnmc_lattice* const* lats, int n_lats) {
+  if (!lats || n_lats < 1) return TNMC_ERR_ARG;
+  for (int i = 0; i < n_lats; ++i)
+    if (!lats[i]) return TNMC_ERR_ARG;
+  return TNMC_OK;
+}
+
+tnmc_status read_counters(size_t n_tasks, tnmc_stats* st) {
+  std::vector<long long> c(3 * n_tasks);
+  HIP_TRY(hipMemcpy(c.data(), g_ws.counters, c.size() * sizeof(long long), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < n_tasks; ++i) {
+    st->proposed += c[3 * i];
+    st->accepted += c[3 * i + 1];
+    st->numeric_faults += c[3 * i + 2];
+  }
+  return TNMC_OK;
+}
+
+tnmc_status finish_timer(Timer& tm, tnmc_stats* st) {
+  if (!tm.on || !st) return TNMC_OK;
+  auto sum = [](std::vector<hipEvent_t>& v, double& acc) -> tnmc_status {
+    for (size_t i = 0; i + 1 < v.size(); i += 2) {
+      HIP_TRY(hipEventSynchronize(v[i + 1]));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, v[i], v[i + 1]));
+      acc += ms;
+    }
+    return TNMC_OK;
+  };
+  tnmc_status r = sum(tm.c_ev, st->contract_ms);
+  if (r != TNMC_OK) return r;
+  return sum(tm.s_ev, st->sample_ms);
+}
+
+// One task run with optional forced layer; used by propose / logq.
+tnmc_status run_single(tnmc_lattice* lat, int chain, int z, uint64_t sweep, const int8_t* force_host,
+                       int8_t* s_new_host, double* rec_host, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  std::vector<Task> tasks{{lat, chain, z}};
+  Plan plan;
+  tnmc_status r = make_plan(tasks, plan);
+  if (r != TNMC_OK) return r;
+  const size_t plane = (size_t)lat->Lx * lat->Ly;
+  if (grow(g_ws.bytes, g_ws.bytes_cap, 2 * plane) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.tasks, g_ws.tasks_cap, (size_t)1) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.dbl, g_ws.dbl_cap, (size_t)lat->Ly + 8) != TNMC_OK) return TNMC_ERR_OOM;
+  double* drec = g_ws.dbl + lat->Ly;   // after this task's logscale
+  plan.desc[0].logscale = g_ws.dbl;
+  plan.desc[0].record = drec;
+  plan.desc[0].counters = nullptr;
+  plan.desc[0].write_back = 0;
+  plan.desc[0].s_new_out = g_ws.bytes;
+  if (force_host) {
+    HIP_TRY(hipMemcpyAsync(g_ws.bytes + plane, force_host, plane, hipMemcpyHostToDevice, s));
+    plan.desc[0].force_new = g_ws.bytes + plane;
+  }
+  HIP_TRY(hipMemcpyAsync(g_ws.tasks, plan.desc.data(), sizeof(TaskDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));   // host buffers above are released on return
+  r = launch_plan(plan, g_ws.tasks, sweep, s, nullptr, nullptr);
+  if (r != TNMC_OK) return r;
+  if (s_new_host) HIP_TRY(hipMemcpyAsync(s_new_host, g_ws.bytes, plane, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(rec_host, drec, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return TNMC_OK;
+}
+
+double qr_flops(double m, double n) {   // Householder, R only
+  if (m >= n) return 2.0 * n * n * (m - n / 3.0);
+  return 2.0 * m * m * (n - m / 3.0);
+}
+double svd_flops(double m, double n) {  // Golub-Reinsch, singular values and right vectors
+  const double a = std::max(m, n), b = std::min(m, n);
+  return 4.0 * a * b * b + 8.0 * b * b * b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tnmc_status_string(tnmc_status s) {
+  switch (s) {
+    case TNMC_OK: return "ok";
+    case TNMC_ERR_ARG: return "invalid argument";
+    case TNMC_ERR_OOM: return "device out of memory";
+    case TNMC_ERR_DEVICE: return "HIP error";
+    case TNMC_ERR_NUMERIC: return "numeric fault";
+    case TNMC_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+const char* tnmc_last_error(void) { return g_last_error.c_str(); }
+
+tnmc_status tnmc_mh_accept(double logq_old, double logq_new, double beta, double dE, double u, int32_t* accepted) {
+  if (!accepted || !(u > 0.0 && u < 1.0) || !std::isfinite(beta)) return TNMC_ERR_ARG;
+  const double lr = logq_old - logq_new - beta * dE;
+  *accepted = (u < std::exp(std::min(0.0, lr))) ? 1 : 0;
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_lattice_init(const tnmc_lattice_desc* ds, tnmc_lattice** out) {
+  if (!ds || !out) return TNMC_ERR_ARG;
+  if (ds->Lx < 1 || ds->Ly < 1 || ds->Lz < 1 || ds->Lx > kLxMax || ds->Ly > kLyMax) return TNMC_ERR_ARG;
+  if (ds->d != 2 && ds->d != 3) return TNMC_ERR_ARG;
+  if (ds->chi < 1 || ds->n_chains < 1 || ds->n_instances < 1 || !ds->J || !ds->beta || !ds->spins)
+    return TNMC_ERR_ARG;
+  if (ds->n_pairs < 0 || (ds->n_pairs > 0 && !ds->pairs) || ds->record_capacity < 0) return TNMC_ERR_ARG;
+  if (ds->precision != TNMC_FP64) return TNMC_ERR_UNSUPPORTED;
+  const int cm = tnmc::chi_bucket(ds->chi);
+  if (cm == 0 || !tnmc::contract_supported(ds->d, cm)) return TNMC_ERR_UNSUPPORTED;
+  for (int c = 0; c < ds->n_chains; ++c) {
+    const int inst = ds->chain_instance ? ds->chain_instance[c] : c % ds->n_instances;
+    if (inst < 0 || inst >= ds->n_instances) return TNMC_ERR_ARG;
+    if (!(ds->beta[c] >= 0.0) || !std::isfinite(ds->beta[c])) return TNMC_ERR_ARG;
+  }
+  for (int p = 0; p < 2 * ds->n_pairs; ++p)
+    if (ds->pairs[p] < 0 || ds->pairs[p] >= ds->n_chains) return TNMC_ERR_ARG;
+  const size_t n = (size_t)ds->Lx * ds->Ly * ds->Lz;
+  for (size_t i = 0; i < n * ds->n_chains; ++i) {
+    const int v = ds->spins[i];
+    if (ds->d == 2 ? (v != 1 && v != -1) : (v < 0 || v >= ds->d)) return TNMC_ERR_ARG;
+  }
+  auto* L = new tnmc_lattice();
+  L->Lx = ds->Lx;
+  L->Ly = ds->Ly;
+  L->Lz = ds->Lz;
+  L->d = ds->d;
+  L->chi = ds->chi;
+  L->chi_max = cm;
+  L->precision = ds->precision;
+  L->n_chains = ds->n_chains;
+  L->n_instances = ds->n_instances;
+  L->n_pairs = ds->n_pairs;
+  L->record_capacity = ds->record_capacity;
+  L->seed = ds->seed;
+  L->chain_instance.resize(ds->n_chains);
+  L->beta.assign(ds->beta, ds->beta + ds->n_chains);
+  L->chain_key.resize(ds->n_chains);
+  for (int c = 0; c < ds->n_chains; ++c) {
+    L->chain_instance[c] = ds->chain_instance ? ds->chain_instance[c] : c % ds->n_instances;
+    L->chain_key[c] = ds->chain_key ? ds->chain_key[c] : (uint64_t)c;
+  }
+  L->pairs.assign(ds->pairs, ds->pairs + 2 * ds->n_pairs);
+  auto fail = [&](tnmc_status r) {
+    tnmc_lattice_free(L);
+    return r;
+  };
+#define INIT_TRY(expr)                                                   \
+  do {                                                                   \
+    hipError_t e_ = (expr);                                              \
+    if (e_ != hipSuccess) {                                              \
+      g_last_error = std::string(#expr) + ": " + hipGetErrorString(e_);  \
+      return fail(e_ == hipErrorOutOfMemory ? TNMC_ERR_OOM : TNMC_ERR_DEVICE); \
+    }                                                                    \
+  } while (0)
+  INIT_TRY(hipMalloc((void**)&L->dJ, (size_t)ds->n_instances * 3 * n * sizeof(float)));
+  INIT_TRY(hipMemcpy(L->dJ, ds->J, (size_t)ds->n_instances * 3 * n * sizeof(float), hipMemcpyHostToDevice));
+  INIT_TRY(hipMalloc((void**)&L->dspins, (size_t)ds->n_chains * n));
+  INIT_TRY(hipMemcpy(L->dspins, ds->spins, (size_t)ds->n_chains * n, hipMemcpyHostToDevice));
+  std::vector<const float*> jc(ds->n_chains);
+  std::vector<int8_t*> sc(ds->n_chains);
+  for (int c = 0; c < ds->n_chains; ++c) {
+    jc[c] = L->J_of(c);
+    sc[c] = L->spins_of(c);
+  }
+  INIT_TRY(hipMalloc((void**)&L->dJc, ds->n_chains * sizeof(float*)));
+  INIT_TRY(hipMemcpy(L->dJc, jc.data(), ds->n_chains * sizeof(float*), hipMemcpyHostToDevice));
+  INIT_TRY(hipMalloc((void**)&L->dSc, ds->n_chains * sizeof(int8_t*)));
+  INIT_TRY(hipMemcpy(L->dSc, sc.data(), ds->n_chains * sizeof(int8_t*), hipMemcpyHostToDevice));
+  if (ds->n_pairs > 0) {
+    std::vector<int> pa(ds->n_pairs), pb(ds->n_pairs);
+    for (int p = 0; p < ds->n_pairs; ++p) {
+      pa[p] = ds->pairs[2 * p];
+      pb[p] = ds->pairs[2 * p + 1];
+    }
+    INIT_TRY(hipMalloc((void**)&L->dpa, ds->n_pairs * sizeof(int)));
+    INIT_TRY(hipMemcpy(L->dpa, pa.data(), ds->n_pairs * sizeof(int), hipMemcpyHostToDevice));
+    INIT_TRY(hipMalloc((void**)&L->dpb, ds->n_pairs * sizeof(int)));
+    INIT_TRY(hipMemcpy(L->dpb, pb.data(), ds->n_pairs * sizeof(int), hipMemcpyHostToDevice));
+  }
+  const size_t cap = std::max(1, ds->record_capacity);
+  INIT_TRY(hipMalloc((void**)&L->dErec, cap * ds->n_chains * sizeof(double)));
+  INIT_TRY(hipMalloc((void**)&L->dMrec, cap * ds->n_chains * sizeof(double)));
+  INIT_TRY(hipMalloc((void**)&L->dqrec, cap * std::max(1, ds->n_pairs) * sizeof(double)));
+  INIT_TRY(hipMalloc((void**)&L->dscal, 8 * sizeof(double)));
+#undef INIT_TRY
+  *out = L;
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_lattice_free(tnmc_lattice* L) {
+  if (!L) return TNMC_ERR_ARG;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {L->dJ, L->dspins, L->dpa, L->dpb, (void*)L->dJc, (void*)L->dSc,
+                  L->dErec, L->dMrec, L->dqrec, L->dscal};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete L;
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_slice_propose(tnmc_lattice* lat, int32_t chain, int32_t z, uint64_t sweep, int8_t* s_new,
+                               double* logq_new, double* logq_old, double* dE, void* stream) {
+  if (!lat || chain < 0 || chain >= lat->n_chains || z < 0 || z >= lat->Lz) return TNMC_ERR_ARG;
+  if (!s_new || !logq_new || !logq_old || !dE) return TNMC_ERR_ARG;
+  double rec[5];
+  tnmc_status r = run_single(lat, chain, z, sweep, nullptr, s_new, rec, (hipStream_t)stream);
+  if (r != TNMC_OK) return r;
+  *logq_new = rec[0];
+  *logq_old = rec[1];
+  *dE = rec[2];
+  if (rec[4] != 0.0 || !std::isfinite(rec[0]) || !std::isfinite(rec[1])) return TNMC_ERR_NUMERIC;
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_slice_logq(tnmc_lattice* lat, int32_t chain, int32_t z, const int8_t* s, double* logq,
+                            void* stream) {
+  if (!lat || chain < 0 || chain >= lat->n_chains || z < 0 || z >= lat->Lz || !s || !logq) return TNMC_ERR_ARG;
+  const size_t plane = (size_t)lat->Lx * lat->Ly;
+  for (size_t i = 0; i < plane; ++i) {
+    const int v = s[i];
+    if (lat->d == 2 ? (v != 1 && v != -1) : (v < 0 || v >= lat->d)) return TNMC_ERR_ARG;
+  }
+  double rec[5];
+  tnmc_status r = run_single(lat, chain, z, 0, s, nullptr, rec, (hipStream_t)stream);
+  if (r != TNMC_OK) return r;
+  *logq = rec[0];
+  if (!std::isfinite(rec[0])) return TNMC_ERR_NUMERIC;
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_half_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t parity, uint64_t sweep,
+                            double* trace, tnmc_stats* stats, void* stream) {
+  if (check_lats(lats, n_lats) != TNMC_OK || (parity != 0 && parity != 1)) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  hipStream_t s = (hipStream_t)stream;
+  auto tasks = half_sweep_tasks(lats, n_lats, parity);
+  Plan plan;
+  tnmc_status r = make_plan(tasks, plan);
+  if (r != TNMC_OK) return r;
+  // trace order is the task order (lattice, chain, z); plan order may differ
+  std::vector<int> pos(tasks.size());
+  {
+    size_t k = 0;
+    // make_plan orders by (d, chi_max) with a stable sort; recompute that permutation
+    std::vector<int> order(tasks.size());
+    for (size_t i = 0; i < tasks.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      const auto* la = tasks[a].lat;
+      const auto* lb = tasks[b].lat;
+      if (la->d != lb->d) return la->d < lb->d;
+      return la->chi_max < lb->chi_max;
+    });
+    for (int i : order) pos[k++] = i;
+  }
+  for (size_t k = 0; k < plan.desc.size(); ++k) {
+    plan.desc[k].record = trace ? trace + 5 * (size_t)pos[k] : nullptr;
+  }
+  if (grow(g_ws.tasks, g_ws.tasks_cap, plan.desc.size()) != TNMC_OK) return TNMC_ERR_OOM;
+  HIP_TRY(hipMemcpyAsync(g_ws.tasks, plan.desc.data(), plan.desc.size() * sizeof(TaskDesc),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (stats) HIP_TRY(hipMemsetAsync(g_ws.counters, 0, 3 * tasks.size() * sizeof(long long), s));
+  Timer tm;
+  tm.on = (stats != nullptr);
+  r = launch_plan(plan, g_ws.tasks, sweep, s, &tm, stats);
+  if (r != TNMC_OK) return r;
+  if (stats) {
+    HIP_TRY(hipStreamSynchronize(s));
+    r = read_counters(tasks.size(), stats);
+    if (r != TNMC_OK) return r;
+    r = finish_timer(tm, stats);
+    if (r != TNMC_OK) return r;
+  }
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
+                       int32_t record, int32_t time_kernels, tnmc_stats* stats, void* stream) {
+  if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<Task> tasks[2] = {half_sweep_tasks(lats, n_lats, 0), half_sweep_tasks(lats, n_lats, 1)};
+  // Both parities share the workspace (they run one after the other).  A plan
+  // may grow the workspace and so move it: plan parity 0 again afterwards so
+  // that both plans point into the final buffers.
+  Plan plan[2];
+  for (int p : {0, 1, 0}) {
+    tnmc_status r = make_plan(tasks[p], plan[p]);
+    if (r != TNMC_OK) return r;
+  }
+  const size_t n0 = plan[0].desc.size(), n1 = plan[1].desc.size();
+  const size_t per_sweep = n0 + n1;
+  if (grow(g_ws.counters, g_ws.counters_cap, 3 * per_sweep) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.tasks, g_ws.tasks_cap, per_sweep) != TNMC_OK) return TNMC_ERR_OOM;
+  for (size_t k = 0; k < n0; ++k) plan[0].desc[k].counters = g_ws.counters + 3 * k;
+  for (size_t k = 0; k < n1; ++k) plan[1].desc[k].counters = g_ws.counters + 3 * (n0 + k);
+  std::vector<TaskDesc> all(plan[0].desc);
+  all.insert(all.end(), plan[1].desc.begin(), plan[1].desc.end());
+  HIP_TRY(hipMemcpyAsync(g_ws.tasks, all.data(), per_sweep * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));   // `all` is released on return
+  HIP_TRY(hipMemsetAsync(g_ws.counters, 0, 3 * per_sweep * sizeof(long long), s));
+  Timer tm;
+  tm.on = (time_kernels != 0 && stats != nullptr);
+  for (int t = 0; t < n_sweeps; ++t) {
+    const uint64_t sw = sweep_offset + (uint64_t)t;
+    tnmc_status r = launch_plan(plan[0], g_ws.tasks, sw, s, &tm, stats);
+    if (r != TNMC_OK) return r;
+    r = launch_plan(plan[1], g_ws.tasks + n0, sw, s, &tm, stats);
+    if (r != TNMC_OK) return r;
+    if (record) {
+      for (int l = 0; l < n_lats; ++l) {
+        tnmc_lattice* L = lats[l];
+        if (L->n_recorded >= L->record_capacity) continue;
+        const int64_t i = L->n_recorded++;
+        HIP_TRY(tnmc::launch_observables(L->dJc, L->dSc, L->n_chains, L->dpa, L->dpb, L->n_pairs, L->Lx, L->Ly,
+                                         L->Lz, L->d, L->dErec + i * L->n_chains, L->dMrec + i * L->n_chains,
+                                         L->dqrec + i * std::max(1, L->n_pairs), s));
+      }
+    }
+  }
+  if (stats) {
+    HIP_TRY(hipStreamSynchronize(s));
+    tnmc_status r = read_counters(per_sweep, stats);
+    if (r != TNMC_OK) return r;
+    r = finish_timer(tm, stats);
+    if (r != TNMC_OK) return r;
+  }
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_get_spins(tnmc_lattice* L, int32_t chain, int8_t* out) {
+  if (!L || !out || chain < 0 || chain >= L->n_chains) return TNMC_ERR_ARG;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(out, L->spins_of(chain), L->sites(), hipMemcpyDeviceToHost));
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_set_spins(tnmc_lattice* L, int32_t chain, const int8_t* in) {
+  if (!L || !in || chain < 0 || chain >= L->n_chains) return TNMC_ERR_ARG;
+  for (size_t i = 0; i < L->sites(); ++i) {
+    const int v = in[i];
+    if (L->d == 2 ? (v != 1 && v != -1) : (v < 0 || v >= L->d)) return TNMC_ERR_ARG;
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(L->spins_of(chain), in, L->sites(), hipMemcpyHostToDevice));
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_energy(tnmc_lattice* L, int32_t chain, double* E) {
+  if (!L || !E || chain < 0 || chain >= L->n_chains) return TNMC_ERR_ARG;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(tnmc::launch_energy(L->J_of(chain), L->spins_of(chain), L->Lx, L->Ly, L->Lz, L->d, L->dscal, 0));
+  HIP_TRY(hipMemcpy(E, L->dscal, sizeof(double), hipMemcpyDeviceToHost));
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_timeseries(tnmc_lattice* L, double* E, double* M, double* q, int64_t* n) {
+  if (!L || !n) return TNMC_ERR_ARG;
+  HIP_TRY(hipDeviceSynchronize());
+  const int64_t k = L->n_recorded;
+  if (E && k) HIP_TRY(hipMemcpy(E, L->dErec, k * L->n_chains * sizeof(double), hipMemcpyDeviceToHost));
+  if (M && k) HIP_TRY(hipMemcpy(M, L->dMrec, k * L->n_chains * sizeof(double), hipMemcpyDeviceToHost));
+  if (q && k && L->n_pairs > 0)
+    HIP_TRY(hipMemcpy(q, L->dqrec, k * L->n_pairs * sizeof(double), hipMemcpyDeviceToHost));
+  *n = k;
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_timeseries_reset(tnmc_lattice* L) {
+  if (!L) return TNMC_ERR_ARG;
+  L->n_recorded = 0;
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_flop_model(int32_t Lx, int32_t Ly, int32_t d, int32_t chi, double* contract_flops,
+                            double* sample_flops) {
+  if (Lx < 1 || Ly < 1 || (d != 2 && d != 3) || chi < 1) return TNMC_ERR_ARG;
+  // bond dimensions of the environments: exact caps min(d^(x+1), d^(Lx-1-x), chi)
+  auto cap = [&](int x) -> double {   // right bond of site x (x < Lx-1)
+    double a = 1.0, b = 1.0;
+    for (int i = 0; i <= x && a < 1e9; ++i) a *= d;
+    for (int i = 0; i < Lx - 1 - x && b < 1e9; ++i) b *= d;
+    return std::min<double>(std::min(a, b), chi);
+  };
+  double total = 0.0;
+  // rows below the top: E_{Ly-2} is built from the trivial E_{Ly-1} (bonds 1),
+  // every other row from a chi-capped environment
+  for (int y = Ly - 1; y >= 1; --y) {
+    const bool trivial = (y == Ly - 1);
+    auto bnd = [&](int x) -> double { return (x < 0 || x >= Lx - 1 || trivial) ? 1.0 : cap(x); };
+    // left sweep
+    double rR = 1.0;
+    std::vector<double> rrows(Lx, 1.0);
+    for (int x = 0; x < Lx - 1; ++x) {
+      const double cl = bnd(x - 1), cr = bnd(x);
+      const double m = rR * d, n = cr * d;
+      total += 2.0 * rR * d * cr * cl;   // M = G (R~ A)
+      total += qr_flops(m, n);
+      rR = std::min(m, n);
+      rrows[x] = rR;
+    }
+    // right sweep
+    double k = 1.0;
+    for (int x = Lx - 1; x >= 1; --x) {
+      const double cl = bnd(x - 1), cr = bnd(x);
+      const double rr = rrows[x - 1];
+      const double nC = d * k;
+      total += 2.0 * d * cl * cr * k;            // AT
+      total += 2.0 * rr * d * cl * k;            // Z
+      total += 2.0 * rr * d * d * k;             // C
+      total += svd_flops(rr, nC);
+      const double kx = std::min<double>(chi, std::min(rr, nC));
+      total += 2.0 * kx * d * d * k;             // V~
+      total += 2.0 * cl * d * kx * k;            // Y
+      total += 2.0 * cl * d * d * kx;            // T
+      k = kx;
+    }
+  }
+  if (contract_flops) *contract_flops = total;
+  total = 0.0;
+  // sampling: two paths, right environments and draws over every row
+  for (int y = 0; y < Ly; ++y) {
+    for (int x = 0; x < Lx; ++x) {
+      const double cl = (x > 0 && y < Ly - 1) ? cap(x - 1) : 1.0;
+      const double cr = (x < Lx - 1 && y < Ly - 1) ? cap(x) : 1.0;
+      total += 2.0 * (2.0 * d * cl * cr + 2.0 * d * cl * cr);
+    }
+  }
+  if (sample_flops) *sample_flops = total;
+  return TNMC_OK;
+}
+
+}  // extern "C"

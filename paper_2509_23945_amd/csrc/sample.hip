@@ -1,0 +1,381 @@
+// Ancestral sampling of a layer from its cached boundary-MPS environments,
+// exact log q of the drawn layer and of the current one (teacher forcing),
+// energy change and Metropolis-Hastings decision (main text "TNMCMC" and
+// Eq. 1; SM S1.C; SM Alg. 2).  One workgroup of two wavefronts per slice task:
+// wavefront 0 draws the new layer, wavefront 1 walks the current layer in lock
+// step (same environments, same row order), so both log q's come from one
+// pass over the environments.
+//
+// Row y is conditioned on the row above through the vertical bonds and on the
+// rows below through E_y.  Within a row, right environments
+//   R_x(al; t) = sum_u exp(beta (Ft(x,u) + Jx(x-1) sig(t,u))) sum_be A_x[u]_{al,be} R_{x+1}(be; u)
+// (t = state of site x-1) are built right to left, then the sites are drawn
+// left to right with weights
+//   w(u) = exp(beta (Ft(x,u) + Jx(x-1) sig(s_{x-1},u))) (l A_x[u]) . R_{x+1}(.; u).
+// Weights are clamped at 0, normalised, floored at 1e-12 and normalised again;
+// the state is the first u with U < p(0)+...+p(u).
+
+#include "device_common.h"
+#include "tnmc_internal.h"
+
+namespace tnmc {
+
+namespace {
+
+constexpr int LXMAX = 64;
+constexpr int LYMAX = 64;
+constexpr double P_FLOOR = 1e-12;
+
+template <int DP, int CHIM>
+struct SampleShared {
+  double l[2][CHIM];                  // left vector per path
+  double ft[2][LXMAX][DP];            // beta * (field + vertical bond to the row above)
+  double jx[LXMAX];                   // beta * Jx(x-1, y)
+  double lq[2];
+  int fault[2];
+  int8_t cfg[2][LYMAX][LXMAX];        // state indices of both paths
+};
+
+template <int DP, int CHIM>
+__global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict__ tasks, uint64_t sweep) {
+  __shared__ SampleShared<DP, CHIM> sh;
+  extern __shared__ double sR[];        // right environments [2][Lx+1][CHIM][DP]
+  constexpr int SITE = DP * CHIM * CHIM;
+  const TaskDesc& t = tasks[blockIdx.x];
+  const int path = threadIdx.x >> 6;     // 0: new layer (drawn), 1: current layer (forced)
+  const int lane = threadIdx.x & 63;
+  const int Lx = t.Lx, Ly = t.Ly, Lz = t.Lz, z = t.z;
+  const double beta = t.beta;
+  const float* __restrict__ J = t.J;
+  int8_t* __restrict__ spins = t.spins;
+  const size_t plane = (size_t)Lx * Ly;
+  const int8_t* forced = (path == 1) ? spins + (size_t)z * plane : t.force_new;
+  const bool contract_fault = (*t.status) != 0;
+  double* Rp = sR + (size_t)path * (Lx + 1) * CHIM * DP;
+#define RENV(x, al, u) Rp[((size_t)(x) * CHIM + (al)) * DP + (u)]
+
+  double logq = 0.0;
+  int fault = 0;
+  for (int y = 0; y < Ly; ++y) {
+    const double* envY = t.env + (size_t)y * Lx * SITE;
+    const int* bondY = t.bond + y * Lx;
+    for (int x = lane; x < Lx; x += 64) {
+      const double jy = (y > 0) ? (double)J[plane * Lz + (size_t)z * plane + (size_t)(y - 1) * Lx + x] : 0.0;
+      const int above = (y > 0) ? sh.cfg[path][y - 1][x] : 0;
+#pragma unroll
+      for (int u = 0; u < DP; ++u) {
+        double f = held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, u);
+        if (y > 0) f += jy * sigma<DP>(u, above);
+        sh.ft[path][x][u] = beta * f;
+      }
+      if (path == 0) sh.jx[x] = (x > 0) ? beta * (double)J[(size_t)z * plane + (size_t)y * Lx + (x - 1)] : 0.0;
+    }
+    if (lane < CHIM) {
+#pragma unroll
+      for (int u = 0; u < DP; ++u) RENV(Lx, lane, u) = (lane == 0) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // right environments R_x, x = Lx-1 .. 1
+    for (int x = Lx - 1; x >= 1; --x) {
+      const int cl = bondY[x - 1];
+      const int cr = bondY[x];
+      const double* A = envY + (size_t)x * SITE;
+      double v[DP];
+#pragma unroll
+      for (int u = 0; u < DP; ++u) v[u] = 0.0;
+      if (lane < cl) {
+#pragma unroll
+        for (int u = 0; u < DP; ++u) {
+          double s = 0.0;
+          for (int be = 0; be < cr; ++be) s += A[(size_t)(u * CHIM + lane) * CHIM + be] * RENV(x + 1, be, u);
+          v[u] = s;
+        }
+      }
+      double rt[DP];
+      double mx = 0.0;
+#pragma unroll
+      for (int tt = 0; tt < DP; ++tt) {
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < DP; ++u) s += v[u] * exp(sh.ft[path][x][u] + sh.jx[x] * sigma<DP>(tt, u));
+        rt[tt] = s;
+        mx = fmax(mx, fabs(s));
+      }
+      mx = wave_max(mx);
+      const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
+      if (lane < CHIM) {
+#pragma unroll
+        for (int tt = 0; tt < DP; ++tt) RENV(x, lane, tt) = rt[tt] * inv;
+      }
+      __syncthreads();
+    }
+    // draws, x = 0 .. Lx-1
+    if (lane < CHIM) sh.l[path][lane] = (lane == 0) ? 1.0 : 0.0;
+    __syncthreads();
+    int prev = 0;
+    for (int x = 0; x < Lx; ++x) {
+      const int cl = (x > 0) ? bondY[x - 1] : 1;
+      const int cr = bondY[x];
+      const double* A = envY + (size_t)x * SITE;
+      double m[DP];
+      double part[DP];
+#pragma unroll
+      for (int u = 0; u < DP; ++u) {
+        m[u] = 0.0;
+        part[u] = 0.0;
+      }
+      if (lane < cr) {
+#pragma unroll
+        for (int u = 0; u < DP; ++u) {
+          double s = 0.0;
+          for (int al = 0; al < cl; ++al) s += sh.l[path][al] * A[(size_t)(u * CHIM + al) * CHIM + lane];
+          m[u] = s;
+          part[u] = s * RENV(x + 1, lane, u);
+        }
+      }
+      double w[DP];
+      double wsum = 0.0;
+      bool bad = false;
+#pragma unroll
+      for (int u = 0; u < DP; ++u) {
+        const double loc = sh.ft[path][x][u] + ((x > 0) ? sh.jx[x] * sigma<DP>(prev, u) : 0.0);
+        const double wu = exp(loc) * wave_sum(part[u]);
+        if (!isfinite(wu)) bad = true;
+        w[u] = fmax(wu, 0.0);
+        wsum += w[u];
+      }
+      double p[DP];
+      if (bad || !(wsum > 0.0) || !isfinite(wsum)) {
+        fault = 1;
+#pragma unroll
+        for (int u = 0; u < DP; ++u) p[u] = 1.0 / DP;
+      } else {
+        double ps = 0.0;
+#pragma unroll
+        for (int u = 0; u < DP; ++u) {
+          p[u] = fmax(w[u] / wsum, P_FLOOR);
+          ps += p[u];
+        }
+#pragma unroll
+        for (int u = 0; u < DP; ++u) p[u] /= ps;
+      }
+      int s;
+      if (forced != nullptr) {
+        s = state_of<DP>(forced[(size_t)y * Lx + x]);
+      } else {
+        const double U = philox_uniform((uint64_t)(y * Lx + x), (uint64_t)z, sweep, 0ull, t.key0, t.key1);
+        s = DP - 1;
+        double c = 0.0;
+#pragma unroll
+        for (int u = 0; u < DP - 1; ++u) {
+          c += p[u];
+          if (U < c) {
+            s = u;
+            break;
+          }
+        }
+      }
+      s = __shfl(s, 0);
+      double lv = 0.0, pchosen = p[0];
+#pragma unroll
+      for (int u = 0; u < DP; ++u)
+        if (u == s) {
+          lv = m[u];
+          pchosen = p[u];
+        }
+      logq += log(pchosen);
+      const double lm = wave_max(fabs(lv));
+      if (!(lm > 0.0) || !isfinite(lm)) fault = 1;
+      const double inv = (lm > 0.0 && isfinite(lm)) ? 1.0 / lm : 1.0;
+      __syncthreads();   // everyone has read l before it is replaced
+      if (lane < CHIM) sh.l[path][lane] = (lane < cr) ? lv * inv : 0.0;
+      if (lane == 0) sh.cfg[path][y][x] = (int8_t)s;
+      prev = s;
+      __syncthreads();
+    }
+  }
+  if (lane == 0) {
+    sh.lq[path] = logq;
+    sh.fault[path] = fault;
+  }
+  __syncthreads();
+  if (path != 0) return;
+
+  // energy change E(new) - E(current) of the layer: in-layer bonds and held-layer field
+  double dE = 0.0;
+  for (int i = lane; i < Ly * Lx; i += 64) {
+    const int y = i / Lx, x = i % Lx;
+    const int a = sh.cfg[0][y][x], o = sh.cfg[1][y][x];
+    double e = -(held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, a) - held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, o));
+    if (x + 1 < Lx) {
+      const double jx = (double)J[(size_t)z * plane + (size_t)y * Lx + x];
+      e -= jx * (sigma<DP>(a, sh.cfg[0][y][x + 1]) - sigma<DP>(o, sh.cfg[1][y][x + 1]));
+    }
+    if (y + 1 < Ly) {
+      const double jy = (double)J[plane * Lz + (size_t)z * plane + (size_t)y * Lx + x];
+      e -= jy * (sigma<DP>(a, sh.cfg[0][y + 1][x]) - sigma<DP>(o, sh.cfg[1][y + 1][x]));
+    }
+    dE += e;
+  }
+  dE = wave_sum(dE);
+  const double lq_new = sh.lq[0], lq_old = sh.lq[1];
+  const int any_fault = sh.fault[0] | sh.fault[1] | (contract_fault ? 1 : 0);
+  const double lr = lq_old - lq_new - beta * dE;
+  const double Uacc = philox_uniform(0ull, (uint64_t)z, sweep, 1ull, t.key0, t.key1);
+  const int accepted = (!any_fault && Uacc < exp(fmin(0.0, lr))) ? 1 : 0;
+  if (t.s_new_out) {
+    for (int i = lane; i < Ly * Lx; i += 64) t.s_new_out[i] = spin_of<DP>(sh.cfg[0][i / Lx][i % Lx]);
+  }
+  if (t.write_back && accepted) {
+    for (int i = lane; i < Ly * Lx; i += 64) spins[(size_t)z * plane + i] = spin_of<DP>(sh.cfg[0][i / Lx][i % Lx]);
+  }
+#undef RENV
+  if (lane == 0) {
+    if (t.record) {
+      t.record[0] = lq_new;
+      t.record[1] = lq_old;
+      t.record[2] = dE;
+      t.record[3] = (double)accepted;
+      t.record[4] = (double)any_fault;
+    }
+    if (t.counters) {
+      t.counters[0] += 1;
+      t.counters[1] += accepted;
+      t.counters[2] += any_fault;
+    }
+  }
+}
+
+template <int DP, int CHIM>
+hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, uint64_t sweep, hipStream_t s) {
+  const size_t bytes = sizeof(double) * 2 * (size_t)(Lx_max + 1) * CHIM * DP;
+  static size_t attr_bytes = 0;
+  if (bytes > 48 * 1024 && bytes > attr_bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)sample_kernel<DP, CHIM>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+    attr_bytes = bytes;
+  }
+  hipLaunchKernelGGL((sample_kernel<DP, CHIM>), dim3(n), dim3(128), bytes, s, tasks, sweep);
+  return hipGetLastError();
+}
+
+// Full-lattice energy of one configuration, FP64: one workgroup of 256.
+template <int DP>
+__global__ __launch_bounds__(256) void energy_kernel(const float* __restrict__ J, const int8_t* __restrict__ s,
+                                                     int Lx, int Ly, int Lz, double* out) {
+  __shared__ double red[4];
+  const size_t n = (size_t)Lx * Ly * Lz;
+  const size_t plane = (size_t)Lx * Ly;
+  double e = 0.0;
+  for (size_t i = threadIdx.x; i < n; i += 256) {
+    const int x = (int)(i % Lx), y = (int)((i / Lx) % Ly), zz = (int)(i / plane);
+    const int u = state_of<DP>(s[i]);
+    if (x + 1 < Lx) e -= (double)J[i] * sigma<DP>(u, state_of<DP>(s[i + 1]));
+    if (y + 1 < Ly) e -= (double)J[n + i] * sigma<DP>(u, state_of<DP>(s[i + Lx]));
+    if (zz + 1 < Lz) e -= (double)J[2 * n + i] * sigma<DP>(u, state_of<DP>(s[i + plane]));
+  }
+  e = block_sum<256>(e, red);
+  if (threadIdx.x == 0) *out = e;
+}
+
+// Per-sweep observables: blocks [0, n_chains) compute E and M of a chain,
+// blocks [n_chains, n_chains + n_pairs) the overlap of a replica pair.
+template <int DP>
+__global__ __launch_bounds__(256) void observables_kernel(const float* const* __restrict__ Jc,
+                                                          int8_t* const* __restrict__ spins, int n_chains,
+                                                          const int* __restrict__ pa, const int* __restrict__ pb,
+                                                          int Lx, int Ly, int Lz, double* E_out, double* M_out,
+                                                          double* q_out) {
+  __shared__ double red[4];
+  const size_t n = (size_t)Lx * Ly * Lz;
+  const size_t plane = (size_t)Lx * Ly;
+  const int b = blockIdx.x;
+  if (b < n_chains) {
+    const float* J = Jc[b];
+    const int8_t* s = spins[b];
+    double e = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    for (size_t i = threadIdx.x; i < n; i += 256) {
+      const int x = (int)(i % Lx), y = (int)((i / Lx) % Ly), zz = (int)(i / plane);
+      const int u = state_of<DP>(s[i]);
+      if (x + 1 < Lx) e -= (double)J[i] * sigma<DP>(u, state_of<DP>(s[i + 1]));
+      if (y + 1 < Ly) e -= (double)J[n + i] * sigma<DP>(u, state_of<DP>(s[i + Lx]));
+      if (zz + 1 < Lz) e -= (double)J[2 * n + i] * sigma<DP>(u, state_of<DP>(s[i + plane]));
+      if constexpr (DP == 2) {
+        m0 += (double)s[i];
+      } else {
+        m0 += (u == 0);
+        m1 += (u == 1);
+        m2 += (u == 2);
+      }
+    }
+    e = block_sum<256>(e, red);
+    m0 = block_sum<256>(m0, red);
+    if constexpr (DP != 2) {
+      m1 = block_sum<256>(m1, red);
+      m2 = block_sum<256>(m2, red);
+    }
+    if (threadIdx.x == 0) {
+      E_out[b] = e;
+      if constexpr (DP == 2) {
+        M_out[b] = m0 / (double)n;
+      } else {
+        const double mx = fmax(m0, fmax(m1, m2));
+        M_out[b] = (DP * mx / (double)n - 1.0) / (DP - 1);
+      }
+    }
+  } else {
+    const int p = b - n_chains;
+    const int8_t* s1 = spins[pa[p]];
+    const int8_t* s2 = spins[pb[p]];
+    double q = 0.0;
+    for (size_t i = threadIdx.x; i < n; i += 256) q += (double)((int)s1[i] * (int)s2[i]);
+    q = block_sum<256>(q, red);
+    if (threadIdx.x == 0) q_out[p] = q / (double)n;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sample(const TaskDesc* tasks, int n, int d, int chi_max, int Lx_max, uint64_t sweep,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (d == 2) {
+    switch (chi_max) {
+      case 4: return launch_sample_t<2, 4>(tasks, n, Lx_max, sweep, s);
+      case 8: return launch_sample_t<2, 8>(tasks, n, Lx_max, sweep, s);
+      case 16: return launch_sample_t<2, 16>(tasks, n, Lx_max, sweep, s);
+      case 32: return launch_sample_t<2, 32>(tasks, n, Lx_max, sweep, s);
+    }
+  } else if (d == 3) {
+    switch (chi_max) {
+      case 4: return launch_sample_t<3, 4>(tasks, n, Lx_max, sweep, s);
+      case 8: return launch_sample_t<3, 8>(tasks, n, Lx_max, sweep, s);
+      case 16: return launch_sample_t<3, 16>(tasks, n, Lx_max, sweep, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_energy(const float* J, const int8_t* spins, int Lx, int Ly, int Lz, int d, double* out,
+                         hipStream_t s) {
+  if (d == 2) hipLaunchKernelGGL(energy_kernel<2>, dim3(1), dim3(256), 0, s, J, spins, Lx, Ly, Lz, out);
+  else hipLaunchKernelGGL(energy_kernel<3>, dim3(1), dim3(256), 0, s, J, spins, Lx, Ly, Lz, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_observables(const float* const* Jc, int8_t* const* spins, int n_chains, const int* pair_a,
+                              const int* pair_b, int n_pairs, int Lx, int Ly, int Lz, int d, double* E_out,
+                              double* M_out, double* q_out, hipStream_t s) {
+  const int nb = n_chains + n_pairs;
+  if (nb <= 0) return hipSuccess;
+  if (d == 2)
+    hipLaunchKernelGGL(observables_kernel<2>, dim3(nb), dim3(256), 0, s, Jc, spins, n_chains, pair_a, pair_b, Lx,
+                       Ly, Lz, E_out, M_out, q_out);
+  else
+    hipLaunchKernelGGL(observables_kernel<3>, dim3(nb), dim3(256), 0, s, Jc, spins, n_chains, pair_a, pair_b, Lx,
+                       Ly, Lz, E_out, M_out, q_out);
+  return hipGetLastError();
+}
+
+}  // namespace tnmc

@@ -1,0 +1,54 @@
+// Internal declarations shared by the HIP kernels and the host side of libtnmc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tnmc {
+
+// One slice task: layer z of one chain.  Everything a kernel needs, with
+// device pointers into the lattice state and into the per-task workspace.
+struct TaskDesc {
+  const float* J;          // couplings of the chain's instance [3][Lz][Ly][Lx]
+  int8_t* spins;           // chain configuration [Lz][Ly][Lx]
+  double* env;             // environments [Ly][Lx][d][chi_max][chi_max]
+  double* rscr;            // R factors of the left sweep [Lx][(d chi_max)^2]
+  int* bond;               // right bond dimension of every environment site [Ly][Lx]
+  int* rrows;              // rows of every R factor [Lx]
+  double* logscale;        // log of the removed scale of every environment [Ly]
+  int* status;             // contraction fault flag of this task (0 = ok)
+  long long* counters;     // per-task running totals {proposed, accepted, faults}
+  const int8_t* force_new; // if set: evaluate this layer instead of sampling [Ly][Lx]
+  int8_t* s_new_out;       // if set: copy of the proposed layer [Ly][Lx]
+  double* record;          // if set: {logq_new, logq_old, dE, accepted, fault}
+  double beta;
+  uint64_t key0, key1;     // Philox key
+  int Lx, Ly, Lz, z, chi, d;
+  int chi_max;             // storage stride of the environment tensors
+  int write_back;          // apply the MH decision to spins
+  int pad_;
+};
+
+// Per-task workspace sizes (doubles / ints) for a (Lx, Ly, d, chi_max) task.
+inline size_t env_doubles(int Lx, int Ly, int d, int chi_max) {
+  return (size_t)Ly * Lx * d * chi_max * chi_max;
+}
+inline size_t rscr_doubles(int Lx, int d, int chi_max) {
+  return (size_t)Lx * (size_t)(d * chi_max) * (d * chi_max);
+}
+
+// Kernel launchers (return hipError_t of the launch).
+hipError_t launch_contract(const TaskDesc* tasks, int n_tasks, int d, int chi_max, hipStream_t s);
+hipError_t launch_sample(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int Lx_max, uint64_t sweep,
+                         hipStream_t s);
+hipError_t launch_energy(const float* J, const int8_t* spins, int Lx, int Ly, int Lz, int d,
+                         double* out, hipStream_t s);
+hipError_t launch_observables(const float* const* Jc, int8_t* const* spins, int n_chains,
+                              const int* pair_a, const int* pair_b, int n_pairs, int Lx, int Ly,
+                              int Lz, int d, double* E_out, double* M_out, double* q_out,
+                              hipStream_t s);
+bool contract_supported(int d, int chi_max);
+size_t contract_lds_bytes(int d, int chi_max);
+int chi_bucket(int chi);   // storage chi_max used for a requested chi (0 if unsupported)
+
+}  // namespace tnmc

@@ -1,0 +1,90 @@
+"""Shared pieces of the GPU parity tests: building a lattice on the device from
+the seeded synthetic inputs and comparing one proposal with the oracle's."""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+
+import paper_2509_23945_amd as tn
+import synth
+from oracle import chain as ochain
+
+# log q tolerance on the FP64 path: 1e-10 absolute, relaxed to 1e-10 relative
+# for |log q| > 1 (two independent SVD codes differ in rounding, amplified
+# along ~L^2 conditionals).
+LOGQ_TOL = 1e-10
+TIE = 1e-9
+
+
+def logq_close(a: float, b: float) -> bool:
+    return abs(a - b) <= LOGQ_TOL * max(1.0, abs(a), abs(b))
+
+
+def announce(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_lattice(Lx, Ly, Lz, d, chi, *, kind="pmj", beta=1.0, seed=0, n_chains=1, init="random",
+                 pairs=None, record_capacity=0, philox_seed=12345):
+    """Couplings (one instance per chain pair) and initial spins from synth; returns
+    (lattice handle, J[n_inst], spins[n_chains], betas)."""
+    n_inst = max(1, (n_chains + 1) // 2) if pairs is not None else n_chains
+    Js = []
+    for i in range(n_inst):
+        if kind == "pmj":
+            Js.append(synth.couplings_pm_j(Lx, Ly, Lz, seed + i))
+        elif kind == "gauss":
+            Js.append(synth.couplings_gauss(Lx, Ly, Lz, seed + i))
+        else:
+            Js.append(synth.couplings_uniform(Lx, Ly, Lz))
+    J = np.stack(Js)
+    spins = []
+    for c in range(n_chains):
+        if init == "random":
+            spins.append(synth.spins_random(Lx, Ly, Lz, 1000 * seed + c + 1, d))
+        else:
+            spins.append(synth.spins_ordered(Lx, Ly, Lz, d))
+    spins = np.stack(spins)
+    betas = np.broadcast_to(np.asarray(beta, dtype=np.float64), (n_chains,)).copy()
+    inst = np.array([c // 2 if pairs is not None else c for c in range(n_chains)], dtype=np.int32)
+    lat = tn.tnmc_lattice_init(Lx=Lx, Ly=Ly, Lz=Lz, d=d, chi=chi, J=J, beta=betas, spins=spins,
+                               chain_instance=inst, seed=philox_seed, pairs=pairs,
+                               record_capacity=record_capacity)
+    return lat, J[inst], spins, betas
+
+
+def compare_proposal(gpu, ref, margins):
+    """gpu = (s_new, lq_new, lq_old, dE, status); ref = oracle.propose record.
+    Returns a dict of discrepancies (empty if identical within the parity bar)
+    and whether a near-tie explains a spin mismatch."""
+    s_new, lq_new, lq_old, dE, st = gpu
+    out = {}
+    if dE != ref["dE"] and np.array_equal(s_new, ref["new"]):
+        out["dE"] = (dE, ref["dE"])
+    if not logq_close(lq_old, ref["logq_old"]):
+        out["logq_old"] = (lq_old, ref["logq_old"])
+    if not np.array_equal(s_new, ref["new"]):
+        tie = min(margins) < TIE if margins else False
+        out["spins"] = ("near-tie" if tie else "mismatch", int(np.sum(s_new != ref["new"])))
+    elif not logq_close(lq_new, ref["logq_new"]):
+        out["logq_new"] = (lq_new, ref["logq_new"])
+    return out
+
+
+def oracle_propose(J, spins, z, beta, chi, d, *, seed, chain, sweep):
+    margins = []
+    rec = ochain.propose(J, spins, z, beta, chi, d, seed=seed, chain=chain, sweep=sweep, margins=margins)
+    return rec, margins
+
+
+def have_gpu() -> bool:
+    if os.environ.get("TNMC_FORCE_NO_GPU"):
+        return False
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False

@@ -1,0 +1,84 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry point,
+validates its arguments without touching a GPU, and its host-only pieces agree
+with the oracle."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import paper_2509_23945_amd as tn
+from oracle import chain as ochain
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(tn.api.LIB_PATH):
+        from paper_2509_23945_amd import build
+        build.build()
+    return tn.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = tn.declared_symbols()
+    assert {"tnmc_lattice_init", "tnmc_slice_propose", "tnmc_mh_accept", "tnmc_sweep"} <= set(names)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing
+
+
+def test_status_strings(lib):
+    assert tn.tnmc_status_string(0) == "ok"
+    assert tn.tnmc_status_string(-1) == "invalid argument"
+    assert tn.tnmc_status_string(-5) == "unsupported configuration"
+
+
+def test_mh_accept_matches_oracle(lib):
+    rng = np.random.Generator(np.random.PCG64(3))
+    for _ in range(2000):
+        lo, ln = rng.normal(-50, 20, size=2)
+        beta = rng.uniform(0, 2)
+        dE = float(rng.integers(-20, 20))
+        u = rng.uniform(1e-12, 1 - 1e-12)
+        assert tn.tnmc_mh_accept(lo, ln, beta, dE, u) == ochain.mh_accept(lo, ln, beta, dE, u)
+    # boundary: u exactly at A is rejected (strict "<")
+    A = math.exp(-1.0)
+    assert not tn.tnmc_mh_accept(-1.0, 0.0, 1.0, 0.0, A)
+    with pytest.raises(tn.TnmcError):
+        tn.tnmc_mh_accept(0.0, 0.0, 1.0, 0.0, 0.0)
+    with pytest.raises(tn.TnmcError):
+        tn.tnmc_mh_accept(0.0, 0.0, 1.0, 0.0, 1.0)
+
+
+def _desc(**kw):
+    base = dict(Lx=4, Ly=4, Lz=4, d=2, chi=4, J=np.zeros((3, 4, 4, 4), np.float32), beta=1.0,
+                spins=np.ones((4, 4, 4), np.int8))
+    base.update(kw)
+    return base
+
+
+@pytest.mark.parametrize("bad", [dict(d=4), dict(chi=0), dict(Lx=0),
+                                 dict(Lx=65, J=np.zeros((3, 4, 4, 65), np.float32), spins=np.ones((4, 4, 65), np.int8)),
+                                 dict(beta=-1.0), dict(spins=np.zeros((4, 4, 4), np.int8)),
+                                 dict(d=3, spins=np.full((4, 4, 4), 3, np.int8)),
+                                 dict(pairs=np.array([[0, 5]]))])
+def test_init_rejects_bad_arguments(lib, bad):
+    with pytest.raises(tn.TnmcError) as ei:
+        tn.tnmc_lattice_init(**_desc(**bad))
+    assert ei.value.status == tn.api.TNMC_ERR_ARG
+
+
+def test_init_rejects_unbuilt_configuration(lib):
+    with pytest.raises(tn.TnmcError) as ei:
+        tn.tnmc_lattice_init(**_desc(chi=200))
+    assert ei.value.status == tn.api.TNMC_ERR_UNSUPPORTED
+
+
+def test_flop_model(lib):
+    c, s = tn.tnmc_flop_model(32, 32, 2, 32)
+    assert 2e9 < c < 6e9 and 0 < s < 1e8
+    c8, _ = tn.tnmc_flop_model(8, 8, 2, 16)
+    assert c8 < c / 100
+    # grows with chi
+    assert tn.tnmc_flop_model(16, 16, 2, 32)[0] > tn.tnmc_flop_model(16, 16, 2, 16)[0]
+    with pytest.raises(tn.TnmcError):
+        tn.tnmc_flop_model(0, 4, 2, 4)
