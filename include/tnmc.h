@@ -143,6 +143,13 @@ tnmc_status tnmc_timeseries_reset(tnmc_lattice* lat);
 tnmc_status tnmc_flop_model(int32_t Lx, int32_t Ly, int32_t d, int32_t chi, double* contract_flops,
                             double* sample_flops);
 
+/* Diagnostics: copy part of the workspace left by the last single-task call
+ * (tnmc_slice_propose / tnmc_slice_logq) to the HOST buffer out (at most
+ * bytes): what = 0 environments [Ly][Lx][d][chi_max][chi_max] doubles,
+ * 1 bond dimensions [Ly][Lx] ints, 2 R-factor row counts [Lx] + fault flag
+ * ints, 3 R factors [Lx][(d chi_max)^2] doubles, 4 log scales [Ly] doubles. */
+tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes);
+
 const char* tnmc_status_string(tnmc_status s);
 /* Text of the last failed HIP call (thread-local). */
 const char* tnmc_last_error(void);

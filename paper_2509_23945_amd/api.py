@@ -29,7 +29,8 @@ TNMC_FP32 = 1
 __all__ = [
     "TnmcError", "load", "declared_symbols", "tnmc_lattice_init", "tnmc_lattice_free", "tnmc_slice_propose",
     "tnmc_slice_logq", "tnmc_mh_accept", "tnmc_sweep", "tnmc_half_sweep", "tnmc_get_spins", "tnmc_set_spins",
-    "tnmc_energy", "tnmc_timeseries", "tnmc_timeseries_reset", "tnmc_flop_model", "tnmc_status_string",
+    "tnmc_energy", "tnmc_timeseries", "tnmc_timeseries_reset", "tnmc_flop_model", "tnmc_debug_workspace",
+    "tnmc_status_string",
     "tnmc_last_error", "Lattice",
 ]
 
@@ -101,6 +102,8 @@ def load():
                                     P(ctypes.c_int64)]
     lib.tnmc_timeseries_reset.argtypes = [vp]
     lib.tnmc_flop_model.argtypes = [ctypes.c_int32] * 4 + [P(ctypes.c_double), P(ctypes.c_double)]
+    lib.tnmc_debug_workspace.argtypes = [ctypes.c_int32, vp, ctypes.c_int64]
+    lib.tnmc_debug_workspace.restype = ctypes.c_int
     lib.tnmc_status_string.argtypes = [ctypes.c_int]
     lib.tnmc_status_string.restype = ctypes.c_char_p
     lib.tnmc_last_error.argtypes = []
@@ -264,6 +267,13 @@ def tnmc_timeseries(lat: Lattice):
 
 def tnmc_timeseries_reset(lat: Lattice) -> None:
     _check(load().tnmc_timeseries_reset(lat.handle), "tnmc_timeseries_reset")
+
+
+def tnmc_debug_workspace(what: int, nbytes: int) -> bytes:
+    """Raw copy of part of the last single-task workspace (diagnostics)."""
+    buf = ctypes.create_string_buffer(nbytes)
+    _check(load().tnmc_debug_workspace(what, buf, nbytes), "tnmc_debug_workspace")
+    return buf.raw
 
 
 def tnmc_flop_model(Lx: int, Ly: int, d: int, chi: int):

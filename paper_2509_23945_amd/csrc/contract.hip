@@ -267,7 +267,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         }
         mx = block_max<NT>(mx, sRed);
         const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
-        if (!(mx > 0.0 && isfinite(mx))) fault = 1;
+        if (!(mx > 0.0 && isfinite(mx))) fault |= 1;
         double* gR = rscr + (size_t)x * D * D;
         for (int w = tid; w < rx * n; w += NT) {
           const int i = w / n, j = w % n;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           }
           nn = block_sum<NT>(nn, sRed);
           const double nrm = sqrt(nn);
-          if (!(nrm > 0.0 && isfinite(nrm))) fault = 1;
+          if (!(nrm > 0.0 && isfinite(nrm))) fault |= 4;
           const double inv = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 1.0;
           for (int w = tid; w < DP * k; w += NT) {
             const int r = w / k, kk = w % k;
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
 #pragma unroll
           for (int r = 0; r < DP; ++r) {
             v[r] = sC[i * LD + r * k + kk] * inv;
-            envN[(size_t)(r * CHIM + rho) * CHIM + kk] = v[r];
+            envN[(size_t)x * SITE + (size_t)(r * CHIM + rho) * CHIM + kk] = v[r];
           }
 #pragma unroll
           for (int b = 0; b < DP; ++b) {
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           }
           logacc += log(nrm);
         } else {
-          fault = 1;
+          fault |= 2;
         }
         if (tid == 0) bondN[x - 1] = kx;
         k = kx;
@@ -470,8 +470,11 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
     __threadfence_block();
     __syncthreads();
   }
-  if (__syncthreads_or(fault) && tid == 0) *t.status = 1;
-  else if (tid == 0) *t.status = 0;
+  // fault bits: 1 = zero/non-finite R factor, 2 = zero/non-finite T, 4 = zero first tensor
+  const int f1 = __syncthreads_or(fault & 1);
+  const int f2 = __syncthreads_or(fault & 2);
+  const int f4 = __syncthreads_or(fault & 4);
+  if (tid == 0) *t.status = (f1 ? 1 : 0) | (f2 ? 2 : 0) | (f4 ? 4 : 0);
 }
 
 template <int DP, int CHIM>

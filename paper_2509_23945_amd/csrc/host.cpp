@@ -259,6 +259,7 @@ tnmc_status finish_timer(Timer& tm, tnmc_stats* st) {
 tnmc_status run_single(tnmc_lattice* lat, int chain, int z, uint64_t sweep, const int8_t* force_host,
                        int8_t* s_new_host, double* rec_host, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_ws.mu);
+  g_last_error.clear();
   std::vector<Task> tasks{{lat, chain, z}};
   Plan plan;
   tnmc_status r = make_plan(tasks, plan);
@@ -432,7 +433,11 @@ tnmc_status tnmc_slice_propose(tnmc_lattice* lat, int32_t chain, int32_t z, uint
   *logq_new = rec[0];
   *logq_old = rec[1];
   *dE = rec[2];
-  if (rec[4] != 0.0 || !std::isfinite(rec[0]) || !std::isfinite(rec[1])) return TNMC_ERR_NUMERIC;
+  if (rec[4] != 0.0 || !std::isfinite(rec[0]) || !std::isfinite(rec[1])) {
+    g_last_error = "numeric fault bits " + std::to_string((int)rec[4]) +
+                   " (1-2: new path, 4-8: current path, 16-64: contraction)";
+    return TNMC_ERR_NUMERIC;
+  }
   return TNMC_OK;
 }
 
@@ -549,6 +554,25 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
     r = finish_timer(tm, stats);
     if (r != TNMC_OK) return r;
   }
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes) {
+  if (!out || bytes < 0) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  const void* src = nullptr;
+  size_t cap = 0;
+  switch (what) {
+    case 0: src = g_ws.env; cap = g_ws.env_cap * sizeof(double); break;
+    case 1: src = g_ws.ints; cap = g_ws.ints_cap * sizeof(int); break;
+    case 2: src = g_ws.ints; cap = g_ws.ints_cap * sizeof(int); break;
+    case 3: src = g_ws.rscr; cap = g_ws.rscr_cap * sizeof(double); break;
+    case 4: src = g_ws.dbl; cap = g_ws.dbl_cap * sizeof(double); break;
+    default: return TNMC_ERR_ARG;
+  }
+  if (!src) return TNMC_ERR_ARG;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(out, src, std::min((size_t)bytes, cap), hipMemcpyDeviceToHost));
   return TNMC_OK;
 }
 

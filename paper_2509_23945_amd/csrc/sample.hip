@@ -50,7 +50,8 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
   int8_t* __restrict__ spins = t.spins;
   const size_t plane = (size_t)Lx * Ly;
   const int8_t* forced = (path == 1) ? spins + (size_t)z * plane : t.force_new;
-  const bool contract_fault = (*t.status) != 0;
+  const int contract_status = *t.status;
+  const bool contract_fault = contract_status != 0;
   double* Rp = sR + (size_t)path * (Lx + 1) * CHIM * DP;
 #define RENV(x, al, u) Rp[((size_t)(x) * CHIM + (al)) * DP + (u)]
 
@@ -146,7 +147,7 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
       }
       double p[DP];
       if (bad || !(wsum > 0.0) || !isfinite(wsum)) {
-        fault = 1;
+        fault |= 1;
 #pragma unroll
         for (int u = 0; u < DP; ++u) p[u] = 1.0 / DP;
       } else {
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
         }
       logq += log(pchosen);
       const double lm = wave_max(fabs(lv));
-      if (!(lm > 0.0) || !isfinite(lm)) fault = 1;
+      if (!(lm > 0.0) || !isfinite(lm)) fault |= 2;
       const double inv = (lm > 0.0 && isfinite(lm)) ? 1.0 / lm : 1.0;
       __syncthreads();   // everyone has read l before it is replaced
       if (lane < CHIM) sh.l[path][lane] = (lane < cr) ? lv * inv : 0.0;
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
   }
   dE = wave_sum(dE);
   const double lq_new = sh.lq[0], lq_old = sh.lq[1];
-  const int any_fault = sh.fault[0] | sh.fault[1] | (contract_fault ? 1 : 0);
+  const int any_fault = (sh.fault[0] | sh.fault[1] | (contract_fault ? 1 : 0)) ? 1 : 0;
   const double lr = lq_old - lq_new - beta * dE;
   const double Uacc = philox_uniform(0ull, (uint64_t)z, sweep, 1ull, t.key0, t.key1);
   const int accepted = (!any_fault && Uacc < exp(fmin(0.0, lr))) ? 1 : 0;
@@ -236,7 +237,8 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
       t.record[1] = lq_old;
       t.record[2] = dE;
       t.record[3] = (double)accepted;
-      t.record[4] = (double)any_fault;
+      // 0 = no fault; else bits 0-1: new path, bits 2-3: current path, bits 4-6: contraction
+      t.record[4] = (double)(sh.fault[0] | (sh.fault[1] << 2) | ((contract_status & 7) << 4));
     }
     if (t.counters) {
       t.counters[0] += 1;
