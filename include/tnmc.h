@@ -101,6 +101,8 @@ typedef struct {
   int64_t proposed, accepted, numeric_faults;
   double contract_ms;           /* summed duration of the contraction launches (HIP events) */
   double sample_ms;             /* summed duration of the sampling/MH launches */
+  double contract_flops;        /* algorithmic FP64 flops of the contractions (textbook counts of
+                                   the QR, SVD and GEMM steps at the bond dimensions used) */
   int64_t contract_launches, sample_launches;
 } tnmc_stats;
 

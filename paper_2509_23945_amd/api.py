@@ -65,7 +65,7 @@ class _Desc(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [
         ("proposed", ctypes.c_int64), ("accepted", ctypes.c_int64), ("numeric_faults", ctypes.c_int64),
-        ("contract_ms", ctypes.c_double), ("sample_ms", ctypes.c_double),
+        ("contract_ms", ctypes.c_double), ("sample_ms", ctypes.c_double), ("contract_flops", ctypes.c_double),
         ("contract_launches", ctypes.c_int64), ("sample_launches", ctypes.c_int64),
     ]
 

@@ -27,6 +27,19 @@ namespace {
 constexpr int NT = 256;
 constexpr int LXMAX = 64;
 constexpr int JACOBI_MAX_SWEEPS = 40;
+// Directions whose weight is below this fraction of the largest one are zero
+// at FP64 resolution: the rank-revealing factorisations stop there and the SVD
+// drops them.  (Gram-Schmidt residuals of dependent rows sit at ~eps sqrt(n),
+// slightly above this, so the right-sweep LQ may keep a few rounding-level
+// directions; its rank is bounded by the left factor's and they are harmless.)
+constexpr double RANK_TOL = 1e-15;
+
+// Orders LDS accesses of one wavefront (lanes of a wavefront run in lock step).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Householder QR of the m x n row-major matrix M (leading dim ld) in LDS, R
 // factor only: on exit the upper trapezoid holds R, the part below the
@@ -43,8 +56,8 @@ __device__ void qr_r_inplace(double* M, int ld, int m, int n, double* scal) {
         const double v = M[i * ld + k];
         s += v * v;
       }
-      s += __shfl_xor(s, 1);
-      s += __shfl_xor(s, 2);
+      s += dpp_mov<0xB1>(s);
+      s += dpp_mov<0x4E>(s);
       if (sub == 0) {
         const double x0 = M[k * ld + k];
         double tau = 0.0, v0 = 0.0;
@@ -66,8 +79,8 @@ __device__ void qr_r_inplace(double* M, int ld, int m, int n, double* scal) {
         double w = 0.0;
         for (int i = k + 1 + sub; i < m; i += 4) w += M[i * ld + k] * M[i * ld + j];
         if (sub == 0) w += v0 * M[k * ld + j];
-        w += __shfl_xor(w, 1);
-        w += __shfl_xor(w, 2);
+        w += dpp_mov<0xB1>(w);
+        w += dpp_mov<0x4E>(w);
         w *= tau;
         for (int i = k + 1 + sub; i < m; i += 4) M[i * ld + j] -= w * M[i * ld + k];
         if (sub == 0) M[k * ld + j] -= w * v0;
@@ -79,21 +92,38 @@ __device__ void qr_r_inplace(double* M, int ld, int m, int n, double* scal) {
 
 // One-sided Jacobi on the rows of the m x n row-major matrix C (ld) in LDS:
 // plane rotations applied from the left until all rows are mutually
-// orthogonal, i.e. C <- W^T C = S V^T.  Round-robin pairing, 8 threads per pair.
-__device__ void jacobi_rows(double* C, int ld, int m, int n) {
-  if (m < 2) return;
-  const int tid = threadIdx.x;
+// orthogonal, i.e. C <- W^T C = S V^T.  Round-robin pairing, 8 threads per
+// pair; each thread keeps its NPL columns of both rows in registers for the
+// round (n <= 8*NPL).  A pair is rotated when its normalised inner product
+// exceeds tol and its inner product exceeds the absolute floor (pairs of rows
+// that are both zero at FP64 resolution are left alone).  WAVE: the caller runs
+// it on one wavefront (at most 8 pairs) with wavefront-level ordering only.
+// Returns the number of sweeps.
+template <int NPL, bool WAVE>
+__device__ int jacobi_rows(double* C, int ld, int m, int n, double floor) {
+  if (m < 2) return 0;
+  const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
+  constexpr int NSLOT = WAVE ? 8 : NT / 8;
   const int p = tid >> 3;
   const int l = tid & 7;
   const int mm = m + (m & 1);
   const int np = mm >> 1;
+  const int nq = (n + 7) >> 3;          // column blocks in use (<= NPL)
   const double tol = 4.0 * 2.220446049250313e-16 * sqrt((double)n);
   for (int sw = 0; sw < JACOBI_MAX_SWEEPS; ++sw) {
     int rotated = 0;
+    // pairing of slot pp in round r: (r + pp, r - pp) mod (mm - 1), slot 0 pairs r with mm - 1;
+    // both indices advance by one per round
+    int i0 = (p == 0) ? 0 : p % (mm - 1);
+    int j0 = (p == 0) ? mm - 1 : (mm - 1 - p % (mm - 1)) % (mm - 1);
     for (int r = 0; r < mm - 1; ++r) {
-      for (int pp = p; pp < np; pp += NT / 8) {
+      int ii = i0, jj = j0;
+      for (int pp = p; pp < np; pp += NSLOT) {
         int i, j;
-        if (pp == 0) {
+        if (pp == p) {
+          i = ii;
+          j = jj;
+        } else if (pp == 0) {
           i = r;
           j = mm - 1;
         } else {
@@ -101,37 +131,314 @@ __device__ void jacobi_rows(double* C, int ld, int m, int n) {
           j = (r - pp + (mm - 1)) % (mm - 1);
         }
         if (i < m && j < m) {
-          double aii = 0.0, ajj = 0.0, aij = 0.0;
-          for (int c = l; c < n; c += 8) {
-            const double x = C[i * ld + c], y = C[j * ld + c];
-            aii += x * x;
-            ajj += y * y;
-            aij += x * y;
-          }
+          double xv[NPL], yv[NPL];
 #pragma unroll
-          for (int o = 1; o < 8; o <<= 1) {
-            aii += __shfl_xor(aii, o);
-            ajj += __shfl_xor(ajj, o);
-            aij += __shfl_xor(aij, o);
+          for (int q = 0; q < NPL; ++q) {
+            const int c = l + 8 * q;
+            xv[q] = 0.0;
+            yv[q] = 0.0;
+            if (q < nq && c < n) {
+              xv[q] = C[i * ld + c];
+              yv[q] = C[j * ld + c];
+            }
           }
-          if (aij != 0.0 && fabs(aij) > tol * sqrt(aii * ajj)) {
-            const double zeta = (ajj - aii) / (2.0 * aij);
-            const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double aii = 0.0, ajj = 0.0, aij = 0.0;
+#pragma unroll
+          for (int q = 0; q < NPL; ++q) {
+            aii += xv[q] * xv[q];
+            ajj += yv[q] * yv[q];
+            aij += xv[q] * yv[q];
+          }
+          aii = group8_sum(aii);
+          ajj = group8_sum(ajj);
+          aij = group8_sum(aij);
+          if (fabs(aij) > floor && fabs(aij) > tol * sqrt(aii * ajj)) {
+            // tangent of the rotation angle that zeroes the off-diagonal Gram entry:
+            // t = 2 a_ij / (d + sign(d) sqrt(d^2 + 4 a_ij^2)), d = a_jj - a_ii
+            const double dd = ajj - aii, b2 = 2.0 * aij;
+            const double den = dd + copysign(sqrt(dd * dd + b2 * b2), dd);
+            const double t = b2 / den;
             const double cs = 1.0 / sqrt(1.0 + t * t);
             const double sn = cs * t;
-            for (int c = l; c < n; c += 8) {
-              const double x = C[i * ld + c], y = C[j * ld + c];
-              C[i * ld + c] = cs * x - sn * y;
-              C[j * ld + c] = sn * x + cs * y;
+#pragma unroll
+            for (int q = 0; q < NPL; ++q) {
+              const int c = l + 8 * q;
+              if (q < nq && c < n) {
+                C[i * ld + c] = cs * xv[q] - sn * yv[q];
+                C[j * ld + c] = sn * xv[q] + cs * yv[q];
+              }
             }
             rotated = 1;
           }
         }
       }
+      if (p != 0) {
+        i0 = (i0 + 1 == mm - 1) ? 0 : i0 + 1;
+        j0 = (j0 + 1 == mm - 1) ? 0 : j0 + 1;
+      } else {
+        i0 = r + 1;
+      }
+      if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      } else {
+        __syncthreads();
+      }
+    }
+    const int any = WAVE ? __any(rotated) : __syncthreads_or(rotated);
+    if (!any) return sw + 1;
+  }
+  return JACOBI_MAX_SWEEPS;
+}
+
+// Single-wavefront variant of qr_pivoted for n <= 64 columns (lane j owns
+// column j): same pivot order, same stopping rule, no workgroup barriers.
+__device__ int qr_pivoted_wave(double* M, int ld, int m, int n, int* perm, double rel_tol, double* tauv = nullptr) {
+  const int lane = threadIdx.x & 63;
+  if (lane < n) perm[lane] = lane;
+  const int kmax = (m < n) ? m : n;
+  // remaining squared norm of this lane's column (rows k..m-1), downdated after
+  // every step and recomputed exactly once it has fallen below 1e-6 of the last
+  // exact value (so decisions near the rank cut always use exact norms)
+  double cn = -1.0, cref = 0.0;
+  if (lane < n) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int i = 0; i < m; ++i) {
+      const double v = M[i * ld + lane];
+      s += v * v;
+    }
+    cn = s;
+    cref = s;
+  }
+  double ref2 = 0.0;
+  int rank = kmax;
+  for (int k = 0; k < kmax; ++k) {
+    double best = (lane >= k && lane < n) ? cn : -1.0;
+    int bj = lane;
+    wave_argmax(best, bj);
+    if (k == 0) ref2 = best;
+    if (!(best > 0.0) || !(best > rel_tol * rel_tol * ref2)) {
+      rank = k;
+      break;
+    }
+    const int pv = bj;
+    if (pv != k) {
+      for (int i = lane; i < m; i += 64) {
+        const double a = M[i * ld + k];
+        M[i * ld + k] = M[i * ld + pv];
+        M[i * ld + pv] = a;
+      }
+      if (lane == 0) {
+        const int tp = perm[k];
+        perm[k] = perm[pv];
+        perm[pv] = tp;
+      }
+      const double cnk = readlane_d(cn, k), cnp = readlane_d(cn, pv);
+      const double crk = readlane_d(cref, k), crp = readlane_d(cref, pv);
+      if (lane == k) {
+        cn = cnp;
+        cref = crp;
+      } else if (lane == pv) {
+        cn = cnk;
+        cref = crk;
+      }
+    }
+    wave_sync();
+    double part = 0.0;
+    for (int i = k + 1 + lane; i < m; i += 64) {
+      const double v = M[i * ld + k];
+      part += v * v;
+    }
+    const double s = wave_sum(part);
+    const double x0 = M[k * ld + k];
+    double tau = 0.0, v0 = 0.0, alpha = x0;
+    if (s > 0.0) {
+      const double nrm = sqrt(x0 * x0 + s);
+      alpha = (x0 >= 0.0) ? -nrm : nrm;
+      v0 = x0 - alpha;
+      tau = 2.0 / (v0 * v0 + s);
+    }
+    if (tauv != nullptr && lane == 0) {
+      tauv[2 * k] = tau;
+      tauv[2 * k + 1] = v0;
+    }
+    if (lane > k && lane < n) {
+      if (tau != 0.0) {
+        double w = v0 * M[k * ld + lane];
+#pragma unroll 8
+        for (int i = k + 1; i < m; ++i) w += M[i * ld + k] * M[i * ld + lane];
+        w *= tau;
+#pragma unroll 8
+        for (int i = k + 1; i < m; ++i) M[i * ld + lane] -= w * M[i * ld + k];
+        M[k * ld + lane] -= w * v0;
+      }
+      const double rkj = M[k * ld + lane];
+      cn -= rkj * rkj;
+      if (cn < 1e-6 * cref) {
+        double t = 0.0;
+#pragma unroll 8
+        for (int i = k + 1; i < m; ++i) {
+          const double v = M[i * ld + lane];
+          t += v * v;
+        }
+        cn = t;
+        cref = t;
+      }
+    }
+    wave_sync();
+    if (lane == 0) M[k * ld + k] = alpha;
+    wave_sync();
+  }
+  return rank;
+}
+
+// The first r columns of Q from a Householder factorisation done by
+// qr_pivoted_wave (reflector k: v = (v0_k at row k, M[i][k] for rows i > k),
+// H_k = I - tau_k v v^T), on one wavefront: Q e_c = H_0 ... H_{r-1} e_c.
+// Column c of Q is written transposed, as row c of V: V[c*vld + i], i < m.
+__device__ void form_q_wave(const double* M, int ld, int m, int r, const double* tauv, double* V, int vld) {
+  const int lane = threadIdx.x & 63;
+  if (lane < r) {
+    for (int i = 0; i < m; ++i) V[lane * vld + i] = (i == lane) ? 1.0 : 0.0;
+  }
+  wave_sync();
+  for (int k = r - 1; k >= 0; --k) {
+    const double tau = tauv[2 * k], v0 = tauv[2 * k + 1];
+    if (tau != 0.0 && lane < r) {
+      double* e = V + lane * vld;
+      double w = v0 * e[k];
+#pragma unroll 8
+      for (int i = k + 1; i < m; ++i) w += M[i * ld + k] * e[i];
+      w *= tau;
+      e[k] -= w * v0;
+#pragma unroll 8
+      for (int i = k + 1; i < m; ++i) e[i] -= w * M[i * ld + k];
+    }
+    wave_sync();
+  }
+}
+
+
+// Rank-revealing Householder QR with column pivoting of the m x n row-major
+// matrix M (leading dim ld) in LDS.  At step k the remaining column of largest
+// norm (rows k..m-1) is moved to position k; the factorisation stops when that
+// norm falls to rel_tol times the largest initial column norm, i.e. when the
+// rest of M is zero at FP64 resolution.  Returns the rank r; rows 0..r-1 of M
+// then hold R in pivoted column order (perm[j] = original index of column j).
+// cn holds n column norms; scal >= 4 doubles.
+__device__ int qr_pivoted(double* M, int ld, int m, int n, int* perm, double* cn, double* scal,
+                          double rel_tol) {
+  const int tid = threadIdx.x;
+  const int grp = tid >> 2;
+  const int sub = tid & 3;
+  for (int j = tid; j < n; j += NT) perm[j] = j;
+  const int kmax = (m < n) ? m : n;
+  double ref2 = 0.0;
+  int rank = kmax;
+  for (int k = 0; k < kmax; ++k) {
+    for (int j = k + grp; j < n; j += NT / 4) {
+      double s = 0.0;
+      for (int i = k + sub; i < m; i += 4) {
+        const double v = M[i * ld + j];
+        s += v * v;
+      }
+      s += dpp_mov<0xB1>(s);
+      s += dpp_mov<0x4E>(s);
+      if (sub == 0) cn[j] = s;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double best = -1.0;
+      int bj = n;
+      for (int j = k + tid; j < n; j += 64) {
+        const double v = cn[j];
+        if (v > best) {
+          best = v;
+          bj = j;
+        }
+      }
+      wave_argmax(best, bj);
+      if (tid == 0) {
+        scal[2] = best;
+        scal[3] = (double)bj;
+      }
+    }
+    __syncthreads();
+    const double best = scal[2];
+    const int pv = (int)scal[3];
+    if (k == 0) ref2 = best;
+    if (!(best > 0.0) || !(best > rel_tol * rel_tol * ref2)) {
+      rank = k;
+      break;
+    }
+    if (pv != k) {
+      for (int i = tid; i < m; i += NT) {
+        const double a = M[i * ld + k];
+        M[i * ld + k] = M[i * ld + pv];
+        M[i * ld + pv] = a;
+      }
+      if (tid == 0) {
+        const int tp = perm[k];
+        perm[k] = perm[pv];
+        perm[pv] = tp;
+      }
       __syncthreads();
     }
-    if (!__syncthreads_or(rotated)) break;
+    if (grp == 0) {
+      double s = 0.0;
+      for (int i = k + 1 + sub; i < m; i += 4) {
+        const double v = M[i * ld + k];
+        s += v * v;
+      }
+      s += dpp_mov<0xB1>(s);
+      s += dpp_mov<0x4E>(s);
+      if (sub == 0) {
+        const double x0 = M[k * ld + k];
+        double tau = 0.0, v0 = 0.0;
+        if (s > 0.0) {
+          const double nrm = sqrt(x0 * x0 + s);
+          const double alpha = (x0 >= 0.0) ? -nrm : nrm;
+          v0 = x0 - alpha;
+          tau = 2.0 / (v0 * v0 + s);
+          M[k * ld + k] = alpha;
+        }
+        scal[0] = tau;
+        scal[1] = v0;
+      }
+    }
+    __syncthreads();
+    const double tau = scal[0], v0 = scal[1];
+    if (tau != 0.0) {
+      for (int j = k + 1 + grp; j < n; j += NT / 4) {
+        double w = 0.0;
+        for (int i = k + 1 + sub; i < m; i += 4) w += M[i * ld + k] * M[i * ld + j];
+        if (sub == 0) w += v0 * M[k * ld + j];
+        w += dpp_mov<0xB1>(w);
+        w += dpp_mov<0x4E>(w);
+        w *= tau;
+        for (int i = k + 1 + sub; i < m; i += 4) M[i * ld + j] -= w * M[i * ld + k];
+        if (sub == 0) M[k * ld + j] -= w * v0;
+      }
+    }
+    __syncthreads();
   }
+  __syncthreads();
+  return rank;
+}
+
+// Textbook flop counts of the steps, at the dimensions actually used (for the
+// roofline): r Householder reflections on an m x n matrix, and a Golub-Reinsch
+// SVD that returns the singular values and right singular vectors.
+__device__ inline double qr_count(double m, double n, double r) {
+  double f = 0.0;
+  for (int k = 0; k < (int)r; ++k) f += 4.0 * (m - k) * (n - k - 1) + 3.0 * (m - k);
+  return f;
+}
+__device__ inline double svd_count(double m, double n) {
+  const double a = (m > n) ? m : n, b = (m > n) ? n : m;
+  return 4.0 * a * b * b + 8.0 * b * b * b;
 }
 
 template <int DP, int CHIM>
@@ -187,6 +494,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
   int* __restrict__ rrows = t.rrows;
   const size_t plane = (size_t)Lx * Ly;
   int fault = 0;
+  double flops = 0.0;   // accumulated by thread 0 only
 
   // E_{Ly-1} = 1: bond dimension 1, every component 1.
   for (int i = tid; i < Lx * DP; i += NT) {
@@ -195,7 +503,6 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
     if (u == 0) bond[(Ly - 1) * Lx + x] = 1;
   }
   if (tid == 0) t.logscale[Ly - 1] = 0.0;
-  __threadfence_block();
   __syncthreads();
 
   for (int y = Ly - 1; y >= 1; --y) {
@@ -258,8 +565,21 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         }
         __syncthreads();
         const int m = rR * DP, n = cr * DP;
-        qr_r_inplace(sM, LD, m, n, sScal);
-        const int rx = (m < n) ? m : n;
+        int* sPerm = sIdx;
+        int rx;
+        if (n <= 64 && m <= 64) {
+          if (tid < 64) {
+            const int r0 = qr_pivoted_wave(sM, LD, m, n, sPerm, RANK_TOL);
+            if (tid == 0) sIdx[D] = r0;   // pass the rank to the other waves
+          }
+          __syncthreads();
+          rx = sIdx[D];
+          __syncthreads();
+        } else {
+          rx = qr_pivoted(sM, LD, m, n, sPerm, sNrm, sScal, RANK_TOL);
+        }
+        if (rx == 0) fault |= 1;
+        if (tid == 0) flops += 2.0 * rR * DP * cr * cl + qr_count(m, n, rx);
         double mx = 0.0;
         for (int w = tid; w < rx * n; w += NT) {
           const int i = w / n, j = w % n;
@@ -268,12 +588,14 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         mx = block_max<NT>(mx, sRed);
         const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
         if (!(mx > 0.0 && isfinite(mx))) fault |= 1;
+        // R_x = R Pi^T: any factor with R_x^T R_x = M^T M serves as the metric of the left part
         double* gR = rscr + (size_t)x * D * D;
         for (int w = tid; w < rx * n; w += NT) {
           const int i = w / n, j = w % n;
           const double v = (j >= i) ? sM[i * LD + j] * inv : 0.0;
-          sR[i * LD + j] = v;
-          gR[(size_t)i * D + j] = v;
+          const int oj = sPerm[j];
+          sR[i * LD + oj] = v;
+          gR[(size_t)i * D + oj] = v;
         }
         if (tid == 0) rrows[x] = rx;
         rR = rx;
@@ -341,6 +663,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
             envN[(size_t)(r * CHIM + 0) * CHIM + kk] = sC[w] * inv;
           }
           if (nrm > 0.0 && isfinite(nrm)) logacc += log(nrm);
+          if (tid == 0) flops += 2.0 * DP * cl * cr * k + 2.0 * DP * DP * k;
           __syncthreads();
           break;
         }
@@ -380,35 +703,96 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           sC[i * LD + r * k + kk] = s;
         }
         __syncthreads();
-        // right singular vectors of C
-        int mrows = rR;
-        if (rR > nC) {
-          qr_r_inplace(sC, LD, rR, nC, sScal);
-          for (int w = tid; w < nC * nC; w += NT) {
-            const int i = w / nC, j = w % nC;
-            if (j < i) sC[i * LD + j] = 0.0;
+        // right singular vectors of C.  When the rank of C does not exceed chi
+        // nothing is truncated and any orthonormal basis of its row space is
+        // exact: a rank-revealing Householder LQ of C (pivoted QR of C^T) on
+        // one wavefront.  Otherwise the truncating SVD (one-sided Jacobi)
+        // picks the chi largest directions.
+        const double* vsrc = sC;
+        int kx = 0;
+        bool need_svd = true;
+        if (rR <= 64 && nC <= 64) {
+          double* sCt = sZ;    // C^T [nC][rR], leading dim D (Z is consumed)
+          double* sV = sR;     // V [rank][nC], leading dim LD (R~ is consumed)
+          double* sTau = sT;   // reflector scalars (T_{x+1} is consumed)
+          for (int w = tid; w < nC * rR; w += NT) {
+            const int c = w / rR, i = w % rR;
+            sCt[c * D + i] = sC[i * LD + c];
           }
           __syncthreads();
-          mrows = nC;
-        }
-        jacobi_rows(sC, LD, mrows, nC);
-        for (int i = tid; i < mrows; i += NT) {
-          double s = 0.0;
-          for (int c = 0; c < nC; ++c) s += sC[i * LD + c] * sC[i * LD + c];
-          sNrm[i] = s;
-        }
-        __syncthreads();
-        const int kx = (chi < mrows) ? chi : mrows;
-        for (int i = tid; i < mrows; i += NT) {
-          const double ni = sNrm[i];
-          int rank = 0;
-          for (int j = 0; j < mrows; ++j) {
-            const double nj = sNrm[j];
-            rank += (nj > ni) || (nj == ni && j < i);
+          if (tid < 64) {
+            const int rk = qr_pivoted_wave(sCt, D, nC, rR, sIdx, RANK_TOL, sTau);
+            if (rk > 0 && rk <= chi) form_q_wave(sCt, D, nC, rk, sTau, sV, LD);
+            if (tid == 0) sIdx[D] = rk;
           }
-          if (rank < kx) sIdx[rank] = i;
+          __syncthreads();
+          const int rk = sIdx[D];
+          if (rk > 0 && rk <= chi) {
+            need_svd = false;
+            kx = rk;
+            vsrc = sV;
+            for (int i = tid; i < kx; i += NT) {
+              sIdx[i] = i;
+              sNrm[i] = 1.0;
+            }
+            if (tid == 0) flops += qr_count(nC, rR, rk) + 4.0 * nC * rk * rk;
+          }
+          __syncthreads();
         }
-        __syncthreads();
+        if (need_svd) {
+          int mrows = rR;
+          if (rR > nC) {
+            qr_r_inplace(sC, LD, rR, nC, sScal);
+            for (int w = tid; w < nC * nC; w += NT) {
+              const int i = w / nC, j = w % nC;
+              if (j < i) sC[i * LD + j] = 0.0;
+            }
+            __syncthreads();
+            mrows = nC;
+          }
+          {
+            double fro = 0.0;
+            for (int w = tid; w < mrows * nC; w += NT) {
+              const double v = sC[(w / nC) * LD + (w % nC)];
+              fro += v * v;
+            }
+            fro = block_sum<NT>(fro, sRed);
+            const double floor = RANK_TOL * RANK_TOL * fro;   // |a_ij| below this: both rows are FP64 zeros
+            if (((mrows + 1) >> 1) <= 8) {
+              if (tid < 64) jacobi_rows<(D + 7) / 8, true>(sC, LD, mrows, nC, floor);
+              __syncthreads();
+            } else {
+              jacobi_rows<(D + 7) / 8, false>(sC, LD, mrows, nC, floor);
+            }
+          }
+          double nmax = 0.0;
+          for (int i = tid; i < mrows; i += NT) {
+            double s = 0.0;
+            for (int c = 0; c < nC; ++c) s += sC[i * LD + c] * sC[i * LD + c];
+            sNrm[i] = s;
+            nmax = fmax(nmax, s);
+          }
+          nmax = block_max<NT>(nmax, sRed);
+          double nkeep = 0.0;
+          for (int i = tid; i < mrows; i += NT) nkeep += (sNrm[i] > RANK_TOL * RANK_TOL * nmax) ? 1.0 : 0.0;
+          nkeep = block_sum<NT>(nkeep, sRed);
+          const int rs = (nkeep >= 1.0) ? (int)nkeep : 1;
+          kx = (chi < rs) ? chi : rs;
+          if (tid == 0) flops += ((rR > nC) ? qr_count(rR, nC, nC) : 0.0) + svd_count(mrows, nC);
+          for (int i = tid; i < mrows; i += NT) {
+            const double ni = sNrm[i];
+            int rank = 0;
+            for (int j = 0; j < mrows; ++j) {
+              const double nj = sNrm[j];
+              rank += (nj > ni) || (nj == ni && j < i);
+            }
+            if (rank < kx) sIdx[rank] = i;
+          }
+          __syncthreads();
+        }
+        if (tid == 0)
+          flops += 2.0 * DP * cl * cr * k + 2.0 * rR * DP * cl * k + 2.0 * rR * DP * DP * k + 2.0 * kx * DP * DP * k +
+                   2.0 * cl * DP * kx * k + 2.0 * cl * DP * DP * kx;
         // V rows (normalised) -> new environment site x, and V~[rho][b][k'] = sum_r G[r][b] V[rho][r*k+k']
         for (int w = tid; w < kx * k; w += NT) {
           const int rho = w / k, kk = w % k;
@@ -418,7 +802,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           double v[DP];
 #pragma unroll
           for (int r = 0; r < DP; ++r) {
-            v[r] = sC[i * LD + r * k + kk] * inv;
+            v[r] = vsrc[i * LD + r * k + kk] * inv;
             envN[(size_t)x * SITE + (size_t)(r * CHIM + rho) * CHIM + kk] = v[r];
           }
 #pragma unroll
@@ -470,12 +854,14 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
     __threadfence_block();
     __syncthreads();
   }
+  if (tid == 0 && t.counters) t.counters[3] += (long long)flops;
   // fault bits: 1 = zero/non-finite R factor, 2 = zero/non-finite T, 4 = zero first tensor
   const int f1 = __syncthreads_or(fault & 1);
   const int f2 = __syncthreads_or(fault & 2);
   const int f4 = __syncthreads_or(fault & 4);
   if (tid == 0) *t.status = (f1 ? 1 : 0) | (f2 ? 2 : 0) | (f4 ? 4 : 0);
 }
+
 
 template <int DP, int CHIM>
 hipError_t launch_contract_t(const TaskDesc* tasks, int n, hipStream_t s) {

@@ -47,15 +47,76 @@ __device__ __forceinline__ int8_t spin_of(int u) {
   else return (int8_t)u;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+// Cross-lane moves through DPP (VALU data path, no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over each aligned group of 8 lanes; every lane of the group gets the
+// same (bitwise) total.
+__device__ __forceinline__ double group8_sum(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]: partner lane ^ 1
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]: partner lane ^ 2
+  v += dpp_mov<0x141>(v);   // row_half_mirror: lane i <-> 7 - i within 8 lanes
   return v;
 }
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wavefront reductions (all 64 lanes active): DPP within each row of 16 lanes
+// (xor 1, xor 2, mirror of 8, mirror of 16), then the four row results are
+// read into scalars and combined.  Every lane returns the same bits.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  v += dpp_mov<0x140>(v);   // row_mirror: lane i <-> 15 - i within 16 lanes
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
 __device__ __forceinline__ double wave_max(double v) {
+  v = fmax(v, dpp_mov<0xB1>(v));
+  v = fmax(v, dpp_mov<0x4E>(v));
+  v = fmax(v, dpp_mov<0x141>(v));
+  v = fmax(v, dpp_mov<0x140>(v));
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
+}
+// Largest value over the wavefront and the smallest lane index holding it
+// (the value's owner passes its own index).
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double& best, int& idx) {
+  const double ob = dpp_mov<CTRL>(best);
+  const int oi = __builtin_amdgcn_mov_dpp(idx, CTRL, 0xf, 0xf, true);
+  if (ob > best || (ob == best && oi < idx)) {
+    best = ob;
+    idx = oi;
+  }
+}
+__device__ __forceinline__ void wave_argmax(double& best, int& idx) {
+  argmax_step<0xB1>(best, idx);
+  argmax_step<0x4E>(best, idx);
+  argmax_step<0x141>(best, idx);
+  argmax_step<0x140>(best, idx);
+  double b = readlane_d(best, 0);
+  int i = __builtin_amdgcn_readlane(idx, 0);
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+  for (int r = 16; r < 64; r += 16) {
+    const double ob = readlane_d(best, r);
+    const int oi = __builtin_amdgcn_readlane(idx, r);
+    if (ob > b || (ob == b && oi < i)) {
+      b = ob;
+      i = oi;
+    }
+  }
+  best = b;
+  idx = i;
 }
 
 // Workgroup reductions over NT threads; red must hold NT/64 doubles.  Every

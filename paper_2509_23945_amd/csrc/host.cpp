@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/tnmc.h"
+#include "tnmc.h"
 #include "tnmc_internal.h"
 
 using tnmc::TaskDesc;
@@ -136,7 +136,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
   if (grow(g_ws.rscr, g_ws.rscr_cap, rscr_need) != TNMC_OK) return TNMC_ERR_OOM;
   if (grow(g_ws.ints, g_ws.ints_cap, int_need) != TNMC_OK) return TNMC_ERR_OOM;
   if (grow(g_ws.dbl, g_ws.dbl_cap, dbl_need) != TNMC_OK) return TNMC_ERR_OOM;
-  if (grow(g_ws.counters, g_ws.counters_cap, 3 * tasks.size()) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.counters, g_ws.counters_cap, tnmc::kCounters * tasks.size()) != TNMC_OK) return TNMC_ERR_OOM;
   plan.desc.clear();
   plan.groups.clear();
   size_t eo = 0, ro = 0, io = 0, dof = 0;
@@ -153,7 +153,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.rrows = g_ws.ints + io + (size_t)L->Ly * L->Lx;
     t.status = g_ws.ints + io + (size_t)L->Ly * L->Lx + L->Lx;
     t.logscale = g_ws.dbl + dof;
-    t.counters = g_ws.counters + 3 * k;
+    t.counters = g_ws.counters + tnmc::kCounters * k;
     t.beta = L->beta[tk.chain];
     t.key0 = L->seed;
     t.key1 = L->chain_key[tk.chain];
@@ -229,12 +229,14 @@ tnmc_status check_lats(tnmc_lattice* const* lats, int n_lats) {
 }
 
 tnmc_status read_counters(size_t n_tasks, tnmc_stats* st) {
-  std::vector<long long> c(3 * n_tasks);
+  const int K = tnmc::kCounters;
+  std::vector<long long> c(K * n_tasks);
   HIP_TRY(hipMemcpy(c.data(), g_ws.counters, c.size() * sizeof(long long), hipMemcpyDeviceToHost));
   for (size_t i = 0; i < n_tasks; ++i) {
-    st->proposed += c[3 * i];
-    st->accepted += c[3 * i + 1];
-    st->numeric_faults += c[3 * i + 2];
+    st->proposed += c[K * i];
+    st->accepted += c[K * i + 1];
+    st->numeric_faults += c[K * i + 2];
+    st->contract_flops += (double)c[K * i + 3];
   }
   return TNMC_OK;
 }
@@ -288,9 +290,11 @@ tnmc_status run_single(tnmc_lattice* lat, int chain, int z, uint64_t sweep, cons
   return TNMC_OK;
 }
 
-double qr_flops(double m, double n) {   // Householder, R only
-  if (m >= n) return 2.0 * n * n * (m - n / 3.0);
-  return 2.0 * m * m * (n - m / 3.0);
+double qr_flops(double m, double n) {   // Householder, R only: min(m, n) reflections
+  double f = 0.0;
+  const int r = (int)std::min(m, n);
+  for (int k = 0; k < r; ++k) f += 4.0 * (m - k) * (n - k - 1) + 3.0 * (m - k);
+  return f;
 }
 double svd_flops(double m, double n) {  // Golub-Reinsch, singular values and right vectors
   const double a = std::max(m, n), b = std::min(m, n);
@@ -488,7 +492,7 @@ tnmc_status tnmc_half_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t p
   HIP_TRY(hipMemcpyAsync(g_ws.tasks, plan.desc.data(), plan.desc.size() * sizeof(TaskDesc),
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (stats) HIP_TRY(hipMemsetAsync(g_ws.counters, 0, 3 * tasks.size() * sizeof(long long), s));
+  if (stats) HIP_TRY(hipMemsetAsync(g_ws.counters, 0, tnmc::kCounters * tasks.size() * sizeof(long long), s));
   Timer tm;
   tm.on = (stats != nullptr);
   r = launch_plan(plan, g_ws.tasks, sweep, s, &tm, stats);
@@ -519,15 +523,15 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
   }
   const size_t n0 = plan[0].desc.size(), n1 = plan[1].desc.size();
   const size_t per_sweep = n0 + n1;
-  if (grow(g_ws.counters, g_ws.counters_cap, 3 * per_sweep) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.counters, g_ws.counters_cap, tnmc::kCounters * per_sweep) != TNMC_OK) return TNMC_ERR_OOM;
   if (grow(g_ws.tasks, g_ws.tasks_cap, per_sweep) != TNMC_OK) return TNMC_ERR_OOM;
-  for (size_t k = 0; k < n0; ++k) plan[0].desc[k].counters = g_ws.counters + 3 * k;
-  for (size_t k = 0; k < n1; ++k) plan[1].desc[k].counters = g_ws.counters + 3 * (n0 + k);
+  for (size_t k = 0; k < n0; ++k) plan[0].desc[k].counters = g_ws.counters + tnmc::kCounters * k;
+  for (size_t k = 0; k < n1; ++k) plan[1].desc[k].counters = g_ws.counters + tnmc::kCounters * (n0 + k);
   std::vector<TaskDesc> all(plan[0].desc);
   all.insert(all.end(), plan[1].desc.begin(), plan[1].desc.end());
   HIP_TRY(hipMemcpyAsync(g_ws.tasks, all.data(), per_sweep * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));   // `all` is released on return
-  HIP_TRY(hipMemsetAsync(g_ws.counters, 0, 3 * per_sweep * sizeof(long long), s));
+  HIP_TRY(hipMemsetAsync(g_ws.counters, 0, tnmc::kCounters * per_sweep * sizeof(long long), s));
   Timer tm;
   tm.on = (time_kernels != 0 && stats != nullptr);
   for (int t = 0; t < n_sweeps; ++t) {
@@ -656,7 +660,8 @@ tnmc_status tnmc_flop_model(int32_t Lx, int32_t Ly, int32_t d, int32_t chi, doub
       total += 2.0 * d * cl * cr * k;            // AT
       total += 2.0 * rr * d * cl * k;            // Z
       total += 2.0 * rr * d * d * k;             // C
-      total += svd_flops(rr, nC);
+      if (rr > nC) total += qr_flops(rr, nC);    // C is tall: QR first
+      total += svd_flops(std::min(rr, nC), nC);
       const double kx = std::min<double>(chi, std::min(rr, nC));
       total += 2.0 * kx * d * d * k;             // V~
       total += 2.0 * cl * d * kx * k;            // Y
