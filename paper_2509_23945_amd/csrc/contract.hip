@@ -294,6 +294,147 @@ __device__ int qr_pivoted_wave(double* M, int ld, int m, int n, int* perm, doubl
   return rank;
 }
 
+// Register-resident column-pivoted Householder QR on one wavefront, for an
+// m x n row-major LDS matrix with m <= MM and n <= 64.  Lane j holds column j
+// in registers; pivot columns are not moved: each lane records the step at
+// which it became the pivot.  The step loop is fully unrolled, so every row
+// index is a compile-time constant and the inner loops shrink with the step.
+// At step k the pivot lane publishes its reflector (rows k..m-1) to LDS W
+// (row k of an MM x MM array; tau and v0 at W[MM*MM + 2k]); the other lanes
+// read it back as broadcasts.  Stops at the same rule as qr_pivoted.
+// MODE_Q = false: the rank rows of R Pi^T go to Out[i*ldo + j] (and Rglob,
+// stride gld), scaled by 1/max|R|, which is returned in *rmax.
+// MODE_Q = true: the first rank columns of Q are written as rows of
+// Out[c*ldo + i], i < m.  Returns the rank.
+template <int MM, bool MODE_Q>
+__device__ int qr_pivoted_reg(const double* M, int ld, int m, int n, double rel_tol, double* W, double* Out,
+                              int ldo, double* Rglob, int gld, double* rmax) {
+  const int lane = threadIdx.x & 63;
+  double col[MM];
+#pragma unroll
+  for (int i = 0; i < MM; ++i) col[i] = (i < m && lane < n) ? M[i * ld + lane] : 0.0;
+  int pstep = (lane < n) ? -1 : (1 << 20);   // step at which this column was the pivot (-1: not yet)
+  const int kmax = (m < n) ? m : n;
+  double ref2 = 0.0;
+  int rank = 0;
+  bool active = true;
+#pragma unroll
+  for (int k = 0; k < MM; ++k) {
+    if (active && k < kmax) {
+      double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+      for (int i = k; i < MM; i += 2) {
+        c0 += col[i] * col[i];
+        if (i + 1 < MM) c1 += col[i + 1] * col[i + 1];
+      }
+      double best = (pstep == -1) ? (c0 + c1) : -1.0;
+      int bj = lane;
+      wave_argmax(best, bj);
+      if (k == 0) ref2 = best;
+      if (!(best > 0.0) || !(best > rel_tol * rel_tol * ref2)) {
+        active = false;
+      } else {
+        const int p = bj;
+        double* wk = W + k * MM;
+        if (lane == p) {
+#pragma unroll
+          for (int i = k; i < MM; ++i) wk[i] = col[i];
+        }
+        wave_sync();
+        double v[MM];
+        double s0 = 0.0, s1 = 0.0;
+        const double x0 = wk[k];
+#pragma unroll
+        for (int i = k + 1; i < MM; ++i) {
+          v[i] = wk[i];
+          if ((i - k) & 1) s0 += v[i] * v[i];
+          else s1 += v[i] * v[i];
+        }
+        const double s = s0 + s1;
+        double tau = 0.0, v0 = 0.0, alpha = x0;
+        if (s > 0.0) {
+          const double nrm = sqrt(x0 * x0 + s);
+          alpha = (x0 >= 0.0) ? -nrm : nrm;
+          v0 = x0 - alpha;
+          tau = 2.0 / (v0 * v0 + s);
+        }
+        if (MODE_Q && lane == 0) {
+          W[MM * MM + 2 * k] = tau;
+          W[MM * MM + 2 * k + 1] = v0;
+        }
+        if (pstep == -1 && lane != p && tau != 0.0) {
+          double w0 = v0 * col[k], w1 = 0.0;
+#pragma unroll
+          for (int i = k + 1; i < MM; ++i) {
+            if ((i - k) & 1) w1 += v[i] * col[i];
+            else w0 += v[i] * col[i];
+          }
+          const double w = tau * (w0 + w1);
+          col[k] -= w * v0;
+#pragma unroll
+          for (int i = k + 1; i < MM; ++i) col[i] -= w * v[i];
+        }
+        if (lane == p) {
+          col[k] = alpha;
+          pstep = k;
+        }
+        rank = k + 1;
+        wave_sync();
+      }
+    }
+  }
+  if constexpr (!MODE_Q) {
+    double mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < MM; ++i) {
+      const bool keep = (i < rank) && (lane < n) && (pstep < 0 || i <= pstep);
+      if (keep) mx = fmax(mx, fabs(col[i]));
+    }
+    mx = wave_max(mx);
+    *rmax = mx;
+    const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
+    if (lane < n) {
+#pragma unroll
+      for (int i = 0; i < MM; ++i) {
+        if (i < rank) {
+          const double val = (pstep < 0 || i <= pstep) ? col[i] * inv : 0.0;
+          Out[i * ldo + lane] = val;
+          if (Rglob) Rglob[(size_t)i * gld + lane] = val;
+        }
+      }
+    }
+  } else {
+    // Q e_c = H_0 ... H_{rank-1} e_c, lane c < rank; reflector k = (v0 at row k, W[k][i] for i > k)
+#pragma unroll
+    for (int i = 0; i < MM; ++i) col[i] = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int kk = MM - 1; kk >= 0; --kk) {
+      if (kk < rank) {
+        const double* wk = W + kk * MM;
+        const double tau = W[MM * MM + 2 * kk], v0 = W[MM * MM + 2 * kk + 1];
+        double v[MM];
+        double w0 = v0 * col[kk], w1 = 0.0;
+#pragma unroll
+        for (int i = kk + 1; i < MM; ++i) {
+          v[i] = wk[i];
+          if ((i - kk) & 1) w1 += v[i] * col[i];
+          else w0 += v[i] * col[i];
+        }
+        const double w = tau * (w0 + w1);
+        col[kk] -= w * v0;
+#pragma unroll
+        for (int i = kk + 1; i < MM; ++i) col[i] -= w * v[i];
+      }
+    }
+    if (lane < rank) {
+#pragma unroll
+      for (int i = 0; i < MM; ++i)
+        if (i < m) Out[lane * ldo + i] = col[i];
+    }
+  }
+  return rank;
+}
+
 // The first r columns of Q from a Householder factorisation done by
 // qr_pivoted_wave (reflector k: v = (v0_k at row k, M[i][k] for rows i > k),
 // H_k = I - tau_k v v^T), on one wavefront: Q e_c = H_0 ... H_{r-1} e_c.
@@ -451,7 +592,9 @@ struct Layout {
   static constexpr int oRed = oH + LXMAX * DP * DP;              // 8 reduction slots + 8 scalars
   static constexpr int oNrm = oRed + 16;                         // [D] row norms
   static constexpr int oIdx = oNrm + D;                          // [D] ints stored as doubles
-  static constexpr int oWork = oIdx + D;
+  static constexpr int MMW = (DP * D > 16) ? 32 : 16;            // largest register-QR tile
+  static constexpr int oW = oIdx + D;                            // register-QR reflectors [MMW][MMW] + 2 MMW
+  static constexpr int oWork = oW + MMW * MMW + 2 * MMW;
   // left sweep
   static constexpr int oA1 = oWork;                              // [DP][CHIM][CHIM]
   static constexpr int oR1 = oA1 + DP * CHIM * CHIM;             // [D][LD]
@@ -481,6 +624,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
   double* sScal = smem + Lay::oRed + 8;
   double* sNrm = smem + Lay::oNrm;
   int* sIdx = reinterpret_cast<int*>(smem + Lay::oIdx);
+  double* sW = smem + Lay::oW;
 
   const TaskDesc& t = tasks[blockIdx.x];
   const int tid = threadIdx.x;
@@ -567,7 +711,24 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         const int m = rR * DP, n = cr * DP;
         int* sPerm = sIdx;
         int rx;
-        if (n <= 64 && m <= 64) {
+        double* gR = rscr + (size_t)x * D * D;
+        const bool in_regs = (m <= Lay::MMW && n <= 64);
+        if (in_regs) {
+          // R Pi^T straight from registers to sR and gR, already scaled
+          if (tid < 64) {
+            double rmax = 0.0;
+            const int r0 = (m <= 16) ? qr_pivoted_reg<16, false>(sM, LD, m, n, RANK_TOL, sW, sR, LD, gR, D, &rmax)
+                                     : qr_pivoted_reg<32, false>(sM, LD, m, n, RANK_TOL, sW, sR, LD, gR, D, &rmax);
+            if (tid == 0) {
+              sIdx[D] = r0;
+              sScal[4] = rmax;
+            }
+          }
+          __syncthreads();
+          rx = sIdx[D];
+          if (!(sScal[4] > 0.0 && isfinite(sScal[4]))) fault |= 1;
+          __syncthreads();
+        } else if (n <= 64 && m <= 64) {
           if (tid < 64) {
             const int r0 = qr_pivoted_wave(sM, LD, m, n, sPerm, RANK_TOL);
             if (tid == 0) sIdx[D] = r0;   // pass the rank to the other waves
@@ -580,22 +741,23 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         }
         if (rx == 0) fault |= 1;
         if (tid == 0) flops += 2.0 * rR * DP * cr * cl + qr_count(m, n, rx);
-        double mx = 0.0;
-        for (int w = tid; w < rx * n; w += NT) {
-          const int i = w / n, j = w % n;
-          if (j >= i) mx = fmax(mx, fabs(sM[i * LD + j]));
-        }
-        mx = block_max<NT>(mx, sRed);
-        const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
-        if (!(mx > 0.0 && isfinite(mx))) fault |= 1;
-        // R_x = R Pi^T: any factor with R_x^T R_x = M^T M serves as the metric of the left part
-        double* gR = rscr + (size_t)x * D * D;
-        for (int w = tid; w < rx * n; w += NT) {
-          const int i = w / n, j = w % n;
-          const double v = (j >= i) ? sM[i * LD + j] * inv : 0.0;
-          const int oj = sPerm[j];
-          sR[i * LD + oj] = v;
-          gR[(size_t)i * D + oj] = v;
+        if (!in_regs) {
+          double mx = 0.0;
+          for (int w = tid; w < rx * n; w += NT) {
+            const int i = w / n, j = w % n;
+            if (j >= i) mx = fmax(mx, fabs(sM[i * LD + j]));
+          }
+          mx = block_max<NT>(mx, sRed);
+          const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
+          if (!(mx > 0.0 && isfinite(mx))) fault |= 1;
+          // R_x = R Pi^T: any factor with R_x^T R_x = M^T M serves as the metric of the left part
+          for (int w = tid; w < rx * n; w += NT) {
+            const int i = w / n, j = w % n;
+            const double v = (j >= i) ? sM[i * LD + j] * inv : 0.0;
+            const int oj = sPerm[j];
+            sR[i * LD + oj] = v;
+            gR[(size_t)i * D + oj] = v;
+          }
         }
         if (tid == 0) rrows[x] = rx;
         rR = rx;
@@ -721,8 +883,15 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           }
           __syncthreads();
           if (tid < 64) {
-            const int rk = qr_pivoted_wave(sCt, D, nC, rR, sIdx, RANK_TOL, sTau);
-            if (rk > 0 && rk <= chi) form_q_wave(sCt, D, nC, rk, sTau, sV, LD);
+            int rk;
+            if (nC <= 16) {
+              rk = qr_pivoted_reg<16, true>(sCt, D, nC, rR, RANK_TOL, sW, sV, LD, nullptr, 0, nullptr);
+            } else if (nC <= 32 && Lay::MMW >= 32) {
+              rk = qr_pivoted_reg<32, true>(sCt, D, nC, rR, RANK_TOL, sW, sV, LD, nullptr, 0, nullptr);
+            } else {
+              rk = qr_pivoted_wave(sCt, D, nC, rR, sIdx, RANK_TOL, sTau);
+              if (rk > 0 && rk <= chi) form_q_wave(sCt, D, nC, rk, sTau, sV, LD);
+            }
             if (tid == 0) sIdx[D] = rk;
           }
           __syncthreads();
