@@ -295,141 +295,175 @@ __device__ int qr_pivoted_wave(double* M, int ld, int m, int n, int* perm, doubl
 }
 
 // Register-resident column-pivoted Householder QR on one wavefront, for an
-// m x n row-major LDS matrix with m <= MM and n <= 64.  Lane j holds column j
-// in registers; pivot columns are not moved: each lane records the step at
-// which it became the pivot.  The step loop is fully unrolled, so every row
-// index is a compile-time constant and the inner loops shrink with the step.
-// At step k the pivot lane publishes its reflector (rows k..m-1) to LDS W
-// (row k of an MM x MM array; tau and v0 at W[MM*MM + 2k]); the other lanes
-// read it back as broadcasts.  Stops at the same rule as qr_pivoted.
+// m x n row-major LDS matrix M (leading dim ld) with m <= MM and n <= 64.
+// Lane j holds a window of column j in registers: col[i] is row base + i,
+// where base advances by U = 4 rows after every U steps (one register shift).
+// Inside a block of U steps every row offset is a compile-time constant, so
+// the loops shrink with the step and the code is one block long.
+// Per step k = base + u:
+//  - every lane stores its window rows u.. to Wc (64 rows of MM + 2 doubles)
+//    while the pivot is being chosen;
+//  - the pivot is the remaining column of largest norm (rows k..m-1), found
+//    by one wavefront maximum over lane-tagged norms (lane_key);
+//  - the factorisation stops when that norm falls to rel_tol times the
+//    largest initial column norm (the rest is zero at FP64 resolution);
+//  - the reflector is read back from the pivot's Wc row and applied to the
+//    other free columns; pivot columns are not moved: the pivot column
+//    becomes (alpha, 0, ...) and drops out.
 // MODE_Q = false: the rank rows of R Pi^T go to Out[i*ldo + j] (and Rglob,
 // stride gld), scaled by 1/max|R|, which is returned in *rmax.
-// MODE_Q = true: the first rank columns of Q are written as rows of
-// Out[c*ldo + i], i < m.  Returns the rank.
+// MODE_Q = true: the reflectors are kept in W (row k: window rows of its
+// block, tau at W[MM*MM + k]) and the first rank columns of Q are written as
+// rows of Out[c*ldo + i], i < m.  Returns the rank.
 template <int MM, bool MODE_Q>
-__device__ int qr_pivoted_reg(const double* M, int ld, int m, int n, double rel_tol, double* W, double* Out,
-                              int ldo, double* Rglob, int gld, double* rmax) {
+__device__ __attribute__((always_inline)) int qr_pivoted_blk(const double* M, int ld, int m, int n, double rel_tol, double* Wc, double* W,
+                              double* Out, int ldo, double* Rglob, int gld, double* rmax) {
+  constexpr int U = 4;
+  constexpr int LDW = MM + 2;
+  static_assert(MM % U == 0, "window must hold whole blocks");
   const int lane = threadIdx.x & 63;
+  double* mine = Wc + lane * LDW;
   double col[MM];
 #pragma unroll
   for (int i = 0; i < MM; ++i) col[i] = (i < m && lane < n) ? M[i * ld + lane] : 0.0;
-  int pstep = (lane < n) ? -1 : (1 << 20);   // step at which this column was the pivot (-1: not yet)
+  bool free_col = lane < n;     // not yet a pivot
   const int kmax = (m < n) ? m : n;
-  double ref2 = 0.0;
+  const double tol2 = rel_tol * rel_tol;
+  double ref2 = 0.0, mx = 0.0;
   int rank = 0;
-  bool active = true;
+  bool stop = kmax <= 0;
+#pragma unroll 1
+  for (int base = 0; !stop; base += U) {
 #pragma unroll
-  for (int k = 0; k < MM; ++k) {
-    if (active && k < kmax) {
-      double c0 = 0.0, c1 = 0.0;
-#pragma unroll
-      for (int i = k; i < MM; i += 2) {
-        c0 += col[i] * col[i];
-        if (i + 1 < MM) c1 += col[i + 1] * col[i + 1];
+    for (int u = 0; u < U; ++u) {
+      const int k = base + u;
+      if (k >= kmax) {
+        stop = true;
+        break;
       }
-      double best = (pstep == -1) ? (c0 + c1) : -1.0;
-      int bj = lane;
-      wave_argmax(best, bj);
+#pragma unroll
+      for (int i = u & ~1; i < MM; i += 2) *reinterpret_cast<double2*>(mine + i) = make_double2(col[i], col[i + 1]);
+      double t4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = u + 1; i < MM; ++i) t4[i & 3] = fma(col[i], col[i], t4[i & 3]);
+      const double t = (t4[0] + t4[1]) + (t4[2] + t4[3]);
+      const double key = wave_max_fast(free_col ? lane_key(fma(col[u], col[u], t), lane) : -1.0);
+      const double best = key_value(key);
       if (k == 0) ref2 = best;
-      if (!(best > 0.0) || !(best > rel_tol * rel_tol * ref2)) {
-        active = false;
-      } else {
-        const int p = bj;
-        double* wk = W + k * MM;
-        if (lane == p) {
-#pragma unroll
-          for (int i = k; i < MM; ++i) wk[i] = col[i];
-        }
-        wave_sync();
-        double v[MM];
-        double s0 = 0.0, s1 = 0.0;
-        const double x0 = wk[k];
-#pragma unroll
-        for (int i = k + 1; i < MM; ++i) {
-          v[i] = wk[i];
-          if ((i - k) & 1) s0 += v[i] * v[i];
-          else s1 += v[i] * v[i];
-        }
-        const double s = s0 + s1;
-        double tau = 0.0, v0 = 0.0, alpha = x0;
-        if (s > 0.0) {
-          const double nrm = sqrt(x0 * x0 + s);
-          alpha = (x0 >= 0.0) ? -nrm : nrm;
-          v0 = x0 - alpha;
-          tau = 2.0 / (v0 * v0 + s);
-        }
-        if (MODE_Q && lane == 0) {
-          W[MM * MM + 2 * k] = tau;
-          W[MM * MM + 2 * k + 1] = v0;
-        }
-        if (pstep == -1 && lane != p && tau != 0.0) {
-          double w0 = v0 * col[k], w1 = 0.0;
-#pragma unroll
-          for (int i = k + 1; i < MM; ++i) {
-            if ((i - k) & 1) w1 += v[i] * col[i];
-            else w0 += v[i] * col[i];
-          }
-          const double w = tau * (w0 + w1);
-          col[k] -= w * v0;
-#pragma unroll
-          for (int i = k + 1; i < MM; ++i) col[i] -= w * v[i];
-        }
-        if (lane == p) {
-          col[k] = alpha;
-          pstep = k;
-        }
-        rank = k + 1;
-        wave_sync();
+      if (!(best > 0.0) || !(best > tol2 * ref2)) {
+        stop = true;
+        break;
       }
+      const int p = key_lane(key);
+      const double s = readlane_d(t, p);
+      wave_sync();
+      const double* pv = Wc + p * LDW;
+      double v[MM];
+#pragma unroll
+      for (int i = u & ~1; i < MM; i += 2) {
+        const double2 q = *reinterpret_cast<const double2*>(pv + i);
+        v[i] = q.x;
+        v[i + 1] = q.y;
+      }
+      const double x0 = v[u];
+      double tau = 0.0, alpha = x0;
+      if (s > 0.0) {
+        const double nrm = sqrt(fma(x0, x0, s));
+        alpha = (x0 >= 0.0) ? -nrm : nrm;
+        v[u] = x0 - alpha;
+        tau = 2.0 / fma(v[u], v[u], s);
+      }
+      if constexpr (MODE_Q) {
+        if (lane == 0) {
+          double* wk = W + k * MM;
+#pragma unroll
+          for (int i = u & ~1; i < MM; i += 2) *reinterpret_cast<double2*>(wk + i) = make_double2(v[i], v[i + 1]);
+          W[MM * MM + k] = tau;
+        }
+      }
+      // every lane applies the reflector (no divergent branch): the pivot
+      // column becomes (alpha, 0, ...) up to rounding, and columns that were
+      // pivots before carry rounding-level residues; neither is read again
+      // except through the masked R row below
+      if (tau != 0.0) {
+        double w4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = u; i < MM; ++i) w4[i & 3] = fma(v[i], col[i], w4[i & 3]);
+        const double ww = tau * ((w4[0] + w4[1]) + (w4[2] + w4[3]));
+#pragma unroll
+        for (int i = u; i < MM; ++i) col[i] = fma(-ww, v[i], col[i]);
+      }
+      const bool piv = (lane == p);
+      if constexpr (!MODE_Q) {
+        const double r = piv ? alpha : (free_col ? col[u] : 0.0);
+        if (lane < n) Out[k * ldo + lane] = r;
+        mx = fmax(mx, fabs(r));
+      }
+      free_col = free_col && !piv;
+      rank = k + 1;
+      wave_sync();
+    }
+    if (!stop) {
+#pragma unroll
+      for (int i = 0; i < MM - U; ++i) col[i] = col[i + U];
+#pragma unroll
+      for (int i = MM - U; i < MM; ++i) col[i] = 0.0;
     }
   }
   if constexpr (!MODE_Q) {
-    double mx = 0.0;
-#pragma unroll
-    for (int i = 0; i < MM; ++i) {
-      const bool keep = (i < rank) && (lane < n) && (pstep < 0 || i <= pstep);
-      if (keep) mx = fmax(mx, fabs(col[i]));
-    }
-    mx = wave_max(mx);
+    mx = wave_max_fast(mx);
     *rmax = mx;
     const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
     if (lane < n) {
-#pragma unroll
-      for (int i = 0; i < MM; ++i) {
-        if (i < rank) {
-          const double val = (pstep < 0 || i <= pstep) ? col[i] * inv : 0.0;
-          Out[i * ldo + lane] = val;
-          if (Rglob) Rglob[(size_t)i * gld + lane] = val;
-        }
+      for (int i = 0; i < rank; ++i) {
+        const double val = Out[i * ldo + lane] * inv;
+        Out[i * ldo + lane] = val;
+        if (Rglob) Rglob[(size_t)i * gld + lane] = val;
       }
     }
   } else {
-    // Q e_c = H_0 ... H_{rank-1} e_c, lane c < rank; reflector k = (v0 at row k, W[k][i] for i > k)
+    // Q e_c = H_0 ... H_{rank-1} e_c for lane c < rank, reflectors applied
+    // from the last block down.  The window of block kb holds rows kb.. as in
+    // the factorisation; moving to the block above shifts it down by U rows
+    // and the rows entering at the top are still those of e_c.
+    double y[MM];
+    int kb = ((rank - 1) / U) * U;
 #pragma unroll
-    for (int i = 0; i < MM; ++i) col[i] = (i == lane) ? 1.0 : 0.0;
+    for (int i = 0; i < MM; ++i) y[i] = (lane == kb + i) ? 1.0 : 0.0;
+#pragma unroll 1
+    for (; kb >= 0 && rank > 0; kb -= U) {
 #pragma unroll
-    for (int kk = MM - 1; kk >= 0; --kk) {
-      if (kk < rank) {
-        const double* wk = W + kk * MM;
-        const double tau = W[MM * MM + 2 * kk], v0 = W[MM * MM + 2 * kk + 1];
-        double v[MM];
-        double w0 = v0 * col[kk], w1 = 0.0;
+      for (int u = U - 1; u >= 0; --u) {
+        const int kk = kb + u;
+        if (kk < rank) {
+          const double* wk = W + kk * MM;
+          const double tau = W[MM * MM + kk];
+          double v[MM];
 #pragma unroll
-        for (int i = kk + 1; i < MM; ++i) {
-          v[i] = wk[i];
-          if ((i - kk) & 1) w1 += v[i] * col[i];
-          else w0 += v[i] * col[i];
+          for (int i = u & ~1; i < MM; i += 2) {
+            const double2 q = *reinterpret_cast<const double2*>(wk + i);
+            v[i] = q.x;
+            v[i + 1] = q.y;
+          }
+          double w4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int i = u; i < MM; ++i) w4[i & 3] = fma(v[i], y[i], w4[i & 3]);
+          const double ww = tau * ((w4[0] + w4[1]) + (w4[2] + w4[3]));
+#pragma unroll
+          for (int i = u; i < MM; ++i) y[i] = fma(-ww, v[i], y[i]);
         }
-        const double w = tau * (w0 + w1);
-        col[kk] -= w * v0;
+      }
+      if (kb > 0) {
 #pragma unroll
-        for (int i = kk + 1; i < MM; ++i) col[i] -= w * v[i];
+        for (int i = MM - 1; i >= U; --i) y[i] = y[i - U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) y[i] = (lane == kb - U + i) ? 1.0 : 0.0;
       }
     }
     if (lane < rank) {
 #pragma unroll
       for (int i = 0; i < MM; ++i)
-        if (i < m) Out[lane * ldo + i] = col[i];
+        if (i < m) Out[lane * ldo + i] = y[i];
     }
   }
   return rank;
@@ -592,23 +626,32 @@ struct Layout {
   static constexpr int oRed = oH + LXMAX * DP * DP;              // 8 reduction slots + 8 scalars
   static constexpr int oNrm = oRed + 16;                         // [D] row norms
   static constexpr int oIdx = oNrm + D;                          // [D] ints stored as doubles
-  static constexpr int MMW = (DP * D > 16) ? 32 : 16;            // largest register-QR tile
-  static constexpr int oW = oIdx + D;                            // register-QR reflectors [MMW][MMW] + 2 MMW
-  static constexpr int oWork = oW + MMW * MMW + 2 * MMW;
-  // left sweep
+  static constexpr int MMW = (DP * D > 16) ? 32 : 16;            // largest register-QR window
+  static constexpr int WC = 64 * (MMW + 2);                      // register-QR column exchange
+  static constexpr int WQ = MMW * MMW + MMW;                     // register-QR reflectors + tau
+  static constexpr int oWork = oIdx + D;
+  // left sweep (the column exchange follows M)
   static constexpr int oA1 = oWork;                              // [DP][CHIM][CHIM]
   static constexpr int oR1 = oA1 + DP * CHIM * CHIM;             // [D][LD]
   static constexpr int oM1 = oR1 + D * LD;                       // [DP*D][LD]
-  static constexpr int end1 = oM1 + DP * D * LD;
-  // right sweep
+  static constexpr int oWcL = oM1 + DP * D * LD;                 // [64][MMW+2]
+  static constexpr int end1 = oWcL + WC;
+  // right sweep; the LQ of C^T runs when A and C are consumed, so its
+  // reflectors and column exchange live there when they fit
   static constexpr int oA2 = oWork;
   static constexpr int oT2 = oA2 + DP * CHIM * CHIM;             // [D][CHIM]
   static constexpr int oAT = oT2 + D * CHIM;                     // [CHIM][DP][CHIM]
   static constexpr int oR2 = oAT + CHIM * DP * CHIM;             // [D][LD]   (later Y)
   static constexpr int oZ = oR2 + D * LD;                        // [D][DP][CHIM] (later V~)
   static constexpr int oC = oZ + D * DP * CHIM;                  // [D][LD]
-  static constexpr int end2 = oC + D * LD;
+  static constexpr int endC = oC + D * LD;
+  static constexpr bool WQ_IN_A = DP * CHIM * CHIM >= WQ;
+  static constexpr bool WC_IN_C = D * LD >= WC;
+  static constexpr int oWq = WQ_IN_A ? oA2 : endC;
+  static constexpr int oWcR = WC_IN_C ? oC : (endC + (WQ_IN_A ? 0 : WQ));
+  static constexpr int end2 = endC + (WQ_IN_A ? 0 : WQ) + (WC_IN_C ? 0 : WC);
   static constexpr int total = (end1 > end2) ? end1 : end2;
+  static_assert(oWcL % 2 == 0 && oWcR % 2 == 0 && oWq % 2 == 0, "16-byte aligned register-QR buffers");
 };
 
 template <int DP, int CHIM>
@@ -617,14 +660,13 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
   constexpr int D = Lay::D;
   constexpr int LD = Lay::LD;
   constexpr int SITE = DP * CHIM * CHIM;
-  extern __shared__ double smem[];
+  extern __shared__ __align__(16) double smem[];
   double* sG = smem + Lay::oG;
   double* sH = smem + Lay::oH;
   double* sRed = smem + Lay::oRed;
   double* sScal = smem + Lay::oRed + 8;
   double* sNrm = smem + Lay::oNrm;
   int* sIdx = reinterpret_cast<int*>(smem + Lay::oIdx);
-  double* sW = smem + Lay::oW;
 
   const TaskDesc& t = tasks[blockIdx.x];
   const int tid = threadIdx.x;
@@ -717,8 +759,9 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           // R Pi^T straight from registers to sR and gR, already scaled
           if (tid < 64) {
             double rmax = 0.0;
-            const int r0 = (m <= 16) ? qr_pivoted_reg<16, false>(sM, LD, m, n, RANK_TOL, sW, sR, LD, gR, D, &rmax)
-                                     : qr_pivoted_reg<32, false>(sM, LD, m, n, RANK_TOL, sW, sR, LD, gR, D, &rmax);
+            double* sWc = smem + Lay::oWcL;
+            const int r0 = (m <= 16) ? qr_pivoted_blk<16, false>(sM, LD, m, n, RANK_TOL, sWc, nullptr, sR, LD, gR, D, &rmax)
+                                     : qr_pivoted_blk<Lay::MMW, false>(sM, LD, m, n, RANK_TOL, sWc, nullptr, sR, LD, gR, D, &rmax);
             if (tid == 0) {
               sIdx[D] = r0;
               sScal[4] = rmax;
@@ -884,10 +927,12 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           __syncthreads();
           if (tid < 64) {
             int rk;
+            double* sWc = smem + Lay::oWcR;
+            double* sWq = smem + Lay::oWq;
             if (nC <= 16) {
-              rk = qr_pivoted_reg<16, true>(sCt, D, nC, rR, RANK_TOL, sW, sV, LD, nullptr, 0, nullptr);
-            } else if (nC <= 32 && Lay::MMW >= 32) {
-              rk = qr_pivoted_reg<32, true>(sCt, D, nC, rR, RANK_TOL, sW, sV, LD, nullptr, 0, nullptr);
+              rk = qr_pivoted_blk<16, true>(sCt, D, nC, rR, RANK_TOL, sWc, sWq, sV, LD, nullptr, 0, nullptr);
+            } else if (nC <= Lay::MMW) {
+              rk = qr_pivoted_blk<Lay::MMW, true>(sCt, D, nC, rR, RANK_TOL, sWc, sWq, sV, LD, nullptr, 0, nullptr);
             } else {
               rk = qr_pivoted_wave(sCt, D, nC, rR, sIdx, RANK_TOL, sTau);
               if (rk > 0 && rk <= chi) form_q_wave(sCt, D, nC, rk, sTau, sV, LD);
@@ -905,6 +950,12 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
               sNrm[i] = 1.0;
             }
             if (tid == 0) flops += qr_count(nC, rR, rk) + 4.0 * nC * rk * rk;
+          } else if (Lay::WC_IN_C && nC <= Lay::MMW) {
+            // the register QR exchanged columns through C's tile: restore C from C^T
+            for (int w = tid; w < nC * rR; w += NT) {
+              const int c = w / rR, i = w % rR;
+              sC[i * LD + c] = sCt[c * D + i];
+            }
           }
           __syncthreads();
         }

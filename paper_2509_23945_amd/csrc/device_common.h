@@ -88,6 +88,41 @@ __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_mov<0x140>(v));
   return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
+// DPP move where lanes outside the enabled rows keep their own value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo0 = (int)(b & 0xffffffffll), hi0 = (int)(b >> 32);
+  const int lo = __builtin_amdgcn_update_dpp(lo0, lo0, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(hi0, hi0, CTRL, ROWS, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// Wavefront maximum: butterfly within each row of 16 lanes, then row_bcast15
+// and row_bcast31 carry the row maxima up to lane 63, which is read once.
+// Every lane returns the same bits.
+__device__ __forceinline__ double wave_max_fast(double v) {
+  v = fmax(v, dpp_mov<0xB1>(v));
+  v = fmax(v, dpp_mov<0x4E>(v));
+  v = fmax(v, dpp_mov<0x141>(v));
+  v = fmax(v, dpp_mov<0x140>(v));
+  v = fmax(v, dpp_rows<0x142, 0xa>(v));   // row_bcast15 into rows 1 and 3
+  v = fmax(v, dpp_rows<0x143, 0xc>(v));   // row_bcast31 into rows 2 and 3
+  return readlane_d(v, 63);
+}
+// A non-negative value with the lane index folded into its six lowest
+// mantissa bits: the maximum of such keys names the largest value (to a
+// relative 2^-46) and, among equal keys, the lowest lane.
+__device__ __forceinline__ double lane_key(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  return __builtin_bit_cast(double, (b & ~63ll) | (long long)(63 - lane));
+}
+__device__ __forceinline__ int key_lane(double key) {
+  return 63 - (int)(__builtin_bit_cast(long long, key) & 63);
+}
+__device__ __forceinline__ double key_value(double key) {
+  return __builtin_bit_cast(double, __builtin_bit_cast(long long, key) & ~63ll);
+}
+
 // Largest value over the wavefront and the smallest lane index holding it
 // (the value's owner passes its own index).
 template <int CTRL>
