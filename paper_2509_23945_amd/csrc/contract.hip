@@ -313,11 +313,15 @@ __device__ int qr_pivoted_wave(double* M, int ld, int m, int n, int* perm, doubl
 // MODE_Q = false: the rank rows of R Pi^T go to Out[i*ldo + j] (and Rglob,
 // stride gld), scaled by 1/max|R|, which is returned in *rmax.
 // MODE_Q = true: the reflectors are kept in W (row k: window rows of its
-// block, tau at W[MM*MM + k]) and the first rank columns of Q are written as
-// rows of Out[c*ldo + i], i < m.  Returns the rank.
+// block; tau at W[kcap*MM + k]) and the first rank columns of Q are written
+// as rows of Out[c*ldo + i], i < m.
+// At most kcap steps are taken; in MODE_Q a factorisation that reaches kcap
+// steps returns kcap without forming Q (the caller needs rank < kcap).
+// Returns the rank.
 template <int MM, bool MODE_Q>
-__device__ __attribute__((always_inline)) int qr_pivoted_blk(const double* M, int ld, int m, int n, double rel_tol, double* Wc, double* W,
-                              double* Out, int ldo, double* Rglob, int gld, double* rmax) {
+__device__ __attribute__((always_inline)) int qr_pivoted_blk(const double* M, int ld, int m, int n, int kcap,
+                                                             double rel_tol, double* Wc, double* W, double* Out,
+                                                             int ldo, double* Rglob, int gld, double* rmax) {
   constexpr int U = 4;
   constexpr int LDW = MM + 2;
   static_assert(MM % U == 0, "window must hold whole blocks");
@@ -327,7 +331,8 @@ __device__ __attribute__((always_inline)) int qr_pivoted_blk(const double* M, in
 #pragma unroll
   for (int i = 0; i < MM; ++i) col[i] = (i < m && lane < n) ? M[i * ld + lane] : 0.0;
   bool free_col = lane < n;     // not yet a pivot
-  const int kmax = (m < n) ? m : n;
+  int kmax = (m < n) ? m : n;
+  if (kcap < kmax) kmax = kcap;
   const double tol2 = rel_tol * rel_tol;
   double ref2 = 0.0, mx = 0.0;
   int rank = 0;
@@ -378,7 +383,7 @@ __device__ __attribute__((always_inline)) int qr_pivoted_blk(const double* M, in
           double* wk = W + k * MM;
 #pragma unroll
           for (int i = u & ~1; i < MM; i += 2) *reinterpret_cast<double2*>(wk + i) = make_double2(v[i], v[i + 1]);
-          W[MM * MM + k] = tau;
+          W[kcap * MM + k] = tau;
         }
       }
       // every lane applies the reflector (no divergent branch): the pivot
@@ -422,6 +427,7 @@ __device__ __attribute__((always_inline)) int qr_pivoted_blk(const double* M, in
       }
     }
   } else {
+    if (rank == kcap) return rank;
     // Q e_c = H_0 ... H_{rank-1} e_c for lane c < rank, reflectors applied
     // from the last block down.  The window of block kb holds rows kb.. as in
     // the factorisation; moving to the block above shifts it down by U rows
@@ -437,7 +443,7 @@ __device__ __attribute__((always_inline)) int qr_pivoted_blk(const double* M, in
         const int kk = kb + u;
         if (kk < rank) {
           const double* wk = W + kk * MM;
-          const double tau = W[MM * MM + kk];
+          const double tau = W[kcap * MM + kk];
           double v[MM];
 #pragma unroll
           for (int i = u & ~1; i < MM; i += 2) {
@@ -626,9 +632,11 @@ struct Layout {
   static constexpr int oRed = oH + LXMAX * DP * DP;              // 8 reduction slots + 8 scalars
   static constexpr int oNrm = oRed + 16;                         // [D] row norms
   static constexpr int oIdx = oNrm + D;                          // [D] ints stored as doubles
-  static constexpr int MMW = (DP * D > 16) ? 32 : 16;            // largest register-QR window
+  // largest register-QR window (rows held per lane)
+  static constexpr int MMW = (D >= 64) ? 64 : ((DP * D > 16) ? 32 : 16);
   static constexpr int WC = 64 * (MMW + 2);                      // register-QR column exchange
-  static constexpr int WQ = MMW * MMW + MMW;                     // register-QR reflectors + tau
+  // LQ reflectors: at most chi + 1 steps (rank > chi means truncation) + tau
+  static constexpr int WQ = ((CHIM + 1) * MMW + (CHIM + 1) + 1) & ~1;
   static constexpr int oWork = oIdx + D;
   // left sweep (the column exchange follows M)
   static constexpr int oA1 = oWork;                              // [DP][CHIM][CHIM]
@@ -645,11 +653,11 @@ struct Layout {
   static constexpr int oZ = oR2 + D * LD;                        // [D][DP][CHIM] (later V~)
   static constexpr int oC = oZ + D * DP * CHIM;                  // [D][LD]
   static constexpr int endC = oC + D * LD;
-  static constexpr bool WQ_IN_A = DP * CHIM * CHIM >= WQ;
-  static constexpr bool WC_IN_C = D * LD >= WC;
-  static constexpr int oWq = WQ_IN_A ? oA2 : endC;
-  static constexpr int oWcR = WC_IN_C ? oC : (endC + (WQ_IN_A ? 0 : WQ));
-  static constexpr int end2 = endC + (WQ_IN_A ? 0 : WQ) + (WC_IN_C ? 0 : WC);
+  // A and T_{x+1} (contiguous) are consumed before the LQ, C after its transpose
+  static constexpr bool WQ_IN_AT = DP * CHIM * CHIM + D * CHIM >= WQ;
+  static constexpr int oWq = WQ_IN_AT ? oA2 : endC;
+  static constexpr int oWcR = WQ_IN_AT ? oC : endC + WQ;         // C's tile and what follows it
+  static constexpr int end2 = oWcR + ((WC > D * LD) ? WC : D * LD);
   static constexpr int total = (end1 > end2) ? end1 : end2;
   static_assert(oWcL % 2 == 0 && oWcR % 2 == 0 && oWq % 2 == 0, "16-byte aligned register-QR buffers");
 };
@@ -760,8 +768,15 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           if (tid < 64) {
             double rmax = 0.0;
             double* sWc = smem + Lay::oWcL;
-            const int r0 = (m <= 16) ? qr_pivoted_blk<16, false>(sM, LD, m, n, RANK_TOL, sWc, nullptr, sR, LD, gR, D, &rmax)
-                                     : qr_pivoted_blk<Lay::MMW, false>(sM, LD, m, n, RANK_TOL, sWc, nullptr, sR, LD, gR, D, &rmax);
+            int r0;
+            if (m <= 16) {
+              r0 = qr_pivoted_blk<16, false>(sM, LD, m, n, m, RANK_TOL, sWc, nullptr, sR, LD, gR, D, &rmax);
+            } else if (m <= 32 || Lay::MMW == 32) {
+              r0 = qr_pivoted_blk<(Lay::MMW < 32 ? Lay::MMW : 32), false>(sM, LD, m, n, m, RANK_TOL, sWc, nullptr, sR, LD,
+                                                                          gR, D, &rmax);
+            } else {
+              r0 = qr_pivoted_blk<Lay::MMW, false>(sM, LD, m, n, m, RANK_TOL, sWc, nullptr, sR, LD, gR, D, &rmax);
+            }
             if (tid == 0) {
               sIdx[D] = r0;
               sScal[4] = rmax;
@@ -930,9 +945,12 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
             double* sWc = smem + Lay::oWcR;
             double* sWq = smem + Lay::oWq;
             if (nC <= 16) {
-              rk = qr_pivoted_blk<16, true>(sCt, D, nC, rR, RANK_TOL, sWc, sWq, sV, LD, nullptr, 0, nullptr);
-            } else if (nC <= Lay::MMW) {
-              rk = qr_pivoted_blk<Lay::MMW, true>(sCt, D, nC, rR, RANK_TOL, sWc, sWq, sV, LD, nullptr, 0, nullptr);
+              rk = qr_pivoted_blk<16, true>(sCt, D, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sV, LD, nullptr, 0, nullptr);
+            } else if (nC <= 32 && Lay::MMW >= 32) {
+              rk = qr_pivoted_blk<(Lay::MMW < 32 ? Lay::MMW : 32), true>(sCt, D, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sV,
+                                                                         LD, nullptr, 0, nullptr);
+            } else if (nC <= Lay::MMW && Lay::MMW > 32) {
+              rk = qr_pivoted_blk<Lay::MMW, true>(sCt, D, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sV, LD, nullptr, 0, nullptr);
             } else {
               rk = qr_pivoted_wave(sCt, D, nC, rR, sIdx, RANK_TOL, sTau);
               if (rk > 0 && rk <= chi) form_q_wave(sCt, D, nC, rk, sTau, sV, LD);
@@ -950,7 +968,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
               sNrm[i] = 1.0;
             }
             if (tid == 0) flops += qr_count(nC, rR, rk) + 4.0 * nC * rk * rk;
-          } else if (Lay::WC_IN_C && nC <= Lay::MMW) {
+          } else if (Lay::WQ_IN_AT && nC <= Lay::MMW) {
             // the register QR exchanged columns through C's tile: restore C from C^T
             for (int w = tid; w < nC * rR; w += NT) {
               const int c = w / rR, i = w % rR;
