@@ -108,21 +108,36 @@ struct Task {
 // in the shared workspace, grouped by kernel instantiation.
 struct Plan {
   std::vector<TaskDesc> desc;
+  std::vector<int> order;   // desc[k] runs tasks[order[k]]
   struct Group {
     int d, chi_max, first, count, lx_max;
   };
   std::vector<Group> groups;
 };
 
+// Relative cost of one slice task, for longest-first ordering: the
+// contraction does Lx Ly factorisations of (d chi)-sized tiles; a layer with
+// one held neighbour (z = 0 or Lz - 1) sees a weaker field, and its boundary
+// states need larger bonds (about twice the work).
+double task_cost(const Task& t) {
+  const auto* L = t.lat;
+  const double dc = (double)L->d * L->chi;
+  const bool edge = (L->Lz > 1) && (t.z == 0 || t.z == L->Lz - 1);
+  return (double)L->Lx * L->Ly * dc * dc * dc * (edge ? 2.0 : 1.0);
+}
+
 tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
-  // order by instantiation so that each group is a contiguous launch
+  // order by instantiation so that each group is a contiguous launch, and
+  // within a group longest task first: workgroups are dispatched in index
+  // order, so the long tasks start in the first wave of the grid
   std::vector<int> order(tasks.size());
   for (size_t i = 0; i < tasks.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     const auto* la = tasks[a].lat;
     const auto* lb = tasks[b].lat;
     if (la->d != lb->d) return la->d < lb->d;
-    return la->chi_max < lb->chi_max;
+    if (la->chi_max != lb->chi_max) return la->chi_max < lb->chi_max;
+    return task_cost(tasks[a]) > task_cost(tasks[b]);
   });
   size_t env_need = 0, rscr_need = 0, int_need = 0, dbl_need = 0;
   for (int i : order) {
@@ -139,6 +154,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
   if (grow(g_ws.counters, g_ws.counters_cap, tnmc::kCounters * tasks.size()) != TNMC_OK) return TNMC_ERR_OOM;
   plan.desc.clear();
   plan.groups.clear();
+  plan.order = order;
   size_t eo = 0, ro = 0, io = 0, dof = 0;
   for (size_t k = 0; k < order.size(); ++k) {
     const Task& tk = tasks[order[k]];
@@ -470,23 +486,9 @@ tnmc_status tnmc_half_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t p
   Plan plan;
   tnmc_status r = make_plan(tasks, plan);
   if (r != TNMC_OK) return r;
-  // trace order is the task order (lattice, chain, z); plan order may differ
-  std::vector<int> pos(tasks.size());
-  {
-    size_t k = 0;
-    // make_plan orders by (d, chi_max) with a stable sort; recompute that permutation
-    std::vector<int> order(tasks.size());
-    for (size_t i = 0; i < tasks.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-      const auto* la = tasks[a].lat;
-      const auto* lb = tasks[b].lat;
-      if (la->d != lb->d) return la->d < lb->d;
-      return la->chi_max < lb->chi_max;
-    });
-    for (int i : order) pos[k++] = i;
-  }
+  // trace order is the task order (lattice, chain, z); descriptor k runs task plan.order[k]
   for (size_t k = 0; k < plan.desc.size(); ++k) {
-    plan.desc[k].record = trace ? trace + 5 * (size_t)pos[k] : nullptr;
+    plan.desc[k].record = trace ? trace + 5 * (size_t)plan.order[k] : nullptr;
   }
   if (grow(g_ws.tasks, g_ws.tasks_cap, plan.desc.size()) != TNMC_OK) return TNMC_ERR_OOM;
   HIP_TRY(hipMemcpyAsync(g_ws.tasks, plan.desc.data(), plan.desc.size() * sizeof(TaskDesc),
