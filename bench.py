@@ -46,10 +46,15 @@ KERNEL_SOURCES = ["contract.hip", "device_common.h", "tnmc_internal.h"]
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources with comments and whitespace removed."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2509_23945_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2509_23945_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -10,12 +10,14 @@
 //   G_x[r][b] = exp(beta (Jy(x,y-1) sig(r,b) + F(y,x,b)))   (vertical bond + held-layer field)
 //   H_x[a][b] = exp(beta Jx(x-1,y) sig(a,b))                 (horizontal bond; 1 at x = 0)
 // with b summed at the right edge.  Truncation: a left-to-right sweep keeps
-// only the triangular factors R_x of QR(R_{x-1} B_x); a right-to-left sweep
-// takes, at each bond, the right singular vectors of C = R_{x-1} (B_x T_{x+1})
-// (one-sided Jacobi on the rows of C) and keeps the min(chi, rank dims)
-// largest; T_x = (B_x T_{x+1}) V_x^T carries the rest of the row to the left.
-// The G/H product form lets every contraction with B_x be done as a small GEMM
-// on A_x followed by d x d scalings.
+// only the triangular factors R_x of a rank-revealing QR(R_{x-1} B_x); a
+// right-to-left sweep takes, at each bond, the row space of
+// C = R_{x-1} (B_x T_{x+1}): when its numerical rank is at most chi, an
+// orthonormal basis from a pivoted LQ of C is exact; otherwise the chi leading
+// right singular vectors (one-sided Jacobi on the rows of C) are kept.
+// T_x = (B_x T_{x+1}) V_x^T carries the rest of the row to the left.  The G/H
+// product form lets every contraction with B_x be done as a small GEMM on A_x
+// followed by d x d scalings.
 
 #include "device_common.h"
 #include "tnmc_internal.h"
