@@ -296,43 +296,58 @@ __device__ int qr_pivoted_wave(double* M, int ld, int m, int n, int* perm, doubl
   return rank;
 }
 
-// Register-resident column-pivoted Householder QR on one wavefront, for an
-// m x n row-major LDS matrix M (leading dim ld) with m <= MM and n <= 64.
-// Lane j holds a window of column j in registers: col[i] is row base + i,
-// where base advances by U = 4 rows after every U steps (one register shift).
-// Inside a block of U steps every row offset is a compile-time constant, so
-// the loops shrink with the step and the code is one block long.
-// Per step k = base + u:
-//  - every lane stores its window rows u.. to Wc (64 rows of MM + 2 doubles)
-//    while the pivot is being chosen;
-//  - the pivot is the remaining column of largest norm (rows k..m-1), found
-//    by one wavefront maximum over lane-tagged norms (lane_key);
-//  - the factorisation stops when that norm falls to rel_tol times the
-//    largest initial column norm (the rest is zero at FP64 resolution);
-//  - the reflector is read back from the pivot's Wc row and applied to the
-//    other free columns; pivot columns are not moved: the pivot column
-//    becomes (alpha, 0, ...) and drops out.
+// Sum over each aligned group of G lanes (G = 1, 2 or 4); every lane of the
+// group gets the same bits.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G >= 2) v += dpp_mov<0xB1>(v);   // partner lane ^ 1
+  if constexpr (G >= 4) v += dpp_mov<0x4E>(v);   // partner lane ^ 2
+  return v;
+}
+
+// Column-pivoted Householder QR held in registers with LPC lanes per column
+// (n <= 64 / LPC columns, m <= MM rows).  Lane (c, h) = (lane / LPC, lane %
+// LPC) holds the window rows i = LPC j + h, j < MR = MM / LPC, of column c:
+// partial norms and dot products over a column are combined by one or two
+// DPP steps, and each lane does 1/LPC of the row work.  The window moves down
+// U = 4 rows (4 / LPC local rows) after every block of U steps, so inside a
+// block every local row index is a compile-time constant; at step u of a
+// block the pivot row is local row u / LPC of the lanes with h = u % LPC.
+// Per step: every lane stores its rows to Wc (row `lane`, MR + 2 doubles)
+// while the pivot is chosen by one wavefront maximum over lane-tagged column
+// norms; the pivot's rows are read back by residue; the reflector is applied
+// by every lane without divergent branches (pivot columns drop out through
+// free_col and the masked R rows).  Stops when the largest remaining column
+// norm falls to rel_tol times the largest initial one, or after kcap steps.
 // MODE_Q = false: the rank rows of R Pi^T go to Out[i*ldo + j] (and Rglob,
 // stride gld), scaled by 1/max|R|, which is returned in *rmax.
-// MODE_Q = true: the reflectors are kept in W (row k: window rows of its
-// block; tau at W[kcap*MM + k]) and the first rank columns of Q are written
-// as rows of Out[c*ldo + i], i < m.
-// At most kcap steps are taken; in MODE_Q a factorisation that reaches kcap
-// steps returns kcap without forming Q (the caller needs rank < kcap).
-// Returns the rank.
-template <int MM, bool MODE_Q>
-__device__ __attribute__((always_inline)) int qr_pivoted_blk(const double* M, int ld, int m, int n, int kcap,
+// MODE_Q = true: reflector k is kept in W[k*MM + h*MR + j] (residue-major,
+// rows of its block's window), tau at W[kcap*MM + k]; the first rank columns
+// of Q are written as rows of Out[c*ldo + i], i < m.  A factorisation that
+// reaches kcap steps returns kcap without forming Q.  Returns the rank.
+template <int MM, int LPC, bool MODE_Q>
+__device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, int ld, int m, int n, int kcap,
                                                              double rel_tol, double* Wc, double* W, double* Out,
                                                              int ldo, double* Rglob, int gld, double* rmax) {
   constexpr int U = 4;
-  constexpr int LDW = MM + 2;
-  static_assert(MM % U == 0, "window must hold whole blocks");
+  constexpr int MR = MM / LPC;
+  constexpr int SH = U / LPC;
+  constexpr int LDW = MR + 2;
+  // a 64-row column per lane leaves no registers for a copy of the reflector:
+  // it is then read from the exchange row twice (dot product, update)
+  constexpr bool V_LDS = MR > 32;
+  static_assert(MM % U == 0 && U % LPC == 0 && MR % 2 == 0, "window must hold whole blocks of paired rows");
   const int lane = threadIdx.x & 63;
+  const int c = lane / LPC;
+  const int h = lane % LPC;
   double* mine = Wc + lane * LDW;
-  double col[MM];
+  double col[MR];
 #pragma unroll
-  for (int i = 0; i < MM; ++i) col[i] = (i < m && lane < n) ? M[i * ld + lane] : 0.0;
-  bool free_col = lane < n;     // not yet a pivot
+  for (int j = 0; j < MR; ++j) {
+    const int i = LPC * j + h;
+    col[j] = (i < m && c < n) ? M[i * ld + c] : 0.0;
+  }
+  bool free_col = c < n;
   int kmax = (m < n) ? m : n;
   if (kcap < kmax) kmax = kcap;
   const double tol2 = rel_tol * rel_tol;
@@ -348,63 +363,93 @@ __device__ __attribute__((always_inline)) int qr_pivoted_blk(const double* M, in
         stop = true;
         break;
       }
+      const int jb = u / LPC;     // boundary local row: the pivot row for h == r
+      const int r = u % LPC;
 #pragma unroll
-      for (int i = u & ~1; i < MM; i += 2) *reinterpret_cast<double2*>(mine + i) = make_double2(col[i], col[i + 1]);
+      for (int j = jb & ~1; j < MR; j += 2) *reinterpret_cast<double2*>(mine + j) = make_double2(col[j], col[j + 1]);
       double t4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int i = u + 1; i < MM; ++i) t4[i & 3] = fma(col[i], col[i], t4[i & 3]);
-      const double t = (t4[0] + t4[1]) + (t4[2] + t4[3]);
-      const double key = wave_max_fast(free_col ? lane_key(fma(col[u], col[u], t), lane) : -1.0);
+      for (int j = jb + 1; j < MR; ++j) t4[j & 3] = fma(col[j], col[j], t4[j & 3]);
+      const double bb = col[jb] * col[jb];
+      double tail = (t4[0] + t4[1]) + (t4[2] + t4[3]);
+      double full = tail + ((h >= r) ? bb : 0.0);
+      tail += (h > r) ? bb : 0.0;
+      tail = group_sum<LPC>(tail);
+      full = group_sum<LPC>(full);
+      const double key = wave_max_fast(free_col ? lane_key(full, lane) : -1.0);
       const double best = key_value(key);
       if (k == 0) ref2 = best;
       if (!(best > 0.0) || !(best > tol2 * ref2)) {
         stop = true;
         break;
       }
-      const int p = key_lane(key);
-      const double s = readlane_d(t, p);
+      const int pl = key_lane(key);   // lowest lane of the pivot column's group
+      const int p = pl / LPC;
+      const double s = readlane_d(tail, pl);
       wave_sync();
-      const double* pv = Wc + p * LDW;
-      double v[MM];
+      const double x0 = Wc[(pl + r) * LDW + jb];
+      const double* pv = Wc + (pl + h) * LDW;
+      double v[V_LDS ? 2 : MR];
+      if constexpr (!V_LDS) {
 #pragma unroll
-      for (int i = u & ~1; i < MM; i += 2) {
-        const double2 q = *reinterpret_cast<const double2*>(pv + i);
-        v[i] = q.x;
-        v[i + 1] = q.y;
+        for (int j = jb & ~1; j < MR; j += 2) {
+          const double2 q = *reinterpret_cast<const double2*>(pv + j);
+          v[j] = q.x;
+          v[j + 1] = q.y;
+        }
       }
-      const double x0 = v[u];
-      double tau = 0.0, alpha = x0;
+      double tau = 0.0, alpha = x0, v0 = x0;
       if (s > 0.0) {
         const double nrm = sqrt(fma(x0, x0, s));
         alpha = (x0 >= 0.0) ? -nrm : nrm;
-        v[u] = x0 - alpha;
-        tau = 2.0 / fma(v[u], v[u], s);
+        v0 = x0 - alpha;
+        tau = 2.0 / fma(v0, v0, s);
       }
+      // reflector entry on the boundary row: v0 on the pivot row, zero above it
+      const double vb = (h == r) ? v0 : ((h > r) ? pv[jb] : 0.0);
+      if constexpr (!V_LDS) v[jb] = vb;
       if constexpr (MODE_Q) {
-        if (lane == 0) {
-          double* wk = W + k * MM;
+        if (lane < LPC) {
+          double* wk = W + k * MM + h * MR;
+          if constexpr (!V_LDS) {
 #pragma unroll
-          for (int i = u & ~1; i < MM; i += 2) *reinterpret_cast<double2*>(wk + i) = make_double2(v[i], v[i + 1]);
-          W[kcap * MM + k] = tau;
+            for (int j = jb & ~1; j < MR; j += 2) *reinterpret_cast<double2*>(wk + j) = make_double2(v[j], v[j + 1]);
+          } else {
+#pragma unroll
+            for (int j = jb + 1; j < MR; ++j) wk[j] = pv[j];
+            wk[jb] = vb;
+          }
         }
+        if (lane == 0) W[kcap * MM + k] = tau;
       }
-      // every lane applies the reflector (no divergent branch): the pivot
-      // column becomes (alpha, 0, ...) up to rounding, and columns that were
-      // pivots before carry rounding-level residues; neither is read again
-      // except through the masked R row below
       if (tau != 0.0) {
         double w4[4] = {0.0, 0.0, 0.0, 0.0};
+        if constexpr (!V_LDS) {
 #pragma unroll
-        for (int i = u; i < MM; ++i) w4[i & 3] = fma(v[i], col[i], w4[i & 3]);
-        const double ww = tau * ((w4[0] + w4[1]) + (w4[2] + w4[3]));
+          for (int j = jb; j < MR; ++j) w4[j & 3] = fma(v[j], col[j], w4[j & 3]);
+        } else {
+          w4[jb & 3] = vb * col[jb];
 #pragma unroll
-        for (int i = u; i < MM; ++i) col[i] = fma(-ww, v[i], col[i]);
+          for (int j = jb + 1; j < MR; ++j) w4[j & 3] = fma(pv[j], col[j], w4[j & 3]);
+        }
+        const double ww = tau * group_sum<LPC>((w4[0] + w4[1]) + (w4[2] + w4[3]));
+        if constexpr (!V_LDS) {
+#pragma unroll
+          for (int j = jb; j < MR; ++j) col[j] = fma(-ww, v[j], col[j]);
+        } else {
+          __asm__ __volatile__("" ::: "memory");   // read the reflector again rather than keep it
+          col[jb] = fma(-ww, vb, col[jb]);
+#pragma unroll
+          for (int j = jb + 1; j < MR; ++j) col[j] = fma(-ww, pv[j], col[j]);
+        }
       }
-      const bool piv = (lane == p);
+      const bool piv = (c == p);
       if constexpr (!MODE_Q) {
-        const double r = piv ? alpha : (free_col ? col[u] : 0.0);
-        if (lane < n) Out[k * ldo + lane] = r;
-        mx = fmax(mx, fabs(r));
+        const double rv = piv ? alpha : (free_col ? col[jb] : 0.0);
+        if (h == r) {
+          if (c < n) Out[k * ldo + c] = rv;
+          mx = fmax(mx, fabs(rv));
+        }
       }
       free_col = free_col && !piv;
       rank = k + 1;
@@ -412,69 +457,93 @@ __device__ __attribute__((always_inline)) int qr_pivoted_blk(const double* M, in
     }
     if (!stop) {
 #pragma unroll
-      for (int i = 0; i < MM - U; ++i) col[i] = col[i + U];
+      for (int j = 0; j < MR - SH; ++j) col[j] = col[j + SH];
 #pragma unroll
-      for (int i = MM - U; i < MM; ++i) col[i] = 0.0;
+      for (int j = MR - SH; j < MR; ++j) col[j] = 0.0;
     }
   }
   if constexpr (!MODE_Q) {
     mx = wave_max_fast(mx);
     *rmax = mx;
     const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
-    if (lane < n) {
-      for (int i = 0; i < rank; ++i) {
-        const double val = Out[i * ldo + lane] * inv;
-        Out[i * ldo + lane] = val;
-        if (Rglob) Rglob[(size_t)i * gld + lane] = val;
+    wave_sync();
+    if (c < n) {
+      for (int i = h; i < rank; i += LPC) {
+        const double val = Out[i * ldo + c] * inv;
+        Out[i * ldo + c] = val;
+        if (Rglob) Rglob[(size_t)i * gld + c] = val;
       }
     }
   } else {
     if (rank == kcap) return rank;
-    // Q e_c = H_0 ... H_{rank-1} e_c for lane c < rank, reflectors applied
-    // from the last block down.  The window of block kb holds rows kb.. as in
-    // the factorisation; moving to the block above shifts it down by U rows
-    // and the rows entering at the top are still those of e_c.
-    double y[MM];
+    // Q e_c = H_0 ... H_{rank-1} e_c for column c < rank, reflectors applied
+    // from the last block down over the same windows as the factorisation;
+    // moving to the block above shifts the window down by U rows, and the
+    // rows entering at the top are still those of e_c.
+    double y[MR];
     int kb = ((rank - 1) / U) * U;
 #pragma unroll
-    for (int i = 0; i < MM; ++i) y[i] = (lane == kb + i) ? 1.0 : 0.0;
+    for (int j = 0; j < MR; ++j) y[j] = (kb + LPC * j + h == c) ? 1.0 : 0.0;
 #pragma unroll 1
     for (; kb >= 0 && rank > 0; kb -= U) {
 #pragma unroll
       for (int u = U - 1; u >= 0; --u) {
         const int kk = kb + u;
         if (kk < rank) {
-          const double* wk = W + kk * MM;
+          const int jb = u / LPC;
+          const double* wk = W + kk * MM + h * MR;
           const double tau = W[kcap * MM + kk];
-          double v[MM];
-#pragma unroll
-          for (int i = u & ~1; i < MM; i += 2) {
-            const double2 q = *reinterpret_cast<const double2*>(wk + i);
-            v[i] = q.x;
-            v[i + 1] = q.y;
-          }
           double w4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int i = u; i < MM; ++i) w4[i & 3] = fma(v[i], y[i], w4[i & 3]);
-          const double ww = tau * ((w4[0] + w4[1]) + (w4[2] + w4[3]));
+          for (int j = jb; j < MR; ++j) w4[j & 3] = fma(wk[j], y[j], w4[j & 3]);
+          const double ww = tau * group_sum<LPC>((w4[0] + w4[1]) + (w4[2] + w4[3]));
+          if constexpr (V_LDS) __asm__ __volatile__("" ::: "memory");
 #pragma unroll
-          for (int i = u; i < MM; ++i) y[i] = fma(-ww, v[i], y[i]);
+          for (int j = jb; j < MR; ++j) y[j] = fma(-ww, wk[j], y[j]);
         }
       }
       if (kb > 0) {
 #pragma unroll
-        for (int i = MM - 1; i >= U; --i) y[i] = y[i - U];
+        for (int j = MR - 1; j >= SH; --j) y[j] = y[j - SH];
 #pragma unroll
-        for (int i = 0; i < U; ++i) y[i] = (lane == kb - U + i) ? 1.0 : 0.0;
+        for (int j = 0; j < SH; ++j) y[j] = (kb - U + LPC * j + h == c) ? 1.0 : 0.0;
       }
     }
-    if (lane < rank) {
+    if (c < rank) {
 #pragma unroll
-      for (int i = 0; i < MM; ++i)
-        if (i < m) Out[lane * ldo + i] = y[i];
+      for (int j = 0; j < MR; ++j) {
+        const int i = LPC * j + h;
+        if (i < m) Out[c * ldo + i] = y[j];
+      }
     }
   }
   return rank;
+}
+
+// Register QR for an m x n tile with m <= MMW and n <= 64: the window is the
+// smallest of 16, 32, 64 rows that holds m, and a column gets 4, 2 or 1 lanes
+// as n allows.
+template <int MMW, bool MODE_Q>
+__device__ __attribute__((always_inline)) int qr_pivoted_reg(const double* M, int ld, int m, int n, int kcap,
+                                                             double rel_tol, double* Wc, double* W, double* Out,
+                                                             int ldo, double* Rglob, int gld, double* rmax) {
+  if constexpr (MMW >= 64) {
+    if (m > 32) {
+      if (n <= 16) return qr_pivoted_lpc<64, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+      if (n <= 32) return qr_pivoted_lpc<64, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+      return qr_pivoted_lpc<64, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+    }
+  }
+  if constexpr (MMW >= 32) {
+    if (m > 16) {
+      if (n <= 16) return qr_pivoted_lpc<32, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+      if (n <= 32) return qr_pivoted_lpc<32, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+      return qr_pivoted_lpc<32, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+    }
+  }
+  if (n <= 16) return qr_pivoted_lpc<16, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+  if (n <= 32) return qr_pivoted_lpc<16, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+  return qr_pivoted_lpc<16, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
 }
 
 // The first r columns of Q from a Householder factorisation done by
@@ -770,15 +839,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           if (tid < 64) {
             double rmax = 0.0;
             double* sWc = smem + Lay::oWcL;
-            int r0;
-            if (m <= 16) {
-              r0 = qr_pivoted_blk<16, false>(sM, LD, m, n, m, RANK_TOL, sWc, nullptr, sR, LD, gR, D, &rmax);
-            } else if (m <= 32 || Lay::MMW == 32) {
-              r0 = qr_pivoted_blk<(Lay::MMW < 32 ? Lay::MMW : 32), false>(sM, LD, m, n, m, RANK_TOL, sWc, nullptr, sR, LD,
-                                                                          gR, D, &rmax);
-            } else {
-              r0 = qr_pivoted_blk<Lay::MMW, false>(sM, LD, m, n, m, RANK_TOL, sWc, nullptr, sR, LD, gR, D, &rmax);
-            }
+            const int r0 = qr_pivoted_reg<Lay::MMW, false>(sM, LD, m, n, m, RANK_TOL, sWc, nullptr, sR, LD, gR, D, &rmax);
             if (tid == 0) {
               sIdx[D] = r0;
               sScal[4] = rmax;
@@ -946,13 +1007,8 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
             int rk;
             double* sWc = smem + Lay::oWcR;
             double* sWq = smem + Lay::oWq;
-            if (nC <= 16) {
-              rk = qr_pivoted_blk<16, true>(sCt, D, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sV, LD, nullptr, 0, nullptr);
-            } else if (nC <= 32 && Lay::MMW >= 32) {
-              rk = qr_pivoted_blk<(Lay::MMW < 32 ? Lay::MMW : 32), true>(sCt, D, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sV,
-                                                                         LD, nullptr, 0, nullptr);
-            } else if (nC <= Lay::MMW && Lay::MMW > 32) {
-              rk = qr_pivoted_blk<Lay::MMW, true>(sCt, D, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sV, LD, nullptr, 0, nullptr);
+            if (nC <= Lay::MMW) {
+              rk = qr_pivoted_reg<Lay::MMW, true>(sCt, D, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sV, LD, nullptr, 0, nullptr);
             } else {
               rk = qr_pivoted_wave(sCt, D, nC, rR, sIdx, RANK_TOL, sTau);
               if (rk > 0 && rk <= chi) form_q_wave(sCt, D, nC, rk, sTau, sV, LD);
