@@ -36,6 +36,26 @@ constexpr int JACOBI_MAX_SWEEPS = 40;
 // directions; its rank is bounded by the left factor's and they are harmless.)
 constexpr double RANK_TOL = 1e-15;
 
+// Quotient w / n for 0 <= w < 2^22 and n >= 1, with inv_n = 1.0f / n:
+// (w + 1/2) / n lies at least 1/(2n) from an integer, and the float product
+// is within w 2^-23 / n of it, so truncation gives the exact quotient.  Saves
+// the integer division sequence in index arithmetic.
+__device__ __forceinline__ int fquot(int w, float inv_n) { return (int)(((float)w + 0.5f) * inv_n); }
+
+// Copies the cl x cr corner of the d site tensors of one environment site
+// (stride CHIM) from global memory to LDS, with threads t0, t0 + nt, ...
+template <int DP, int CHIM>
+__device__ __forceinline__ void stage_site(double* sA, const double* gA, int cl, int cr, int t0, int nt) {
+  const int n2 = cl * cr;
+  const float inv2 = 1.0f / (float)n2, inv1 = 1.0f / (float)cr;
+  for (int i = t0; i < DP * n2; i += nt) {
+    const int u = fquot(i, inv2);
+    const int rem = i - u * n2;
+    const int al = fquot(rem, inv1), be = rem - al * cr;
+    sA[(u * CHIM + al) * CHIM + be] = gA[(size_t)(u * CHIM + al) * CHIM + be];
+  }
+}
+
 // Orders LDS accesses of one wavefront (lanes of a wavefront run in lock step).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -322,13 +342,15 @@ __device__ __forceinline__ double group_sum(double v) {
 // MODE_Q = false: the rank rows of R Pi^T go to Out[i*ldo + j] (and Rglob,
 // stride gld), scaled by 1/max|R|, which is returned in *rmax.
 // MODE_Q = true: reflector k is kept in W[k*MM + h*MR + j] (residue-major,
-// rows of its block's window), tau at W[kcap*MM + k]; the first rank columns
-// of Q are written as rows of Out[c*ldo + i], i < m.  A factorisation that
-// reaches kcap steps returns kcap without forming Q.  Returns the rank.
+// rows of its block's window), tau in Wt[k]; the first rank columns of Q are
+// written as rows of Out[c*ldo + i], i < m.  A factorisation that reaches kcap
+// steps returns kcap without forming Q (so W and Wt need kcap - 1 entries).
+// Returns the rank.
 template <int MM, int LPC, bool MODE_Q>
 __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, int ld, int m, int n, int kcap,
-                                                             double rel_tol, double* Wc, double* W, double* Out,
-                                                             int ldo, double* Rglob, int gld, double* rmax) {
+                                                             double rel_tol, double* Wc, double* W, double* Wt,
+                                                             double* Out, int ldo, double* Rglob, int gld,
+                                                             double* rmax) {
   constexpr int U = 4;
   constexpr int MR = MM / LPC;
   constexpr int SH = U / LPC;
@@ -409,7 +431,7 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
       const double vb = (h == r) ? v0 : ((h > r) ? pv[jb] : 0.0);
       if constexpr (!V_LDS) v[jb] = vb;
       if constexpr (MODE_Q) {
-        if (lane < LPC) {
+        if (lane < LPC && k < kcap - 1) {
           double* wk = W + k * MM + h * MR;
           if constexpr (!V_LDS) {
 #pragma unroll
@@ -420,7 +442,7 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
             wk[jb] = vb;
           }
         }
-        if (lane == 0) W[kcap * MM + k] = tau;
+        if (lane == 0 && k < kcap - 1) Wt[k] = tau;
       }
       if (tau != 0.0) {
         double w4[4] = {0.0, 0.0, 0.0, 0.0};
@@ -492,7 +514,7 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
         if (kk < rank) {
           const int jb = u / LPC;
           const double* wk = W + kk * MM + h * MR;
-          const double tau = W[kcap * MM + kk];
+          const double tau = Wt[kk];
           double w4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int j = jb; j < MR; ++j) w4[j & 3] = fma(wk[j], y[j], w4[j & 3]);
@@ -525,25 +547,26 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
 // as n allows.
 template <int MMW, bool MODE_Q>
 __device__ __attribute__((always_inline)) int qr_pivoted_reg(const double* M, int ld, int m, int n, int kcap,
-                                                             double rel_tol, double* Wc, double* W, double* Out,
-                                                             int ldo, double* Rglob, int gld, double* rmax) {
+                                                             double rel_tol, double* Wc, double* W, double* Wt,
+                                                             double* Out, int ldo, double* Rglob, int gld,
+                                                             double* rmax) {
   if constexpr (MMW >= 64) {
     if (m > 32) {
-      if (n <= 16) return qr_pivoted_lpc<64, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
-      if (n <= 32) return qr_pivoted_lpc<64, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
-      return qr_pivoted_lpc<64, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+      if (n <= 16) return qr_pivoted_lpc<64, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      if (n <= 32) return qr_pivoted_lpc<64, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      return qr_pivoted_lpc<64, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
     }
   }
   if constexpr (MMW >= 32) {
     if (m > 16) {
-      if (n <= 16) return qr_pivoted_lpc<32, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
-      if (n <= 32) return qr_pivoted_lpc<32, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
-      return qr_pivoted_lpc<32, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+      if (n <= 16) return qr_pivoted_lpc<32, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      if (n <= 32) return qr_pivoted_lpc<32, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      return qr_pivoted_lpc<32, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
     }
   }
-  if (n <= 16) return qr_pivoted_lpc<16, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
-  if (n <= 32) return qr_pivoted_lpc<16, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
-  return qr_pivoted_lpc<16, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Out, ldo, Rglob, gld, rmax);
+  if (n <= 16) return qr_pivoted_lpc<16, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+  if (n <= 32) return qr_pivoted_lpc<16, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+  return qr_pivoted_lpc<16, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
 }
 
 // The first r columns of Q from a Householder factorisation done by
@@ -703,11 +726,14 @@ struct Layout {
   static constexpr int oRed = oH + LXMAX * DP * DP;              // 8 reduction slots + 8 scalars
   static constexpr int oNrm = oRed + 16;                         // [D] row norms
   static constexpr int oIdx = oNrm + D;                          // [D] ints stored as doubles
-  // largest register-QR window (rows held per lane)
-  static constexpr int MMW = (D >= 64) ? 64 : ((DP * D > 16) ? 32 : 16);
+  // largest register-QR windows (rows held per lane): the left QR has up to
+  // DP * D rows, the LQ of C^T at most D
+  static constexpr int MMW = (D >= 32) ? 64 : ((DP * D > 16) ? 32 : 16);
+  static constexpr int MMQ = (D >= 64) ? 64 : ((D >= 32) ? 32 : 16);
   static constexpr int WC = 64 * (MMW + 2);                      // register-QR column exchange
-  // LQ reflectors: at most chi + 1 steps (rank > chi means truncation) + tau
-  static constexpr int WQ = ((CHIM + 1) * MMW + (CHIM + 1) + 1) & ~1;
+  static constexpr int WCQ = 64 * (MMQ + 2);
+  // LQ reflectors: at most chi of them are kept (step chi + 1 only detects truncation)
+  static constexpr int WQ = CHIM * MMQ;
   static constexpr int oWork = oIdx + D;
   // left sweep (the column exchange follows M)
   static constexpr int oA1 = oWork;                              // [DP][CHIM][CHIM]
@@ -724,11 +750,14 @@ struct Layout {
   static constexpr int oZ = oR2 + D * LD;                        // [D][DP][CHIM] (later V~)
   static constexpr int oC = oZ + D * DP * CHIM;                  // [D][LD]
   static constexpr int endC = oC + D * LD;
-  // A and T_{x+1} (contiguous) are consumed before the LQ, C after its transpose
-  static constexpr bool WQ_IN_AT = DP * CHIM * CHIM + D * CHIM >= WQ;
-  static constexpr int oWq = WQ_IN_AT ? oA2 : endC;
-  static constexpr int oWcR = WQ_IN_AT ? oC : endC + WQ;         // C's tile and what follows it
-  static constexpr int end2 = oWcR + ((WC > D * LD) ? WC : D * LD);
+  // during the LQ: T_{x+1} is consumed (its tile holds the reflectors), C is
+  // not needed (its tile and what follows hold the column exchange) and A_{x-1}
+  // is staged into A's tile
+  static constexpr int oWcR = oC;
+  static constexpr int endWc = oC + ((WCQ > D * LD) ? WCQ : D * LD);
+  static constexpr bool WQ_IN_T = WQ <= D * CHIM;                // small tiles: after the exchange
+  static constexpr int oWq = WQ_IN_T ? oT2 : endWc;
+  static constexpr int end2 = WQ_IN_T ? endWc : endWc + WQ;
   static constexpr int total = (end1 > end2) ? end1 : end2;
   static_assert(oWcL % 2 == 0 && oWcR % 2 == 0 && oWq % 2 == 0, "16-byte aligned register-QR buffers");
 };
@@ -791,42 +820,37 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
       double* sM = smem + Lay::oM1;
       int rR = 1;
       if (tid == 0) sR[0] = 1.0;
+      // the site tensor of x is staged in sA before step x: A_0 here, the
+      // next one by the idle wavefronts while wavefront 0 factorises
+      stage_site<DP, CHIM>(sA, envY, 1, bondY[0], tid, NT);
+      __syncthreads();
       for (int x = 0; x < Lx - 1; ++x) {
         const int cl = (x > 0) ? bondY[x - 1] : 1;
         const int cr = bondY[x];
         const int na = (x > 0) ? DP : 1;
-        const double* gA = envY + (size_t)x * SITE;
-        for (int i = tid; i < DP * cl * cr; i += NT) {
-          const int u = i / (cl * cr), al = (i / cr) % cl, be = i % cr;
-          sA[(u * CHIM + al) * CHIM + be] = gA[(size_t)(u * CHIM + al) * CHIM + be];
-        }
-        __syncthreads();
-        // R~[i][al*d + b] = sum_a R[i][al*na + a] H[a][b]  (in place, one (i, al) per thread)
+        // M[(i,r)][(be,b)] = G[r][b] sum_al R~[i][al*d+b] A[b][al][be],
+        // R~[i][al*d+b] = sum_a R[i][al*na+a] H[a][b]  (H folded in)
         const double* Hx = sH + x * DP * DP;
-        for (int w = tid; w < rR * cl; w += NT) {
-          const int i = w / cl, al = w % cl;
-          double v[DP];
-#pragma unroll
-          for (int a = 0; a < DP; ++a) v[a] = (a < na) ? sR[i * LD + al * na + a] : 0.0;
-          double o[DP];
-#pragma unroll
-          for (int b = 0; b < DP; ++b) {
-            double s = 0.0;
-            for (int a = 0; a < na; ++a) s += v[a] * Hx[a * DP + b];
-            o[b] = s;
-          }
-#pragma unroll
-          for (int b = 0; b < DP; ++b) sR[i * LD + al * DP + b] = o[b];
-        }
-        __syncthreads();
-        // M[(i,r)][(be,b)] = G[r][b] sum_al R~[i][al*d+b] A[b][al][be]
         const double* Gx = sG + x * DP * DP;
-        for (int w = tid; w < rR * DP * cr; w += NT) {
-          const int i = w / (DP * cr), b = (w / cr) % DP, be = w % cr;
-          double s = 0.0;
-          for (int al = 0; al < cl; ++al) s += sR[i * LD + al * DP + b] * sA[(b * CHIM + al) * CHIM + be];
+        {
+          const int nb = DP * cr;
+          const float inv_nb = 1.0f / (float)nb, inv_cr = 1.0f / (float)cr;
+          for (int w = tid; w < rR * nb; w += NT) {
+            const int i = fquot(w, inv_nb);
+            const int rem = w - i * nb;
+            const int b = fquot(rem, inv_cr), be = rem - b * cr;
+            double hb[DP];
 #pragma unroll
-          for (int r = 0; r < DP; ++r) sM[(i * DP + r) * LD + be * DP + b] = Gx[r * DP + b] * s;
+            for (int a = 0; a < DP; ++a) hb[a] = Hx[a * DP + b];
+            double s = 0.0;
+            for (int al = 0; al < cl; ++al) {
+              double rt = 0.0;
+              for (int a = 0; a < na; ++a) rt = fma(sR[i * LD + al * na + a], hb[a], rt);
+              s = fma(rt, sA[(b * CHIM + al) * CHIM + be], s);
+            }
+#pragma unroll
+            for (int r = 0; r < DP; ++r) sM[(i * DP + r) * LD + be * DP + b] = Gx[r * DP + b] * s;
+          }
         }
         __syncthreads();
         const int m = rR * DP, n = cr * DP;
@@ -834,31 +858,39 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         int rx;
         double* gR = rscr + (size_t)x * D * D;
         const bool in_regs = (m <= Lay::MMW && n <= 64);
+        // site tensor of x + 1 (for the right sweep's first step when x + 1 = Lx - 1)
+        const int ncl = cr, ncr = bondY[x + 1];
+        const double* gAn = envY + (size_t)(x + 1) * SITE;
         if (in_regs) {
           // R Pi^T straight from registers to sR and gR, already scaled
           if (tid < 64) {
             double rmax = 0.0;
             double* sWc = smem + Lay::oWcL;
-            const int r0 = qr_pivoted_reg<Lay::MMW, false>(sM, LD, m, n, m, RANK_TOL, sWc, nullptr, sR, LD, gR, D, &rmax);
+            const int r0 = qr_pivoted_reg<Lay::MMW, false>(sM, LD, m, n, m, RANK_TOL, sWc, nullptr, nullptr, sR, LD, gR, D,
+                                                          &rmax);
             if (tid == 0) {
               sIdx[D] = r0;
               sScal[4] = rmax;
             }
+          } else {
+            stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid - 64, NT - 64);
           }
           __syncthreads();
-          rx = sIdx[D];
+          rx = sIdx[D];   // rewritten only after the next step's first barrier
           if (!(sScal[4] > 0.0 && isfinite(sScal[4]))) fault |= 1;
-          __syncthreads();
         } else if (n <= 64 && m <= 64) {
           if (tid < 64) {
             const int r0 = qr_pivoted_wave(sM, LD, m, n, sPerm, RANK_TOL);
             if (tid == 0) sIdx[D] = r0;   // pass the rank to the other waves
+          } else {
+            stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid - 64, NT - 64);
           }
           __syncthreads();
           rx = sIdx[D];
           __syncthreads();
         } else {
           rx = qr_pivoted(sM, LD, m, n, sPerm, sNrm, sScal, RANK_TOL);
+          stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid, NT);
         }
         if (rx == 0) fault |= 1;
         if (tid == 0) flops += 2.0 * rR * DP * cr * cl + qr_count(m, n, rx);
@@ -882,7 +914,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         }
         if (tid == 0) rrows[x] = rx;
         rR = rx;
-        __syncthreads();
+        if (!in_regs) __syncthreads();   // the register path's barrier above already orders sR and sA
       }
     }
 
@@ -901,31 +933,59 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
       double logacc = 0.0;
       int k = 1;           // columns of T_{x+1}
       if (tid == 0) bondN[Lx - 1] = 1;
+      // registers per thread for the R_{x-1} loads
+      constexpr int PR = (D * CHIM + NT - 1) / NT;
       for (int x = Lx - 1; x >= 0; --x) {
+        // sA holds A_x: staged during the left sweep for x = Lx - 1, else
+        // prefetched while the previous step factorised
         const int cl = (x > 0) ? bondY[x - 1] : 1;
         const int cr = bondY[x];
         const bool last = (x == Lx - 1);
-        const double* gA = envY + (size_t)x * SITE;
-        for (int i = tid; i < DP * cl * cr; i += NT) {
-          const int u = i / (cl * cr), al = (i / cr) % cl, be = i % cr;
-          sA[(u * CHIM + al) * CHIM + be] = gA[(size_t)(u * CHIM + al) * CHIM + be];
-        }
-        __syncthreads();
-        // AT[al][b][k'] = sum_be A[b][al][be] T[be*d + b][k']  (b summed later at the edge)
-        for (int w = tid; w < cl * DP * k; w += NT) {
-          const int al = w / (DP * k), b = (w / k) % DP, kk = w % k;
-          double s;
-          if (last) {
-            s = sA[(b * CHIM + al) * CHIM + 0];
-          } else {
-            s = 0.0;
-            for (int be = 0; be < cr; ++be) s += sA[(b * CHIM + al) * CHIM + be] * sT[(be * DP + b) * CHIM + kk];
-          }
-          sAT[(al * DP + b) * CHIM + kk] = s;
-        }
-        __syncthreads();
         const double* Gx = sG + x * DP * DP;
         const double* Hx = sH + x * DP * DP;
+        // R_{x-1} is read from global memory while AT is formed
+        const int rR = (x > 0) ? rrows[x - 1] : 0;
+        const int nri = rR * cl;
+        const float inv_cl = 1.0f / (float)cl;
+        const double* gR = rscr + (size_t)((x > 0) ? x - 1 : 0) * D * D;
+        double pr[PR][DP];
+#pragma unroll
+        for (int q = 0; q < PR; ++q) {
+          const int w = tid + q * NT;
+          if (w < nri) {
+            const int i = fquot(w, inv_cl), al = w - i * cl;
+#pragma unroll
+            for (int a = 0; a < DP; ++a) pr[q][a] = gR[(size_t)i * D + al * DP + a];
+          }
+        }
+        // AT[al][b][k'] = sum_be A[b][al][be] T[be*d + b][k']  (b summed later at the edge)
+        {
+          const int nb = DP * k;
+          const float inv_nb = 1.0f / (float)nb, inv_k = 1.0f / (float)k;
+          for (int w = tid; w < cl * nb; w += NT) {
+            const int al = fquot(w, inv_nb);
+            const int rem = w - al * nb;
+            const int b = fquot(rem, inv_k), kk = rem - b * k;
+            double s;
+            if (last) {
+              s = sA[(b * CHIM + al) * CHIM + 0];
+            } else {
+              s = 0.0;
+              for (int be = 0; be < cr; ++be) s = fma(sA[(b * CHIM + al) * CHIM + be], sT[(be * DP + b) * CHIM + kk], s);
+            }
+            sAT[(al * DP + b) * CHIM + kk] = s;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < PR; ++q) {
+          const int w = tid + q * NT;
+          if (w < nri) {
+            const int i = fquot(w, inv_cl), al = w - i * cl;
+#pragma unroll
+            for (int a = 0; a < DP; ++a) sR[i * LD + al * DP + a] = pr[q][a];
+          }
+        }
+        __syncthreads();
         if (x == 0) {
           // first tensor of E_{y-1}: P[r][k'] = sum_b G[r][b] AT[0][b][k'], normalised
           double nn = 0.0;
@@ -950,70 +1010,72 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           __syncthreads();
           break;
         }
-        // R~ of R_{x-1} with the horizontal bond of site x
-        const int rR = rrows[x - 1];
         const int Dl = cl * DP;
-        const double* gR = rscr + (size_t)(x - 1) * D * D;
-        for (int w = tid; w < rR * cl; w += NT) {
-          const int i = w / cl, al = w % cl;
-          double v[DP];
-#pragma unroll
-          for (int a = 0; a < DP; ++a) v[a] = gR[(size_t)i * D + al * DP + a];
-#pragma unroll
-          for (int b = 0; b < DP; ++b) {
-            double s = 0.0;
-#pragma unroll
-            for (int a = 0; a < DP; ++a) s += v[a] * Hx[a * DP + b];
-            sR[i * LD + al * DP + b] = s;
-          }
-        }
-        __syncthreads();
-        // Z[i][b][k'] = sum_al R~[i][al*d+b] AT[al][b][k']
-        for (int w = tid; w < rR * DP * k; w += NT) {
-          const int i = w / (DP * k), b = (w / k) % DP, kk = w % k;
-          double s = 0.0;
-          for (int al = 0; al < cl; ++al) s += sR[i * LD + al * DP + b] * sAT[(al * DP + b) * CHIM + kk];
-          sZ[(i * DP + b) * CHIM + kk] = s;
-        }
-        __syncthreads();
-        // C[i][r*k + k'] = sum_b G[r][b] Z[i][b][k']
         const int nC = DP * k;
-        for (int w = tid; w < rR * nC; w += NT) {
-          const int i = w / nC, r = (w / k) % DP, kk = w % k;
-          double s = 0.0;
+        const bool lq_try = (rR <= 64 && nC <= 64);
+        const bool lq_reg = lq_try && nC <= Lay::MMQ;
+        double* sCt = sZ;    // C^T [nC][rR], leading dim D
+        // C[i][r*k + k'] = sum_b G[r][b] sum_al R~[i][al*d+b] AT[al][b][k'],
+        // R~[i][al*d+b] = sum_a R[i][al*d+a] H[a][b]; stored transposed for
+        // the LQ, and as C too when the LQ may not take the register path
+        {
+          const float inv_k = 1.0f / (float)k;
+          for (int w = tid; w < rR * k; w += NT) {
+            const int i = fquot(w, inv_k), kk = w - i * k;
+            double z[DP];
 #pragma unroll
-          for (int b = 0; b < DP; ++b) s += Gx[r * DP + b] * sZ[(i * DP + b) * CHIM + kk];
-          sC[i * LD + r * k + kk] = s;
+            for (int b = 0; b < DP; ++b) z[b] = 0.0;
+            for (int al = 0; al < cl; ++al) {
+              double rv[DP];
+#pragma unroll
+              for (int a = 0; a < DP; ++a) rv[a] = sR[i * LD + al * DP + a];
+#pragma unroll
+              for (int b = 0; b < DP; ++b) {
+                double rt = 0.0;
+#pragma unroll
+                for (int a = 0; a < DP; ++a) rt = fma(rv[a], Hx[a * DP + b], rt);
+                z[b] = fma(rt, sAT[(al * DP + b) * CHIM + kk], z[b]);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < DP; ++r) {
+              double c = 0.0;
+#pragma unroll
+              for (int b = 0; b < DP; ++b) c = fma(Gx[r * DP + b], z[b], c);
+              sCt[(r * k + kk) * D + i] = c;
+              if (!lq_reg) sC[i * LD + r * k + kk] = c;
+            }
+          }
         }
         __syncthreads();
         // right singular vectors of C.  When the rank of C does not exceed chi
         // nothing is truncated and any orthonormal basis of its row space is
         // exact: a rank-revealing Householder LQ of C (pivoted QR of C^T) on
         // one wavefront.  Otherwise the truncating SVD (one-sided Jacobi)
-        // picks the chi largest directions.
+        // picks the chi largest directions.  Meanwhile the other wavefronts
+        // fetch A_{x-1} into registers.
         const double* vsrc = sC;
         int kx = 0;
         bool need_svd = true;
-        if (rR <= 64 && nC <= 64) {
-          double* sCt = sZ;    // C^T [nC][rR], leading dim D (Z is consumed)
-          double* sV = sR;     // V [rank][nC], leading dim LD (R~ is consumed)
+        const int pcl = (x > 1) ? bondY[x - 2] : 1, pcr = bondY[x - 1];
+        const double* gAp = envY + (size_t)(x - 1) * SITE;
+        if (lq_try) {
+          double* sV = sR;     // V [rank][nC], leading dim LD (R is consumed)
           double* sTau = sT;   // reflector scalars (T_{x+1} is consumed)
-          for (int w = tid; w < nC * rR; w += NT) {
-            const int c = w / rR, i = w % rR;
-            sCt[c * D + i] = sC[i * LD + c];
-          }
-          __syncthreads();
           if (tid < 64) {
             int rk;
             double* sWc = smem + Lay::oWcR;
             double* sWq = smem + Lay::oWq;
-            if (nC <= Lay::MMW) {
-              rk = qr_pivoted_reg<Lay::MMW, true>(sCt, D, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sV, LD, nullptr, 0, nullptr);
+            if (lq_reg) {
+              rk = qr_pivoted_reg<Lay::MMQ, true>(sCt, D, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sNrm, sV, LD, nullptr, 0,
+                                                  nullptr);
             } else {
               rk = qr_pivoted_wave(sCt, D, nC, rR, sIdx, RANK_TOL, sTau);
               if (rk > 0 && rk <= chi) form_q_wave(sCt, D, nC, rk, sTau, sV, LD);
             }
             if (tid == 0) sIdx[D] = rk;
+          } else {
+            stage_site<DP, CHIM>(sA, gAp, pcl, pcr, tid - 64, NT - 64);
           }
           __syncthreads();
           const int rk = sIdx[D];
@@ -1026,14 +1088,16 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
               sNrm[i] = 1.0;
             }
             if (tid == 0) flops += qr_count(nC, rR, rk) + 4.0 * nC * rk * rk;
-          } else if (Lay::WQ_IN_AT && nC <= Lay::MMW) {
-            // the register QR exchanged columns through C's tile: restore C from C^T
+          } else if (lq_reg) {
+            // truncation: the SVD needs C itself
             for (int w = tid; w < nC * rR; w += NT) {
               const int c = w / rR, i = w % rR;
               sC[i * LD + c] = sCt[c * D + i];
             }
           }
           __syncthreads();
+        } else {
+          stage_site<DP, CHIM>(sA, gAp, pcl, pcr, tid, NT);
         }
         if (need_svd) {
           int mrows = rR;
@@ -1090,8 +1154,9 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           flops += 2.0 * DP * cl * cr * k + 2.0 * rR * DP * cl * k + 2.0 * rR * DP * DP * k + 2.0 * kx * DP * DP * k +
                    2.0 * cl * DP * kx * k + 2.0 * cl * DP * DP * kx;
         // V rows (normalised) -> new environment site x, and V~[rho][b][k'] = sum_r G[r][b] V[rho][r*k+k']
+        const float inv_k = 1.0f / (float)k, inv_kx = 1.0f / (float)kx, inv_dkx = 1.0f / (float)(DP * kx);
         for (int w = tid; w < kx * k; w += NT) {
-          const int rho = w / k, kk = w % k;
+          const int rho = fquot(w, inv_k), kk = w - rho * k;
           const int i = sIdx[rho];
           const double nr = sqrt(sNrm[i]);
           const double inv = (nr > 0.0) ? 1.0 / nr : 0.0;
@@ -1112,16 +1177,18 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         __syncthreads();
         // Y[al][b][rho] = sum_k' AT[al][b][k'] V~[rho][b][k']
         for (int w = tid; w < cl * DP * kx; w += NT) {
-          const int al = w / (DP * kx), b = (w / kx) % DP, rho = w % kx;
+          const int al = fquot(w, inv_dkx);
+          const int rem = w - al * DP * kx;
+          const int b = fquot(rem, inv_kx), rho = rem - b * kx;
           double s = 0.0;
-          for (int kk = 0; kk < k; ++kk) s += sAT[(al * DP + b) * CHIM + kk] * sVt[(rho * DP + b) * CHIM + kk];
+          for (int kk = 0; kk < k; ++kk) s = fma(sAT[(al * DP + b) * CHIM + kk], sVt[(rho * DP + b) * CHIM + kk], s);
           sY[(al * DP + b) * CHIM + rho] = s;
         }
         __syncthreads();
         // T_x[al*d + a][rho] = sum_b H[a][b] Y[al][b][rho], then normalise
         double nn = 0.0;
         for (int w = tid; w < Dl * kx; w += NT) {
-          const int row = w / kx, rho = w % kx;
+          const int row = fquot(w, inv_kx), rho = w - row * kx;
           const int al = row / DP, a = row % DP;
           double s = 0.0;
 #pragma unroll
@@ -1134,7 +1201,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         if (nrm > 0.0 && isfinite(nrm)) {
           const double inv = 1.0 / nrm;
           for (int w = tid; w < Dl * kx; w += NT) {
-            const int row = w / kx, rho = w % kx;
+            const int row = fquot(w, inv_kx), rho = w - row * kx;
             sT[row * CHIM + rho] *= inv;
           }
           logacc += log(nrm);
