@@ -36,12 +36,6 @@ constexpr int JACOBI_MAX_SWEEPS = 40;
 // directions; its rank is bounded by the left factor's and they are harmless.)
 constexpr double RANK_TOL = 1e-15;
 
-// Quotient w / n for 0 <= w < 2^22 and n >= 1, with inv_n = 1.0f / n:
-// (w + 1/2) / n lies at least 1/(2n) from an integer, and the float product
-// is within w 2^-23 / n of it, so truncation gives the exact quotient.  Saves
-// the integer division sequence in index arithmetic.
-__device__ __forceinline__ int fquot(int w, float inv_n) { return (int)(((float)w + 0.5f) * inv_n); }
-
 // Copies the cl x cr corner of the d site tensors of one environment site
 // (stride CHIM) from global memory to LDS, with threads t0, t0 + nt, ...
 template <int DP, int CHIM>
@@ -843,10 +837,27 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
 #pragma unroll
             for (int a = 0; a < DP; ++a) hb[a] = Hx[a * DP + b];
             double s = 0.0;
-            for (int al = 0; al < cl; ++al) {
-              double rt = 0.0;
-              for (int a = 0; a < na; ++a) rt = fma(sR[i * LD + al * na + a], hb[a], rt);
-              s = fma(rt, sA[(b * CHIM + al) * CHIM + be], s);
+            const double* Ri = sR + i * LD;
+            const double* Ab = sA + b * CHIM * CHIM + be;
+            for (int al0 = 0; al0 < cl; al0 += 4) {
+              // four values of al per group, loads first (indices clamped into the tiles)
+              double rv[4][DP], av[4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int al = (al0 + q < CHIM) ? al0 + q : CHIM - 1;
+#pragma unroll
+                for (int a = 0; a < DP; ++a) rv[q][a] = (a < na) ? Ri[al * na + a] : 0.0;
+                av[q] = Ab[al * CHIM];
+              }
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                if (al0 + q < cl) {
+                  double rt = 0.0;
+#pragma unroll
+                  for (int a = 0; a < DP; ++a) rt = fma(rv[q][a], hb[a], rt);
+                  s = fma(rt, av[q], s);
+                }
+              }
             }
 #pragma unroll
             for (int r = 0; r < DP; ++r) sM[(i * DP + r) * LD + be * DP + b] = Gx[r * DP + b] * s;
@@ -970,8 +981,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
             if (last) {
               s = sA[(b * CHIM + al) * CHIM + 0];
             } else {
-              s = 0.0;
-              for (int be = 0; be < cr; ++be) s = fma(sA[(b * CHIM + al) * CHIM + be], sT[(be * DP + b) * CHIM + kk], s);
+              s = lds_dot<CHIM>(sA + (b * CHIM + al) * CHIM, 1, sT + b * CHIM + kk, DP * CHIM, cr);
             }
             sAT[(al * DP + b) * CHIM + kk] = s;
           }
@@ -1025,16 +1035,34 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
             double z[DP];
 #pragma unroll
             for (int b = 0; b < DP; ++b) z[b] = 0.0;
-            for (int al = 0; al < cl; ++al) {
-              double rv[DP];
+            double hm[DP][DP];
 #pragma unroll
-              for (int a = 0; a < DP; ++a) rv[a] = sR[i * LD + al * DP + a];
+            for (int a = 0; a < DP; ++a)
 #pragma unroll
-              for (int b = 0; b < DP; ++b) {
-                double rt = 0.0;
+              for (int b = 0; b < DP; ++b) hm[a][b] = Hx[a * DP + b];
+            const double* Ri = sR + i * LD;
+            for (int al0 = 0; al0 < cl; al0 += 4) {
+              // four values of al per group, loads first (indices clamped into the tiles)
+              double rv[4][DP], atv[4][DP];
 #pragma unroll
-                for (int a = 0; a < DP; ++a) rt = fma(rv[a], Hx[a * DP + b], rt);
-                z[b] = fma(rt, sAT[(al * DP + b) * CHIM + kk], z[b]);
+              for (int q = 0; q < 4; ++q) {
+                const int al = (al0 + q < CHIM) ? al0 + q : CHIM - 1;
+#pragma unroll
+                for (int a = 0; a < DP; ++a) rv[q][a] = Ri[al * DP + a];
+#pragma unroll
+                for (int b = 0; b < DP; ++b) atv[q][b] = sAT[(al * DP + b) * CHIM + kk];
+              }
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                if (al0 + q < cl) {
+#pragma unroll
+                  for (int b = 0; b < DP; ++b) {
+                    double rt = 0.0;
+#pragma unroll
+                    for (int a = 0; a < DP; ++a) rt = fma(rv[q][a], hm[a][b], rt);
+                    z[b] = fma(rt, atv[q][b], z[b]);
+                  }
+                }
               }
             }
 #pragma unroll
@@ -1180,8 +1208,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           const int al = fquot(w, inv_dkx);
           const int rem = w - al * DP * kx;
           const int b = fquot(rem, inv_kx), rho = rem - b * kx;
-          double s = 0.0;
-          for (int kk = 0; kk < k; ++kk) s = fma(sAT[(al * DP + b) * CHIM + kk], sVt[(rho * DP + b) * CHIM + kk], s);
+          const double s = lds_dot<CHIM>(sAT + (al * DP + b) * CHIM, 1, sVt + (rho * DP + b) * CHIM, 1, k);
           sY[(al * DP + b) * CHIM + rho] = s;
         }
         __syncthreads();

@@ -28,6 +28,36 @@ __device__ inline double philox_uniform(uint64_t c0, uint64_t c1, uint64_t c2, u
   return ((double)(c0 >> 11) + 0.5) * 0x1p-53;
 }
 
+// Quotient w / n for 0 <= w < 2^22 and n >= 1, with inv_n = 1.0f / n:
+// (w + 1/2) / n lies at least 1/(2n) from an integer, and the float product
+// is within w 2^-23 / n of it, so truncation gives the exact quotient.  Saves
+// the integer division sequence in index arithmetic.
+__device__ __forceinline__ int fquot(int w, float inv_n) { return (int)(((float)w + 0.5f) * inv_n); }
+
+// sum_{j < n} a[j*sa] b[j*sb] over LDS operands, n <= NMAX: the loads are
+// issued eight at a time (indices up to the next multiple of 8 below NMAX must
+// be addressable; their values are discarded) so that one wait covers each
+// group, with two accumulation chains.
+template <int NMAX>
+__device__ __forceinline__ double lds_dot(const double* a, int sa, const double* b, int sb, int n) {
+  double s0 = 0.0, s1 = 0.0;
+  for (int j0 = 0; j0 < n; j0 += 8) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = (j0 + q < NMAX) ? j0 + q : NMAX - 1;
+      av[q] = a[j * sa];
+      bv[q] = b[j * sb];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) {
+      if (j0 + q < n) s0 = fma(av[q], bv[q], s0);
+      if (j0 + q + 1 < n) s1 = fma(av[q + 1], bv[q + 1], s1);
+    }
+  }
+  return s0 + s1;
+}
+
 // sig(u, v): s_u s_v for Ising (u=0 is s=+1), delta(u, v) for Potts.
 template <int DP>
 __device__ __forceinline__ double sigma(int u, int v) {
@@ -80,6 +110,21 @@ __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_mov<0x141>(v);
   v += dpp_mov<0x140>(v);   // row_mirror: lane i <-> 15 - i within 16 lanes
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+// N independent wavefront sums, their DPP steps interleaved; every lane gets
+// the same bits, equal to wave_sum of each value.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0xB1>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0x4E>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0x141>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0x140>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = (readlane_d(v[i], 0) + readlane_d(v[i], 16)) + (readlane_d(v[i], 32) + readlane_d(v[i], 48));
 }
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_mov<0xB1>(v));

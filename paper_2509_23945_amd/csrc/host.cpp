@@ -110,7 +110,7 @@ struct Plan {
   std::vector<TaskDesc> desc;
   std::vector<int> order;   // desc[k] runs tasks[order[k]]
   struct Group {
-    int d, chi_max, first, count, lx_max;
+    int d, chi_max, first, count, lx_max, ly_max;
   };
   std::vector<Group> groups;
 };
@@ -186,10 +186,11 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     io += (size_t)L->Ly * L->Lx + L->Lx + 1;
     dof += (size_t)L->Ly;
     if (plan.groups.empty() || plan.groups.back().d != L->d || plan.groups.back().chi_max != L->chi_max) {
-      plan.groups.push_back({L->d, L->chi_max, (int)k, 0, 0});
+      plan.groups.push_back({L->d, L->chi_max, (int)k, 0, 0, 0});
     }
     plan.groups.back().count += 1;
     plan.groups.back().lx_max = std::max(plan.groups.back().lx_max, L->Lx);
+    plan.groups.back().ly_max = std::max(plan.groups.back().ly_max, L->Ly);
     plan.desc.push_back(t);
   }
   return TNMC_OK;
@@ -222,7 +223,7 @@ tnmc_status launch_plan(const Plan& plan, const TaskDesc* dtasks, uint64_t sweep
   }
   for (const auto& g : plan.groups) {
     if (tm && tm->on && tm->mark(tm->s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
-    HIP_TRY(tnmc::launch_sample(dtasks + g.first, g.count, g.d, g.chi_max, g.lx_max, sweep, s));
+    HIP_TRY(tnmc::launch_sample(dtasks + g.first, g.count, g.d, g.chi_max, g.lx_max, g.ly_max, sweep, s));
     if (tm && tm->on && tm->mark(tm->s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
     if (st) st->sample_launches += 1;
   }

@@ -24,26 +24,87 @@ namespace {
 
 constexpr int LXMAX = 64;
 constexpr int LYMAX = 64;
+constexpr int NTS = 128;              // one wavefront per path
 constexpr double P_FLOOR = 1e-12;
 
 template <int DP, int CHIM>
 struct SampleShared {
-  double l[2][CHIM];                  // left vector per path
-  double ft[2][LXMAX][DP];            // beta * (field + vertical bond to the row above)
-  double jx[LXMAX];                   // beta * Jx(x-1, y)
+  double l[2][2][CHIM];               // left vector per path, two buffers alternating by site
+  double et[2][LXMAX][DP][DP];        // exp(beta (F(x,u) + Jy sig(u, above)) + beta Jx(x-1) sig(t,u)) [path][x][t][u]
+  double uni[LXMAX];                  // the row's uniforms (drawn path)
+  double pch[2][LXMAX];               // probability of the state taken at each site of the row
   double lq[2];
   int fault[2];
-  int8_t cfg[2][LYMAX][LXMAX];        // state indices of both paths
 };
 
+// Site tensor x of an environment row (the cl x cr corner of each of its d
+// matrices, row stride CHIM) into registers, then into an LDS tile with the
+// same layout.  Each of the d*cl rows is covered by TPR threads, TPR
+// consecutive columns at a time; one quotient per row and pass.
 template <int DP, int CHIM>
-__global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict__ tasks, uint64_t sweep) {
+struct SiteCopy {
+  static constexpr int TPR = CHIM < 8 ? CHIM : 8;           // threads per row
+  static constexpr int CPT = CHIM / TPR;                     // columns per thread
+  static constexpr int RPP = NTS / TPR;                      // rows per pass
+  static constexpr int PASSES = (DP * CHIM + RPP - 1) / RPP;
+  static constexpr int PF = PASSES * CPT;
+};
+template <int DP, int CHIM, int PF>
+__device__ __forceinline__ void site_fetch(double (&pf)[PF], const double* __restrict__ g, int cl, int cr, int tid) {
+  using SC = SiteCopy<DP, CHIM>;
+  static_assert(PF == SC::PF, "register buffer matches the copy geometry");
+  const float inv_cl = 1.0f / (float)cl;
+  const int c0 = tid % SC::TPR, r0 = tid / SC::TPR;
+#pragma unroll
+  for (int p = 0; p < SC::PASSES; ++p) {
+    const int row = r0 + p * SC::RPP;
+    if (row < DP * cl) {
+      const int u = fquot(row, inv_cl), al = row - u * cl;
+      const double* src = g + (size_t)(u * CHIM + al) * CHIM;
+#pragma unroll
+      for (int j = 0; j < SC::CPT; ++j) {
+        const int c = c0 + j * SC::TPR;
+        if (c < cr) pf[p * SC::CPT + j] = src[c];
+      }
+    }
+  }
+}
+template <int DP, int CHIM, int PF>
+__device__ __forceinline__ void site_commit(double* sA, const double (&pf)[PF], int cl, int cr, int tid) {
+  using SC = SiteCopy<DP, CHIM>;
+  static_assert(PF == SC::PF, "register buffer matches the copy geometry");
+  const float inv_cl = 1.0f / (float)cl;
+  const int c0 = tid % SC::TPR, r0 = tid / SC::TPR;
+#pragma unroll
+  for (int p = 0; p < SC::PASSES; ++p) {
+    const int row = r0 + p * SC::RPP;
+    if (row < DP * cl) {
+      const int u = fquot(row, inv_cl), al = row - u * cl;
+      double* dst = sA + (u * CHIM + al) * CHIM;
+#pragma unroll
+      for (int j = 0; j < SC::CPT; ++j) {
+        const int c = c0 + j * SC::TPR;
+        if (c < cr) dst[c] = pf[p * SC::CPT + j];
+      }
+    }
+  }
+}
+
+// Dynamic LDS: right environments [2][lx_max+1][CHIM][DP], site tensors
+// [2][DP*CHIM*CHIM] (the one in use and the next one), states [2][ly_max][lx_max].
+// The next site tensor is read from global memory into registers while the
+// current one is used, so each step waits on LDS only.
+template <int DP, int CHIM>
+__global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict__ tasks, uint64_t sweep, int lx_max,
+                                                     int ly_max) {
   __shared__ SampleShared<DP, CHIM> sh;
-  extern __shared__ double sR[];        // right environments [2][Lx+1][CHIM][DP]
+  extern __shared__ __align__(16) double dyn[];
   constexpr int SITE = DP * CHIM * CHIM;
+  constexpr int PF = SiteCopy<DP, CHIM>::PF;
   const TaskDesc& t = tasks[blockIdx.x];
-  const int path = threadIdx.x >> 6;     // 0: new layer (drawn), 1: current layer (forced)
-  const int lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int path = tid >> 6;             // 0: new layer (drawn), 1: current layer (forced)
+  const int lane = tid & 63;
   const int Lx = t.Lx, Ly = t.Ly, Lz = t.Lz, z = t.z;
   const double beta = t.beta;
   const float* __restrict__ J = t.J;
@@ -52,24 +113,41 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
   const int8_t* forced = (path == 1) ? spins + (size_t)z * plane : t.force_new;
   const int contract_status = *t.status;
   const bool contract_fault = contract_status != 0;
-  double* Rp = sR + (size_t)path * (Lx + 1) * CHIM * DP;
+  double* Rp = dyn + (size_t)path * (lx_max + 1) * CHIM * DP;
+  double* sAb = dyn + (size_t)2 * (lx_max + 1) * CHIM * DP;
+  int8_t* cfg = reinterpret_cast<int8_t*>(sAb + 2 * SITE);
 #define RENV(x, al, u) Rp[((size_t)(x) * CHIM + (al)) * DP + (u)]
+#define CFG(p, y, x) cfg[((size_t)(p) * ly_max + (y)) * lx_max + (x)]
 
+  double pf[PF];
+  int buf = 0;
+  {
+    const int cl = (Lx > 1) ? t.bond[Lx - 2] : 1, cr = t.bond[Lx - 1];
+    site_fetch<DP, CHIM, PF>(pf, t.env + (size_t)(Lx - 1) * SITE, cl, cr, tid);
+    site_commit<DP, CHIM, PF>(sAb, pf, cl, cr, tid);
+  }
   double logq = 0.0;
   int fault = 0;
   for (int y = 0; y < Ly; ++y) {
     const double* envY = t.env + (size_t)y * Lx * SITE;
     const int* bondY = t.bond + y * Lx;
+    // the row's local weights and (drawn path) uniforms, one site per lane
     for (int x = lane; x < Lx; x += 64) {
       const double jy = (y > 0) ? (double)J[plane * Lz + (size_t)z * plane + (size_t)(y - 1) * Lx + x] : 0.0;
-      const int above = (y > 0) ? sh.cfg[path][y - 1][x] : 0;
+      const int above = (y > 0) ? CFG(path, y - 1, x) : 0;
+      double ftv[DP];
 #pragma unroll
       for (int u = 0; u < DP; ++u) {
         double f = held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, u);
         if (y > 0) f += jy * sigma<DP>(u, above);
-        sh.ft[path][x][u] = beta * f;
+        ftv[u] = beta * f;
       }
-      if (path == 0) sh.jx[x] = (x > 0) ? beta * (double)J[(size_t)z * plane + (size_t)y * Lx + (x - 1)] : 0.0;
+      const double jxv = (x > 0) ? beta * (double)J[(size_t)z * plane + (size_t)y * Lx + (x - 1)] : 0.0;
+#pragma unroll
+      for (int tt = 0; tt < DP; ++tt)
+#pragma unroll
+        for (int u = 0; u < DP; ++u) sh.et[path][x][tt][u] = exp(ftv[u] + jxv * sigma<DP>(tt, u));
+      if (path == 0) sh.uni[x] = philox_uniform((uint64_t)(y * Lx + x), (uint64_t)z, sweep, 0ull, t.key0, t.key1);
     }
     if (lane < CHIM) {
 #pragma unroll
@@ -80,16 +158,16 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
     for (int x = Lx - 1; x >= 1; --x) {
       const int cl = bondY[x - 1];
       const int cr = bondY[x];
-      const double* A = envY + (size_t)x * SITE;
+      const int ncl = (x > 1) ? bondY[x - 2] : 1, ncr = bondY[x - 1];
+      site_fetch<DP, CHIM, PF>(pf, envY + (size_t)(x - 1) * SITE, ncl, ncr, tid);
+      const double* A = sAb + buf * SITE;
       double v[DP];
 #pragma unroll
       for (int u = 0; u < DP; ++u) v[u] = 0.0;
       if (lane < cl) {
 #pragma unroll
         for (int u = 0; u < DP; ++u) {
-          double s = 0.0;
-          for (int be = 0; be < cr; ++be) s += A[(size_t)(u * CHIM + lane) * CHIM + be] * RENV(x + 1, be, u);
-          v[u] = s;
+          v[u] = lds_dot<CHIM>(A + (u * CHIM + lane) * CHIM, 1, &RENV(x + 1, 0, u), DP, cr);
         }
       }
       double rt[DP];
@@ -98,7 +176,7 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
       for (int tt = 0; tt < DP; ++tt) {
         double s = 0.0;
 #pragma unroll
-        for (int u = 0; u < DP; ++u) s += v[u] * exp(sh.ft[path][x][u] + sh.jx[x] * sigma<DP>(tt, u));
+        for (int u = 0; u < DP; ++u) s += v[u] * sh.et[path][x][tt][u];
         rt[tt] = s;
         mx = fmax(mx, fabs(s));
       }
@@ -108,16 +186,33 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
 #pragma unroll
         for (int tt = 0; tt < DP; ++tt) RENV(x, lane, tt) = rt[tt] * inv;
       }
+      site_commit<DP, CHIM, PF>(sAb + (buf ^ 1) * SITE, pf, ncl, ncr, tid);
+      buf ^= 1;
       __syncthreads();
     }
     // draws, x = 0 .. Lx-1
-    if (lane < CHIM) sh.l[path][lane] = (lane == 0) ? 1.0 : 0.0;
+    if (lane < CHIM) sh.l[path][0][lane] = (lane == 0) ? 1.0 : 0.0;
     __syncthreads();
     int prev = 0;
+    int lb = 0;
     for (int x = 0; x < Lx; ++x) {
       const int cl = (x > 0) ? bondY[x - 1] : 1;
       const int cr = bondY[x];
-      const double* A = envY + (size_t)x * SITE;
+      // next site tensor: x + 1 of this row, or the last one of the next row
+      int ncl = 1, ncr = 1;
+      const double* gn = nullptr;
+      if (x + 1 < Lx) {
+        ncl = bondY[x];
+        ncr = bondY[x + 1];
+        gn = envY + (size_t)(x + 1) * SITE;
+      } else if (y + 1 < Ly) {
+        ncl = (Lx > 1) ? bondY[Lx + Lx - 2] : 1;
+        ncr = bondY[Lx + Lx - 1];
+        gn = envY + (size_t)(Lx + Lx - 1) * SITE;
+      }
+      if (gn) site_fetch<DP, CHIM, PF>(pf, gn, ncl, ncr, tid);
+      const double* A = sAb + buf * SITE;
+      const double* l = sh.l[path][lb];
       double m[DP];
       double part[DP];
 #pragma unroll
@@ -128,19 +223,18 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
       if (lane < cr) {
 #pragma unroll
         for (int u = 0; u < DP; ++u) {
-          double s = 0.0;
-          for (int al = 0; al < cl; ++al) s += sh.l[path][al] * A[(size_t)(u * CHIM + al) * CHIM + lane];
+          const double s = lds_dot<CHIM>(l, 1, A + u * CHIM * CHIM + lane, CHIM, cl);
           m[u] = s;
           part[u] = s * RENV(x + 1, lane, u);
         }
       }
+      wave_sum_n<DP>(part);
       double w[DP];
       double wsum = 0.0;
       bool bad = false;
 #pragma unroll
       for (int u = 0; u < DP; ++u) {
-        const double loc = sh.ft[path][x][u] + ((x > 0) ? sh.jx[x] * sigma<DP>(prev, u) : 0.0);
-        const double wu = exp(loc) * wave_sum(part[u]);
+        const double wu = sh.et[path][x][prev][u] * part[u];
         if (!isfinite(wu)) bad = true;
         w[u] = fmax(wu, 0.0);
         wsum += w[u];
@@ -151,20 +245,22 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
 #pragma unroll
         for (int u = 0; u < DP; ++u) p[u] = 1.0 / DP;
       } else {
+        const double iw = 1.0 / wsum;
         double ps = 0.0;
 #pragma unroll
         for (int u = 0; u < DP; ++u) {
-          p[u] = fmax(w[u] / wsum, P_FLOOR);
+          p[u] = fmax(w[u] * iw, P_FLOOR);
           ps += p[u];
         }
+        const double ip = 1.0 / ps;
 #pragma unroll
-        for (int u = 0; u < DP; ++u) p[u] /= ps;
+        for (int u = 0; u < DP; ++u) p[u] *= ip;
       }
       int s;
       if (forced != nullptr) {
         s = state_of<DP>(forced[(size_t)y * Lx + x]);
       } else {
-        const double U = philox_uniform((uint64_t)(y * Lx + x), (uint64_t)z, sweep, 0ull, t.key0, t.key1);
+        const double U = sh.uni[x];
         s = DP - 1;
         double c = 0.0;
 #pragma unroll
@@ -176,7 +272,6 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
           }
         }
       }
-      s = __shfl(s, 0);
       double lv = 0.0, pchosen = p[0];
 #pragma unroll
       for (int u = 0; u < DP; ++u)
@@ -184,16 +279,24 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
           lv = m[u];
           pchosen = p[u];
         }
-      logq += log(pchosen);
+      if (lane == 0) {
+        sh.pch[path][x] = pchosen;
+        CFG(path, y, x) = (int8_t)s;
+      }
       const double lm = wave_max(fabs(lv));
       if (!(lm > 0.0) || !isfinite(lm)) fault |= 2;
       const double inv = (lm > 0.0 && isfinite(lm)) ? 1.0 / lm : 1.0;
-      __syncthreads();   // everyone has read l before it is replaced
-      if (lane < CHIM) sh.l[path][lane] = (lane < cr) ? lv * inv : 0.0;
-      if (lane == 0) sh.cfg[path][y][x] = (int8_t)s;
+      if (lane < CHIM) sh.l[path][lb ^ 1][lane] = (lane < cr) ? lv * inv : 0.0;
+      if (gn) {
+        site_commit<DP, CHIM, PF>(sAb + (buf ^ 1) * SITE, pf, ncl, ncr, tid);
+        buf ^= 1;
+      }
+      lb ^= 1;
       prev = s;
       __syncthreads();
     }
+    // log q of the row: sum of the logs of the probabilities taken
+    logq += wave_sum((lane < Lx) ? log(sh.pch[path][lane]) : 0.0);
   }
   if (lane == 0) {
     sh.lq[path] = logq;
@@ -206,15 +309,15 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
   double dE = 0.0;
   for (int i = lane; i < Ly * Lx; i += 64) {
     const int y = i / Lx, x = i % Lx;
-    const int a = sh.cfg[0][y][x], o = sh.cfg[1][y][x];
+    const int a = CFG(0, y, x), o = CFG(1, y, x);
     double e = -(held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, a) - held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, o));
     if (x + 1 < Lx) {
       const double jx = (double)J[(size_t)z * plane + (size_t)y * Lx + x];
-      e -= jx * (sigma<DP>(a, sh.cfg[0][y][x + 1]) - sigma<DP>(o, sh.cfg[1][y][x + 1]));
+      e -= jx * (sigma<DP>(a, CFG(0, y, x + 1)) - sigma<DP>(o, CFG(1, y, x + 1)));
     }
     if (y + 1 < Ly) {
       const double jy = (double)J[plane * Lz + (size_t)z * plane + (size_t)y * Lx + x];
-      e -= jy * (sigma<DP>(a, sh.cfg[0][y + 1][x]) - sigma<DP>(o, sh.cfg[1][y + 1][x]));
+      e -= jy * (sigma<DP>(a, CFG(0, y + 1, x)) - sigma<DP>(o, CFG(1, y + 1, x)));
     }
     dE += e;
   }
@@ -225,12 +328,13 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
   const double Uacc = philox_uniform(0ull, (uint64_t)z, sweep, 1ull, t.key0, t.key1);
   const int accepted = (!any_fault && Uacc < exp(fmin(0.0, lr))) ? 1 : 0;
   if (t.s_new_out) {
-    for (int i = lane; i < Ly * Lx; i += 64) t.s_new_out[i] = spin_of<DP>(sh.cfg[0][i / Lx][i % Lx]);
+    for (int i = lane; i < Ly * Lx; i += 64) t.s_new_out[i] = spin_of<DP>(CFG(0, i / Lx, i % Lx));
   }
   if (t.write_back && accepted) {
-    for (int i = lane; i < Ly * Lx; i += 64) spins[(size_t)z * plane + i] = spin_of<DP>(sh.cfg[0][i / Lx][i % Lx]);
+    for (int i = lane; i < Ly * Lx; i += 64) spins[(size_t)z * plane + i] = spin_of<DP>(CFG(0, i / Lx, i % Lx));
   }
 #undef RENV
+#undef CFG
   if (lane == 0) {
     if (t.record) {
       t.record[0] = lq_new;
@@ -249,8 +353,9 @@ __global__ __launch_bounds__(128) void sample_kernel(const TaskDesc* __restrict_
 }
 
 template <int DP, int CHIM>
-hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, uint64_t sweep, hipStream_t s) {
-  const size_t bytes = sizeof(double) * 2 * (size_t)(Lx_max + 1) * CHIM * DP;
+hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep, hipStream_t s) {
+  const size_t bytes = sizeof(double) * (2 * (size_t)(Lx_max + 1) * CHIM * DP + 2 * (size_t)DP * CHIM * CHIM) +
+                       2 * (size_t)Lx_max * Ly_max;
   static size_t attr_bytes = 0;
   if (bytes > 48 * 1024 && bytes > attr_bytes) {
     hipError_t e = hipFuncSetAttribute((const void*)sample_kernel<DP, CHIM>,
@@ -258,7 +363,7 @@ hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, uint64_t sw
     if (e != hipSuccess) return e;
     attr_bytes = bytes;
   }
-  hipLaunchKernelGGL((sample_kernel<DP, CHIM>), dim3(n), dim3(128), bytes, s, tasks, sweep);
+  hipLaunchKernelGGL((sample_kernel<DP, CHIM>), dim3(n), dim3(NTS), bytes, s, tasks, sweep, Lx_max, Ly_max);
   return hipGetLastError();
 }
 
@@ -339,21 +444,21 @@ __global__ __launch_bounds__(256) void observables_kernel(const float* const* __
 
 }  // namespace
 
-hipError_t launch_sample(const TaskDesc* tasks, int n, int d, int chi_max, int Lx_max, uint64_t sweep,
+hipError_t launch_sample(const TaskDesc* tasks, int n, int d, int chi_max, int Lx_max, int Ly_max, uint64_t sweep,
                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (d == 2) {
     switch (chi_max) {
-      case 4: return launch_sample_t<2, 4>(tasks, n, Lx_max, sweep, s);
-      case 8: return launch_sample_t<2, 8>(tasks, n, Lx_max, sweep, s);
-      case 16: return launch_sample_t<2, 16>(tasks, n, Lx_max, sweep, s);
-      case 32: return launch_sample_t<2, 32>(tasks, n, Lx_max, sweep, s);
+      case 4: return launch_sample_t<2, 4>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 8: return launch_sample_t<2, 8>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 16: return launch_sample_t<2, 16>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 32: return launch_sample_t<2, 32>(tasks, n, Lx_max, Ly_max, sweep, s);
     }
   } else if (d == 3) {
     switch (chi_max) {
-      case 4: return launch_sample_t<3, 4>(tasks, n, Lx_max, sweep, s);
-      case 8: return launch_sample_t<3, 8>(tasks, n, Lx_max, sweep, s);
-      case 16: return launch_sample_t<3, 16>(tasks, n, Lx_max, sweep, s);
+      case 4: return launch_sample_t<3, 4>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 8: return launch_sample_t<3, 8>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 16: return launch_sample_t<3, 16>(tasks, n, Lx_max, Ly_max, sweep, s);
     }
   }
   return hipErrorInvalidValue;

@@ -41,8 +41,8 @@ inline size_t rscr_doubles(int Lx, int d, int chi_max) {
 
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_contract(const TaskDesc* tasks, int n_tasks, int d, int chi_max, hipStream_t s);
-hipError_t launch_sample(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int Lx_max, uint64_t sweep,
-                         hipStream_t s);
+hipError_t launch_sample(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int Lx_max, int Ly_max,
+                         uint64_t sweep, hipStream_t s);
 hipError_t launch_energy(const float* J, const int8_t* spins, int Lx, int Ly, int Lz, int d,
                          double* out, hipStream_t s);
 hipError_t launch_observables(const float* const* Jc, int8_t* const* spins, int n_chains,
