@@ -416,10 +416,13 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
       }
       double tau = 0.0, alpha = x0, v0 = x0;
       if (s > 0.0) {
-        const double nrm = sqrt(fma(x0, x0, s));
+        // alpha = -sign(x0) |x|, v0 = x0 - alpha = x0 + sign(x0) |x| (no
+        // cancellation), tau = 2 / (v0^2 + s) = 1 / (|x| (|x| + |x0|))
+        const double q = fma(x0, x0, s);
+        const double nrm = q * rsqrt_nr(q);
         alpha = (x0 >= 0.0) ? -nrm : nrm;
         v0 = x0 - alpha;
-        tau = 2.0 / fma(v0, v0, s);
+        tau = rcp_nr(nrm * (nrm + fabs(x0)));
       }
       // reflector entry on the boundary row: v0 on the pivot row, zero above it
       const double vb = (h == r) ? v0 : ((h > r) ? pv[jb] : 0.0);

@@ -58,6 +58,26 @@ __device__ __forceinline__ double lds_dot(const double* a, int sa, const double*
   return s0 + s1;
 }
 
+// 1/sqrt(q) for a positive normal q: the hardware estimate refined by two
+// Newton steps y <- y (3 - q y^2) / 2 (quadratic convergence; a few ulp).
+__device__ __forceinline__ double rsqrt_nr(double q) {
+  const double h = 0.5 * q;
+  double y = __builtin_amdgcn_rsq(q);
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+// 1/d for a normal d: the hardware estimate refined by two Newton steps
+// y <- y (2 - d y).
+__device__ __forceinline__ double rcp_nr(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-d, y, 1.0);
+  y = fma(y, e, y);
+  return y;
+}
+
 // sig(u, v): s_u s_v for Ising (u=0 is s=+1), delta(u, v) for Potts.
 template <int DP>
 __device__ __forceinline__ double sigma(int u, int v) {
