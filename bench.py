@@ -32,10 +32,15 @@ import synth  # noqa: E402
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 
 WORKLOADS = {
-    # name: L, chi, beta, instances, replicas
+    # single-lattice 3D EA +-J: L, chi, beta, instances, replicas
     "ea32": dict(L=32, chi=32, beta=1.0, n_inst=16, n_rep=2),
     "ea16": dict(L=16, chi=32, beta=1.0, n_inst=64, n_rep=2),
     "ea8": dict(L=8, chi=16, beta=0.5, n_inst=1, n_rep=1),
+    # heterogeneous batch: Gaussian couplings, chain k has L = Ls[k % 3],
+    # chi = chis[(k // 3) % 3] and beta drawn uniformly in [0.5, 1.5]; chains of
+    # the chi = 64 class are left out (that tile size is not built)
+    "c3": dict(mixed=True, n_chains=512, Ls=(16, 24, 32), chis=(16, 32, 64), built_chis=(16, 32),
+               beta_range=(0.5, 1.5)),
 }
 PHILOX_SEED = 20250928
 # HBM bytes per contraction launch, measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
@@ -76,6 +81,7 @@ def measured_traffic(workload: str):
 
 
 def build_inputs(name: str):
+    """Single-lattice workloads: (cfg, J[n_inst], spins[n_chains], instance of each chain, pairs, betas)."""
     cfg = WORKLOADS[name]
     L, n_inst, n_rep = cfg["L"], cfg["n_inst"], cfg["n_rep"]
     J = np.stack([synth.couplings_pm_j(L, L, L, i) for i in range(n_inst)])
@@ -86,7 +92,29 @@ def build_inputs(name: str):
     return cfg, J, spins, inst, pairs, betas
 
 
+def build_groups(name: str):
+    """The workload as a list of lattices: dicts with L, chi, J, spins, inst, pairs, betas."""
+    cfg = WORKLOADS[name]
+    if not cfg.get("mixed"):
+        _, J, spins, inst, pairs, betas = build_inputs(name)
+        return [dict(L=cfg["L"], chi=cfg["chi"], J=J, spins=spins, inst=inst, pairs=pairs, betas=betas)]
+    all_betas = synth.betas_uniform(cfg["n_chains"], *cfg["beta_range"], seed=PHILOX_SEED)
+    by_class = {}
+    for k in range(cfg["n_chains"]):
+        L, chi = cfg["Ls"][k % 3], cfg["chis"][(k // 3) % 3]
+        if chi in cfg["built_chis"]:
+            by_class.setdefault((L, chi), []).append(k)
+    groups = []
+    for (L, chi), ks in sorted(by_class.items()):
+        J = np.stack([synth.couplings_gauss(L, L, L, k) for k in ks])
+        spins = np.stack([synth.spins_random(L, L, L, 1000 * k + 1) for k in ks])
+        groups.append(dict(L=L, chi=chi, J=J, spins=spins, inst=np.arange(len(ks), dtype=np.int32), pairs=None,
+                           betas=all_betas[ks]))
+    return groups
+
+
 def make_lattice(name: str, record_capacity: int = 0):
+    """Single-lattice workloads: (lattice, cfg, J, spins, inst, betas)."""
     import paper_2509_23945_amd as tn
     cfg, J, spins, inst, pairs, betas = build_inputs(name)
     L = cfg["L"]
@@ -96,12 +124,21 @@ def make_lattice(name: str, record_capacity: int = 0):
     return lat, cfg, J, spins, inst, betas
 
 
+def make_lattices(name: str, record_capacity: int = 0):
+    import paper_2509_23945_amd as tn
+    groups = build_groups(name)
+    lats = [tn.tnmc_lattice_init(Lx=g["L"], Ly=g["L"], Lz=g["L"], d=2, chi=g["chi"], J=g["J"], beta=g["betas"],
+                                 spins=g["spins"], chain_instance=g["inst"], seed=PHILOX_SEED, pairs=g["pairs"],
+                                 record_capacity=record_capacity) for g in groups]
+    return lats, groups
+
+
 _INPUTS = {}
 
 
 def _worker_inputs(name: str):
     if name not in _INPUTS:
-        _INPUTS[name] = build_inputs(name)
+        _INPUTS[name] = build_groups(name)
     return _INPUTS[name]
 
 
@@ -114,31 +151,40 @@ def _oracle_warm(name: str) -> int:
 
 def _oracle_task(args):
     """One slice update of the workload by the FP64 oracle (cpu_baseline leg)."""
-    name, chain, z = args
+    name, gi, chain, z = args
     from threadpoolctl import threadpool_limits
     from oracle import chain as ochain
-    cfg, J, spins, inst, _, betas = _worker_inputs(name)
+    g = _worker_inputs(name)[gi]
     with threadpool_limits(1):
         t = time.perf_counter()
-        ochain.propose(J[inst[chain]], spins[chain], z, betas[chain], cfg["chi"], 2, seed=PHILOX_SEED,
-                       chain=chain, sweep=0)
+        ochain.propose(g["J"][g["inst"][chain]], g["spins"][chain], z, g["betas"][chain], g["chi"], 2,
+                       seed=PHILOX_SEED, chain=chain, sweep=0)
         return time.perf_counter() - t
 
 
-def cpu_baseline(name: str, per_worker: int = 4):
+def cpu_baseline(name: str, per_worker: int = 6):
+    """The FP64 oracle on the host cores over a bounded sample of the workload's slice updates
+    (spread over its lattices in proportion to their share of slice updates)."""
     import multiprocessing as mp
-    cfg = WORKLOADS[name]
+    groups = build_groups(name)
     cores = max(1, min(16, os.cpu_count() or 1))
-    n_chains = cfg["n_inst"] * cfg["n_rep"]
-    tasks = [(name, k % n_chains, (2 * k) % cfg["L"]) for k in range(cores * per_worker)]
+    n = cores * per_worker
+    weights = np.array([len(g["inst"]) * g["L"] for g in groups], dtype=float)
+    counts = np.floor(weights / weights.sum() * n).astype(int)
+    counts[np.argmax(weights)] += n - counts.sum()
+    tasks = []
+    for gi, (g, c) in enumerate(zip(groups, counts)):
+        nch = len(g["inst"])
+        tasks += [(name, gi, k % nch, (2 * k) % g["L"]) for k in range(c)]
     ctx = mp.get_context("spawn")
     with ctx.Pool(cores) as pool:
         pool.map(_oracle_warm, [name] * cores, chunksize=1)
         t0 = time.perf_counter()
         per = pool.map(_oracle_task, tasks, chunksize=per_worker)
         wall = time.perf_counter() - t0
+    shapes = ", ".join(f"L={g['L']} chi={g['chi']}: {c}" for g, c in zip(groups, counts) if c)
     return {"value": len(tasks) / wall, "unit": "slice updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{len(tasks)} slice updates of the {name} workload (L={cfg['L']}, chi={cfg['chi']}), "
+            "sample": f"{len(tasks)} slice updates of the {name} workload ({shapes}), "
                       f"{per_worker} per worker process, numpy single-threaded; wall {wall:.1f} s, "
                       f"{np.sum(per):.1f} s of CPU work, mean {np.mean(per):.2f} s per update per core"}
 
@@ -162,45 +208,60 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
-    lat, cfg, J, spins, inst, betas = make_lattice(args.workload, record_capacity=args.steps)
-    L = cfg["L"]
-    n_chains = cfg["n_inst"] * cfg["n_rep"]
-    print(f"[bench] workload {args.workload}: {n_chains} chains of {L}^3, chi={cfg['chi']}, "
-          f"warmup {args.warmup}", file=sys.stderr, flush=True)
+    lats, groups = make_lattices(args.workload, record_capacity=args.steps)
+    cfg = WORKLOADS[args.workload]
+    n_chains = sum(len(g["inst"]) for g in groups)
+    updates_per_sweep = sum(len(g["inst"]) * g["L"] for g in groups)
+    print(f"[bench] workload {args.workload}: {n_chains} chains in {len(lats)} lattices, "
+          f"{updates_per_sweep} slice updates per sweep, warmup {args.warmup}", file=sys.stderr, flush=True)
     if args.warmup:
-        tn.tnmc_sweep([lat], args.warmup, sweep_offset=0, stream=stream)
-    tn.tnmc_timeseries_reset(lat)
+        tn.tnmc_sweep(lats, args.warmup, sweep_offset=0, stream=stream)
+    for lat in lats:
+        tn.tnmc_timeseries_reset(lat)
     torch.cuda.synchronize()
     print(f"[bench] timing {args.steps} sweeps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    st = tn.tnmc_sweep([lat], args.steps, sweep_offset=args.warmup, record=True, time_kernels=True,
-                       stream=stream)
+    st = tn.tnmc_sweep(lats, args.steps, sweep_offset=args.warmup, record=True, time_kernels=True, stream=stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     secs = t1 - t0
-    updates = args.steps * n_chains * L
-    value = updates / secs
+    value = args.steps * updates_per_sweep / secs
 
     # algorithmic flops: textbook QR/SVD/GEMM counts at the bond dimensions each task used,
     # accumulated by the kernel; the fixed-chi model is reported beside it
-    flops_model, _ = tn.tnmc_flop_model(L, L, 2, cfg["chi"])
-    tasks_per_launch = n_chains * (L // 2)
     launches = max(1, st["contract_launches"])
+    tasks_per_sweep = sum(len(g["inst"]) * g["L"] for g in groups)
     avg_launch_s = st["contract_ms"] / 1e3 / launches
     flops_per_launch = st["contract_flops"] / launches
     achieved = flops_per_launch / avg_launch_s / 1e12
+    kernels = sorted({g["chi"] if g["chi"] > 16 else 16 for g in groups})
+    flops_model = sum(tn.tnmc_flop_model(g["L"], g["L"], 2, g["chi"])[0] * len(g["inst"]) * g["L"]
+                      for g in groups) / tasks_per_sweep
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(args.workload),
-                "kernel": "contract_kernel<2,32>", "avg_launch_ms": avg_launch_s * 1e3,
-                "flops_per_task": flops_per_launch / tasks_per_launch, "flops_per_task_fixed_chi": flops_model,
-                "tasks_per_launch": tasks_per_launch}
+                "kernel": " + ".join(f"contract_kernel<2,{c}>" for c in kernels),
+                "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
+                "flops_per_task": st["contract_flops"] / (args.steps * tasks_per_sweep),
+                "flops_per_task_fixed_chi": flops_model,
+                "tasks_per_launch": args.steps * tasks_per_sweep / launches}
 
-    _, _, q = tn.tnmc_timeseries(lat)
     indep = None
     tau = None
-    if q.shape[0] >= 100 and q.shape[1] > 0:
-        indep, tau, _ = analysis.independent_samples_per_second(q, secs / args.steps)
+    if len(lats) == 1:
+        _, _, q = tn.tnmc_timeseries(lats[0])
+        if q.shape[0] >= 100 and q.shape[1] > 0:
+            indep, tau, _ = analysis.independent_samples_per_second(q, secs / args.steps)
 
+    if cfg.get("mixed"):
+        desc = (f"heterogeneous batch, Gaussian J (2^-20 grid), open BC: chain k of {cfg['n_chains']} has "
+                f"L={list(cfg['Ls'])}[k%3], chi={list(cfg['chis'])}[(k//3)%3], beta uniform in "
+                f"{list(cfg['beta_range'])}; the chi=64 class ({cfg['n_chains'] - n_chains} chains) left out")
+        data = "synthetic (seeded Gaussian couplings, seeded betas, random initial spins)"
+    else:
+        L = cfg["L"]
+        desc = (f"3D EA +-J {L}^3 open BC, beta={cfg['beta']}, chi={cfg['chi']}, "
+                f"{cfg['n_inst']} instances x {cfg['n_rep']} replicas")
+        data = "synthetic (seeded +-J couplings, random initial spins)"
     out = {
         "metric": "slice updates/s (TNMCMC-1 slice proposal, FP64 plain)",
         "value": value,
@@ -213,10 +274,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded +-J couplings, random initial spins)",
-        "config": {"workload": f"3D EA +-J {L}^3 open BC, beta={cfg['beta']}, chi={cfg['chi']}, "
-                               f"{cfg['n_inst']} instances x {cfg['n_rep']} replicas",
-                   "chains": n_chains, "slice_updates_per_step": n_chains * L, "parallelism": "none (1 GPU)"},
+        "data": data,
+        "config": {"workload": desc, "chains": n_chains, "slice_updates_per_step": updates_per_sweep,
+                   "parallelism": "none (1 GPU)"},
         "acceptance": st["accepted"] / max(1, st["proposed"]),
         "numeric_faults": st["numeric_faults"],
         "contract_ms_per_step": st["contract_ms"] / args.steps,

@@ -155,3 +155,29 @@ def test_invalid_calls_are_rejected():
         assert ei.value.status == tn.api.TNMC_ERR_ARG
     with pytest.raises(tn.TnmcError):
         tn.tnmc_slice_logq(lat, 0, 0, np.zeros((4, 4), np.int8))
+
+
+def test_heterogeneous_batch_like_c3():
+    """The mixed batch of the c3 workload at small sizes: three lattice sizes x two
+    bond dimensions (one truncating), Gaussian couplings and a spread of beta, all in
+    one tnmc_sweep call (one launch per bond-dimension class, longest task first).
+    Every chain's layers after two sweeps equal the oracle's."""
+    gh.announce("c3-like heterogeneous batch")
+    rng_b = synth.betas_uniform(12, 0.5, 1.5, seed=7)
+    lats, refs = [], []
+    k = 0
+    for L in (6, 8, 10):
+        for chi in (4, 8):
+            betas = rng_b[k:k + 2]
+            lat, J, spins, b = gh.make_lattice(L, L, L, 2, chi, kind="gauss", beta=betas, seed=50 + k, n_chains=2)
+            lats.append(lat)
+            refs.append([(J[c], spins[c].copy(), b[c], chi, c) for c in range(2)])
+            k += 2
+    for t in range(2):
+        tn.tnmc_sweep(lats, 1, sweep_offset=t)
+        for chains in refs:
+            for (J, s, beta, chi, c) in chains:
+                ochain.sweep(J, s, beta, chi, 2, seed=12345, chain=c, sweep_index=t)
+    for lat, chains in zip(lats, refs):
+        for (J, s, beta, chi, c) in chains:
+            assert np.array_equal(tn.tnmc_get_spins(lat, c), s), (lat.Lx, chi, c)
