@@ -279,6 +279,7 @@ def main():
                    "parallelism": "none (1 GPU)"},
         "acceptance": st["accepted"] / max(1, st["proposed"]),
         "numeric_faults": st["numeric_faults"],
+        "contract_retries": st["contract_retries"],
         "contract_ms_per_step": st["contract_ms"] / args.steps,
         "sample_ms_per_step": st["sample_ms"] / args.steps,
         "tau_int_q": tau,

@@ -104,6 +104,8 @@ typedef struct {
   double contract_flops;        /* algorithmic FP64 flops of the contractions (textbook counts of
                                    the QR, SVD and GEMM steps at the bond dimensions used) */
   int64_t contract_launches, sample_launches;
+  int64_t contract_retries;     /* slice tasks whose left-sweep rank outgrew the compact LDS layout
+                                   (two workgroups per CU) and were contracted again with the full one */
 } tnmc_stats;
 
 /* n_sweeps sweeps of every chain of every lattice in lats[0..n_lats-1]

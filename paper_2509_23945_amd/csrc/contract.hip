@@ -60,6 +60,7 @@ __device__ __forceinline__ void wave_sync() {
 // Householder QR of the m x n row-major matrix M (leading dim ld) in LDS, R
 // factor only: on exit the upper trapezoid holds R, the part below the
 // diagonal holds the reflectors.  4 threads per column.
+template <int NTH>
 __device__ void qr_r_inplace(double* M, int ld, int m, int n, double* scal) {
   const int tid = threadIdx.x;
   const int grp = tid >> 2;
@@ -91,7 +92,7 @@ __device__ void qr_r_inplace(double* M, int ld, int m, int n, double* scal) {
     __syncthreads();
     const double tau = scal[0], v0 = scal[1];
     if (tau != 0.0) {
-      for (int j = k + 1 + grp; j < n; j += NT / 4) {
+      for (int j = k + 1 + grp; j < n; j += NTH / 4) {
         double w = 0.0;
         for (int i = k + 1 + sub; i < m; i += 4) w += M[i * ld + k] * M[i * ld + j];
         if (sub == 0) w += v0 * M[k * ld + j];
@@ -115,11 +116,11 @@ __device__ void qr_r_inplace(double* M, int ld, int m, int n, double* scal) {
 // that are both zero at FP64 resolution are left alone).  WAVE: the caller runs
 // it on one wavefront (at most 8 pairs) with wavefront-level ordering only.
 // Returns the number of sweeps.
-template <int NPL, bool WAVE>
+template <int NPL, bool WAVE, int NTH>
 __device__ int jacobi_rows(double* C, int ld, int m, int n, double floor) {
   if (m < 2) return 0;
   const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
-  constexpr int NSLOT = WAVE ? 8 : NT / 8;
+  constexpr int NSLOT = WAVE ? 8 : NTH / 8;
   const int p = tid >> 3;
   const int l = tid & 7;
   const int mm = m + (m & 1);
@@ -600,17 +601,18 @@ __device__ void form_q_wave(const double* M, int ld, int m, int r, const double*
 // rest of M is zero at FP64 resolution.  Returns the rank r; rows 0..r-1 of M
 // then hold R in pivoted column order (perm[j] = original index of column j).
 // cn holds n column norms; scal >= 4 doubles.
+template <int NTH>
 __device__ int qr_pivoted(double* M, int ld, int m, int n, int* perm, double* cn, double* scal,
                           double rel_tol) {
   const int tid = threadIdx.x;
   const int grp = tid >> 2;
   const int sub = tid & 3;
-  for (int j = tid; j < n; j += NT) perm[j] = j;
+  for (int j = tid; j < n; j += NTH) perm[j] = j;
   const int kmax = (m < n) ? m : n;
   double ref2 = 0.0;
   int rank = kmax;
   for (int k = 0; k < kmax; ++k) {
-    for (int j = k + grp; j < n; j += NT / 4) {
+    for (int j = k + grp; j < n; j += NTH / 4) {
       double s = 0.0;
       for (int i = k + sub; i < m; i += 4) {
         const double v = M[i * ld + j];
@@ -646,7 +648,7 @@ __device__ int qr_pivoted(double* M, int ld, int m, int n, int* perm, double* cn
       break;
     }
     if (pv != k) {
-      for (int i = tid; i < m; i += NT) {
+      for (int i = tid; i < m; i += NTH) {
         const double a = M[i * ld + k];
         M[i * ld + k] = M[i * ld + pv];
         M[i * ld + pv] = a;
@@ -683,7 +685,7 @@ __device__ int qr_pivoted(double* M, int ld, int m, int n, int* perm, double* cn
     __syncthreads();
     const double tau = scal[0], v0 = scal[1];
     if (tau != 0.0) {
-      for (int j = k + 1 + grp; j < n; j += NT / 4) {
+      for (int j = k + 1 + grp; j < n; j += NTH / 4) {
         double w = 0.0;
         for (int i = k + 1 + sub; i < m; i += 4) w += M[i * ld + k] * M[i * ld + j];
         if (sub == 0) w += v0 * M[k * ld + j];
@@ -713,10 +715,23 @@ __device__ inline double svd_count(double m, double n) {
   return 4.0 * a * b * b + 8.0 * b * b * b;
 }
 
-template <int DP, int CHIM>
+// LDS layout of the contraction, in doubles.  The full layout holds every
+// tile at its largest size (left-sweep R factors of up to D rows, tiles of
+// DP * D rows): one workgroup of 256 threads per CU at d = 2, chi = 32.
+// The compact layout (CMP) caps the left-sweep rank at RCAP = chi_max rows and
+// fits two workgroups of 128 threads per CU: the column exchange of the
+// register QR overlays the tile it factorises (read into registers first),
+// the right sweep reads site tensors from global memory, and C (needed only
+// when truncating) lives in T's tile.  A task whose left rank exceeds RCAP
+// stops and is redone with the full layout.
+template <int DP, int CHIM, bool CMP = false>
 struct Layout {
+  static constexpr int NTH = CMP ? 128 : 256;   // threads per workgroup
   static constexpr int D = DP * CHIM;   // largest bond after the MPO
   static constexpr int LD = D + 1;      // padded row stride of the square tiles
+  static constexpr int RCAP = CMP ? CHIM : D;                    // largest left-sweep rank
+  static constexpr int RROWS = CMP ? RCAP + 1 : D;               // rows of R tiles (a capped QR may reach RCAP + 1)
+  static constexpr int RSZ = (RROWS * LD + 1) & ~1;
   // common part
   static constexpr int oG = 0;                                   // [LXMAX][DP][DP]
   static constexpr int oH = oG + LXMAX * DP * DP;                // [LXMAX][DP][DP]
@@ -724,44 +739,55 @@ struct Layout {
   static constexpr int oNrm = oRed + 16;                         // [D] row norms
   static constexpr int oIdx = oNrm + D;                          // [D] ints stored as doubles
   // largest register-QR windows (rows held per lane): the left QR has up to
-  // DP * D rows, the LQ of C^T at most D
-  static constexpr int MMW = (D >= 32) ? 64 : ((DP * D > 16) ? 32 : 16);
+  // DP * RCAP rows, the LQ of C^T at most D
+  static constexpr int MMW = CMP ? ((DP * RCAP >= 32) ? 64 : ((DP * RCAP > 16) ? 32 : 16))
+                                : ((D >= 32) ? 64 : ((DP * D > 16) ? 32 : 16));
   static constexpr int MMQ = (D >= 64) ? 64 : ((D >= 32) ? 32 : 16);
   static constexpr int WC = 64 * (MMW + 2);                      // register-QR column exchange
-  static constexpr int WCQ = 64 * (MMQ + 2);
+  static constexpr int WCQ = 64 * (MMQ / (CMP ? 2 : 1) + 2);     // compact: the LQ has n <= RCAP <= 32 columns
   // LQ reflectors: at most chi of them are kept (step chi + 1 only detects truncation)
   static constexpr int WQ = CHIM * MMQ;
   static constexpr int oWork = oIdx + D;
-  // left sweep (the column exchange follows M)
+  // left sweep
+  static constexpr int MT = (CMP ? D : DP * D) * LD;             // M: up to DP * RCAP rows
   static constexpr int oA1 = oWork;                              // [DP][CHIM][CHIM]
-  static constexpr int oR1 = oA1 + DP * CHIM * CHIM;             // [D][LD]
-  static constexpr int oM1 = oR1 + D * LD;                       // [DP*D][LD]
-  static constexpr int oWcL = oM1 + DP * D * LD;                 // [64][MMW+2]
-  static constexpr int end1 = oWcL + WC;
-  // right sweep; the LQ of C^T runs when A and C are consumed, so its
-  // reflectors and column exchange live there when they fit
-  static constexpr int oA2 = oWork;
-  static constexpr int oT2 = oA2 + DP * CHIM * CHIM;             // [D][CHIM]
+  static constexpr int oR1 = oA1 + DP * CHIM * CHIM;             // [RROWS][LD]
+  static constexpr int oM1 = oR1 + RSZ;                          // [DP*RCAP][LD]
+  static constexpr int oWcL = CMP ? oM1 : oM1 + MT;              // [64][MMW+2]
+  static constexpr int end1 = CMP ? oM1 + ((WC > MT) ? WC : MT) : oWcL + WC;
+  // right sweep
+  static constexpr int oA2 = oWork;                              // full layout only
+  static constexpr int oT2 = CMP ? oWork : oA2 + DP * CHIM * CHIM;   // [D][CHIM]
   static constexpr int oAT = oT2 + D * CHIM;                     // [CHIM][DP][CHIM]
-  static constexpr int oR2 = oAT + CHIM * DP * CHIM;             // [D][LD]   (later Y)
-  static constexpr int oZ = oR2 + D * LD;                        // [D][DP][CHIM] (later V~)
-  static constexpr int oC = oZ + D * DP * CHIM;                  // [D][LD]
-  static constexpr int endC = oC + D * LD;
-  // during the LQ: T_{x+1} is consumed (its tile holds the reflectors), C is
-  // not needed (its tile and what follows hold the column exchange) and A_{x-1}
-  // is staged into A's tile
-  static constexpr int oWcR = oC;
-  static constexpr int endWc = oC + ((WCQ > D * LD) ? WCQ : D * LD);
+  static constexpr int oR2 = oAT + CHIM * DP * CHIM;             // [RROWS][LD]   (later V, Y)
+  static constexpr int oZ = oR2 + (CMP ? RSZ : D * LD);          // C^T, then V~
+  static constexpr int CTLD = CMP ? RCAP + 1 : D;                // leading dimension of C^T
+  static constexpr int ZSZ0 = CMP ? D * CTLD : D * DP * CHIM;
+  static constexpr int ZSZ = CMP ? ((ZSZ0 > WCQ ? ZSZ0 : WCQ) > DP * CHIM * CHIM ? (ZSZ0 > WCQ ? ZSZ0 : WCQ)
+                                                                                 : DP * CHIM * CHIM)
+                                 : ZSZ0;
+  static constexpr int oC = CMP ? oT2 : oZ + ZSZ;                // C: [RCAP][D] (compact) or [D][LD]
+  static constexpr int LDC = CMP ? D : LD;
+  static constexpr int endC = CMP ? oZ + ZSZ : oC + D * LD;
+  // during the LQ: T_{x+1} is consumed (its tile holds the reflectors); in the
+  // full layout C's tile and what follows hold the column exchange and A_{x-1}
+  // is staged into A's tile; in the compact one the exchange overlays C^T
+  static constexpr int oWcR = CMP ? oZ : oC;
+  static constexpr int endWc = CMP ? endC : oC + ((WCQ > D * LD) ? WCQ : D * LD);
   static constexpr bool WQ_IN_T = WQ <= D * CHIM;                // small tiles: after the exchange
   static constexpr int oWq = WQ_IN_T ? oT2 : endWc;
   static constexpr int end2 = WQ_IN_T ? endWc : endWc + WQ;
   static constexpr int total = (end1 > end2) ? end1 : end2;
   static_assert(oWcL % 2 == 0 && oWcR % 2 == 0 && oWq % 2 == 0, "16-byte aligned register-QR buffers");
+  static_assert(!CMP || RCAP * D <= D * CHIM, "compact: C fits T's tile");
 };
 
-template <int DP, int CHIM>
-__global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict__ tasks) {
-  using Lay = Layout<DP, CHIM>;
+// retry = 1: only tasks that a compact launch left unfinished (status 8) run.
+template <int DP, int CHIM, bool CMP>
+__global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(const TaskDesc* __restrict__ tasks,
+                                                                            int retry) {
+  using Lay = Layout<DP, CHIM, CMP>;
+  constexpr int NTK = Lay::NTH;
   constexpr int D = Lay::D;
   constexpr int LD = Lay::LD;
   constexpr int SITE = DP * CHIM * CHIM;
@@ -775,6 +801,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
 
   const TaskDesc& t = tasks[blockIdx.x];
   const int tid = threadIdx.x;
+  if (retry && *t.status != 8) return;
   const int Lx = t.Lx, Ly = t.Ly, Lz = t.Lz, z = t.z, chi = t.chi;
   const double beta = t.beta;
   const float* __restrict__ J = t.J;
@@ -788,7 +815,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
   double flops = 0.0;   // accumulated by thread 0 only
 
   // E_{Ly-1} = 1: bond dimension 1, every component 1.
-  for (int i = tid; i < Lx * DP; i += NT) {
+  for (int i = tid; i < Lx * DP; i += NTK) {
     const int x = i / DP, u = i % DP;
     env[((size_t)(Ly - 1) * Lx + x) * SITE + (size_t)u * CHIM * CHIM] = 1.0;
     if (u == 0) bond[(Ly - 1) * Lx + x] = 1;
@@ -798,7 +825,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
 
   for (int y = Ly - 1; y >= 1; --y) {
     // ---- local weights of row y ----
-    for (int i = tid; i < Lx * DP * DP; i += NT) {
+    for (int i = tid; i < Lx * DP * DP; i += NTK) {
       const int x = i / (DP * DP), r = (i / DP) % DP, b = i % DP;
       const double jy = (double)J[plane * Lz + (size_t)z * plane + (size_t)(y - 1) * Lx + x];
       const double f = held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, b);
@@ -819,7 +846,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
       if (tid == 0) sR[0] = 1.0;
       // the site tensor of x is staged in sA before step x: A_0 here, the
       // next one by the idle wavefronts while wavefront 0 factorises
-      stage_site<DP, CHIM>(sA, envY, 1, bondY[0], tid, NT);
+      stage_site<DP, CHIM>(sA, envY, 1, bondY[0], tid, NTK);
       __syncthreads();
       for (int x = 0; x < Lx - 1; ++x) {
         const int cl = (x > 0) ? bondY[x - 1] : 1;
@@ -832,7 +859,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         {
           const int nb = DP * cr;
           const float inv_nb = 1.0f / (float)nb, inv_cr = 1.0f / (float)cr;
-          for (int w = tid; w < rR * nb; w += NT) {
+          for (int w = tid; w < rR * nb; w += NTK) {
             const int i = fquot(w, inv_nb);
             const int rem = w - i * nb;
             const int b = fquot(rem, inv_cr), be = rem - b * cr;
@@ -880,45 +907,55 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           if (tid < 64) {
             double rmax = 0.0;
             double* sWc = smem + Lay::oWcL;
-            const int r0 = qr_pivoted_reg<Lay::MMW, false>(sM, LD, m, n, m, RANK_TOL, sWc, nullptr, nullptr, sR, LD, gR, D,
-                                                          &rmax);
+            const int r0 = qr_pivoted_reg<Lay::MMW, false>(sM, LD, m, n, CMP ? Lay::RCAP + 1 : m, RANK_TOL, sWc, nullptr,
+                                                          nullptr, sR, LD, gR, D, &rmax);
             if (tid == 0) {
               sIdx[D] = r0;
               sScal[4] = rmax;
             }
-          } else {
-            stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid - 64, NT - 64);
+          } else if (!CMP || x + 1 < Lx - 1) {
+            stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid - 64, NTK - 64);
           }
           __syncthreads();
           rx = sIdx[D];   // rewritten only after the next step's first barrier
           if (!(sScal[4] > 0.0 && isfinite(sScal[4]))) fault |= 1;
+          if constexpr (CMP) {
+            if (rx > Lay::RCAP) {
+              // the left rank outgrows the compact tiles: leave the task to the full layout
+              if (tid == 0) {
+                *t.status = 8;
+                if (t.counters) t.counters[4] += 1;
+              }
+              return;
+            }
+          }
         } else if (n <= 64 && m <= 64) {
           if (tid < 64) {
             const int r0 = qr_pivoted_wave(sM, LD, m, n, sPerm, RANK_TOL);
             if (tid == 0) sIdx[D] = r0;   // pass the rank to the other waves
           } else {
-            stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid - 64, NT - 64);
+            stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid - 64, NTK - 64);
           }
           __syncthreads();
           rx = sIdx[D];
           __syncthreads();
         } else {
-          rx = qr_pivoted(sM, LD, m, n, sPerm, sNrm, sScal, RANK_TOL);
-          stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid, NT);
+          rx = qr_pivoted<NTK>(sM, LD, m, n, sPerm, sNrm, sScal, RANK_TOL);
+          stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid, NTK);
         }
         if (rx == 0) fault |= 1;
         if (tid == 0) flops += 2.0 * rR * DP * cr * cl + qr_count(m, n, rx);
         if (!in_regs) {
           double mx = 0.0;
-          for (int w = tid; w < rx * n; w += NT) {
+          for (int w = tid; w < rx * n; w += NTK) {
             const int i = w / n, j = w % n;
             if (j >= i) mx = fmax(mx, fabs(sM[i * LD + j]));
           }
-          mx = block_max<NT>(mx, sRed);
+          mx = block_max<NTK>(mx, sRed);
           const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
           if (!(mx > 0.0 && isfinite(mx))) fault |= 1;
           // R_x = R Pi^T: any factor with R_x^T R_x = M^T M serves as the metric of the left part
-          for (int w = tid; w < rx * n; w += NT) {
+          for (int w = tid; w < rx * n; w += NTK) {
             const int i = w / n, j = w % n;
             const double v = (j >= i) ? sM[i * LD + j] * inv : 0.0;
             const int oj = sPerm[j];
@@ -948,10 +985,11 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
       int k = 1;           // columns of T_{x+1}
       if (tid == 0) bondN[Lx - 1] = 1;
       // registers per thread for the R_{x-1} loads
-      constexpr int PR = (D * CHIM + NT - 1) / NT;
+      constexpr int PR = (Lay::RCAP * CHIM + NTK - 1) / NTK;
       for (int x = Lx - 1; x >= 0; --x) {
-        // sA holds A_x: staged during the left sweep for x = Lx - 1, else
-        // prefetched while the previous step factorised
+        // full layout: sA holds A_x (staged during the left sweep for x = Lx - 1,
+        // else prefetched while the previous step factorised); compact: A_x is
+        // read from global memory
         const int cl = (x > 0) ? bondY[x - 1] : 1;
         const int cr = bondY[x];
         const bool last = (x == Lx - 1);
@@ -965,7 +1003,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         double pr[PR][DP];
 #pragma unroll
         for (int q = 0; q < PR; ++q) {
-          const int w = tid + q * NT;
+          const int w = tid + q * NTK;
           if (w < nri) {
             const int i = fquot(w, inv_cl), al = w - i * cl;
 #pragma unroll
@@ -976,22 +1014,18 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         {
           const int nb = DP * k;
           const float inv_nb = 1.0f / (float)nb, inv_k = 1.0f / (float)k;
-          for (int w = tid; w < cl * nb; w += NT) {
+          for (int w = tid; w < cl * nb; w += NTK) {
             const int al = fquot(w, inv_nb);
             const int rem = w - al * nb;
             const int b = fquot(rem, inv_k), kk = rem - b * k;
-            double s;
-            if (last) {
-              s = sA[(b * CHIM + al) * CHIM + 0];
-            } else {
-              s = lds_dot<CHIM>(sA + (b * CHIM + al) * CHIM, 1, sT + b * CHIM + kk, DP * CHIM, cr);
-            }
+            const double* Arow = (CMP ? envY + (size_t)x * SITE : sA) + (b * CHIM + al) * CHIM;
+            const double s = last ? Arow[0] : lds_dot<CHIM>(Arow, 1, sT + b * CHIM + kk, DP * CHIM, cr);
             sAT[(al * DP + b) * CHIM + kk] = s;
           }
         }
 #pragma unroll
         for (int q = 0; q < PR; ++q) {
-          const int w = tid + q * NT;
+          const int w = tid + q * NTK;
           if (w < nri) {
             const int i = fquot(w, inv_cl), al = w - i * cl;
 #pragma unroll
@@ -1002,7 +1036,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         if (x == 0) {
           // first tensor of E_{y-1}: P[r][k'] = sum_b G[r][b] AT[0][b][k'], normalised
           double nn = 0.0;
-          for (int w = tid; w < DP * k; w += NT) {
+          for (int w = tid; w < DP * k; w += NTK) {
             const int r = w / k, kk = w % k;
             double s = 0.0;
 #pragma unroll
@@ -1010,11 +1044,11 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
             sC[w] = s;
             nn += s * s;
           }
-          nn = block_sum<NT>(nn, sRed);
+          nn = block_sum<NTK>(nn, sRed);
           const double nrm = sqrt(nn);
           if (!(nrm > 0.0 && isfinite(nrm))) fault |= 4;
           const double inv = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 1.0;
-          for (int w = tid; w < DP * k; w += NT) {
+          for (int w = tid; w < DP * k; w += NTK) {
             const int r = w / k, kk = w % k;
             envN[(size_t)(r * CHIM + 0) * CHIM + kk] = sC[w] * inv;
           }
@@ -1027,13 +1061,14 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         const int nC = DP * k;
         const bool lq_try = (rR <= 64 && nC <= 64);
         const bool lq_reg = lq_try && nC <= Lay::MMQ;
-        double* sCt = sZ;    // C^T [nC][rR], leading dim D
+        double* sCt = sZ;    // C^T [nC][rR], leading dim CTLD
+        constexpr int CTLD = Lay::CTLD, LDC = Lay::LDC;
         // C[i][r*k + k'] = sum_b G[r][b] sum_al R~[i][al*d+b] AT[al][b][k'],
         // R~[i][al*d+b] = sum_a R[i][al*d+a] H[a][b]; stored transposed for
         // the LQ, and as C too when the LQ may not take the register path
         {
           const float inv_k = 1.0f / (float)k;
-          for (int w = tid; w < rR * k; w += NT) {
+          for (int w = tid; w < rR * k; w += NTK) {
             const int i = fquot(w, inv_k), kk = w - i * k;
             double z[DP];
 #pragma unroll
@@ -1073,8 +1108,8 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
               double c = 0.0;
 #pragma unroll
               for (int b = 0; b < DP; ++b) c = fma(Gx[r * DP + b], z[b], c);
-              sCt[(r * k + kk) * D + i] = c;
-              if (!lq_reg) sC[i * LD + r * k + kk] = c;
+              sCt[(r * k + kk) * CTLD + i] = c;
+              if (!lq_reg) sC[i * LDC + r * k + kk] = c;
             }
           }
         }
@@ -1086,6 +1121,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         // picks the chi largest directions.  Meanwhile the other wavefronts
         // fetch A_{x-1} into registers.
         const double* vsrc = sC;
+        int vld = LDC;
         int kx = 0;
         bool need_svd = true;
         const int pcl = (x > 1) ? bondY[x - 2] : 1, pcr = bondY[x - 1];
@@ -1098,15 +1134,15 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
             double* sWc = smem + Lay::oWcR;
             double* sWq = smem + Lay::oWq;
             if (lq_reg) {
-              rk = qr_pivoted_reg<Lay::MMQ, true>(sCt, D, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sNrm, sV, LD, nullptr, 0,
-                                                  nullptr);
+              rk = qr_pivoted_reg<Lay::MMQ, true>(sCt, CTLD, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sNrm, sV, LD, nullptr,
+                                                  0, nullptr);
             } else {
-              rk = qr_pivoted_wave(sCt, D, nC, rR, sIdx, RANK_TOL, sTau);
-              if (rk > 0 && rk <= chi) form_q_wave(sCt, D, nC, rk, sTau, sV, LD);
+              rk = qr_pivoted_wave(sCt, CTLD, nC, rR, sIdx, RANK_TOL, sTau);
+              if (rk > 0 && rk <= chi) form_q_wave(sCt, CTLD, nC, rk, sTau, sV, LD);
             }
             if (tid == 0) sIdx[D] = rk;
-          } else {
-            stage_site<DP, CHIM>(sA, gAp, pcl, pcr, tid - 64, NT - 64);
+          } else if (!CMP) {
+            stage_site<DP, CHIM>(sA, gAp, pcl, pcr, tid - 64, NTK - 64);
           }
           __syncthreads();
           const int rk = sIdx[D];
@@ -1114,63 +1150,64 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
             need_svd = false;
             kx = rk;
             vsrc = sV;
-            for (int i = tid; i < kx; i += NT) {
+            vld = LD;
+            for (int i = tid; i < kx; i += NTK) {
               sIdx[i] = i;
               sNrm[i] = 1.0;
             }
             if (tid == 0) flops += qr_count(nC, rR, rk) + 4.0 * nC * rk * rk;
           } else if (lq_reg) {
             // truncation: the SVD needs C itself
-            for (int w = tid; w < nC * rR; w += NT) {
+            for (int w = tid; w < nC * rR; w += NTK) {
               const int c = w / rR, i = w % rR;
-              sC[i * LD + c] = sCt[c * D + i];
+              sC[i * LDC + c] = sCt[c * CTLD + i];
             }
           }
           __syncthreads();
-        } else {
-          stage_site<DP, CHIM>(sA, gAp, pcl, pcr, tid, NT);
+        } else if (!CMP) {
+          stage_site<DP, CHIM>(sA, gAp, pcl, pcr, tid, NTK);
         }
         if (need_svd) {
           int mrows = rR;
           if (rR > nC) {
-            qr_r_inplace(sC, LD, rR, nC, sScal);
-            for (int w = tid; w < nC * nC; w += NT) {
+            qr_r_inplace<NTK>(sC, LDC, rR, nC, sScal);
+            for (int w = tid; w < nC * nC; w += NTK) {
               const int i = w / nC, j = w % nC;
-              if (j < i) sC[i * LD + j] = 0.0;
+              if (j < i) sC[i * LDC + j] = 0.0;
             }
             __syncthreads();
             mrows = nC;
           }
           {
             double fro = 0.0;
-            for (int w = tid; w < mrows * nC; w += NT) {
-              const double v = sC[(w / nC) * LD + (w % nC)];
+            for (int w = tid; w < mrows * nC; w += NTK) {
+              const double v = sC[(w / nC) * LDC + (w % nC)];
               fro += v * v;
             }
-            fro = block_sum<NT>(fro, sRed);
+            fro = block_sum<NTK>(fro, sRed);
             const double floor = RANK_TOL * RANK_TOL * fro;   // |a_ij| below this: both rows are FP64 zeros
             if (((mrows + 1) >> 1) <= 8) {
-              if (tid < 64) jacobi_rows<(D + 7) / 8, true>(sC, LD, mrows, nC, floor);
+              if (tid < 64) jacobi_rows<(D + 7) / 8, true, NTK>(sC, LDC, mrows, nC, floor);
               __syncthreads();
             } else {
-              jacobi_rows<(D + 7) / 8, false>(sC, LD, mrows, nC, floor);
+              jacobi_rows<(D + 7) / 8, false, NTK>(sC, LDC, mrows, nC, floor);
             }
           }
           double nmax = 0.0;
-          for (int i = tid; i < mrows; i += NT) {
+          for (int i = tid; i < mrows; i += NTK) {
             double s = 0.0;
-            for (int c = 0; c < nC; ++c) s += sC[i * LD + c] * sC[i * LD + c];
+            for (int c = 0; c < nC; ++c) s += sC[i * LDC + c] * sC[i * LDC + c];
             sNrm[i] = s;
             nmax = fmax(nmax, s);
           }
-          nmax = block_max<NT>(nmax, sRed);
+          nmax = block_max<NTK>(nmax, sRed);
           double nkeep = 0.0;
-          for (int i = tid; i < mrows; i += NT) nkeep += (sNrm[i] > RANK_TOL * RANK_TOL * nmax) ? 1.0 : 0.0;
-          nkeep = block_sum<NT>(nkeep, sRed);
+          for (int i = tid; i < mrows; i += NTK) nkeep += (sNrm[i] > RANK_TOL * RANK_TOL * nmax) ? 1.0 : 0.0;
+          nkeep = block_sum<NTK>(nkeep, sRed);
           const int rs = (nkeep >= 1.0) ? (int)nkeep : 1;
           kx = (chi < rs) ? chi : rs;
           if (tid == 0) flops += ((rR > nC) ? qr_count(rR, nC, nC) : 0.0) + svd_count(mrows, nC);
-          for (int i = tid; i < mrows; i += NT) {
+          for (int i = tid; i < mrows; i += NTK) {
             const double ni = sNrm[i];
             int rank = 0;
             for (int j = 0; j < mrows; ++j) {
@@ -1186,7 +1223,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
                    2.0 * cl * DP * kx * k + 2.0 * cl * DP * DP * kx;
         // V rows (normalised) -> new environment site x, and V~[rho][b][k'] = sum_r G[r][b] V[rho][r*k+k']
         const float inv_k = 1.0f / (float)k, inv_kx = 1.0f / (float)kx, inv_dkx = 1.0f / (float)(DP * kx);
-        for (int w = tid; w < kx * k; w += NT) {
+        for (int w = tid; w < kx * k; w += NTK) {
           const int rho = fquot(w, inv_k), kk = w - rho * k;
           const int i = sIdx[rho];
           const double nr = sqrt(sNrm[i]);
@@ -1194,7 +1231,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           double v[DP];
 #pragma unroll
           for (int r = 0; r < DP; ++r) {
-            v[r] = vsrc[i * LD + r * k + kk] * inv;
+            v[r] = vsrc[i * vld + r * k + kk] * inv;
             envN[(size_t)x * SITE + (size_t)(r * CHIM + rho) * CHIM + kk] = v[r];
           }
 #pragma unroll
@@ -1207,7 +1244,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         }
         __syncthreads();
         // Y[al][b][rho] = sum_k' AT[al][b][k'] V~[rho][b][k']
-        for (int w = tid; w < cl * DP * kx; w += NT) {
+        for (int w = tid; w < cl * DP * kx; w += NTK) {
           const int al = fquot(w, inv_dkx);
           const int rem = w - al * DP * kx;
           const int b = fquot(rem, inv_kx), rho = rem - b * kx;
@@ -1217,7 +1254,7 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
         __syncthreads();
         // T_x[al*d + a][rho] = sum_b H[a][b] Y[al][b][rho], then normalise
         double nn = 0.0;
-        for (int w = tid; w < Dl * kx; w += NT) {
+        for (int w = tid; w < Dl * kx; w += NTK) {
           const int row = fquot(w, inv_kx), rho = w - row * kx;
           const int al = row / DP, a = row % DP;
           double s = 0.0;
@@ -1226,11 +1263,11 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
           sT[row * CHIM + rho] = s;
           nn += s * s;
         }
-        nn = block_sum<NT>(nn, sRed);
+        nn = block_sum<NTK>(nn, sRed);
         const double nrm = sqrt(nn);
         if (nrm > 0.0 && isfinite(nrm)) {
           const double inv = 1.0 / nrm;
-          for (int w = tid; w < Dl * kx; w += NT) {
+          for (int w = tid; w < Dl * kx; w += NTK) {
             const int row = fquot(w, inv_kx), rho = w - row * kx;
             sT[row * CHIM + rho] *= inv;
           }
@@ -1256,18 +1293,37 @@ __global__ __launch_bounds__(NT) void contract_kernel(const TaskDesc* __restrict
 }
 
 
-template <int DP, int CHIM>
-hipError_t launch_contract_t(const TaskDesc* tasks, int n, hipStream_t s) {
-  const size_t bytes = sizeof(double) * Layout<DP, CHIM>::total;
+template <int DP, int CHIM, bool CMP>
+hipError_t launch_contract_k(const TaskDesc* tasks, int n, int retry, hipStream_t s) {
+  using Lay = Layout<DP, CHIM, CMP>;
+  const size_t bytes = sizeof(double) * Lay::total;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)contract_kernel<DP, CHIM>,
+    hipError_t e = hipFuncSetAttribute((const void*)contract_kernel<DP, CHIM, CMP>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((contract_kernel<DP, CHIM>), dim3(n), dim3(NT), bytes, s, tasks);
+  hipLaunchKernelGGL((contract_kernel<DP, CHIM, CMP>), dim3(n), dim3(Lay::NTH), bytes, s, tasks, retry);
   return hipGetLastError();
+}
+
+// Two workgroups per CU need at most half of the 160 KB of LDS each.
+constexpr size_t kHalfLds = 80 * 1024;
+
+template <int DP, int CHIM>
+hipError_t launch_contract_t(const TaskDesc* tasks, int n, hipStream_t s) {
+  constexpr bool use_compact = sizeof(double) * Layout<DP, CHIM, false>::total > kHalfLds &&
+                               sizeof(double) * Layout<DP, CHIM, true>::total <= kHalfLds;
+  if constexpr (use_compact) {
+    // every task in the compact layout (two per CU), then the few whose left
+    // rank outgrew it with the full one
+    hipError_t e = launch_contract_k<DP, CHIM, true>(tasks, n, 0, s);
+    if (e != hipSuccess) return e;
+    return launch_contract_k<DP, CHIM, false>(tasks, n, 1, s);
+  } else {
+    return launch_contract_k<DP, CHIM, false>(tasks, n, 0, s);
+  }
 }
 
 }  // namespace

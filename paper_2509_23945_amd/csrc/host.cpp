@@ -254,6 +254,7 @@ tnmc_status read_counters(size_t n_tasks, tnmc_stats* st) {
     st->accepted += c[K * i + 1];
     st->numeric_faults += c[K * i + 2];
     st->contract_flops += (double)c[K * i + 3];
+    st->contract_retries += c[K * i + 4];
   }
   return TNMC_OK;
 }

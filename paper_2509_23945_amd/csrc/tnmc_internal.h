@@ -6,7 +6,7 @@
 
 namespace tnmc {
 
-constexpr int kCounters = 4;   // per-task counters, see TaskDesc::counters
+constexpr int kCounters = 5;   // per-task counters, see TaskDesc::counters
 
 // One slice task: layer z of one chain.  Everything a kernel needs, with
 // device pointers into the lattice state and into the per-task workspace.
@@ -18,8 +18,9 @@ struct TaskDesc {
   int* bond;               // right bond dimension of every environment site [Ly][Lx]
   int* rrows;              // rows of every R factor [Lx]
   double* logscale;        // log of the removed scale of every environment [Ly]
-  int* status;             // contraction fault bits of this task (0 = ok)
-  long long* counters;     // per-task running totals {proposed, accepted, faults, contraction flops}
+  int* status;             // contraction fault bits of this task (0 = ok; 8 = left unfinished by a compact launch)
+  long long* counters;     // per-task running totals {proposed, accepted, faults, contraction flops,
+                           //  contractions redone with the full LDS layout}
   const int8_t* force_new; // if set: evaluate this layer instead of sampling [Ly][Lx]
   int8_t* s_new_out;       // if set: copy of the proposed layer [Ly][Lx]
   double* record;          // if set: {logq_new, logq_old, dE, accepted, fault}
