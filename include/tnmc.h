@@ -154,6 +154,13 @@ tnmc_status tnmc_flop_model(int32_t Lx, int32_t Ly, int32_t d, int32_t chi, doub
  * ints, 3 R factors [Lx][(d chi_max)^2] doubles, 4 log scales [Ly] doubles. */
 tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes);
 
+/* Test hook: what = 0 sends every slice task of the configurations that use
+ * the compact two-per-CU contraction layout through its overflow path (the
+ * full tile layout held in global memory), so that path can be checked
+ * against the oracle; value 1 = on, 0 = off (default).  Results are the same
+ * either way.  Returns TNMC_ERR_ARG for an unknown what. */
+tnmc_status tnmc_debug_set(int32_t what, int32_t value);
+
 const char* tnmc_status_string(tnmc_status s);
 /* Text of the last failed HIP call (thread-local). */
 const char* tnmc_last_error(void);

@@ -29,7 +29,7 @@ TNMC_FP32 = 1
 __all__ = [
     "TnmcError", "load", "declared_symbols", "tnmc_lattice_init", "tnmc_lattice_free", "tnmc_slice_propose",
     "tnmc_slice_logq", "tnmc_mh_accept", "tnmc_sweep", "tnmc_half_sweep", "tnmc_get_spins", "tnmc_set_spins",
-    "tnmc_energy", "tnmc_timeseries", "tnmc_timeseries_reset", "tnmc_flop_model", "tnmc_debug_workspace",
+    "tnmc_energy", "tnmc_timeseries", "tnmc_timeseries_reset", "tnmc_flop_model", "tnmc_debug_workspace", "tnmc_debug_set",
     "tnmc_status_string",
     "tnmc_last_error", "Lattice",
 ]
@@ -105,6 +105,8 @@ def load():
     lib.tnmc_flop_model.argtypes = [ctypes.c_int32] * 4 + [P(ctypes.c_double), P(ctypes.c_double)]
     lib.tnmc_debug_workspace.argtypes = [ctypes.c_int32, vp, ctypes.c_int64]
     lib.tnmc_debug_workspace.restype = ctypes.c_int
+    lib.tnmc_debug_set.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.tnmc_debug_set.restype = ctypes.c_int
     lib.tnmc_status_string.argtypes = [ctypes.c_int]
     lib.tnmc_status_string.restype = ctypes.c_char_p
     lib.tnmc_last_error.argtypes = []
@@ -275,6 +277,11 @@ def tnmc_debug_workspace(what: int, nbytes: int) -> bytes:
     buf = ctypes.create_string_buffer(nbytes)
     _check(load().tnmc_debug_workspace(what, buf, nbytes), "tnmc_debug_workspace")
     return buf.raw
+
+
+def tnmc_debug_set(what: int, value: int) -> None:
+    """Test hook (see include/tnmc.h): what = 0 forces the compact layout's overflow path."""
+    _check(load().tnmc_debug_set(what, value), "tnmc_debug_set")
 
 
 def tnmc_flop_model(Lx: int, Ly: int, d: int, chi: int):

@@ -50,11 +50,20 @@ __device__ __forceinline__ void stage_site(double* sA, const double* gA, int cl,
   }
 }
 
-// Orders LDS accesses of one wavefront (lanes of a wavefront run in lock step).
+// Orders the tile accesses of one wavefront (lanes of a wavefront run in lock
+// step).  GM: the tiles are in global memory (the retry path of the compact
+// layout), which needs workgroup-scope ordering.
+template <bool GM = false>
 __device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if constexpr (GM) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 // Householder QR of the m x n row-major matrix M (leading dim ld) in LDS, R
@@ -116,7 +125,7 @@ __device__ void qr_r_inplace(double* M, int ld, int m, int n, double* scal) {
 // that are both zero at FP64 resolution are left alone).  WAVE: the caller runs
 // it on one wavefront (at most 8 pairs) with wavefront-level ordering only.
 // Returns the number of sweeps.
-template <int NPL, bool WAVE, int NTH>
+template <int NPL, bool WAVE, int NTH, bool GM = false>
 __device__ int jacobi_rows(double* C, int ld, int m, int n, double floor) {
   if (m < 2) return 0;
   const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
@@ -196,9 +205,7 @@ __device__ int jacobi_rows(double* C, int ld, int m, int n, double floor) {
         i0 = r + 1;
       }
       if constexpr (WAVE) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync<GM>();
       } else {
         __syncthreads();
       }
@@ -211,6 +218,7 @@ __device__ int jacobi_rows(double* C, int ld, int m, int n, double floor) {
 
 // Single-wavefront variant of qr_pivoted for n <= 64 columns (lane j owns
 // column j): same pivot order, same stopping rule, no workgroup barriers.
+template <bool GM = false>
 __device__ int qr_pivoted_wave(double* M, int ld, int m, int n, int* perm, double rel_tol, double* tauv = nullptr) {
   const int lane = threadIdx.x & 63;
   if (lane < n) perm[lane] = lane;
@@ -262,7 +270,7 @@ __device__ int qr_pivoted_wave(double* M, int ld, int m, int n, int* perm, doubl
         cref = crk;
       }
     }
-    wave_sync();
+    wave_sync<GM>();
     double part = 0.0;
     for (int i = k + 1 + lane; i < m; i += 64) {
       const double v = M[i * ld + k];
@@ -304,9 +312,9 @@ __device__ int qr_pivoted_wave(double* M, int ld, int m, int n, int* perm, doubl
         cref = t;
       }
     }
-    wave_sync();
+    wave_sync<GM>();
     if (lane == 0) M[k * ld + k] = alpha;
-    wave_sync();
+    wave_sync<GM>();
   }
   return rank;
 }
@@ -341,7 +349,7 @@ __device__ __forceinline__ double group_sum(double v) {
 // written as rows of Out[c*ldo + i], i < m.  A factorisation that reaches kcap
 // steps returns kcap without forming Q (so W and Wt need kcap - 1 entries).
 // Returns the rank.
-template <int MM, int LPC, bool MODE_Q>
+template <int MM, int LPC, bool MODE_Q, bool GM = false>
 __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, int ld, int m, int n, int kcap,
                                                              double rel_tol, double* Wc, double* W, double* Wt,
                                                              double* Out, int ldo, double* Rglob, int gld,
@@ -403,7 +411,7 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
       const int pl = key_lane(key);   // lowest lane of the pivot column's group
       const int p = pl / LPC;
       const double s = readlane_d(tail, pl);
-      wave_sync();
+      wave_sync<GM>();
       const double x0 = Wc[(pl + r) * LDW + jb];
       const double* pv = Wc + (pl + h) * LDW;
       double v[V_LDS ? 2 : MR];
@@ -473,7 +481,7 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
       }
       free_col = free_col && !piv;
       rank = k + 1;
-      wave_sync();
+      wave_sync<GM>();
     }
     if (!stop) {
 #pragma unroll
@@ -486,7 +494,7 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
     mx = wave_max_fast(mx);
     *rmax = mx;
     const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
-    wave_sync();
+    wave_sync<GM>();
     if (c < n) {
       for (int i = h; i < rank; i += LPC) {
         const double val = Out[i * ldo + c] * inv;
@@ -543,40 +551,41 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
 // Register QR for an m x n tile with m <= MMW and n <= 64: the window is the
 // smallest of 16, 32, 64 rows that holds m, and a column gets 4, 2 or 1 lanes
 // as n allows.
-template <int MMW, bool MODE_Q>
+template <int MMW, bool MODE_Q, bool GM = false>
 __device__ __attribute__((always_inline)) int qr_pivoted_reg(const double* M, int ld, int m, int n, int kcap,
                                                              double rel_tol, double* Wc, double* W, double* Wt,
                                                              double* Out, int ldo, double* Rglob, int gld,
                                                              double* rmax) {
   if constexpr (MMW >= 64) {
     if (m > 32) {
-      if (n <= 16) return qr_pivoted_lpc<64, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
-      if (n <= 32) return qr_pivoted_lpc<64, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
-      return qr_pivoted_lpc<64, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      if (n <= 16) return qr_pivoted_lpc<64, 4, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      if (n <= 32) return qr_pivoted_lpc<64, 2, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      return qr_pivoted_lpc<64, 1, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
     }
   }
   if constexpr (MMW >= 32) {
     if (m > 16) {
-      if (n <= 16) return qr_pivoted_lpc<32, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
-      if (n <= 32) return qr_pivoted_lpc<32, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
-      return qr_pivoted_lpc<32, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      if (n <= 16) return qr_pivoted_lpc<32, 4, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      if (n <= 32) return qr_pivoted_lpc<32, 2, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      return qr_pivoted_lpc<32, 1, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
     }
   }
-  if (n <= 16) return qr_pivoted_lpc<16, 4, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
-  if (n <= 32) return qr_pivoted_lpc<16, 2, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
-  return qr_pivoted_lpc<16, 1, MODE_Q>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+  if (n <= 16) return qr_pivoted_lpc<16, 4, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+  if (n <= 32) return qr_pivoted_lpc<16, 2, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+  return qr_pivoted_lpc<16, 1, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
 }
 
 // The first r columns of Q from a Householder factorisation done by
 // qr_pivoted_wave (reflector k: v = (v0_k at row k, M[i][k] for rows i > k),
 // H_k = I - tau_k v v^T), on one wavefront: Q e_c = H_0 ... H_{r-1} e_c.
 // Column c of Q is written transposed, as row c of V: V[c*vld + i], i < m.
+template <bool GM = false>
 __device__ void form_q_wave(const double* M, int ld, int m, int r, const double* tauv, double* V, int vld) {
   const int lane = threadIdx.x & 63;
   if (lane < r) {
     for (int i = 0; i < m; ++i) V[lane * vld + i] = (i == lane) ? 1.0 : 0.0;
   }
-  wave_sync();
+  wave_sync<GM>();
   for (int k = r - 1; k >= 0; --k) {
     const double tau = tauv[2 * k], v0 = tauv[2 * k + 1];
     if (tau != 0.0 && lane < r) {
@@ -589,7 +598,7 @@ __device__ void form_q_wave(const double* M, int ld, int m, int r, const double*
 #pragma unroll 8
       for (int i = k + 1; i < m; ++i) e[i] -= w * M[i * ld + k];
     }
-    wave_sync();
+    wave_sync<GM>();
   }
 }
 
@@ -782,8 +791,11 @@ struct Layout {
   static_assert(!CMP || RCAP * D <= D * CHIM, "compact: C fits T's tile");
 };
 
-// retry = 1: only tasks that a compact launch left unfinished (status 8) run.
-template <int DP, int CHIM, bool CMP>
+// retry = 1: only tasks that a compact launch left unfinished (status 8) run;
+// retry = -1: every task is left unfinished (test hook).
+// GM: the tiles live in the task's global scratch instead of LDS (the retry
+// launch then needs no LDS and starts on any CU at once; overflows are rare).
+template <int DP, int CHIM, bool CMP, bool GM = false>
 __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(const TaskDesc* __restrict__ tasks,
                                                                             int retry) {
   using Lay = Layout<DP, CHIM, CMP>;
@@ -791,17 +803,21 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
   constexpr int D = Lay::D;
   constexpr int LD = Lay::LD;
   constexpr int SITE = DP * CHIM * CHIM;
-  extern __shared__ __align__(16) double smem[];
+  extern __shared__ __align__(16) double lds[];
+  const TaskDesc& t = tasks[blockIdx.x];
+  const int tid = threadIdx.x;
+  if (retry < 0) {   // test hook: leave every task to the retry launch
+    if (tid == 0) *t.status = 8;
+    return;
+  }
+  if (retry && *t.status != 8) return;
+  double* smem = GM ? t.gscr : lds;
   double* sG = smem + Lay::oG;
   double* sH = smem + Lay::oH;
   double* sRed = smem + Lay::oRed;
   double* sScal = smem + Lay::oRed + 8;
   double* sNrm = smem + Lay::oNrm;
   int* sIdx = reinterpret_cast<int*>(smem + Lay::oIdx);
-
-  const TaskDesc& t = tasks[blockIdx.x];
-  const int tid = threadIdx.x;
-  if (retry && *t.status != 8) return;
   const int Lx = t.Lx, Ly = t.Ly, Lz = t.Lz, z = t.z, chi = t.chi;
   const double beta = t.beta;
   const float* __restrict__ J = t.J;
@@ -907,7 +923,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
           if (tid < 64) {
             double rmax = 0.0;
             double* sWc = smem + Lay::oWcL;
-            const int r0 = qr_pivoted_reg<Lay::MMW, false>(sM, LD, m, n, CMP ? Lay::RCAP + 1 : m, RANK_TOL, sWc, nullptr,
+            const int r0 = qr_pivoted_reg<Lay::MMW, false, GM>(sM, LD, m, n, CMP ? Lay::RCAP + 1 : m, RANK_TOL, sWc, nullptr,
                                                           nullptr, sR, LD, gR, D, &rmax);
             if (tid == 0) {
               sIdx[D] = r0;
@@ -931,7 +947,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
           }
         } else if (n <= 64 && m <= 64) {
           if (tid < 64) {
-            const int r0 = qr_pivoted_wave(sM, LD, m, n, sPerm, RANK_TOL);
+            const int r0 = qr_pivoted_wave<GM>(sM, LD, m, n, sPerm, RANK_TOL);
             if (tid == 0) sIdx[D] = r0;   // pass the rank to the other waves
           } else {
             stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid - 64, NTK - 64);
@@ -1134,11 +1150,11 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
             double* sWc = smem + Lay::oWcR;
             double* sWq = smem + Lay::oWq;
             if (lq_reg) {
-              rk = qr_pivoted_reg<Lay::MMQ, true>(sCt, CTLD, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sNrm, sV, LD, nullptr,
+              rk = qr_pivoted_reg<Lay::MMQ, true, GM>(sCt, CTLD, nC, rR, chi + 1, RANK_TOL, sWc, sWq, sNrm, sV, LD, nullptr,
                                                   0, nullptr);
             } else {
-              rk = qr_pivoted_wave(sCt, CTLD, nC, rR, sIdx, RANK_TOL, sTau);
-              if (rk > 0 && rk <= chi) form_q_wave(sCt, CTLD, nC, rk, sTau, sV, LD);
+              rk = qr_pivoted_wave<GM>(sCt, CTLD, nC, rR, sIdx, RANK_TOL, sTau);
+              if (rk > 0 && rk <= chi) form_q_wave<GM>(sCt, CTLD, nC, rk, sTau, sV, LD);
             }
             if (tid == 0) sIdx[D] = rk;
           } else if (!CMP) {
@@ -1187,10 +1203,10 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
             fro = block_sum<NTK>(fro, sRed);
             const double floor = RANK_TOL * RANK_TOL * fro;   // |a_ij| below this: both rows are FP64 zeros
             if (((mrows + 1) >> 1) <= 8) {
-              if (tid < 64) jacobi_rows<(D + 7) / 8, true, NTK>(sC, LDC, mrows, nC, floor);
+              if (tid < 64) jacobi_rows<(D + 7) / 8, true, NTK, GM>(sC, LDC, mrows, nC, floor);
               __syncthreads();
             } else {
-              jacobi_rows<(D + 7) / 8, false, NTK>(sC, LDC, mrows, nC, floor);
+              jacobi_rows<(D + 7) / 8, false, NTK, GM>(sC, LDC, mrows, nC, floor);
             }
           }
           double nmax = 0.0;
@@ -1293,20 +1309,22 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
 }
 
 
-template <int DP, int CHIM, bool CMP>
+template <int DP, int CHIM, bool CMP, bool GM = false>
 hipError_t launch_contract_k(const TaskDesc* tasks, int n, int retry, hipStream_t s) {
   using Lay = Layout<DP, CHIM, CMP>;
-  const size_t bytes = sizeof(double) * Lay::total;
+  const size_t bytes = GM ? 0 : sizeof(double) * Lay::total;
   static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)contract_kernel<DP, CHIM, CMP>,
+  if (!attr_set && bytes > 48 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)contract_kernel<DP, CHIM, CMP, GM>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((contract_kernel<DP, CHIM, CMP>), dim3(n), dim3(Lay::NTH), bytes, s, tasks, retry);
+  hipLaunchKernelGGL((contract_kernel<DP, CHIM, CMP, GM>), dim3(n), dim3(Lay::NTH), bytes, s, tasks, retry);
   return hipGetLastError();
 }
+
+int g_force_retry = 0;
 
 // Two workgroups per CU need at most half of the 160 KB of LDS each.
 constexpr size_t kHalfLds = 80 * 1024;
@@ -1317,16 +1335,19 @@ hipError_t launch_contract_t(const TaskDesc* tasks, int n, hipStream_t s) {
                                sizeof(double) * Layout<DP, CHIM, true>::total <= kHalfLds;
   if constexpr (use_compact) {
     // every task in the compact layout (two per CU), then the few whose left
-    // rank outgrew it with the full one
-    hipError_t e = launch_contract_k<DP, CHIM, true>(tasks, n, 0, s);
+    // rank outgrew it with the full layout held in global memory (no LDS, so
+    // the launch is not held back by other work resident on the CUs)
+    hipError_t e = launch_contract_k<DP, CHIM, true>(tasks, n, g_force_retry ? -1 : 0, s);
     if (e != hipSuccess) return e;
-    return launch_contract_k<DP, CHIM, false>(tasks, n, 1, s);
+    return launch_contract_k<DP, CHIM, false, true>(tasks, n, 1, s);
   } else {
     return launch_contract_k<DP, CHIM, false>(tasks, n, 0, s);
   }
 }
 
 }  // namespace
+
+void set_force_retry(int on) { g_force_retry = on; }
 
 size_t contract_lds_bytes(int d, int chi_max) {
   if (d == 2) {

@@ -24,6 +24,7 @@ struct TaskDesc {
   const int8_t* force_new; // if set: evaluate this layer instead of sampling [Ly][Lx]
   int8_t* s_new_out;       // if set: copy of the proposed layer [Ly][Lx]
   double* record;          // if set: {logq_new, logq_old, dE, accepted, fault}
+  double* gscr;            // global scratch holding the full contraction tile layout (retry path)
   double beta;
   uint64_t key0, key1;     // Philox key
   int Lx, Ly, Lz, z, chi, d;
@@ -52,6 +53,7 @@ hipError_t launch_observables(const float* const* Jc, int8_t* const* spins, int 
                               hipStream_t s);
 bool contract_supported(int d, int chi_max);
 size_t contract_lds_bytes(int d, int chi_max);
+void set_force_retry(int on);   // test hook: every compact-layout task takes the retry path
 int chi_bucket(int chi);   // storage chi_max used for a requested chi (0 if unsupported)
 
 }  // namespace tnmc

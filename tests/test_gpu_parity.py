@@ -49,6 +49,35 @@ def test_propose_matches_oracle(case):
         assert not diff or diff.get("spins", ("",))[0] == "near-tie", diff
 
 
+# cases whose configuration uses the compact two-per-CU contraction layout
+COMPACT_CASES = [c for c in CASES if (c[3] == 2 and c[6] > 16) or (c[3] == 3 and c[6] > 8)]
+
+
+@pytest.mark.parametrize("case", COMPACT_CASES, ids=lambda c: "x".join(map(str, c[:3])) + f"-d{c[3]}-chi{c[6]}")
+def test_overflow_path_matches_oracle(case):
+    """The compact layout's overflow path (full tile layout in global memory),
+    forced for every task through the test hook, agrees with the oracle as the
+    LDS paths do; one sweep through it equals one through the normal path."""
+    Lx, Ly, Lz, d, kind, beta, chi, z = case
+    gh.announce(f"overflow path {case}")
+    lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, d, chi, kind=kind, beta=beta, seed=3)
+    tn.tnmc_debug_set(0, 1)
+    try:
+        gpu = tn.tnmc_slice_propose(lat, 0, z, 0)
+        assert gpu[4] == 0
+        ref, margins = gh.oracle_propose(J[0], spins[0], z, beta, chi, d, seed=12345, chain=0, sweep=0)
+        diff = gh.compare_proposal(gpu, ref, margins)
+        assert not diff or diff.get("spins", ("",))[0] == "near-tie", diff
+        st = tn.tnmc_sweep([lat], 1, sweep_offset=0)
+        assert st["numeric_faults"] == 0
+        forced = tn.tnmc_get_spins(lat, 0)
+    finally:
+        tn.tnmc_debug_set(0, 0)
+    lat2 = gh.make_lattice(Lx, Ly, Lz, d, chi, kind=kind, beta=beta, seed=3)[0]
+    tn.tnmc_sweep([lat2], 1, sweep_offset=0)
+    assert np.array_equal(forced, tn.tnmc_get_spins(lat2, 0))
+
+
 @pytest.mark.parametrize("case", [(6, 5, 3, 2, "pmj", 1.0, 3), (5, 5, 1, 2, "ferro", 0.44, 2),
                                   (4, 4, 3, 3, "ferro", 0.6, 3)])
 def test_logq_of_arbitrary_layers(case):
