@@ -807,10 +807,13 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
   const TaskDesc& t = tasks[blockIdx.x];
   const int tid = threadIdx.x;
   if (retry < 0) {   // test hook: leave every task to the retry launch
-    if (tid == 0) *t.status = 8;
+    if (tid == 0) *t.status = 8 | ((t.Ly - 1) << 8);
     return;
   }
-  if (retry && *t.status != 8) return;
+  // a retry resumes at the row where the compact launch stopped (status bits
+  // 8 and up), with the fault bits it had collected (bits 4-6)
+  const int st0 = retry ? *t.status : 0;
+  if (retry && (st0 & 15) != 8) return;
   double* smem = GM ? t.gscr : lds;
   double* sG = smem + Lay::oG;
   double* sH = smem + Lay::oH;
@@ -827,19 +830,22 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
   int* __restrict__ bond = t.bond;
   int* __restrict__ rrows = t.rrows;
   const size_t plane = (size_t)Lx * Ly;
-  int fault = 0;
+  int fault = retry ? ((st0 >> 4) & 7) : 0;
   double flops = 0.0;   // accumulated by thread 0 only
 
   // E_{Ly-1} = 1: bond dimension 1, every component 1.
-  for (int i = tid; i < Lx * DP; i += NTK) {
-    const int x = i / DP, u = i % DP;
-    env[((size_t)(Ly - 1) * Lx + x) * SITE + (size_t)u * CHIM * CHIM] = 1.0;
-    if (u == 0) bond[(Ly - 1) * Lx + x] = 1;
+  const int y_top = retry ? (st0 >> 8) : Ly - 1;
+  if (y_top == Ly - 1) {
+    for (int i = tid; i < Lx * DP; i += NTK) {
+      const int x = i / DP, u = i % DP;
+      env[((size_t)(Ly - 1) * Lx + x) * SITE + (size_t)u * CHIM * CHIM] = 1.0;
+      if (u == 0) bond[(Ly - 1) * Lx + x] = 1;
+    }
+    if (tid == 0) t.logscale[Ly - 1] = 0.0;
   }
-  if (tid == 0) t.logscale[Ly - 1] = 0.0;
   __syncthreads();
 
-  for (int y = Ly - 1; y >= 1; --y) {
+  for (int y = y_top; y >= 1; --y) {
     // ---- local weights of row y ----
     for (int i = tid; i < Lx * DP * DP; i += NTK) {
       const int x = i / (DP * DP), r = (i / DP) % DP, b = i % DP;
@@ -937,9 +943,12 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
           if (!(sScal[4] > 0.0 && isfinite(sScal[4]))) fault |= 1;
           if constexpr (CMP) {
             if (rx > Lay::RCAP) {
-              // the left rank outgrows the compact tiles: leave the task to the full layout
+              // the left rank outgrows the compact tiles: leave the rest of the
+              // task, from this row on, to the full layout
+              const int f = (__syncthreads_or(fault & 1) ? 1 : 0) | (__syncthreads_or(fault & 2) ? 2 : 0) |
+                            (__syncthreads_or(fault & 4) ? 4 : 0);
               if (tid == 0) {
-                *t.status = 8;
+                *t.status = 8 | (f << 4) | (y << 8);
                 if (t.counters) t.counters[4] += 1;
               }
               return;

@@ -18,7 +18,8 @@ struct TaskDesc {
   int* bond;               // right bond dimension of every environment site [Ly][Lx]
   int* rrows;              // rows of every R factor [Lx]
   double* logscale;        // log of the removed scale of every environment [Ly]
-  int* status;             // contraction fault bits of this task (0 = ok; 8 = left unfinished by a compact launch)
+  int* status;             // contraction fault bits of this task (0 = ok); a compact launch that leaves the
+                           // task unfinished writes 8 | fault bits << 4 | row to resume at << 8
   long long* counters;     // per-task running totals {proposed, accepted, faults, contraction flops,
                            //  contractions redone with the full LDS layout}
   const int8_t* force_new; // if set: evaluate this layer instead of sampling [Ly][Lx]
