@@ -189,7 +189,8 @@ def test_invalid_calls_are_rejected():
 def test_heterogeneous_batch_like_c3():
     """The mixed batch of the c3 workload at small sizes: three lattice sizes x two
     bond dimensions (one truncating), Gaussian couplings and a spread of beta, all in
-    one tnmc_sweep call (one launch per bond-dimension class, longest task first).
+    one tnmc_sweep call (launches grouped by layer class and bond dimension,
+    longest task first).
     Every chain's layers after two sweeps equal the oracle's."""
     gh.announce("c3-like heterogeneous batch")
     rng_b = synth.betas_uniform(12, 0.5, 1.5, seed=7)
