@@ -124,13 +124,27 @@ def make_lattice(name: str, record_capacity: int = 0):
     return lat, cfg, J, spins, inst, betas
 
 
-def make_lattices(name: str, record_capacity: int = 0):
+def make_lattices(name: str, record_capacity: int = 0, precision: int = 0):
     import paper_2509_23945_amd as tn
     groups = build_groups(name)
     lats = [tn.tnmc_lattice_init(Lx=g["L"], Ly=g["L"], Lz=g["L"], d=2, chi=g["chi"], J=g["J"], beta=g["betas"],
                                  spins=g["spins"], chain_instance=g["inst"], seed=PHILOX_SEED, pairs=g["pairs"],
-                                 record_capacity=record_capacity) for g in groups]
+                                 record_capacity=record_capacity, precision=precision) for g in groups]
     return lats, groups
+
+
+def time_form(tn, lats, warmup: int, steps: int, stream):
+    """Warm up, then time `steps` sweeps of every lattice; returns (seconds, stats)."""
+    import torch
+    if warmup:
+        tn.tnmc_sweep(lats, warmup, sweep_offset=0, stream=stream)
+    for lat in lats:
+        tn.tnmc_timeseries_reset(lat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = tn.tnmc_sweep(lats, steps, sweep_offset=warmup, record=True, time_kernels=True, stream=stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, st
 
 
 _INPUTS = {}
@@ -196,10 +210,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="ea32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-reduced", action="store_true", help="skip the FP32-environment form")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
-              "design only, see DESIGN.md", file=sys.stderr)
+              "design only: chains are independent, so each GPU would run its own share of them", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -214,17 +229,8 @@ def main():
     updates_per_sweep = sum(len(g["inst"]) * g["L"] for g in groups)
     print(f"[bench] workload {args.workload}: {n_chains} chains in {len(lats)} lattices, "
           f"{updates_per_sweep} slice updates per sweep, warmup {args.warmup}", file=sys.stderr, flush=True)
-    if args.warmup:
-        tn.tnmc_sweep(lats, args.warmup, sweep_offset=0, stream=stream)
-    for lat in lats:
-        tn.tnmc_timeseries_reset(lat)
-    torch.cuda.synchronize()
     print(f"[bench] timing {args.steps} sweeps", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    st = tn.tnmc_sweep(lats, args.steps, sweep_offset=args.warmup, record=True, time_kernels=True, stream=stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    secs = t1 - t0
+    secs, st = time_form(tn, lats, args.warmup, args.steps, stream)
     value = args.steps * updates_per_sweep / secs
 
     # algorithmic flops: textbook QR/SVD/GEMM counts at the bond dimensions each task used,
@@ -291,6 +297,22 @@ def main():
         "indep_samples_per_s": indep,
         "roofline": roofline,
     }
+    if not args.no_reduced:
+        # the reduced-precision form on the same inputs: FP32 environments, rank
+        # cut-off at FP32 resolution, FP64 factorisations, log q and MH
+        print(f"[bench] reduced-precision form: timing {args.steps} sweeps", file=sys.stderr, flush=True)
+        lats32, _ = make_lattices(args.workload, record_capacity=args.steps, precision=tn.TNMC_FP32)
+        secs32, st32 = time_form(tn, lats32, args.warmup, args.steps, stream)
+        v32 = args.steps * updates_per_sweep / secs32
+        out["reduced_precision"] = {
+            "form": "environments stored in FP32, rank cut-off 1e-6; factorisations, log q, dE, MH in FP64",
+            "value": v32, "unit": "slice updates/s", "ms_per_step": secs32 / args.steps * 1e3,
+            "vs_fp64": v32 / value, "acceptance": st32["accepted"] / max(1, st32["proposed"]),
+            "numeric_faults": st32["numeric_faults"],
+            "contract_ms_per_step": st32["contract_ms"] / args.steps,
+            "sample_ms_per_step": st32["sample_ms"] / args.steps}
+        for lat in lats32:
+            tn.tnmc_lattice_free(lat)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)

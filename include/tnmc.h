@@ -42,7 +42,7 @@ typedef enum {
   TNMC_ERR_UNSUPPORTED = -5  /* (d, chi, precision) combination not built */
 } tnmc_status;
 
-enum { TNMC_FP64 = 0, TNMC_FP32 = 1 };   /* contraction precision */
+enum { TNMC_FP64 = 0, TNMC_FP32 = 1 };   /* storage precision of the boundary-MPS environments */
 
 typedef struct tnmc_lattice tnmc_lattice;  /* opaque; owns the device state it allocates */
 
@@ -54,7 +54,13 @@ typedef struct {
   int32_t Lx, Ly, Lz;           /* 1 <= Lx, Ly; 1 <= Lz */
   int32_t d;                    /* 2 (Ising / EA) or 3 (Potts) */
   int32_t chi;                  /* boundary-MPS bond dimension, >= 1 */
-  int32_t precision;            /* TNMC_FP64 */
+  int32_t precision;            /* TNMC_FP64, or TNMC_FP32: the reduced-precision form.  The
+                                   environments are stored in FP32 and the rank-revealing
+                                   factorisations cut at 1e-6 relative (FP32 resolution) instead
+                                   of 1e-15; all arithmetic, log q, dE and the MH test stay FP64.
+                                   The proposal q changes (log q by ~1e-6 relative), the chain's
+                                   stationary law does not: q(old) and q(new) come from the same
+                                   environments (SM S2.A, MH of main text Eq. 1). */
   int32_t n_chains;             /* >= 1 */
   int32_t n_instances;          /* >= 1, number of coupling sets */
   const float* J;               /* [n_instances][3][Lz][Ly][Lx] */

@@ -31,7 +31,7 @@ __all__ = [
     "tnmc_slice_logq", "tnmc_mh_accept", "tnmc_sweep", "tnmc_half_sweep", "tnmc_get_spins", "tnmc_set_spins",
     "tnmc_energy", "tnmc_timeseries", "tnmc_timeseries_reset", "tnmc_flop_model", "tnmc_debug_workspace", "tnmc_debug_set",
     "tnmc_status_string",
-    "tnmc_last_error", "Lattice",
+    "tnmc_last_error", "Lattice", "TNMC_FP64", "TNMC_FP32",
 ]
 
 
@@ -78,7 +78,12 @@ _lib = None
 
 
 def load():
-    """Load libtnmc.so (raises if it has not been built)."""
+    """Load libtnmc.so (raises if it has not been built).
+
+    The library links the system HIP runtime; torch wheels carry a runtime of
+    their own.  A process that uses both must let torch initialise its GPU
+    state first (any torch.cuda call), or torch finds no device afterwards;
+    device pointers and the null stream work across the two."""
     global _lib
     if _lib is not None:
         return _lib

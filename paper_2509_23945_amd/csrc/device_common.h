@@ -34,19 +34,20 @@ __device__ inline double philox_uniform(uint64_t c0, uint64_t c1, uint64_t c2, u
 // the integer division sequence in index arithmetic.
 __device__ __forceinline__ int fquot(int w, float inv_n) { return (int)(((float)w + 0.5f) * inv_n); }
 
-// sum_{j < n} a[j*sa] b[j*sb] over LDS operands, n <= NMAX: the loads are
+// sum_{j < n} a[j*sa] b[j*sb] in FP64 over LDS operands (a may also be a
+// global FP64 or FP32 array), n <= NMAX: the loads are
 // issued eight at a time (indices up to the next multiple of 8 below NMAX must
 // be addressable; their values are discarded) so that one wait covers each
 // group, with two accumulation chains.
-template <int NMAX>
-__device__ __forceinline__ double lds_dot(const double* a, int sa, const double* b, int sb, int n) {
+template <int NMAX, typename TA>
+__device__ __forceinline__ double lds_dot(const TA* a, int sa, const double* b, int sb, int n) {
   double s0 = 0.0, s1 = 0.0;
   for (int j0 = 0; j0 < n; j0 += 8) {
     double av[8], bv[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int j = (j0 + q < NMAX) ? j0 + q : NMAX - 1;
-      av[q] = a[j * sa];
+      av[q] = (double)a[j * sa];
       bv[q] = b[j * sb];
     }
 #pragma unroll

@@ -114,7 +114,7 @@ struct Plan {
   std::vector<TaskDesc> desc;
   std::vector<int> order;   // desc[k] runs tasks[order[k]]
   struct Group {
-    int d, chi_max, first, count, lx_max, ly_max, key;
+    int d, chi_max, first, count, lx_max, ly_max, key, precision;
   };
   std::vector<Group> groups;
 };
@@ -142,13 +142,14 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     if (tasks[a].key != tasks[b].key) return tasks[a].key < tasks[b].key;
     if (la->d != lb->d) return la->d < lb->d;
     if (la->chi_max != lb->chi_max) return la->chi_max < lb->chi_max;
+    if (la->precision != lb->precision) return la->precision < lb->precision;
     return task_cost(tasks[a]) > task_cost(tasks[b]);
   });
   size_t env_need = 0, rscr_need = 0, int_need = 0, dbl_need = 0, gscr_need = 0;
   for (int i : order) {
     const auto* L = tasks[i].lat;
     gscr_need += tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double);
-    env_need += tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max);
+    env_need += tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision);
     rscr_need += tnmc::rscr_doubles(L->Lx, L->d, L->chi_max);
     int_need += (size_t)L->Ly * L->Lx + L->Lx + 1;
     dbl_need += (size_t)L->Ly;
@@ -179,6 +180,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.logscale = g_ws.dbl + dof;
     t.counters = g_ws.counters + tnmc::kCounters * k;
     t.beta = L->beta[tk.chain];
+    t.rank_tol = (L->precision == TNMC_FP32) ? tnmc::kRankTolF32 : tnmc::kRankTolF64;
     t.key0 = L->seed;
     t.key1 = L->chain_key[tk.chain];
     t.Lx = L->Lx;
@@ -189,14 +191,14 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.d = L->d;
     t.chi_max = L->chi_max;
     t.write_back = 1;
-    eo += tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max);
+    eo += tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision);
     go += tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double);
     ro += tnmc::rscr_doubles(L->Lx, L->d, L->chi_max);
     io += (size_t)L->Ly * L->Lx + L->Lx + 1;
     dof += (size_t)L->Ly;
     if (plan.groups.empty() || plan.groups.back().d != L->d || plan.groups.back().chi_max != L->chi_max ||
-        plan.groups.back().key != tk.key) {
-      plan.groups.push_back({L->d, L->chi_max, (int)k, 0, 0, 0, tk.key});
+        plan.groups.back().key != tk.key || plan.groups.back().precision != L->precision) {
+      plan.groups.push_back({L->d, L->chi_max, (int)k, 0, 0, 0, tk.key, L->precision});
     }
     plan.groups.back().count += 1;
     plan.groups.back().lx_max = std::max(plan.groups.back().lx_max, L->Lx);
@@ -227,13 +229,14 @@ tnmc_status launch_plan(const Plan& plan, const TaskDesc* dtasks, uint64_t sweep
                         tnmc_stats* st) {
   for (const auto& g : plan.groups) {
     if (tm && tm->on && tm->mark(tm->c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
-    HIP_TRY(tnmc::launch_contract(dtasks + g.first, g.count, g.d, g.chi_max, s));
+    HIP_TRY(tnmc::launch_contract(dtasks + g.first, g.count, g.d, g.chi_max, g.precision, s));
     if (tm && tm->on && tm->mark(tm->c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
     if (st) st->contract_launches += 1;
   }
   for (const auto& g : plan.groups) {
     if (tm && tm->on && tm->mark(tm->s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
-    HIP_TRY(tnmc::launch_sample(dtasks + g.first, g.count, g.d, g.chi_max, g.lx_max, g.ly_max, sweep, s));
+    HIP_TRY(tnmc::launch_sample(dtasks + g.first, g.count, g.d, g.chi_max, g.precision, g.lx_max, g.ly_max, sweep,
+                                s));
     if (tm && tm->on && tm->mark(tm->s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
     if (st) st->sample_launches += 1;
   }
@@ -361,7 +364,7 @@ tnmc_status tnmc_lattice_init(const tnmc_lattice_desc* ds, tnmc_lattice** out) {
   if (ds->chi < 1 || ds->n_chains < 1 || ds->n_instances < 1 || !ds->J || !ds->beta || !ds->spins)
     return TNMC_ERR_ARG;
   if (ds->n_pairs < 0 || (ds->n_pairs > 0 && !ds->pairs) || ds->record_capacity < 0) return TNMC_ERR_ARG;
-  if (ds->precision != TNMC_FP64) return TNMC_ERR_UNSUPPORTED;
+  if (ds->precision != TNMC_FP64 && ds->precision != TNMC_FP32) return TNMC_ERR_UNSUPPORTED;
   const int cm = tnmc::chi_bucket(ds->chi);
   if (cm == 0 || !tnmc::contract_supported(ds->d, cm)) return TNMC_ERR_UNSUPPORTED;
   for (int c = 0; c < ds->n_chains; ++c) {
@@ -631,10 +634,10 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
         if (issued[h] && gst[h] != st) HIP_TRY(hipStreamWaitEvent(st, ev[h], 0));
       const TaskDesc* dt = g_ws.tasks + g.first;
       if (tm.on && tm.mark(tm.c_ev, st) != TNMC_OK) return TNMC_ERR_DEVICE;
-      HIP_TRY(tnmc::launch_contract(dt, g.count, g.d, g.chi_max, st));
+      HIP_TRY(tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, st));
       if (tm.on && tm.mark(tm.c_ev, st) != TNMC_OK) return TNMC_ERR_DEVICE;
       if (tm.on && tm.mark(tm.s_ev, st) != TNMC_OK) return TNMC_ERR_DEVICE;
-      HIP_TRY(tnmc::launch_sample(dt, g.count, g.d, g.chi_max, g.lx_max, g.ly_max, sw, st));
+      HIP_TRY(tnmc::launch_sample(dt, g.count, g.d, g.chi_max, g.precision, g.lx_max, g.ly_max, sw, st));
       if (tm.on && tm.mark(tm.s_ev, st) != TNMC_OK) return TNMC_ERR_DEVICE;
       HIP_TRY(hipEventRecord(ev[gi], st));
       issued[gi] = 1;

@@ -23,7 +23,6 @@ namespace tnmc {
 namespace {
 
 constexpr int LXMAX = 64;
-constexpr int LYMAX = 64;
 constexpr int NTS = 128;              // one wavefront per path
 constexpr double P_FLOOR = 1e-12;
 
@@ -49,8 +48,8 @@ struct SiteCopy {
   static constexpr int PASSES = (DP * CHIM + RPP - 1) / RPP;
   static constexpr int PF = PASSES * CPT;
 };
-template <int DP, int CHIM, int PF>
-__device__ __forceinline__ void site_fetch(double (&pf)[PF], const double* __restrict__ g, int cl, int cr, int tid) {
+template <int DP, int CHIM, int PF, typename ET>
+__device__ __forceinline__ void site_fetch(double (&pf)[PF], const ET* __restrict__ g, int cl, int cr, int tid) {
   using SC = SiteCopy<DP, CHIM>;
   static_assert(PF == SC::PF, "register buffer matches the copy geometry");
   const float inv_cl = 1.0f / (float)cl;
@@ -60,11 +59,11 @@ __device__ __forceinline__ void site_fetch(double (&pf)[PF], const double* __res
     const int row = r0 + p * SC::RPP;
     if (row < DP * cl) {
       const int u = fquot(row, inv_cl), al = row - u * cl;
-      const double* src = g + (size_t)(u * CHIM + al) * CHIM;
+      const ET* src = g + (size_t)(u * CHIM + al) * CHIM;
 #pragma unroll
       for (int j = 0; j < SC::CPT; ++j) {
         const int c = c0 + j * SC::TPR;
-        if (c < cr) pf[p * SC::CPT + j] = src[c];
+        if (c < cr) pf[p * SC::CPT + j] = (double)src[c];
       }
     }
   }
@@ -93,8 +92,9 @@ __device__ __forceinline__ void site_commit(double* sA, const double (&pf)[PF], 
 // Dynamic LDS: right environments [2][lx_max+1][CHIM][DP], site tensors
 // [2][DP*CHIM*CHIM] (the one in use and the next one), states [2][ly_max][lx_max].
 // The next site tensor is read from global memory into registers while the
-// current one is used, so each step waits on LDS only.
-template <int DP, int CHIM>
+// current one is used, so each step waits on LDS only.  ET: storage type of
+// the environments (double or float); the walk itself is FP64.
+template <typename ET, int DP, int CHIM>
 __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict__ tasks, uint64_t sweep, int lx_max,
                                                      int ly_max) {
   __shared__ SampleShared<DP, CHIM> sh;
@@ -102,6 +102,7 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
   constexpr int SITE = DP * CHIM * CHIM;
   constexpr int PF = SiteCopy<DP, CHIM>::PF;
   const TaskDesc& t = tasks[blockIdx.x];
+  const ET* __restrict__ env = static_cast<const ET*>(t.env);
   const int tid = threadIdx.x;
   const int path = tid >> 6;             // 0: new layer (drawn), 1: current layer (forced)
   const int lane = tid & 63;
@@ -123,13 +124,13 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
   int buf = 0;
   {
     const int cl = (Lx > 1) ? t.bond[Lx - 2] : 1, cr = t.bond[Lx - 1];
-    site_fetch<DP, CHIM, PF>(pf, t.env + (size_t)(Lx - 1) * SITE, cl, cr, tid);
+    site_fetch<DP, CHIM, PF>(pf, env + (size_t)(Lx - 1) * SITE, cl, cr, tid);
     site_commit<DP, CHIM, PF>(sAb, pf, cl, cr, tid);
   }
   double logq = 0.0;
   int fault = 0;
   for (int y = 0; y < Ly; ++y) {
-    const double* envY = t.env + (size_t)y * Lx * SITE;
+    const ET* envY = env + (size_t)y * Lx * SITE;
     const int* bondY = t.bond + y * Lx;
     // the row's local weights and (drawn path) uniforms, one site per lane
     for (int x = lane; x < Lx; x += 64) {
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
       const int cr = bondY[x];
       // next site tensor: x + 1 of this row, or the last one of the next row
       int ncl = 1, ncr = 1;
-      const double* gn = nullptr;
+      const ET* gn = nullptr;
       if (x + 1 < Lx) {
         ncl = bondY[x];
         ncr = bondY[x + 1];
@@ -352,18 +353,18 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
   }
 }
 
-template <int DP, int CHIM>
+template <typename ET, int DP, int CHIM>
 hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep, hipStream_t s) {
   const size_t bytes = sizeof(double) * (2 * (size_t)(Lx_max + 1) * CHIM * DP + 2 * (size_t)DP * CHIM * CHIM) +
                        2 * (size_t)Lx_max * Ly_max;
   static size_t attr_bytes = 0;
   if (bytes > 48 * 1024 && bytes > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)sample_kernel<DP, CHIM>,
+    hipError_t e = hipFuncSetAttribute((const void*)sample_kernel<ET, DP, CHIM>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
     attr_bytes = bytes;
   }
-  hipLaunchKernelGGL((sample_kernel<DP, CHIM>), dim3(n), dim3(NTS), bytes, s, tasks, sweep, Lx_max, Ly_max);
+  hipLaunchKernelGGL((sample_kernel<ET, DP, CHIM>), dim3(n), dim3(NTS), bytes, s, tasks, sweep, Lx_max, Ly_max);
   return hipGetLastError();
 }
 
@@ -444,24 +445,31 @@ __global__ __launch_bounds__(256) void observables_kernel(const float* const* __
 
 }  // namespace
 
-hipError_t launch_sample(const TaskDesc* tasks, int n, int d, int chi_max, int Lx_max, int Ly_max, uint64_t sweep,
-                         hipStream_t s) {
+template <typename ET>
+hipError_t launch_sample_et(const TaskDesc* tasks, int n, int d, int chi_max, int Lx_max, int Ly_max, uint64_t sweep,
+                            hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (d == 2) {
     switch (chi_max) {
-      case 4: return launch_sample_t<2, 4>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 8: return launch_sample_t<2, 8>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 16: return launch_sample_t<2, 16>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 32: return launch_sample_t<2, 32>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 4: return launch_sample_t<ET, 2, 4>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 8: return launch_sample_t<ET, 2, 8>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 16: return launch_sample_t<ET, 2, 16>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 32: return launch_sample_t<ET, 2, 32>(tasks, n, Lx_max, Ly_max, sweep, s);
     }
   } else if (d == 3) {
     switch (chi_max) {
-      case 4: return launch_sample_t<3, 4>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 8: return launch_sample_t<3, 8>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 16: return launch_sample_t<3, 16>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 4: return launch_sample_t<ET, 3, 4>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 8: return launch_sample_t<ET, 3, 8>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 16: return launch_sample_t<ET, 3, 16>(tasks, n, Lx_max, Ly_max, sweep, s);
     }
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_sample(const TaskDesc* tasks, int n, int d, int chi_max, int precision, int Lx_max, int Ly_max,
+                         uint64_t sweep, hipStream_t s) {
+  if (precision == kPrecF32) return launch_sample_et<float>(tasks, n, d, chi_max, Lx_max, Ly_max, sweep, s);
+  return launch_sample_et<double>(tasks, n, d, chi_max, Lx_max, Ly_max, sweep, s);
 }
 
 hipError_t launch_energy(const float* J, const int8_t* spins, int Lx, int Ly, int Lz, int d, double* out,

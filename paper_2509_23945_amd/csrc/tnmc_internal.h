@@ -8,12 +8,27 @@ namespace tnmc {
 
 constexpr int kCounters = 5;   // per-task counters, see TaskDesc::counters
 
+// Storage precision of the environments (same values as TNMC_FP64 / TNMC_FP32).
+constexpr int kPrecF64 = 0;
+constexpr int kPrecF32 = 1;
+
+// Relative cut-off of the rank-revealing factorisations: directions whose
+// weight is below this fraction of the largest one are dropped.  FP64 storage:
+// such directions are zero at FP64 resolution.  (Gram-Schmidt residuals of
+// dependent rows sit at ~eps sqrt(n), slightly above this, so the right-sweep
+// LQ may keep a few rounding-level directions; its rank is bounded by the left
+// factor's and they are harmless.)  FP32 storage: the stored environments
+// carry relative rounding of 2^-24, so directions below ~1e-7 are rounding
+// noise; the cut sits a decade above it.
+constexpr double kRankTolF64 = 1e-15;
+constexpr double kRankTolF32 = 1e-6;
+
 // One slice task: layer z of one chain.  Everything a kernel needs, with
 // device pointers into the lattice state and into the per-task workspace.
 struct TaskDesc {
   const float* J;          // couplings of the chain's instance [3][Lz][Ly][Lx]
   int8_t* spins;           // chain configuration [Lz][Ly][Lx]
-  double* env;             // environments [Ly][Lx][d][chi_max][chi_max]
+  void* env;               // environments [Ly][Lx][d][chi_max][chi_max], double or float
   double* rscr;            // R factors of the left sweep [Lx][(d chi_max)^2]
   int* bond;               // right bond dimension of every environment site [Ly][Lx]
   int* rrows;              // rows of every R factor [Lx]
@@ -27,6 +42,7 @@ struct TaskDesc {
   double* record;          // if set: {logq_new, logq_old, dE, accepted, fault}
   double* gscr;            // global scratch holding the full contraction tile layout (retry path)
   double beta;
+  double rank_tol;         // kRankTolF64 or kRankTolF32
   uint64_t key0, key1;     // Philox key
   int Lx, Ly, Lz, z, chi, d;
   int chi_max;             // storage stride of the environment tensors
@@ -34,18 +50,21 @@ struct TaskDesc {
   int pad_;
 };
 
-// Per-task workspace sizes (doubles / ints) for a (Lx, Ly, d, chi_max) task.
-inline size_t env_doubles(int Lx, int Ly, int d, int chi_max) {
-  return (size_t)Ly * Lx * d * chi_max * chi_max;
+// Per-task workspace sizes (doubles / ints) for a (Lx, Ly, d, chi_max) task;
+// FP32 environments take half the doubles (rounded up).
+inline size_t env_doubles(int Lx, int Ly, int d, int chi_max, int precision = kPrecF64) {
+  const size_t n = (size_t)Ly * Lx * d * chi_max * chi_max;
+  return precision == kPrecF32 ? (n + 1) / 2 : n;
 }
 inline size_t rscr_doubles(int Lx, int d, int chi_max) {
   return (size_t)Lx * (size_t)(d * chi_max) * (d * chi_max);
 }
 
 // Kernel launchers (return hipError_t of the launch).
-hipError_t launch_contract(const TaskDesc* tasks, int n_tasks, int d, int chi_max, hipStream_t s);
-hipError_t launch_sample(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int Lx_max, int Ly_max,
-                         uint64_t sweep, hipStream_t s);
+hipError_t launch_contract(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int precision, hipStream_t s);
+hipError_t launch_contract_f32(const TaskDesc* tasks, int n_tasks, int d, int chi_max, hipStream_t s);
+hipError_t launch_sample(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int precision, int Lx_max,
+                         int Ly_max, uint64_t sweep, hipStream_t s);
 hipError_t launch_energy(const float* J, const int8_t* spins, int Lx, int Ly, int Lz, int d,
                          double* out, hipStream_t s);
 hipError_t launch_observables(const float* const* Jc, int8_t* const* spins, int n_chains,

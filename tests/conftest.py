@@ -26,3 +26,15 @@ def _single_thread_blas():
         return
     with threadpool_limits(1):
         yield
+
+
+def pytest_collection_finish(session):
+    """torch bundles a HIP runtime of its own beside the one libtnmc links
+    against; in one process, torch's must initialise first or it finds no GPU.
+    GPU sessions therefore touch torch's runtime before any test runs."""
+    if any(item.get_closest_marker("gpu") for item in session.items):
+        try:
+            import torch
+        except ImportError:  # pragma: no cover
+            return
+        torch.cuda.is_available()

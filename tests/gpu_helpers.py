@@ -13,13 +13,20 @@ from oracle import chain as ochain
 
 # log q tolerance on the FP64 path: 1e-10 absolute, relaxed to 1e-10 relative
 # for |log q| > 1 (two independent SVD codes differ in rounding, amplified
-# along ~L^2 conditionals; see DESIGN.md "Parity bar").
+# along ~L^2 conditionals).
 LOGQ_TOL = 1e-10
+# reduced-precision form (FP32 environments): log q within 1e-4 relative of the
+# FP64 oracle's log q of the same configuration
+LOGQ_TOL_REDUCED = 1e-4
 TIE = 1e-9
 
 
 def logq_close(a: float, b: float) -> bool:
     return abs(a - b) <= LOGQ_TOL * max(1.0, abs(a), abs(b))
+
+
+def logq_close_reduced(a: float, b: float) -> bool:
+    return abs(a - b) <= LOGQ_TOL_REDUCED * max(1.0, abs(a), abs(b))
 
 
 def announce(msg: str) -> None:
@@ -28,7 +35,7 @@ def announce(msg: str) -> None:
 
 
 def make_lattice(Lx, Ly, Lz, d, chi, *, kind="pmj", beta=1.0, seed=0, n_chains=1, init="random",
-                 pairs=None, record_capacity=0, philox_seed=12345):
+                 pairs=None, record_capacity=0, philox_seed=12345, precision=tn.TNMC_FP64):
     """Couplings (one instance per chain pair) and initial spins from synth; returns
     (lattice handle, J[n_inst], spins[n_chains], betas)."""
     n_inst = max(1, (n_chains + 1) // 2) if pairs is not None else n_chains
@@ -52,7 +59,7 @@ def make_lattice(Lx, Ly, Lz, d, chi, *, kind="pmj", beta=1.0, seed=0, n_chains=1
     inst = np.array([c // 2 if pairs is not None else c for c in range(n_chains)], dtype=np.int32)
     lat = tn.tnmc_lattice_init(Lx=Lx, Ly=Ly, Lz=Lz, d=d, chi=chi, J=J, beta=betas, spins=spins,
                                chain_instance=inst, seed=philox_seed, pairs=pairs,
-                               record_capacity=record_capacity)
+                               record_capacity=record_capacity, precision=precision)
     return lat, J[inst], spins, betas
 
 

@@ -1,0 +1,84 @@
+"""The reduced-precision form of the contraction against the FP64 oracle.
+
+Environments are stored in FP32 and the rank-revealing factorisations cut at
+FP32 resolution; log q, dE and the MH test stay FP64.  The proposal q is then
+an approximation of the FP64 one, so spins are not expected to match the
+oracle's draws.  What is checked, on the GPU's own proposals:
+
+* log q of the current layer and of the drawn layer within 1e-4 relative of
+  the FP64 oracle's log q of the same configurations (forced evaluation);
+* dE exact (a full-lattice energy difference of the oracle's model);
+* the Markov chain stays exact: with a truncated (chi = 1) proposal on a
+  2x2x4 lattice, chain averages of E and M^2 over independent GPU chains match
+  exact enumeration within statistical error.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import bruteforce as bf
+import gpu_helpers as gh
+import paper_2509_23945_amd as tn
+from oracle import chain as ochain
+from oracle import model
+from test_gpu_parity import CASES
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:3])) + f"-d{c[3]}-{c[4]}-chi{c[6]}-z{c[7]}")
+def test_fp32_logq_of_own_proposals(case):
+    Lx, Ly, Lz, d, kind, beta, chi, z = case
+    gh.announce(f"fp32 propose case {case}")
+    lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, d, chi, kind=kind, beta=beta, seed=3, precision=tn.TNMC_FP32)
+    lq_cur = ochain.slice_logq(J[0], spins[0], z, spins[0][z], beta, chi, d)
+    for sweep in (0, 7):
+        s_new, lq_new, lq_old, dE, st = tn.tnmc_slice_propose(lat, 0, z, sweep)
+        assert st == 0
+        assert gh.logq_close_reduced(lq_old, lq_cur), (lq_old, lq_cur)
+        o_new = ochain.slice_logq(J[0], spins[0], z, s_new, beta, chi, d)
+        assert gh.logq_close_reduced(lq_new, o_new), (lq_new, o_new)
+        after = spins[0].copy()
+        after[z] = s_new
+        assert dE == model.energy(J[0], after, d) - model.energy(J[0], spins[0], d)
+        # the forced evaluation entry point sees the same environments
+        assert abs(tn.tnmc_slice_logq(lat, 0, z, s_new) - lq_new) <= 1e-12 * max(1.0, abs(lq_new))
+
+
+def test_fp32_exact_regime_is_near_boltzmann():
+    """Untruncated 3x3 layer: FP32 log q(s) = -beta E(s) - log Z within 1e-4 relative."""
+    gh.announce("fp32 exact regime 3x3")
+    lat, J, spins, _ = gh.make_lattice(3, 3, 3, 2, 4, kind="gauss", beta=1.1, seed=5, precision=tn.TNMC_FP32)
+    cfgs, E = bf.layer_energies(J[0], spins[0], 1, 2)
+    logz = bf.logsumexp(-1.1 * E)
+    for i in range(0, len(cfgs), 7):
+        layer = model.from_states(np.array(cfgs[i]), 2)
+        g = tn.tnmc_slice_logq(lat, 0, 1, layer)
+        assert gh.logq_close_reduced(g, -1.1 * E[i] - logz)
+
+
+def test_fp32_chain_averages_match_enumeration():
+    """64 independent chains, each on its own 2x2x4 +-J instance, chi = 1
+    (truncated, so proposals are rejected at times): the deviations of each
+    chain's averages of E and M^2 over sweeps 50..399 from its exact
+    enumeration average have mean zero within four standard errors."""
+    gh.announce("fp32 chain averages 2x2x4")
+    Lx, Ly, Lz, beta, n_chains, n_sweeps = 2, 2, 4, 1.0, 64, 400
+    lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, 2, 1, kind="pmj", beta=beta, seed=3, n_chains=n_chains,
+                                       record_capacity=n_sweeps, precision=tn.TNMC_FP32)
+    st = tn.tnmc_sweep([lat], n_sweeps, record=True)
+    assert st["numeric_faults"] == 0 and st["accepted"] < st["proposed"]
+    E, M, _ = tn.tnmc_timeseries(lat)
+    assert E.shape == (n_sweeps, n_chains)
+    devs_E, devs_M2 = [], []
+    for c in range(n_chains):
+        states, En = bf.lattice_states(J[c], Lx, Ly, Lz, 2)
+        w = np.exp(-beta * (En - En.min()))
+        w /= w.sum()
+        Mn = np.sum(1 - 2 * states, axis=(1, 2, 3)) / 16.0
+        devs_E.append(E[50:, c].mean() - float(np.sum(w * En)))
+        devs_M2.append((M[50:, c] ** 2).mean() - float(np.sum(w * Mn * Mn)))
+    for devs in (np.array(devs_E), np.array(devs_M2)):
+        err = devs.std(ddof=1) / math.sqrt(len(devs))
+        assert abs(devs.mean()) < 4 * err + 1e-12, (devs.mean(), err)
