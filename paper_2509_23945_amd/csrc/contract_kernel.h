@@ -39,8 +39,8 @@ constexpr int JACOBI_MAX_SWEEPS = 40;
 // Copies the cl x cr corner of the d site tensors of one environment site
 // (stride CHIM) from global memory (FP64 or FP32) to an FP64 LDS tile, with
 // threads t0, t0 + nt, ...
-template <int DP, int CHIM, typename ET>
-__device__ __forceinline__ void stage_site(double* sA, const ET* gA, int cl, int cr, int t0, int nt) {
+template <int DP, int CHIM, typename GP>
+__device__ __forceinline__ void stage_site(double* sA, GP gA, int cl, int cr, int t0, int nt) {
   const int n2 = cl * cr;
   const float inv2 = 1.0f / (float)n2, inv1 = 1.0f / (float)cr;
   for (int i = t0; i < DP * n2; i += nt) {
@@ -353,7 +353,7 @@ __device__ __forceinline__ double group_sum(double v) {
 template <int MM, int LPC, bool MODE_Q, bool GM = false>
 __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, int ld, int m, int n, int kcap,
                                                              double rel_tol, double* Wc, double* W, double* Wt,
-                                                             double* Out, int ldo, double* Rglob, int gld,
+                                                             double* Out, int ldo, gptr<double> Rglob, int gld,
                                                              double* rmax) {
   constexpr int U = 4;
   constexpr int MR = MM / LPC;
@@ -555,7 +555,7 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
 template <int MMW, bool MODE_Q, bool GM = false>
 __device__ __attribute__((always_inline)) int qr_pivoted_reg(const double* M, int ld, int m, int n, int kcap,
                                                              double rel_tol, double* Wc, double* W, double* Wt,
-                                                             double* Out, int ldo, double* Rglob, int gld,
+                                                             double* Out, int ldo, gptr<double> Rglob, int gld,
                                                              double* rmax) {
   if constexpr (MMW >= 64) {
     if (m > 32) {
@@ -748,6 +748,7 @@ struct Layout {
   static constexpr int oRed = oH + LXMAX * DP * DP;              // 8 reduction slots + 8 scalars
   static constexpr int oNrm = oRed + 16;                         // [D] row norms
   static constexpr int oIdx = oNrm + D;                          // [D] ints stored as doubles
+  static constexpr int oBnd = oIdx + D;                          // [2][LXMAX] ints: bonds of E_y, left ranks
   // largest register-QR windows (rows held per lane): the left QR has up to
   // DP * RCAP rows, the LQ of C^T at most D
   static constexpr int MMW = CMP ? ((DP * RCAP >= 32) ? 64 : ((DP * RCAP > 16) ? 32 : 16))
@@ -757,7 +758,7 @@ struct Layout {
   static constexpr int WCQ = 64 * (MMQ / (CMP ? 2 : 1) + 2);     // compact: the LQ has n <= RCAP <= 32 columns
   // LQ reflectors: at most chi of them are kept (step chi + 1 only detects truncation)
   static constexpr int WQ = CHIM * MMQ;
-  static constexpr int oWork = oIdx + D;
+  static constexpr int oWork = oBnd + LXMAX;
   // left sweep
   static constexpr int MT = (CMP ? D : DP * D) * LD;             // M: up to DP * RCAP rows
   static constexpr int oA1 = oWork;                              // [DP][CHIM][CHIM]
@@ -824,15 +825,16 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
   double* sScal = smem + Lay::oRed + 8;
   double* sNrm = smem + Lay::oNrm;
   int* sIdx = reinterpret_cast<int*>(smem + Lay::oIdx);
+  int* bondY = reinterpret_cast<int*>(smem + Lay::oBnd);   // bond dimensions of E_y, row by row
+  int* sRr = bondY + LXMAX;                                 // rows of each R factor of the row
   const int Lx = t.Lx, Ly = t.Ly, Lz = t.Lz, z = t.z, chi = t.chi;
   const double beta = t.beta;
-  const float* __restrict__ J = t.J;
-  const int8_t* __restrict__ spins = t.spins;
-  ET* __restrict__ env = static_cast<ET*>(t.env);
+  const gptr<const float> J = gmem(t.J);
+  const gptr<const int8_t> spins = gmem(static_cast<const int8_t*>(t.spins));
+  const gptr<ET> env = gmem(static_cast<ET*>(t.env));
   const double rtol = t.rank_tol;   // relative cut-off of the rank-revealing factorisations
-  double* __restrict__ rscr = t.rscr;
-  int* __restrict__ bond = t.bond;
-  int* __restrict__ rrows = t.rrows;
+  const gptr<double> rscr = gmem(t.rscr);
+  const gptr<int> bond = gmem(t.bond);
   const size_t plane = (size_t)Lx * Ly;
   int fault = retry ? ((st0 >> 4) & 7) : 0;
   double flops = 0.0;   // accumulated by thread 0 only
@@ -859,8 +861,8 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
       const double jx = (x > 0) ? (double)J[(size_t)z * plane + (size_t)y * Lx + (x - 1)] : 0.0;
       sH[i] = (x > 0) ? exp(beta * jx * sigma<DP>(r, b)) : 1.0;   // here r plays the role of a
     }
-    const ET* envY = env + (size_t)y * Lx * SITE;
-    const int* bondY = bond + y * Lx;
+    for (int x = tid; x < Lx; x += NTK) bondY[x] = bond[(size_t)y * Lx + x];
+    const gptr<const ET> envY = env + (size_t)y * Lx * SITE;
     __syncthreads();
 
     // ---- left-to-right QR sweep: R_x = R(QR(R_{x-1} B_x)) ----
@@ -923,11 +925,11 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         const int m = rR * DP, n = cr * DP;
         int* sPerm = sIdx;
         int rx;
-        double* gR = rscr + (size_t)x * D * D;
+        const gptr<double> gR = rscr + (size_t)x * D * D;
         const bool in_regs = (m <= Lay::MMW && n <= 64);
         // site tensor of x + 1 (for the right sweep's first step when x + 1 = Lx - 1)
         const int ncl = cr, ncr = bondY[x + 1];
-        const ET* gAn = envY + (size_t)(x + 1) * SITE;
+        const gptr<const ET> gAn = envY + (size_t)(x + 1) * SITE;
         if (in_regs) {
           // R Pi^T straight from registers to sR and gR, already scaled
           if (tid < 64) {
@@ -992,7 +994,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
             gR[(size_t)i * D + oj] = v;
           }
         }
-        if (tid == 0) rrows[x] = rx;
+        if (tid == 0) sRr[x] = rx;
         rR = rx;
         if (!in_regs) __syncthreads();   // the register path's barrier above already orders sR and sA
       }
@@ -1008,8 +1010,8 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
       double* sC = smem + Lay::oC;
       double* sY = sR;     // reused after C is formed
       double* sVt = sZ;    // reused after C is formed
-      ET* envN = env + (size_t)(y - 1) * Lx * SITE;
-      int* bondN = bond + (y - 1) * Lx;
+      const gptr<ET> envN = env + (size_t)(y - 1) * Lx * SITE;
+      const gptr<int> bondN = bond + (y - 1) * Lx;
       double logacc = 0.0;
       int k = 1;           // columns of T_{x+1}
       if (tid == 0) bondN[Lx - 1] = 1;
@@ -1025,10 +1027,10 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         const double* Gx = sG + x * DP * DP;
         const double* Hx = sH + x * DP * DP;
         // R_{x-1} is read from global memory while AT is formed
-        const int rR = (x > 0) ? rrows[x - 1] : 0;
+        const int rR = (x > 0) ? sRr[x - 1] : 0;
         const int nri = rR * cl;
         const float inv_cl = 1.0f / (float)cl;
-        const double* gR = rscr + (size_t)((x > 0) ? x - 1 : 0) * D * D;
+        const gptr<const double> gR = rscr + (size_t)((x > 0) ? x - 1 : 0) * D * D;
         double pr[PR][DP];
 #pragma unroll
         for (int q = 0; q < PR; ++q) {
@@ -1049,7 +1051,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
             const int b = fquot(rem, inv_k), kk = rem - b * k;
             double s;
             if constexpr (CMP) {
-              const ET* Arow = envY + (size_t)x * SITE + (b * CHIM + al) * CHIM;
+              const gptr<const ET> Arow = envY + (size_t)x * SITE + (b * CHIM + al) * CHIM;
               s = last ? (double)Arow[0] : lds_dot<CHIM>(Arow, 1, sT + b * CHIM + kk, DP * CHIM, cr);
             } else {
               const double* Arow = sA + (b * CHIM + al) * CHIM;
@@ -1160,7 +1162,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         int kx = 0;
         bool need_svd = true;
         const int pcl = (x > 1) ? bondY[x - 2] : 1, pcr = bondY[x - 1];
-        const ET* gAp = envY + (size_t)(x - 1) * SITE;
+        const gptr<const ET> gAp = envY + (size_t)(x - 1) * SITE;
         if (lq_try) {
           double* sV = sR;     // V [rank][nC], leading dim LD (R is consumed)
           double* sTau = sT;   // reflector scalars (T_{x+1} is consumed)

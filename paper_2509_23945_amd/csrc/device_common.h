@@ -34,13 +34,25 @@ __device__ inline double philox_uniform(uint64_t c0, uint64_t c1, uint64_t c2, u
 // the integer division sequence in index arithmetic.
 __device__ __forceinline__ int fquot(int w, float inv_n) { return (int)(((float)w + 0.5f) * inv_n); }
 
+// Global-memory view of a pointer.  Accesses through a plain pointer loaded
+// from a task descriptor compile to flat instructions, which count against the
+// LDS counter as well: every later wait for an LDS result then also waits for
+// them, so a prefetch from global memory would not overlap LDS work.  Through
+// this view they are global instructions and count only against vmcnt.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T* p) {
+  return (gptr<T>)p;
+}
+
 // sum_{j < n} a[j*sa] b[j*sb] in FP64 over LDS operands (a may also be a
 // global FP64 or FP32 array), n <= NMAX: the loads are
 // issued eight at a time (indices up to the next multiple of 8 below NMAX must
 // be addressable; their values are discarded) so that one wait covers each
 // group, with two accumulation chains.
-template <int NMAX, typename TA>
-__device__ __forceinline__ double lds_dot(const TA* a, int sa, const double* b, int sb, int n) {
+template <int NMAX, typename AP>
+__device__ __forceinline__ double lds_dot(AP a, int sa, const double* b, int sb, int n) {
   double s0 = 0.0, s1 = 0.0;
   for (int j0 = 0; j0 < n; j0 += 8) {
     double av[8], bv[8];
@@ -248,9 +260,8 @@ __device__ inline double block_max(double v, double* red) {
 }
 
 // Field of the held layers on site (x, y) of layer z for state u (not times beta).
-template <int DP>
-__device__ inline double held_field(const float* __restrict__ J, const int8_t* __restrict__ spins,
-                                    int Lx, int Ly, int Lz, int z, int y, int x, int u) {
+template <int DP, typename JP, typename SP>
+__device__ inline double held_field(JP J, SP spins, int Lx, int Ly, int Lz, int z, int y, int x, int u) {
   const size_t plane = (size_t)Lx * Ly;
   const size_t site = (size_t)y * Lx + x;
   double f = 0.0;

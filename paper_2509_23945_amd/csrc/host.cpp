@@ -151,7 +151,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     gscr_need += tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double);
     env_need += tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision);
     rscr_need += tnmc::rscr_doubles(L->Lx, L->d, L->chi_max);
-    int_need += (size_t)L->Ly * L->Lx + L->Lx + 1;
+    int_need += (size_t)L->Ly * L->Lx + 1;
     dbl_need += (size_t)L->Ly;
   }
   if (grow(g_ws.env, g_ws.env_cap, env_need) != TNMC_OK) return TNMC_ERR_OOM;
@@ -175,8 +175,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.rscr = g_ws.rscr + ro;
     t.gscr = g_ws.gscr + go;
     t.bond = g_ws.ints + io;
-    t.rrows = g_ws.ints + io + (size_t)L->Ly * L->Lx;
-    t.status = g_ws.ints + io + (size_t)L->Ly * L->Lx + L->Lx;
+    t.status = g_ws.ints + io + (size_t)L->Ly * L->Lx;
     t.logscale = g_ws.dbl + dof;
     t.counters = g_ws.counters + tnmc::kCounters * k;
     t.beta = L->beta[tk.chain];
@@ -194,7 +193,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     eo += tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision);
     go += tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double);
     ro += tnmc::rscr_doubles(L->Lx, L->d, L->chi_max);
-    io += (size_t)L->Ly * L->Lx + L->Lx + 1;
+    io += (size_t)L->Ly * L->Lx + 1;
     dof += (size_t)L->Ly;
     if (plan.groups.empty() || plan.groups.back().d != L->d || plan.groups.back().chi_max != L->chi_max ||
         plan.groups.back().key != tk.key || plan.groups.back().precision != L->precision) {

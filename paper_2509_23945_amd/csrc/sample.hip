@@ -32,14 +32,21 @@ struct SampleShared {
   double et[2][LXMAX][DP][DP];        // exp(beta (F(x,u) + Jy sig(u, above)) + beta Jx(x-1) sig(t,u)) [path][x][t][u]
   double uni[LXMAX];                  // the row's uniforms (drawn path)
   double pch[2][LXMAX];               // probability of the state taken at each site of the row
+  int bnd[2][LXMAX];                  // bond dimensions of E_y and E_{y+1}
   double lq[2];
   int fault[2];
 };
 
 // Site tensor x of an environment row (the cl x cr corner of each of its d
-// matrices, row stride CHIM) into registers, then into an LDS tile with the
-// same layout.  Each of the d*cl rows is covered by TPR threads, TPR
+// matrices, row stride CHIM) into registers, then into an LDS tile of rows
+// padded to CHIM + 1 (a wavefront reading one row per lane then spreads over
+// the LDS banks).  Each of the d*cl rows is covered by TPR threads, TPR
 // consecutive columns at a time; one quotient per row and pass.
+template <int CHIM>
+constexpr int site_ld() { return CHIM + 1; }
+template <int DP, int CHIM>
+constexpr int site_lds() { return DP * CHIM * site_ld<CHIM>(); }
+
 template <int DP, int CHIM>
 struct SiteCopy {
   static constexpr int TPR = CHIM < 8 ? CHIM : 8;           // threads per row
@@ -48,8 +55,8 @@ struct SiteCopy {
   static constexpr int PASSES = (DP * CHIM + RPP - 1) / RPP;
   static constexpr int PF = PASSES * CPT;
 };
-template <int DP, int CHIM, int PF, typename ET>
-__device__ __forceinline__ void site_fetch(double (&pf)[PF], const ET* __restrict__ g, int cl, int cr, int tid) {
+template <int DP, int CHIM, int PF, typename GP>
+__device__ __forceinline__ void site_fetch(double (&pf)[PF], GP g, int cl, int cr, int tid) {
   using SC = SiteCopy<DP, CHIM>;
   static_assert(PF == SC::PF, "register buffer matches the copy geometry");
   const float inv_cl = 1.0f / (float)cl;
@@ -59,7 +66,7 @@ __device__ __forceinline__ void site_fetch(double (&pf)[PF], const ET* __restric
     const int row = r0 + p * SC::RPP;
     if (row < DP * cl) {
       const int u = fquot(row, inv_cl), al = row - u * cl;
-      const ET* src = g + (size_t)(u * CHIM + al) * CHIM;
+      const GP src = g + (size_t)(u * CHIM + al) * CHIM;
 #pragma unroll
       for (int j = 0; j < SC::CPT; ++j) {
         const int c = c0 + j * SC::TPR;
@@ -79,7 +86,7 @@ __device__ __forceinline__ void site_commit(double* sA, const double (&pf)[PF], 
     const int row = r0 + p * SC::RPP;
     if (row < DP * cl) {
       const int u = fquot(row, inv_cl), al = row - u * cl;
-      double* dst = sA + (u * CHIM + al) * CHIM;
+      double* dst = sA + (u * CHIM + al) * site_ld<CHIM>();
 #pragma unroll
       for (int j = 0; j < SC::CPT; ++j) {
         const int c = c0 + j * SC::TPR;
@@ -89,8 +96,41 @@ __device__ __forceinline__ void site_commit(double* sA, const double (&pf)[PF], 
   }
 }
 
+// out[u] = sum_{j < n} a[u*AU + j*as] b[u*bu + j*bs] for u < DP (n <= NMAX),
+// LDS operands: the d dot products share one loop whose loads are issued
+// eight indices at a time (indices up to the next multiple of 8 below NMAX
+// must be addressable; their values are discarded).  AU = 0: a is shared.
+template <int DP, int NMAX, int AU>
+__device__ __forceinline__ void dot_n(double (&out)[DP], const double* a, int as, const double* b, int bu, int bs,
+                                      int n) {
+#pragma unroll
+  for (int u = 0; u < DP; ++u) out[u] = 0.0;
+  for (int j0 = 0; j0 < n; j0 += 8) {
+    double av[AU ? DP : 1][8], bv[DP][8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = (j0 + q < NMAX) ? j0 + q : NMAX - 1;
+#pragma unroll
+      for (int u = 0; u < (AU ? DP : 1); ++u) av[u][q] = a[u * AU + j * as];
+#pragma unroll
+      for (int u = 0; u < DP; ++u) bv[u][q] = b[u * bu + j * bs];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (j0 + q < n) {
+#pragma unroll
+        for (int u = 0; u < DP; ++u) out[u] = fma(av[AU ? u : 0][q], bv[u][q], out[u]);
+      }
+    }
+  }
+}
+
+// 1/v for a positive finite v: refined hardware reciprocal, exact division
+// below the normal range.
+__device__ __forceinline__ double recip(double v) { return (v > 1e-300) ? rcp_nr(v) : 1.0 / v; }
+
 // Dynamic LDS: right environments [2][lx_max+1][CHIM][DP], site tensors
-// [2][DP*CHIM*CHIM] (the one in use and the next one), states [2][ly_max][lx_max].
+// [2][DP*CHIM*(CHIM+1)] (the one in use and the next one), states [2][ly_max][lx_max].
 // The next site tensor is read from global memory into registers while the
 // current one is used, so each step waits on LDS only.  ET: storage type of
 // the environments (double or float); the walk itself is FP64.
@@ -99,41 +139,53 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
                                                      int ly_max) {
   __shared__ SampleShared<DP, CHIM> sh;
   extern __shared__ __align__(16) double dyn[];
-  constexpr int SITE = DP * CHIM * CHIM;
+  constexpr int SITE = DP * CHIM * CHIM;        // global layout of a site
+  constexpr int SLD = site_ld<CHIM>();          // LDS row stride of a site tile
+  constexpr int SITEL = site_lds<DP, CHIM>();   // LDS size of a site tile
   constexpr int PF = SiteCopy<DP, CHIM>::PF;
   const TaskDesc& t = tasks[blockIdx.x];
-  const ET* __restrict__ env = static_cast<const ET*>(t.env);
+  const gptr<const ET> env = gmem(static_cast<const ET*>(t.env));
   const int tid = threadIdx.x;
   const int path = tid >> 6;             // 0: new layer (drawn), 1: current layer (forced)
   const int lane = tid & 63;
   const int Lx = t.Lx, Ly = t.Ly, Lz = t.Lz, z = t.z;
   const double beta = t.beta;
-  const float* __restrict__ J = t.J;
-  int8_t* __restrict__ spins = t.spins;
+  const gptr<const float> J = gmem(t.J);
+  const gptr<int8_t> spins = gmem(t.spins);
+  const gptr<const int> bond = gmem(static_cast<const int*>(t.bond));
   const size_t plane = (size_t)Lx * Ly;
-  const int8_t* forced = (path == 1) ? spins + (size_t)z * plane : t.force_new;
+  const gptr<const int8_t> forced = (path == 1) ? gmem(static_cast<const int8_t*>(t.spins + (size_t)z * plane))
+                                                : gmem(t.force_new);
   const int contract_status = *t.status;
   const bool contract_fault = contract_status != 0;
   double* Rp = dyn + (size_t)path * (lx_max + 1) * CHIM * DP;
   double* sAb = dyn + (size_t)2 * (lx_max + 1) * CHIM * DP;
-  int8_t* cfg = reinterpret_cast<int8_t*>(sAb + 2 * SITE);
+  int8_t* cfg = reinterpret_cast<int8_t*>(sAb + 2 * SITEL);
 #define RENV(x, al, u) Rp[((size_t)(x) * CHIM + (al)) * DP + (u)]
 #define CFG(p, y, x) cfg[((size_t)(p) * ly_max + (y)) * lx_max + (x)]
 
   double pf[PF];
   int buf = 0;
   {
-    const int cl = (Lx > 1) ? t.bond[Lx - 2] : 1, cr = t.bond[Lx - 1];
+    const int cl = (Lx > 1) ? bond[Lx - 2] : 1, cr = bond[Lx - 1];
     site_fetch<DP, CHIM, PF>(pf, env + (size_t)(Lx - 1) * SITE, cl, cr, tid);
     site_commit<DP, CHIM, PF>(sAb, pf, cl, cr, tid);
   }
   double logq = 0.0;
   int fault = 0;
   for (int y = 0; y < Ly; ++y) {
-    const ET* envY = env + (size_t)y * Lx * SITE;
-    const int* bondY = t.bond + y * Lx;
-    // the row's local weights and (drawn path) uniforms, one site per lane
+    const gptr<const ET> envY = env + (size_t)y * Lx * SITE;
+    // bond dimensions of this row's and the next row's environments, read once
+    const int* bondY = sh.bnd[y & 1];
+    const int* bondN = sh.bnd[(y + 1) & 1];
+    // the row's local weights and (drawn path) uniforms, one site per lane; a
+    // forced configuration goes to the configuration tile ahead of the walk
     for (int x = lane; x < Lx; x += 64) {
+      if (path == 0) {
+        if (y == 0) sh.bnd[0][x] = bond[x];
+        if (y + 1 < Ly) sh.bnd[(y + 1) & 1][x] = bond[(size_t)(y + 1) * Lx + x];
+      }
+      if (forced) CFG(path, y, x) = (int8_t)state_of<DP>(forced[(size_t)y * Lx + x]);
       const double jy = (y > 0) ? (double)J[plane * Lz + (size_t)z * plane + (size_t)(y - 1) * Lx + x] : 0.0;
       const int above = (y > 0) ? CFG(path, y - 1, x) : 0;
       double ftv[DP];
@@ -161,15 +213,14 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
       const int cr = bondY[x];
       const int ncl = (x > 1) ? bondY[x - 2] : 1, ncr = bondY[x - 1];
       site_fetch<DP, CHIM, PF>(pf, envY + (size_t)(x - 1) * SITE, ncl, ncr, tid);
-      const double* A = sAb + buf * SITE;
+      const double* A = sAb + buf * SITEL;
       double v[DP];
+      // lanes past cl read row cl - 1 (in the tile) and drop the result
+      const int al = (lane < cl) ? lane : cl - 1;
+      dot_n<DP, CHIM, CHIM * SLD>(v, A + al * SLD, 1, &RENV(x + 1, 0, 0), 1, DP, cr);
+      if (lane >= cl) {
 #pragma unroll
-      for (int u = 0; u < DP; ++u) v[u] = 0.0;
-      if (lane < cl) {
-#pragma unroll
-        for (int u = 0; u < DP; ++u) {
-          v[u] = lds_dot<CHIM>(A + (u * CHIM + lane) * CHIM, 1, &RENV(x + 1, 0, u), DP, cr);
-        }
+        for (int u = 0; u < DP; ++u) v[u] = 0.0;
       }
       double rt[DP];
       double mx = 0.0;
@@ -181,13 +232,13 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
         rt[tt] = s;
         mx = fmax(mx, fabs(s));
       }
-      mx = wave_max(mx);
-      const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
+      mx = wave_max_fast(mx);
+      const double inv = (mx > 0.0 && isfinite(mx)) ? recip(mx) : 1.0;
       if (lane < CHIM) {
 #pragma unroll
         for (int tt = 0; tt < DP; ++tt) RENV(x, lane, tt) = rt[tt] * inv;
       }
-      site_commit<DP, CHIM, PF>(sAb + (buf ^ 1) * SITE, pf, ncl, ncr, tid);
+      site_commit<DP, CHIM, PF>(sAb + (buf ^ 1) * SITEL, pf, ncl, ncr, tid);
       buf ^= 1;
       __syncthreads();
     }
@@ -201,33 +252,28 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
       const int cr = bondY[x];
       // next site tensor: x + 1 of this row, or the last one of the next row
       int ncl = 1, ncr = 1;
-      const ET* gn = nullptr;
+      gptr<const ET> gn = nullptr;
       if (x + 1 < Lx) {
         ncl = bondY[x];
         ncr = bondY[x + 1];
         gn = envY + (size_t)(x + 1) * SITE;
       } else if (y + 1 < Ly) {
-        ncl = (Lx > 1) ? bondY[Lx + Lx - 2] : 1;
-        ncr = bondY[Lx + Lx - 1];
+        ncl = (Lx > 1) ? bondN[Lx - 2] : 1;
+        ncr = bondN[Lx - 1];
         gn = envY + (size_t)(Lx + Lx - 1) * SITE;
       }
       if (gn) site_fetch<DP, CHIM, PF>(pf, gn, ncl, ncr, tid);
-      const double* A = sAb + buf * SITE;
+      const double* A = sAb + buf * SITEL;
       const double* l = sh.l[path][lb];
       double m[DP];
       double part[DP];
+      // lanes past cr read column cr - 1 (in the tile) and drop the result
+      const int be = (lane < cr) ? lane : cr - 1;
+      dot_n<DP, CHIM, 0>(m, l, 1, A + be, CHIM * SLD, SLD, cl);
 #pragma unroll
       for (int u = 0; u < DP; ++u) {
-        m[u] = 0.0;
-        part[u] = 0.0;
-      }
-      if (lane < cr) {
-#pragma unroll
-        for (int u = 0; u < DP; ++u) {
-          const double s = lds_dot<CHIM>(l, 1, A + u * CHIM * CHIM + lane, CHIM, cl);
-          m[u] = s;
-          part[u] = s * RENV(x + 1, lane, u);
-        }
+        if (lane >= cr) m[u] = 0.0;
+        part[u] = m[u] * RENV(x + 1, be, u);
       }
       wave_sum_n<DP>(part);
       double w[DP];
@@ -246,20 +292,20 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
 #pragma unroll
         for (int u = 0; u < DP; ++u) p[u] = 1.0 / DP;
       } else {
-        const double iw = 1.0 / wsum;
+        const double iw = recip(wsum);
         double ps = 0.0;
 #pragma unroll
         for (int u = 0; u < DP; ++u) {
           p[u] = fmax(w[u] * iw, P_FLOOR);
           ps += p[u];
         }
-        const double ip = 1.0 / ps;
+        const double ip = recip(ps);
 #pragma unroll
         for (int u = 0; u < DP; ++u) p[u] *= ip;
       }
       int s;
-      if (forced != nullptr) {
-        s = state_of<DP>(forced[(size_t)y * Lx + x]);
+      if (forced) {
+        s = CFG(path, y, x);
       } else {
         const double U = sh.uni[x];
         s = DP - 1;
@@ -273,23 +319,32 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
           }
         }
       }
-      double lv = 0.0, pchosen = p[0];
+      double lv = 0.0, pchosen = p[0], ws = 0.0;
 #pragma unroll
       for (int u = 0; u < DP; ++u)
         if (u == s) {
           lv = m[u];
           pchosen = p[u];
+          ws = part[u];
         }
       if (lane == 0) {
         sh.pch[path][x] = pchosen;
         CFG(path, y, x) = (int8_t)s;
       }
-      const double lm = wave_max(fabs(lv));
-      if (!(lm > 0.0) || !isfinite(lm)) fault |= 2;
-      const double inv = (lm > 0.0 && isfinite(lm)) ? 1.0 / lm : 1.0;
+      // the next left vector is l A_x[s] scaled so that its contraction with
+      // R_{x+1}(.; s) is 1; where that contraction is not a safe scale (zero,
+      // negative or extreme) the largest entry is scaled to 1 instead
+      double inv;
+      if (ws > 1e-150 && ws < 1e150) {
+        inv = rcp_nr(ws);
+      } else {
+        const double lm = wave_max_fast(fabs(lv));
+        if (!(lm > 0.0) || !isfinite(lm)) fault |= 2;
+        inv = (lm > 0.0 && isfinite(lm)) ? recip(lm) : 1.0;
+      }
       if (lane < CHIM) sh.l[path][lb ^ 1][lane] = (lane < cr) ? lv * inv : 0.0;
       if (gn) {
-        site_commit<DP, CHIM, PF>(sAb + (buf ^ 1) * SITE, pf, ncl, ncr, tid);
+        site_commit<DP, CHIM, PF>(sAb + (buf ^ 1) * SITEL, pf, ncl, ncr, tid);
         buf ^= 1;
       }
       lb ^= 1;
@@ -355,7 +410,7 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
 
 template <typename ET, int DP, int CHIM>
 hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep, hipStream_t s) {
-  const size_t bytes = sizeof(double) * (2 * (size_t)(Lx_max + 1) * CHIM * DP + 2 * (size_t)DP * CHIM * CHIM) +
+  const size_t bytes = sizeof(double) * (2 * (size_t)(Lx_max + 1) * CHIM * DP + 2 * (size_t)site_lds<DP, CHIM>()) +
                        2 * (size_t)Lx_max * Ly_max;
   static size_t attr_bytes = 0;
   if (bytes > 48 * 1024 && bytes > attr_bytes) {

@@ -31,7 +31,6 @@ struct TaskDesc {
   void* env;               // environments [Ly][Lx][d][chi_max][chi_max], double or float
   double* rscr;            // R factors of the left sweep [Lx][(d chi_max)^2]
   int* bond;               // right bond dimension of every environment site [Ly][Lx]
-  int* rrows;              // rows of every R factor [Lx]
   double* logscale;        // log of the removed scale of every environment [Ly]
   int* status;             // contraction fault bits of this task (0 = ok); a compact launch that leaves the
                            // task unfinished writes 8 | fault bits << 4 | row to resume at << 8
