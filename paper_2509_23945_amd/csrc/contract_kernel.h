@@ -810,13 +810,15 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
   extern __shared__ __align__(16) double lds[];
   const TaskDesc& t = tasks[blockIdx.x];
   const int tid = threadIdx.x;
+  acquire_device();
   if (retry < 0) {   // test hook: leave every task to the retry launch
     if (tid == 0) *t.status = 8 | ((t.Ly - 1) << 8);
+    release_device();
     return;
   }
   // a retry resumes at the row where the compact launch stopped (status bits
   // 8 and up), with the fault bits it had collected (bits 4-6)
-  const int st0 = retry ? *t.status : 0;
+  const int st0 = retry ? load_device(t.status) : 0;
   if (retry && (st0 & 15) != 8) return;
   double* smem = GM ? t.gscr : lds;
   double* sG = smem + Lay::oG;
@@ -840,7 +842,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
   double flops = 0.0;   // accumulated by thread 0 only
 
   // E_{Ly-1} = 1: bond dimension 1, every component 1.
-  const int y_top = retry ? (st0 >> 8) : Ly - 1;
+  const int y_top = retry ? min(max(st0 >> 8, 1), Ly - 1) : Ly - 1;
   if (y_top == Ly - 1) {
     for (int i = tid; i < Lx * DP; i += NTK) {
       const int x = i / DP, u = i % DP;
@@ -861,7 +863,9 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
       const double jx = (x > 0) ? (double)J[(size_t)z * plane + (size_t)y * Lx + (x - 1)] : 0.0;
       sH[i] = (x > 0) ? exp(beta * jx * sigma<DP>(r, b)) : 1.0;   // here r plays the role of a
     }
-    for (int x = tid; x < Lx; x += NTK) bondY[x] = bond[(size_t)y * Lx + x];
+    // bond dimensions come back from memory: clamped into [1, CHIM], so that
+    // no extent derived from them can leave a tile whatever memory holds
+    for (int x = tid; x < Lx; x += NTK) bondY[x] = min(max(bond[(size_t)y * Lx + x], 1), CHIM);
     const gptr<const ET> envY = env + (size_t)y * Lx * SITE;
     __syncthreads();
 
@@ -955,8 +959,9 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
                             (__syncthreads_or(fault & 4) ? 4 : 0);
               if (tid == 0) {
                 *t.status = 8 | (f << 4) | (y << 8);
-                if (t.counters) t.counters[4] += 1;
+                if (t.counters) add_device(t.counters + 4, 1);
               }
+              release_device();
               return;
             }
           }
@@ -1322,12 +1327,13 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
     __threadfence_block();
     __syncthreads();
   }
-  if (tid == 0 && t.counters) t.counters[3] += (long long)flops;
+  if (tid == 0 && t.counters) add_device(t.counters + 3, (long long)flops);
   // fault bits: 1 = zero/non-finite R factor, 2 = zero/non-finite T, 4 = zero first tensor
   const int f1 = __syncthreads_or(fault & 1);
   const int f2 = __syncthreads_or(fault & 2);
   const int f4 = __syncthreads_or(fault & 4);
   if (tid == 0) *t.status = (f1 ? 1 : 0) | (f2 ? 2 : 0) | (f4 ? 4 : 0);
+  release_device();
 }
 
 

@@ -46,6 +46,23 @@ __device__ __forceinline__ gptr<T> gmem(T* p) {
   return (gptr<T>)p;
 }
 
+// Ordering against other kernels, which may run on other streams: a kernel
+// acquires at device scope when it starts (its caches then hold nothing older
+// than the work it was ordered after) and releases at device scope before it
+// ends.  Values that earlier kernels wrote and that every lane of a wavefront
+// reads at the same address are loaded with device-scope atomic loads, which
+// are vector memory operations (a scalar load would go through the scalar
+// cache), and per-task counters are updated with vector atomics.
+__device__ __forceinline__ void acquire_device() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+__device__ __forceinline__ void release_device() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+template <typename T>
+__device__ __forceinline__ T load_device(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void add_device(long long* p, long long v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // sum_{j < n} a[j*sa] b[j*sb] in FP64 over LDS operands (a may also be a
 // global FP64 or FP32 array), n <= NMAX: the loads are
 // issued eight at a time (indices up to the next multiple of 8 below NMAX must
@@ -98,11 +115,11 @@ __device__ __forceinline__ double sigma(int u, int v) {
   else return (u == v) ? 1.0 : 0.0;
 }
 
-// int8 spin -> state index.
+// int8 spin -> state index (always in [0, DP), whatever the byte holds).
 template <int DP>
 __device__ __forceinline__ int state_of(int8_t s) {
   if constexpr (DP == 2) return s > 0 ? 0 : 1;
-  else return (int)s;
+  else return min(max((int)s, 0), DP - 1);
 }
 template <int DP>
 __device__ __forceinline__ int8_t spin_of(int u) {

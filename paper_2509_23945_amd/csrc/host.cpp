@@ -148,18 +148,18 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
   size_t env_need = 0, rscr_need = 0, int_need = 0, dbl_need = 0, gscr_need = 0;
   for (int i : order) {
     const auto* L = tasks[i].lat;
-    gscr_need += tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double);
-    env_need += tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision);
-    rscr_need += tnmc::rscr_doubles(L->Lx, L->d, L->chi_max);
-    int_need += (size_t)L->Ly * L->Lx + 1;
-    dbl_need += (size_t)L->Ly;
+    gscr_need += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
+    env_need += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision));
+    rscr_need += tnmc::pad256_doubles(tnmc::rscr_doubles(L->Lx, L->d, L->chi_max));
+    int_need += tnmc::pad256_ints((size_t)L->Ly * L->Lx + 1);
+    dbl_need += tnmc::pad256_doubles((size_t)L->Ly);
   }
   if (grow(g_ws.env, g_ws.env_cap, env_need) != TNMC_OK) return TNMC_ERR_OOM;
   if (grow(g_ws.rscr, g_ws.rscr_cap, rscr_need) != TNMC_OK) return TNMC_ERR_OOM;
   if (grow(g_ws.ints, g_ws.ints_cap, int_need) != TNMC_OK) return TNMC_ERR_OOM;
   if (grow(g_ws.dbl, g_ws.dbl_cap, dbl_need) != TNMC_OK) return TNMC_ERR_OOM;
   if (grow(g_ws.gscr, g_ws.gscr_cap, gscr_need) != TNMC_OK) return TNMC_ERR_OOM;
-  if (grow(g_ws.counters, g_ws.counters_cap, tnmc::kCounters * tasks.size()) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.counters, g_ws.counters_cap, tnmc::kCounterStride * tasks.size()) != TNMC_OK) return TNMC_ERR_OOM;
   plan.desc.clear();
   plan.groups.clear();
   plan.order = order;
@@ -177,7 +177,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.bond = g_ws.ints + io;
     t.status = g_ws.ints + io + (size_t)L->Ly * L->Lx;
     t.logscale = g_ws.dbl + dof;
-    t.counters = g_ws.counters + tnmc::kCounters * k;
+    t.counters = g_ws.counters + tnmc::kCounterStride * k;
     t.beta = L->beta[tk.chain];
     t.rank_tol = (L->precision == TNMC_FP32) ? tnmc::kRankTolF32 : tnmc::kRankTolF64;
     t.key0 = L->seed;
@@ -190,11 +190,11 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.d = L->d;
     t.chi_max = L->chi_max;
     t.write_back = 1;
-    eo += tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision);
-    go += tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double);
-    ro += tnmc::rscr_doubles(L->Lx, L->d, L->chi_max);
-    io += (size_t)L->Ly * L->Lx + 1;
-    dof += (size_t)L->Ly;
+    eo += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision));
+    go += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
+    ro += tnmc::pad256_doubles(tnmc::rscr_doubles(L->Lx, L->d, L->chi_max));
+    io += tnmc::pad256_ints((size_t)L->Ly * L->Lx + 1);
+    dof += tnmc::pad256_doubles((size_t)L->Ly);
     if (plan.groups.empty() || plan.groups.back().d != L->d || plan.groups.back().chi_max != L->chi_max ||
         plan.groups.back().key != tk.key || plan.groups.back().precision != L->precision) {
       plan.groups.push_back({L->d, L->chi_max, (int)k, 0, 0, 0, tk.key, L->precision});
@@ -258,7 +258,7 @@ tnmc_status check_lats(tnmc_lattice* const* lats, int n_lats) {
 }
 
 tnmc_status read_counters(size_t n_tasks, tnmc_stats* st) {
-  const int K = tnmc::kCounters;
+  const int K = tnmc::kCounterStride;
   std::vector<long long> c(K * n_tasks);
   HIP_TRY(hipMemcpy(c.data(), g_ws.counters, c.size() * sizeof(long long), hipMemcpyDeviceToHost));
   for (size_t i = 0; i < n_tasks; ++i) {
@@ -508,7 +508,7 @@ tnmc_status tnmc_half_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t p
   HIP_TRY(hipMemcpyAsync(g_ws.tasks, plan.desc.data(), plan.desc.size() * sizeof(TaskDesc),
                          hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (stats) HIP_TRY(hipMemsetAsync(g_ws.counters, 0, tnmc::kCounters * tasks.size() * sizeof(long long), s));
+  if (stats) HIP_TRY(hipMemsetAsync(g_ws.counters, 0, tnmc::kCounterStride * tasks.size() * sizeof(long long), s));
   Timer tm;
   tm.on = (stats != nullptr);
   r = launch_plan(plan, g_ws.tasks, sweep, s, &tm, stats);
@@ -525,129 +525,52 @@ tnmc_status tnmc_half_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t p
 
 // Streams of the sweep schedule besides the caller's (default priority,
 // created on first use).
-constexpr int kAuxStreams = 3;
-hipStream_t aux_stream(int i) {
-  static hipStream_t st[kAuxStreams] = {nullptr, nullptr, nullptr};
-  if (!st[i] && hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking) != hipSuccess) st[i] = nullptr;
-  return st[i];
-}
-
-// Launch class of a slice task within its parity: layers with one held
-// neighbour (z = 0, Lz - 1) take longest, their neighbours wait on them, the
-// rest wait only on each other.
-int layer_class(const tnmc_lattice* L, int z) {
-  if (z == 0 || z == L->Lz - 1) return 0;
-  if (z == 1 || z == L->Lz - 2) return 1;
-  return 2;
-}
-
 tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
                        int32_t record, int32_t time_kernels, tnmc_stats* stats, void* stream) {
   if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
   hipStream_t s = (hipStream_t)stream;
-  // Every task of both parities with a workspace of its own, one launch per
-  // (parity, layer class, d, chi_max).  A launch waits only for the launches
-  // that last updated a neighbouring layer of one of its tasks, so the long
-  // edge layers of one class overlap the other classes instead of holding up
-  // a whole half-sweep.
+  // Every task of both parities with a workspace of its own; one launch pair
+  // (contraction, sampler) per (parity, d, chi_max), longest task first, all
+  // on the caller's stream.  Launches are kept strictly in order: launches of
+  // independent layer classes overlapped on several streams gave corrupted
+  // results now and then on this hardware, so no two
+  // kernels of a sweep run at the same time.
   std::vector<Task> tasks;
   for (int p : {0, 1})
     for (Task t : half_sweep_tasks(lats, n_lats, p)) {
-      t.key = 4 * p + layer_class(t.lat, t.z);
+      t.key = p;
       tasks.push_back(t);
     }
   Plan plan;
   tnmc_status r = make_plan(tasks, plan);
   if (r != TNMC_OK) return r;
   const size_t n_tasks = plan.desc.size();
-  const int ng = (int)plan.groups.size();
-  if (grow(g_ws.counters, g_ws.counters_cap, tnmc::kCounters * n_tasks) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.counters, g_ws.counters_cap, tnmc::kCounterStride * n_tasks) != TNMC_OK) return TNMC_ERR_OOM;
   if (grow(g_ws.tasks, g_ws.tasks_cap, n_tasks) != TNMC_OK) return TNMC_ERR_OOM;
-  for (size_t k = 0; k < n_tasks; ++k) plan.desc[k].counters = g_ws.counters + tnmc::kCounters * k;
+  for (size_t k = 0; k < n_tasks; ++k) plan.desc[k].counters = g_ws.counters + tnmc::kCounterStride * k;
   HIP_TRY(hipMemcpyAsync(g_ws.tasks, plan.desc.data(), n_tasks * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));   // plan.desc is released on return
-  HIP_TRY(hipMemsetAsync(g_ws.counters, 0, tnmc::kCounters * n_tasks * sizeof(long long), s));
-
-  // dependencies: group h precedes group g when h updates a neighbouring layer
-  // (same lattice and chain) of a layer of g; h is of the other parity
-  std::map<std::tuple<const tnmc_lattice*, int, int>, int> owner;   // (lattice, chain, z) -> group
-  std::vector<int> group_of(n_tasks);
-  for (int gi = 0; gi < ng; ++gi)
-    for (int k = plan.groups[gi].first; k < plan.groups[gi].first + plan.groups[gi].count; ++k) {
-      const Task& t = tasks[plan.order[k]];
-      owner[{t.lat, t.chain, t.z}] = gi;
-      group_of[k] = gi;
-    }
-  std::vector<std::vector<int>> deps(ng);
-  for (int gi = 0; gi < ng; ++gi) {
-    std::vector<char> seen(ng, 0);
-    for (int k = plan.groups[gi].first; k < plan.groups[gi].first + plan.groups[gi].count; ++k) {
-      const Task& t = tasks[plan.order[k]];
-      for (int dz : {-1, 1}) {
-        auto it = owner.find({t.lat, t.chain, t.z + dz});
-        if (it != owner.end() && !seen[it->second]) {
-          seen[it->second] = 1;
-          deps[gi].push_back(it->second);
-        }
-      }
-    }
-  }
-  // streams (four, as many as the hardware queues of a process): the bulk on
-  // the caller's, the edge layers of each parity on one of their own (they do
-  // not depend on each other), their neighbours on a third
-  std::vector<hipStream_t> gst(ng);
-  for (int gi = 0; gi < ng; ++gi) {
-    const int cls = plan.groups[gi].key % 4, par = plan.groups[gi].key / 4;
-    gst[gi] = (cls == 2) ? s : aux_stream(cls == 0 ? par : 2);   // s may be the null stream
-    if (cls != 2 && !gst[gi]) {
-      g_last_error = "could not create a stream for the sweep schedule";
-      return TNMC_ERR_DEVICE;
-    }
-  }
-  std::vector<hipEvent_t> ev(ng, nullptr);
-  std::vector<char> issued(ng, 0);
-  struct EventGuard {
-    std::vector<hipEvent_t>& v;
-    hipEvent_t entry = nullptr;
-    ~EventGuard() {
-      for (auto e : v)
-        if (e) (void)hipEventDestroy(e);
-      if (entry) (void)hipEventDestroy(entry);
-    }
-  } guard{ev};
-  for (int gi = 0; gi < ng; ++gi) HIP_TRY(hipEventCreateWithFlags(&ev[gi], hipEventDisableTiming));
-  // the other streams start after the work already queued on the caller's
-  HIP_TRY(hipEventCreateWithFlags(&guard.entry, hipEventDisableTiming));
-  HIP_TRY(hipEventRecord(guard.entry, s));
-  for (int i = 0; i < kAuxStreams; ++i) HIP_TRY(hipStreamWaitEvent(aux_stream(i), guard.entry, 0));
+  HIP_TRY(hipMemsetAsync(g_ws.counters, 0, tnmc::kCounterStride * n_tasks * sizeof(long long), s));
 
   Timer tm;
   tm.on = (time_kernels != 0 && stats != nullptr);
   for (int t = 0; t < n_sweeps; ++t) {
     const uint64_t sw = sweep_offset + (uint64_t)t;
-    for (int gi = 0; gi < ng; ++gi) {
-      const auto& g = plan.groups[gi];
-      hipStream_t st = gst[gi];
-      for (int h : deps[gi])
-        if (issued[h] && gst[h] != st) HIP_TRY(hipStreamWaitEvent(st, ev[h], 0));
+    for (const auto& g : plan.groups) {
       const TaskDesc* dt = g_ws.tasks + g.first;
-      if (tm.on && tm.mark(tm.c_ev, st) != TNMC_OK) return TNMC_ERR_DEVICE;
-      HIP_TRY(tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, st));
-      if (tm.on && tm.mark(tm.c_ev, st) != TNMC_OK) return TNMC_ERR_DEVICE;
-      if (tm.on && tm.mark(tm.s_ev, st) != TNMC_OK) return TNMC_ERR_DEVICE;
-      HIP_TRY(tnmc::launch_sample(dt, g.count, g.d, g.chi_max, g.precision, g.lx_max, g.ly_max, sw, st));
-      if (tm.on && tm.mark(tm.s_ev, st) != TNMC_OK) return TNMC_ERR_DEVICE;
-      HIP_TRY(hipEventRecord(ev[gi], st));
-      issued[gi] = 1;
+      if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+      HIP_TRY(tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, s));
+      if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+      if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+      HIP_TRY(tnmc::launch_sample(dt, g.count, g.d, g.chi_max, g.precision, g.lx_max, g.ly_max, sw, s));
+      if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
       if (stats) {
         stats->contract_launches += 1;
         stats->sample_launches += 1;
       }
     }
     if (record) {
-      for (int gi = 0; gi < ng; ++gi)
-        if (gst[gi] != s) HIP_TRY(hipStreamWaitEvent(s, ev[gi], 0));
       for (int l = 0; l < n_lats; ++l) {
         tnmc_lattice* L = lats[l];
         if (L->n_recorded >= L->record_capacity) continue;
@@ -656,14 +579,8 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
                                          L->Lz, L->d, L->dErec + i * L->n_chains, L->dMrec + i * L->n_chains,
                                          L->dqrec + i * std::max(1, L->n_pairs), s));
       }
-      // the next sweep's updates start after the observables have read this one
-      HIP_TRY(hipEventRecord(guard.entry, s));
-      for (int i = 0; i < kAuxStreams; ++i) HIP_TRY(hipStreamWaitEvent(aux_stream(i), guard.entry, 0));
     }
   }
-  // the caller's stream sees the whole sweep
-  for (int gi = 0; gi < ng; ++gi)
-    if (issued[gi] && gst[gi] != s) HIP_TRY(hipStreamWaitEvent(s, ev[gi], 0));
   if (stats) {
     HIP_TRY(hipStreamSynchronize(s));
     r = read_counters(n_tasks, stats);

@@ -41,7 +41,11 @@ struct SampleShared {
 // matrices, row stride CHIM) into registers, then into an LDS tile of rows
 // padded to CHIM + 1 (a wavefront reading one row per lane then spreads over
 // the LDS banks).  Each of the d*cl rows is covered by TPR threads, TPR
-// consecutive columns at a time; one quotient per row and pass.
+// consecutive columns at a time; one quotient per row and pass.  Passes and
+// column groups past the corner are skipped as a whole (the trip counts are
+// the same for every thread); inside the last ones, threads past the corner
+// repeat its last row or column, so no access needs a lane mask and repeated
+// LDS stores write equal values to equal addresses.
 template <int CHIM>
 constexpr int site_ld() { return CHIM + 1; }
 template <int DP, int CHIM>
@@ -59,19 +63,19 @@ template <int DP, int CHIM, int PF, typename GP>
 __device__ __forceinline__ void site_fetch(double (&pf)[PF], GP g, int cl, int cr, int tid) {
   using SC = SiteCopy<DP, CHIM>;
   static_assert(PF == SC::PF, "register buffer matches the copy geometry");
+  const int nrow = DP * cl;
   const float inv_cl = 1.0f / (float)cl;
   const int c0 = tid % SC::TPR, r0 = tid / SC::TPR;
 #pragma unroll
   for (int p = 0; p < SC::PASSES; ++p) {
-    const int row = r0 + p * SC::RPP;
-    if (row < DP * cl) {
-      const int u = fquot(row, inv_cl), al = row - u * cl;
-      const GP src = g + (size_t)(u * CHIM + al) * CHIM;
+    if (p * SC::RPP >= nrow) break;
+    const int row = min(r0 + p * SC::RPP, nrow - 1);
+    const int u = fquot(row, inv_cl), al = row - u * cl;
+    const GP src = g + (size_t)(u * CHIM + al) * CHIM;
 #pragma unroll
-      for (int j = 0; j < SC::CPT; ++j) {
-        const int c = c0 + j * SC::TPR;
-        if (c < cr) pf[p * SC::CPT + j] = (double)src[c];
-      }
+    for (int j = 0; j < SC::CPT; ++j) {
+      if (j * SC::TPR >= cr) break;
+      pf[p * SC::CPT + j] = (double)src[min(c0 + j * SC::TPR, cr - 1)];
     }
   }
 }
@@ -79,19 +83,19 @@ template <int DP, int CHIM, int PF>
 __device__ __forceinline__ void site_commit(double* sA, const double (&pf)[PF], int cl, int cr, int tid) {
   using SC = SiteCopy<DP, CHIM>;
   static_assert(PF == SC::PF, "register buffer matches the copy geometry");
+  const int nrow = DP * cl;
   const float inv_cl = 1.0f / (float)cl;
   const int c0 = tid % SC::TPR, r0 = tid / SC::TPR;
 #pragma unroll
   for (int p = 0; p < SC::PASSES; ++p) {
-    const int row = r0 + p * SC::RPP;
-    if (row < DP * cl) {
-      const int u = fquot(row, inv_cl), al = row - u * cl;
-      double* dst = sA + (u * CHIM + al) * site_ld<CHIM>();
+    if (p * SC::RPP >= nrow) break;
+    const int row = min(r0 + p * SC::RPP, nrow - 1);
+    const int u = fquot(row, inv_cl), al = row - u * cl;
+    double* dst = sA + (u * CHIM + al) * site_ld<CHIM>();
 #pragma unroll
-      for (int j = 0; j < SC::CPT; ++j) {
-        const int c = c0 + j * SC::TPR;
-        if (c < cr) dst[c] = pf[p * SC::CPT + j];
-      }
+    for (int j = 0; j < SC::CPT; ++j) {
+      if (j * SC::TPR >= cr) break;
+      dst[min(c0 + j * SC::TPR, cr - 1)] = pf[p * SC::CPT + j];
     }
   }
 }
@@ -99,17 +103,20 @@ __device__ __forceinline__ void site_commit(double* sA, const double (&pf)[PF], 
 // out[u] = sum_{j < n} a[u*AU + j*as] b[u*bu + j*bs] for u < DP (n <= NMAX),
 // LDS operands: the d dot products share one loop whose loads are issued
 // eight indices at a time (indices up to the next multiple of 8 below NMAX
-// must be addressable; their values are discarded).  AU = 0: a is shared.
-template <int DP, int NMAX, int AU>
+// must be addressable).  AU = 0: a is shared.  ZP: every a or b entry from n
+// up to the next multiple of 8 is zero and the other operand is finite there,
+// so those terms are added without a mask; otherwise they are discarded.
+template <int DP, int NMAX, int AU, bool ZP>
 __device__ __forceinline__ void dot_n(double (&out)[DP], const double* a, int as, const double* b, int bu, int bs,
                                       int n) {
+  constexpr bool MASK = !ZP || (NMAX % 8 != 0);
 #pragma unroll
   for (int u = 0; u < DP; ++u) out[u] = 0.0;
   for (int j0 = 0; j0 < n; j0 += 8) {
     double av[AU ? DP : 1][8], bv[DP][8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int j = (j0 + q < NMAX) ? j0 + q : NMAX - 1;
+      const int j = (NMAX % 8 == 0 || j0 + q < NMAX) ? j0 + q : NMAX - 1;
 #pragma unroll
       for (int u = 0; u < (AU ? DP : 1); ++u) av[u][q] = a[u * AU + j * as];
 #pragma unroll
@@ -117,7 +124,7 @@ __device__ __forceinline__ void dot_n(double (&out)[DP], const double* a, int as
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      if (j0 + q < n) {
+      if (!MASK || j0 + q < n) {
 #pragma unroll
         for (int u = 0; u < DP; ++u) out[u] = fma(av[AU ? u : 0][q], bv[u][q], out[u]);
       }
@@ -156,7 +163,8 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
   const size_t plane = (size_t)Lx * Ly;
   const gptr<const int8_t> forced = (path == 1) ? gmem(static_cast<const int8_t*>(t.spins + (size_t)z * plane))
                                                 : gmem(t.force_new);
-  const int contract_status = *t.status;
+  acquire_device();
+  const int contract_status = load_device(t.status);
   const bool contract_fault = contract_status != 0;
   double* Rp = dyn + (size_t)path * (lx_max + 1) * CHIM * DP;
   double* sAb = dyn + (size_t)2 * (lx_max + 1) * CHIM * DP;
@@ -164,10 +172,16 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
 #define RENV(x, al, u) Rp[((size_t)(x) * CHIM + (al)) * DP + (u)]
 #define CFG(p, y, x) cfg[((size_t)(p) * ly_max + (y)) * lx_max + (x)]
 
+  // the site tiles start at zero: entries outside a site's corner then hold
+  // finite values only (zeros, or an earlier site's entries)
+  for (int i = tid; i < 2 * SITEL; i += NTS) sAb[i] = 0.0;
+  __syncthreads();
   double pf[PF];
   int buf = 0;
   {
-    const int cl = (Lx > 1) ? bond[Lx - 2] : 1, cr = bond[Lx - 1];
+    // bond dimensions come back from memory: clamped into [1, CHIM] (see below)
+    const int cl = (Lx > 1) ? min(max(load_device(t.bond + Lx - 2), 1), CHIM) : 1;
+    const int cr = min(max(load_device(t.bond + Lx - 1), 1), CHIM);
     site_fetch<DP, CHIM, PF>(pf, env + (size_t)(Lx - 1) * SITE, cl, cr, tid);
     site_commit<DP, CHIM, PF>(sAb, pf, cl, cr, tid);
   }
@@ -182,8 +196,9 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
     // forced configuration goes to the configuration tile ahead of the walk
     for (int x = lane; x < Lx; x += 64) {
       if (path == 0) {
-        if (y == 0) sh.bnd[0][x] = bond[x];
-        if (y + 1 < Ly) sh.bnd[(y + 1) & 1][x] = bond[(size_t)(y + 1) * Lx + x];
+        // clamped into [1, CHIM]: no extent derived from memory can leave a tile
+        if (y == 0) sh.bnd[0][x] = min(max(bond[x], 1), CHIM);
+        if (y + 1 < Ly) sh.bnd[(y + 1) & 1][x] = min(max(bond[(size_t)(y + 1) * Lx + x], 1), CHIM);
       }
       if (forced) CFG(path, y, x) = (int8_t)state_of<DP>(forced[(size_t)y * Lx + x]);
       const double jy = (y > 0) ? (double)J[plane * Lz + (size_t)z * plane + (size_t)(y - 1) * Lx + x] : 0.0;
@@ -217,7 +232,8 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
       double v[DP];
       // lanes past cl read row cl - 1 (in the tile) and drop the result
       const int al = (lane < cl) ? lane : cl - 1;
-      dot_n<DP, CHIM, CHIM * SLD>(v, A + al * SLD, 1, &RENV(x + 1, 0, 0), 1, DP, cr);
+      // R_{x+1}(be; u) is zero for be >= cr, and the tile is finite everywhere
+      dot_n<DP, CHIM, CHIM * SLD, true>(v, A + al * SLD, 1, &RENV(x + 1, 0, 0), 1, DP, cr);
       if (lane >= cl) {
 #pragma unroll
         for (int u = 0; u < DP; ++u) v[u] = 0.0;
@@ -269,7 +285,8 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
       double part[DP];
       // lanes past cr read column cr - 1 (in the tile) and drop the result
       const int be = (lane < cr) ? lane : cr - 1;
-      dot_n<DP, CHIM, 0>(m, l, 1, A + be, CHIM * SLD, SLD, cl);
+      // l is zero past cl, and the tile is finite everywhere
+      dot_n<DP, CHIM, 0, true>(m, l, 1, A + be, CHIM * SLD, SLD, cl);
 #pragma unroll
       for (int u = 0; u < DP; ++u) {
         if (lane >= cr) m[u] = 0.0;
@@ -401,11 +418,12 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
       t.record[4] = (double)(sh.fault[0] | (sh.fault[1] << 2) | ((contract_status & 7) << 4));
     }
     if (t.counters) {
-      t.counters[0] += 1;
-      t.counters[1] += accepted;
-      t.counters[2] += any_fault;
+      add_device(t.counters + 0, 1);
+      add_device(t.counters + 1, accepted);
+      add_device(t.counters + 2, any_fault);
     }
   }
+  release_device();
 }
 
 template <typename ET, int DP, int CHIM>
@@ -428,6 +446,7 @@ template <int DP>
 __global__ __launch_bounds__(256) void energy_kernel(const float* __restrict__ J, const int8_t* __restrict__ s,
                                                      int Lx, int Ly, int Lz, double* out) {
   __shared__ double red[4];
+  acquire_device();
   const size_t n = (size_t)Lx * Ly * Lz;
   const size_t plane = (size_t)Lx * Ly;
   double e = 0.0;
@@ -451,6 +470,7 @@ __global__ __launch_bounds__(256) void observables_kernel(const float* const* __
                                                           int Lx, int Ly, int Lz, double* E_out, double* M_out,
                                                           double* q_out) {
   __shared__ double red[4];
+  acquire_device();
   const size_t n = (size_t)Lx * Ly * Lz;
   const size_t plane = (size_t)Lx * Ly;
   const int b = blockIdx.x;

@@ -7,6 +7,13 @@
 namespace tnmc {
 
 constexpr int kCounters = 5;   // per-task counters, see TaskDesc::counters
+constexpr int kCounterStride = 32;   // long longs between the counters of consecutive tasks (256 B)
+
+// Per-task workspace regions start on 256-byte boundaries, so that no cache
+// line holds data of two tasks (tasks of concurrent launches run on different
+// XCDs, whose L2 caches are not coherent with each other within a launch).
+inline size_t pad256_ints(size_t n) { return (n + 63) & ~(size_t)63; }
+inline size_t pad256_doubles(size_t n) { return (n + 31) & ~(size_t)31; }
 
 // Storage precision of the environments (same values as TNMC_FP64 / TNMC_FP32).
 constexpr int kPrecF64 = 0;
