@@ -734,6 +734,61 @@ __device__ inline double svd_count(double m, double n) {
 // the right sweep reads site tensors from global memory, and C (needed only
 // when truncating) lives in T's tile.  A task whose left rank exceeds RCAP
 // stops and is redone with the full layout.
+// C[i][r*k + k'] = sum_b G[r][b] sum_al R~[i][al*d+b] AT[al][b][k'] with
+// R~[i][al*d+b] = sum_a R[i][al*d+a] H[a][b], for i < rR (rows of R, row
+// stride LD) and k' < k: written transposed to Ct (leading dimension CTLD)
+// when to_ct, and as C (leading dimension LDC) when to_c.
+template <int DP, int CHIM, int NTK, int LD, int CTLD, int LDC>
+__device__ __attribute__((always_inline)) void form_c(const double* sR, const double* sAT, const double* Hx,
+                                                      const double* Gx, double* sCt, double* sC, int rR, int k,
+                                                      int cl, int tid, bool to_ct, bool to_c) {
+  const float inv_k = 1.0f / (float)k;
+  for (int w = tid; w < rR * k; w += NTK) {
+    const int i = fquot(w, inv_k), kk = w - i * k;
+    double z[DP];
+#pragma unroll
+    for (int b = 0; b < DP; ++b) z[b] = 0.0;
+    double hm[DP][DP];
+#pragma unroll
+    for (int a = 0; a < DP; ++a)
+#pragma unroll
+      for (int b = 0; b < DP; ++b) hm[a][b] = Hx[a * DP + b];
+    const double* Ri = sR + i * LD;
+    for (int al0 = 0; al0 < cl; al0 += 4) {
+      // four values of al per group, loads first (indices clamped into the tiles)
+      double rv[4][DP], atv[4][DP];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int al = (al0 + q < CHIM) ? al0 + q : CHIM - 1;
+#pragma unroll
+        for (int a = 0; a < DP; ++a) rv[q][a] = Ri[al * DP + a];
+#pragma unroll
+        for (int b = 0; b < DP; ++b) atv[q][b] = sAT[(al * DP + b) * CHIM + kk];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (al0 + q < cl) {
+#pragma unroll
+          for (int b = 0; b < DP; ++b) {
+            double rt = 0.0;
+#pragma unroll
+            for (int a = 0; a < DP; ++a) rt = fma(rv[q][a], hm[a][b], rt);
+            z[b] = fma(rt, atv[q][b], z[b]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < DP; ++r) {
+      double c = 0.0;
+#pragma unroll
+      for (int b = 0; b < DP; ++b) c = fma(Gx[r * DP + b], z[b], c);
+      if (to_ct) sCt[(r * k + kk) * CTLD + i] = c;
+      if (to_c) sC[i * LDC + r * k + kk] = c;
+    }
+  }
+}
+
 template <int DP, int CHIM, bool CMP = false>
 struct Layout {
   static constexpr int NTH = CMP ? 128 : 256;   // threads per workgroup
@@ -1107,54 +1162,9 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         constexpr int CTLD = Lay::CTLD, LDC = Lay::LDC;
         // C[i][r*k + k'] = sum_b G[r][b] sum_al R~[i][al*d+b] AT[al][b][k'],
         // R~[i][al*d+b] = sum_a R[i][al*d+a] H[a][b]; stored transposed for
-        // the LQ, and as C too when the LQ may not take the register path
-        {
-          const float inv_k = 1.0f / (float)k;
-          for (int w = tid; w < rR * k; w += NTK) {
-            const int i = fquot(w, inv_k), kk = w - i * k;
-            double z[DP];
-#pragma unroll
-            for (int b = 0; b < DP; ++b) z[b] = 0.0;
-            double hm[DP][DP];
-#pragma unroll
-            for (int a = 0; a < DP; ++a)
-#pragma unroll
-              for (int b = 0; b < DP; ++b) hm[a][b] = Hx[a * DP + b];
-            const double* Ri = sR + i * LD;
-            for (int al0 = 0; al0 < cl; al0 += 4) {
-              // four values of al per group, loads first (indices clamped into the tiles)
-              double rv[4][DP], atv[4][DP];
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const int al = (al0 + q < CHIM) ? al0 + q : CHIM - 1;
-#pragma unroll
-                for (int a = 0; a < DP; ++a) rv[q][a] = Ri[al * DP + a];
-#pragma unroll
-                for (int b = 0; b < DP; ++b) atv[q][b] = sAT[(al * DP + b) * CHIM + kk];
-              }
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                if (al0 + q < cl) {
-#pragma unroll
-                  for (int b = 0; b < DP; ++b) {
-                    double rt = 0.0;
-#pragma unroll
-                    for (int a = 0; a < DP; ++a) rt = fma(rv[q][a], hm[a][b], rt);
-                    z[b] = fma(rt, atv[q][b], z[b]);
-                  }
-                }
-              }
-            }
-#pragma unroll
-            for (int r = 0; r < DP; ++r) {
-              double c = 0.0;
-#pragma unroll
-              for (int b = 0; b < DP; ++b) c = fma(Gx[r * DP + b], z[b], c);
-              sCt[(r * k + kk) * CTLD + i] = c;
-              if (!lq_reg) sC[i * LDC + r * k + kk] = c;
-            }
-          }
-        }
+        // the LQ (to_ct), and as C (to_c) when the LQ may not take the
+        // register path
+        form_c<DP, CHIM, NTK, LD, Lay::CTLD, Lay::LDC>(sR, sAT, Hx, Gx, sCt, sC, rR, k, cl, tid, true, !lq_reg);
         __syncthreads();
         // right singular vectors of C.  When the rank of C does not exceed chi
         // nothing is truncated and any orthonormal basis of its row space is
@@ -1199,10 +1209,18 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
             }
             if (tid == 0) flops += qr_count(nC, rR, rk) + 4.0 * nC * rk * rk;
           } else if (lq_reg) {
-            // truncation: the SVD needs C itself
-            for (int w = tid; w < nC * rR; w += NTK) {
-              const int c = w / rR, i = w % rR;
-              sC[i * LDC + c] = sCt[c * CTLD + i];
+            // truncation: the SVD needs C itself.  The register LQ's column
+            // exchange overlaid C in the full layout (C^T is intact and is
+            // transposed back) but C^T in the compact one, where C is formed
+            // again: R_{x-1} and AT are intact (Q is not formed when the LQ
+            // stops at chi + 1 steps)
+            if constexpr (CMP) {
+              form_c<DP, CHIM, NTK, LD, Lay::CTLD, Lay::LDC>(sR, sAT, Hx, Gx, sCt, sC, rR, k, cl, tid, false, true);
+            } else {
+              for (int w = tid; w < nC * rR; w += NTK) {
+                const int c = w / rR, i = w % rR;
+                sC[i * LDC + c] = sCt[c * CTLD + i];
+              }
             }
           }
           __syncthreads();
@@ -1239,6 +1257,9 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
           for (int i = tid; i < mrows; i += NTK) {
             double s = 0.0;
             for (int c = 0; c < nC; ++c) s += sC[i * LDC + c] * sC[i * LDC + c];
+            // a non-finite row ranks as a zero one (the ranking below is then
+            // a permutation whatever the values; T then carries the fault)
+            if (!isfinite(s)) s = 0.0;
             sNrm[i] = s;
             nmax = fmax(nmax, s);
           }
@@ -1267,7 +1288,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         const float inv_k = 1.0f / (float)k, inv_kx = 1.0f / (float)kx, inv_dkx = 1.0f / (float)(DP * kx);
         for (int w = tid; w < kx * k; w += NTK) {
           const int rho = fquot(w, inv_k), kk = w - rho * k;
-          const int i = sIdx[rho];
+          const int i = min(max(sIdx[rho], 0), D - 1);
           const double nr = sqrt(sNrm[i]);
           const double inv = (nr > 0.0) ? 1.0 / nr : 0.0;
           double v[DP];

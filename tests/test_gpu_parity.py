@@ -33,6 +33,8 @@ CASES = [
     (6, 5, 3, 3, "ferro", 0.55, 4, 1),     # Potts, truncated
     (16, 16, 16, 2, "pmj", 1.0, 32, 5),    # 16^3 layer at chi=32
     (32, 32, 3, 2, "pmj", 1.0, 32, 1),     # 32x32 layer at chi=32 (largest shape)
+    (16, 16, 3, 2, "pmj", 1.0, 20, 1),     # compact layout, truncating (rank > chi)
+    (7, 6, 3, 3, "ferro", 0.55, 10, 1),    # Potts, compact layout, truncating
 ]
 
 
