@@ -846,6 +846,7 @@ struct Layout {
   static constexpr int total = (end1 > end2) ? end1 : end2;
   static_assert(oWcL % 2 == 0 && oWcR % 2 == 0 && oWq % 2 == 0, "16-byte aligned register-QR buffers");
   static_assert(!CMP || RCAP * D <= D * CHIM, "compact: C fits T's tile");
+  static_assert(!CMP || 2 * RCAP <= D, "compact: the LDS LQ's reflector scalars fit the norm buffer");
 };
 
 // retry = 1: only tasks that a compact launch left unfinished (status 8) run;
@@ -1180,7 +1181,10 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         const gptr<const ET> gAp = envY + (size_t)(x - 1) * SITE;
         if (lq_try) {
           double* sV = sR;     // V [rank][nC], leading dim LD (R is consumed)
-          double* sTau = sT;   // reflector scalars (T_{x+1} is consumed)
+          // reflector scalars of the LDS LQ: T_{x+1} is consumed, but in the
+          // compact layout T's tile holds C, which a truncation still needs;
+          // there the norm buffer takes them (2 min(nC, rR) <= 2 RCAP <= D)
+          double* sTau = CMP ? sNrm : sT;
           if (tid < 64) {
             int rk;
             double* sWc = smem + Lay::oWcR;

@@ -35,6 +35,7 @@ CASES = [
     (32, 32, 3, 2, "pmj", 1.0, 32, 1),     # 32x32 layer at chi=32 (largest shape)
     (16, 16, 3, 2, "pmj", 1.0, 20, 1),     # compact layout, truncating (rank > chi)
     (7, 6, 3, 3, "ferro", 0.55, 10, 1),    # Potts, compact layout, truncating
+    (8, 6, 3, 3, "ferro", 0.55, 14, 1),    # Potts, compact, truncating after an LQ of more than 32 rows
 ]
 
 
