@@ -47,7 +47,7 @@ PHILOX_SEED = 20250928
 # (scaled by a plain copy of known size); valid only for the kernel sources it was
 # taken on, identified by their hash
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_kernel_ea32_hbm.md")
-KERNEL_SOURCES = ["contract.hip", "device_common.h", "tnmc_internal.h"]
+KERNEL_SOURCES = ["contract_kernel.h", "contract.hip", "device_common.h", "tnmc_internal.h"]
 
 
 def kernel_source_hash() -> str:
