@@ -9,8 +9,9 @@ int g_force_retry = 0;
 
 void set_force_retry(int on) { g_force_retry = on; }
 
-// LDS bytes of the full tile layout (the per-task global scratch of the retry
-// path holds the same layout); independent of the environment storage type.
+// Bytes of the full tile layout: the LDS of a full-layout workgroup, and the
+// per-task global scratch of the retry path (and of d = 3, chi = 32, whose
+// tiles always live there); independent of the environment storage type.
 size_t contract_lds_bytes(int d, int chi_max) {
   if (d == 2) {
     switch (chi_max) {
@@ -24,6 +25,7 @@ size_t contract_lds_bytes(int d, int chi_max) {
       case 4: return sizeof(double) * Layout<3, 4>::total;
       case 8: return sizeof(double) * Layout<3, 8>::total;
       case 16: return sizeof(double) * Layout<3, 16>::total;
+      case 32: return sizeof(double) * Layout<3, 32>::total;
     }
   }
   return 0;

@@ -1379,12 +1379,18 @@ hipError_t launch_contract_k(const TaskDesc* tasks, int n, int retry, hipStream_
 
 // Two workgroups per CU need at most half of the 160 KB of LDS each.
 constexpr size_t kHalfLds = 80 * 1024;
+constexpr size_t kCuLds = 160 * 1024;
 
 template <typename ET, int DP, int CHIM>
 hipError_t launch_contract_t(const TaskDesc* tasks, int n, hipStream_t s) {
   constexpr bool use_compact = sizeof(double) * Layout<DP, CHIM, false>::total > kHalfLds &&
                                sizeof(double) * Layout<DP, CHIM, true>::total <= kHalfLds;
-  if constexpr (use_compact) {
+  constexpr bool use_global = !use_compact && sizeof(double) * Layout<DP, CHIM, false>::total > kCuLds;
+  if constexpr (use_global) {
+    // the full tile layout exceeds a CU's LDS (d = 3, chi = 32): every tile
+    // in the task's global scratch
+    return launch_contract_k<ET, DP, CHIM, false, true>(tasks, n, 0, s);
+  } else if constexpr (use_compact) {
     // every task in the compact layout (two per CU), then the few whose left
     // rank outgrew it with the full layout held in global memory (no LDS, so
     // the launch is not held back by other work resident on the CUs)
@@ -1412,6 +1418,7 @@ hipError_t launch_contract_et(const TaskDesc* tasks, int n, int d, int chi_max, 
       case 4: return launch_contract_t<ET, 3, 4>(tasks, n, s);
       case 8: return launch_contract_t<ET, 3, 8>(tasks, n, s);
       case 16: return launch_contract_t<ET, 3, 16>(tasks, n, s);
+      case 32: return launch_contract_t<ET, 3, 32>(tasks, n, s);
     }
   }
   return hipErrorInvalidValue;

@@ -366,6 +366,8 @@ tnmc_status tnmc_lattice_init(const tnmc_lattice_desc* ds, tnmc_lattice** out) {
   if (ds->precision != TNMC_FP64 && ds->precision != TNMC_FP32) return TNMC_ERR_UNSUPPORTED;
   const int cm = tnmc::chi_bucket(ds->chi);
   if (cm == 0 || !tnmc::contract_supported(ds->d, cm)) return TNMC_ERR_UNSUPPORTED;
+  // the sampler keeps a row of right environments and two site tiles in LDS
+  if (tnmc::sample_lds_bytes(ds->d, cm, ds->Lx, ds->Ly) > 160 * 1024) return TNMC_ERR_UNSUPPORTED;
   for (int c = 0; c < ds->n_chains; ++c) {
     const int inst = ds->chain_instance ? ds->chain_instance[c] : c % ds->n_instances;
     if (inst < 0 || inst >= ds->n_instances) return TNMC_ERR_ARG;

@@ -426,10 +426,16 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
   release_device();
 }
 
+// Dynamic LDS of a sampler workgroup for layers of at most Lx_max x Ly_max sites.
+template <int DP, int CHIM>
+size_t sample_dyn_bytes(int Lx_max, int Ly_max) {
+  return sizeof(double) * (2 * (size_t)(Lx_max + 1) * CHIM * DP + 2 * (size_t)site_lds<DP, CHIM>()) +
+         2 * (size_t)Lx_max * Ly_max;
+}
+
 template <typename ET, int DP, int CHIM>
 hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep, hipStream_t s) {
-  const size_t bytes = sizeof(double) * (2 * (size_t)(Lx_max + 1) * CHIM * DP + 2 * (size_t)site_lds<DP, CHIM>()) +
-                       2 * (size_t)Lx_max * Ly_max;
+  const size_t bytes = sample_dyn_bytes<DP, CHIM>(Lx_max, Ly_max);
   static size_t attr_bytes = 0;
   if (bytes > 48 * 1024 && bytes > attr_bytes) {
     hipError_t e = hipFuncSetAttribute((const void*)sample_kernel<ET, DP, CHIM>,
@@ -536,9 +542,29 @@ hipError_t launch_sample_et(const TaskDesc* tasks, int n, int d, int chi_max, in
       case 4: return launch_sample_t<ET, 3, 4>(tasks, n, Lx_max, Ly_max, sweep, s);
       case 8: return launch_sample_t<ET, 3, 8>(tasks, n, Lx_max, Ly_max, sweep, s);
       case 16: return launch_sample_t<ET, 3, 16>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 32: return launch_sample_t<ET, 3, 32>(tasks, n, Lx_max, Ly_max, sweep, s);
     }
   }
   return hipErrorInvalidValue;
+}
+
+size_t sample_lds_bytes(int d, int chi_max, int Lx, int Ly) {
+  if (d == 2) {
+    switch (chi_max) {
+      case 4: return sizeof(SampleShared<2, 4>) + sample_dyn_bytes<2, 4>(Lx, Ly);
+      case 8: return sizeof(SampleShared<2, 8>) + sample_dyn_bytes<2, 8>(Lx, Ly);
+      case 16: return sizeof(SampleShared<2, 16>) + sample_dyn_bytes<2, 16>(Lx, Ly);
+      case 32: return sizeof(SampleShared<2, 32>) + sample_dyn_bytes<2, 32>(Lx, Ly);
+    }
+  } else if (d == 3) {
+    switch (chi_max) {
+      case 4: return sizeof(SampleShared<3, 4>) + sample_dyn_bytes<3, 4>(Lx, Ly);
+      case 8: return sizeof(SampleShared<3, 8>) + sample_dyn_bytes<3, 8>(Lx, Ly);
+      case 16: return sizeof(SampleShared<3, 16>) + sample_dyn_bytes<3, 16>(Lx, Ly);
+      case 32: return sizeof(SampleShared<3, 32>) + sample_dyn_bytes<3, 32>(Lx, Ly);
+    }
+  }
+  return 0;
 }
 
 hipError_t launch_sample(const TaskDesc* tasks, int n, int d, int chi_max, int precision, int Lx_max, int Ly_max,

@@ -79,6 +79,7 @@ hipError_t launch_observables(const float* const* Jc, int8_t* const* spins, int 
                               hipStream_t s);
 bool contract_supported(int d, int chi_max);
 size_t contract_lds_bytes(int d, int chi_max);
+size_t sample_lds_bytes(int d, int chi_max, int Lx, int Ly);   // static + dynamic LDS of a sampler workgroup
 void set_force_retry(int on);   // test hook: every compact-layout task takes the retry path
 int chi_bucket(int chi);   // storage chi_max used for a requested chi (0 if unsupported)
 

@@ -36,6 +36,8 @@ CASES = [
     (16, 16, 3, 2, "pmj", 1.0, 20, 1),     # compact layout, truncating (rank > chi)
     (7, 6, 3, 3, "ferro", 0.55, 10, 1),    # Potts, compact layout, truncating
     (8, 6, 3, 3, "ferro", 0.55, 14, 1),    # Potts, compact, truncating after an LQ of more than 32 rows
+    (5, 4, 3, 3, "ferro", 0.55, 20, 1),    # Potts, chi_max = 32 (every tile in global memory), exact
+    (7, 7, 3, 3, "ferro", 0.55, 24, 1),    # Potts, chi_max = 32, truncating
 ]
 
 
@@ -53,7 +55,7 @@ def test_propose_matches_oracle(case):
 
 
 # cases whose configuration uses the compact two-per-CU contraction layout
-COMPACT_CASES = [c for c in CASES if (c[3] == 2 and c[6] > 16) or (c[3] == 3 and c[6] > 8)]
+COMPACT_CASES = [c for c in CASES if (c[3] == 2 and c[6] > 16) or (c[3] == 3 and 8 < c[6] <= 16)]
 
 
 @pytest.mark.parametrize("case", COMPACT_CASES, ids=lambda c: "x".join(map(str, c[:3])) + f"-d{c[3]}-chi{c[6]}")
@@ -187,6 +189,11 @@ def test_invalid_calls_are_rejected():
         assert ei.value.status == tn.api.TNMC_ERR_ARG
     with pytest.raises(tn.TnmcError):
         tn.tnmc_slice_logq(lat, 0, 0, np.zeros((4, 4), np.int8))
+    # chi above 32, and Potts chi = 32 rows too long for the sampler's LDS, are not built
+    for (L, d, chi) in ((8, 2, 40), (64, 3, 32)):
+        with pytest.raises(tn.TnmcError) as ei:
+            gh.make_lattice(L, 2, 2, d, chi, kind="ferro", seed=1)
+        assert ei.value.status == tn.api.TNMC_ERR_UNSUPPORTED
 
 
 def test_heterogeneous_batch_like_c3():
