@@ -190,9 +190,9 @@ def test_invalid_calls_are_rejected():
     with pytest.raises(tn.TnmcError):
         tn.tnmc_slice_logq(lat, 0, 0, np.zeros((4, 4), np.int8))
     # chi above 32, and Potts chi = 32 rows too long for the sampler's LDS, are not built
-    for (L, d, chi) in ((8, 2, 40), (64, 3, 32)):
+    for (Lx, Ly, d, chi) in ((8, 2, 2, 40), (64, 64, 3, 32)):
         with pytest.raises(tn.TnmcError) as ei:
-            gh.make_lattice(L, 2, 2, d, chi, kind="ferro", seed=1)
+            gh.make_lattice(Lx, Ly, 2, d, chi, kind="ferro", seed=1)
         assert ei.value.status == tn.api.TNMC_ERR_UNSUPPORTED
 
 
