@@ -52,8 +52,8 @@ __device__ __forceinline__ void stage_site(double* sA, GP gA, int cl, int cr, in
 }
 
 // Orders the tile accesses of one wavefront (lanes of a wavefront run in lock
-// step).  GM: the tiles are in global memory (the retry path of the compact
-// layout), which needs workgroup-scope ordering.
+// step).  GM: the tiles are in global memory (layouts larger than a CU's
+// LDS), which needs workgroup-scope ordering.
 template <bool GM = false>
 __device__ __forceinline__ void wave_sync() {
   if constexpr (GM) {
@@ -851,8 +851,8 @@ struct Layout {
 
 // retry = 1: only tasks that a compact launch left unfinished (status 8) run;
 // retry = -1: every task is left unfinished (test hook).
-// GM: the tiles live in the task's global scratch instead of LDS (the retry
-// launch then needs no LDS and starts on any CU at once; overflows are rare).
+// GM: the tiles live in the task's global scratch instead of LDS (for the
+// full layouts that exceed a CU's LDS).
 // ET: storage type of the environments (double, or float for the
 // reduced-precision form); all arithmetic is FP64.
 template <typename ET, int DP, int CHIM, bool CMP, bool GM = false>
@@ -1392,11 +1392,12 @@ hipError_t launch_contract_t(const TaskDesc* tasks, int n, hipStream_t s) {
     return launch_contract_k<ET, DP, CHIM, false, true>(tasks, n, 0, s);
   } else if constexpr (use_compact) {
     // every task in the compact layout (two per CU), then the few whose left
-    // rank outgrew it with the full layout held in global memory (no LDS, so
-    // the launch is not held back by other work resident on the CUs)
+    // rank outgrew it, from the row where they stopped, with the full layout
+    // in LDS (one per CU; the launch starts once the compact one has ended, so
+    // the whole chip is free for them)
     hipError_t e = launch_contract_k<ET, DP, CHIM, true>(tasks, n, g_force_retry ? -1 : 0, s);
     if (e != hipSuccess) return e;
-    return launch_contract_k<ET, DP, CHIM, false, true>(tasks, n, 1, s);
+    return launch_contract_k<ET, DP, CHIM, false>(tasks, n, 1, s);
   } else {
     return launch_contract_k<ET, DP, CHIM, false>(tasks, n, 0, s);
   }
