@@ -33,6 +33,10 @@ size_t contract_lds_bytes(int d, int chi_max) {
 
 bool contract_supported(int d, int chi_max) { return contract_lds_bytes(d, chi_max) != 0; }
 
+// Whether the (d, chi_max) contraction keeps its tiles in per-task global
+// scratch (its full layout exceeds a CU's LDS).
+bool contract_uses_global(int d, int chi_max) { return contract_lds_bytes(d, chi_max) > kCuLds; }
+
 int chi_bucket(int chi) {
   if (chi <= 4) return 4;
   if (chi <= 8) return 8;

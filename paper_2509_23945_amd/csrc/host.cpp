@@ -148,7 +148,8 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
   size_t env_need = 0, rscr_need = 0, int_need = 0, dbl_need = 0, gscr_need = 0;
   for (int i : order) {
     const auto* L = tasks[i].lat;
-    gscr_need += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
+    if (tnmc::contract_uses_global(L->d, L->chi_max))
+      gscr_need += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
     env_need += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision));
     rscr_need += tnmc::pad256_doubles(tnmc::rscr_doubles(L->Lx, L->d, L->chi_max));
     int_need += tnmc::pad256_ints((size_t)L->Ly * L->Lx + 1);
@@ -173,7 +174,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.spins = L->spins_of(tk.chain);
     t.env = g_ws.env + eo;
     t.rscr = g_ws.rscr + ro;
-    t.gscr = g_ws.gscr + go;
+    t.gscr = tnmc::contract_uses_global(L->d, L->chi_max) ? g_ws.gscr + go : nullptr;
     t.bond = g_ws.ints + io;
     t.status = g_ws.ints + io + (size_t)L->Ly * L->Lx;
     t.logscale = g_ws.dbl + dof;
@@ -191,7 +192,8 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.chi_max = L->chi_max;
     t.write_back = 1;
     eo += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision));
-    go += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
+    if (tnmc::contract_uses_global(L->d, L->chi_max))
+      go += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
     ro += tnmc::pad256_doubles(tnmc::rscr_doubles(L->Lx, L->d, L->chi_max));
     io += tnmc::pad256_ints((size_t)L->Ly * L->Lx + 1);
     dof += tnmc::pad256_doubles((size_t)L->Ly);

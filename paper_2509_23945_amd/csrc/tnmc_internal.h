@@ -46,7 +46,7 @@ struct TaskDesc {
   const int8_t* force_new; // if set: evaluate this layer instead of sampling [Ly][Lx]
   int8_t* s_new_out;       // if set: copy of the proposed layer [Ly][Lx]
   double* record;          // if set: {logq_new, logq_old, dE, accepted, fault}
-  double* gscr;            // global scratch holding the full contraction tile layout (retry path)
+  double* gscr;            // global scratch for the full contraction tile layout, where it exceeds a CU's LDS
   double beta;
   double rank_tol;         // kRankTolF64 or kRankTolF32
   uint64_t key0, key1;     // Philox key
@@ -78,6 +78,7 @@ hipError_t launch_observables(const float* const* Jc, int8_t* const* spins, int 
                               int Lz, int d, double* E_out, double* M_out, double* q_out,
                               hipStream_t s);
 bool contract_supported(int d, int chi_max);
+bool contract_uses_global(int d, int chi_max);   // tiles in the per-task global scratch (gscr)
 size_t contract_lds_bytes(int d, int chi_max);
 size_t sample_lds_bytes(int d, int chi_max, int Lx, int Ly);   // static + dynamic LDS of a sampler workgroup
 void set_force_retry(int on);   // test hook: every compact-layout task takes the retry path
