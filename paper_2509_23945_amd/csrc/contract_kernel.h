@@ -550,18 +550,23 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
 }
 
 // Register QR for an m x n tile with m <= MMW and n <= 64: the window is the
-// smallest of 16, 32, 64 rows that holds m, and a column gets 4, 2 or 1 lanes
-// as n allows.
+// smallest of 16, 32, 48, 64 rows that holds m, and a column gets 4, 2 or 1
+// lanes as n allows.
 template <int MMW, bool MODE_Q, bool GM = false>
 __device__ __attribute__((always_inline)) int qr_pivoted_reg(const double* M, int ld, int m, int n, int kcap,
                                                              double rel_tol, double* Wc, double* W, double* Wt,
                                                              double* Out, int ldo, gptr<double> Rglob, int gld,
                                                              double* rmax) {
   if constexpr (MMW >= 64) {
-    if (m > 32) {
+    if (m > 48) {
       if (n <= 16) return qr_pivoted_lpc<64, 4, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
       if (n <= 32) return qr_pivoted_lpc<64, 2, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
       return qr_pivoted_lpc<64, 1, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+    }
+    if (m > 32) {
+      if (n <= 16) return qr_pivoted_lpc<48, 4, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      if (n <= 32) return qr_pivoted_lpc<48, 2, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      return qr_pivoted_lpc<48, 1, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
     }
   }
   if constexpr (MMW >= 32) {
