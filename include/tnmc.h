@@ -161,10 +161,11 @@ tnmc_status tnmc_flop_model(int32_t Lx, int32_t Ly, int32_t d, int32_t chi, doub
 tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes);
 
 /* Test hook: what = 0 sends every slice task of the configurations that use
- * the compact two-per-CU contraction layout through its overflow path (the
- * full tile layout held in global memory), so that path can be checked
- * against the oracle; value 1 = on, 0 = off (default).  Results are the same
- * either way.  Returns TNMC_ERR_ARG for an unknown what. */
+ * the compact two-per-CU contraction layout through its overflow path (a
+ * second launch with the full tile layout in LDS, one task per CU), so that
+ * path can be checked against the oracle; value 1 = on, 0 = off (default).
+ * Results are the same either way.  Process-wide, not per handle.  Returns
+ * TNMC_ERR_ARG for an unknown what. */
 tnmc_status tnmc_debug_set(int32_t what, int32_t value);
 
 const char* tnmc_status_string(tnmc_status s);

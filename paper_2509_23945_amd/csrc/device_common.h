@@ -161,21 +161,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_mov<0x140>(v);   // row_mirror: lane i <-> 15 - i within 16 lanes
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
-// N independent wavefront sums, their DPP steps interleaved; every lane gets
-// the same bits, equal to wave_sum of each value.
-template <int N>
-__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0xB1>(v[i]);
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0x4E>(v[i]);
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0x141>(v[i]);
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0x140>(v[i]);
-#pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = (readlane_d(v[i], 0) + readlane_d(v[i], 16)) + (readlane_d(v[i], 32) + readlane_d(v[i], 48));
-}
 __device__ __forceinline__ double wave_max(double v) {
   v = fmax(v, dpp_mov<0xB1>(v));
   v = fmax(v, dpp_mov<0x4E>(v));
@@ -191,6 +176,35 @@ __device__ __forceinline__ double dpp_rows(double v) {
   const int lo = __builtin_amdgcn_update_dpp(lo0, lo0, CTRL, ROWS, 0xf, false);
   const int hi = __builtin_amdgcn_update_dpp(hi0, hi0, CTRL, ROWS, 0xf, false);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// DPP move where lanes outside the enabled rows read zero.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows_zero(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// N independent wavefront sums, their DPP steps interleaved: butterflies
+// within each row of 16 lanes, then row_bcast15 (rows 1 and 3 add rows 0 and
+// 2) and row_bcast31 (rows 2 and 3 add row 1), so lane 63 holds the total and
+// is read once.  Every lane gets the same bits.
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0xB1>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0x4E>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0x141>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_mov<0x140>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_rows_zero<0x142, 0xa>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] += dpp_rows_zero<0x143, 0xc>(v[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = readlane_d(v[i], 63);
 }
 // Wavefront maximum: butterfly within each row of 16 lanes, then row_bcast15
 // and row_bcast31 carry the row maxima up to lane 63, which is read once.
