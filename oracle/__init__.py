@@ -13,9 +13,11 @@ library steps and no blocking or fusion beyond what the method states:
 * ``sampler`` - ancestral sampling with exact log q, and teacher forcing
 * ``chain``   - Metropolis-Hastings slice update and even/odd sweeps
 * ``autocorr``- integrated autocorrelation time
+* ``nn``      - the learned autoregressive proposal: masked-convolution
+  network, log q, sampling, loss gradient, Adam and its MH slice update
 
 Every part is pinned by the ``-m "not gpu"`` tests against brute-force
 enumeration, row transfer matrices, closed forms, exact stationarity and a
 library generator; none is "parity unpinned".
 """
-from . import autocorr, bmps, chain, model, philox, sampler  # noqa: F401
+from . import autocorr, bmps, chain, model, nn, philox, sampler  # noqa: F401

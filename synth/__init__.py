@@ -95,3 +95,15 @@ def slice_problem(Lx: int, Ly: int, seed: int, d: int = 2, kind: str = "pmj"):
         raise ValueError(kind)
     s = spins_random(Lx, Ly, 3, seed + 7919, d)
     return J, s
+
+
+def nn_params(seed: int, shapes, scale: float = 1.0) -> np.ndarray:
+    """Flat float32 parameters of a stack of 3x3 convolutions, shapes = [(c_in,
+    c_out), ...]: per layer W[c_out][c_in][3][3] ~ N(0, scale^2 2 / (9 c_in))
+    then b[c_out] ~ N(0, (0.1 scale)^2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for ci, co in shapes:
+        parts.append(rng.standard_normal(co * ci * 9) * scale * np.sqrt(2.0 / (9 * ci)))
+        parts.append(rng.standard_normal(co) * 0.1 * scale)
+    return np.concatenate(parts).astype(np.float32)
