@@ -168,6 +168,91 @@ tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes);
  * TNMC_ERR_ARG for an unknown what. */
 tnmc_status tnmc_debug_set(int32_t what, int32_t value);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal.  Any exactly normalised proposal q with an exact log q
+ * leaves the Metropolis-Hastings chain of main text Eq. 1 exact; here q is an
+ * autoregressive masked-convolution network q_theta(s | cond) over the sites
+ * of an Ising layer, in the tensor-network sampler's site order (rows, then
+ * sites within a row; SM S1.C), used in place of the boundary-MPS
+ * conditionals.  The network is not part of the paper; its shape is fixed:
+ *  - input per site: four condition channels, seen through full 3x3 windows:
+ *    Jz(z-1) s(z-1), Jz(z) s(z+1), Jx(z), Jy(z) (0 where the neighbour layer
+ *    or the bond does not exist), and the layer's spins (+1/-1) seen through a
+ *    mask that hides the centre and later sites;
+ *  - five 3x3 layers of 32 channels with ReLU (the first reads the input, the
+ *    next four read the previous layer masked to earlier sites and the
+ *    centre), and a 3x3 output channel masked the same way: the logit l of
+ *    P(s = +1), clipped to [-30, 30]; zero padding at the open edges;
+ *  - parameters: TNMC_NN_PARAMS FP32 numbers, per layer W[c_out][c_in][3][3]
+ *    then b[c_out] (c_in, c_out = (5,32), (32,32) x4, (32,1)); masked weights
+ *    are stored but unused.
+ * Convolutions run in FP32; probabilities, log q, dE and the MH test in FP64.
+ * Site j of a drawn layer takes +1 when its uniform (Philox counter
+ * (y*Lx+x, z, sweep, 0), as for the TN sampler) is below P(s_j = +1).
+ * Ising lattices (d = 2) only; layers up to 64 sites wide whose sampler fits
+ * in 160 KB of LDS (TNMC_ERR_UNSUPPORTED otherwise).
+ * Batched entry points take DEVICE pointers: cond [n][4][Ly][Lx] float,
+ * s [n][Ly][Lx] int8; they are stream-ordered on hip_stream. */
+enum { TNMC_NN_PARAMS = 38753 };
+typedef struct tnmc_nn tnmc_nn;   /* opaque; owns its parameters, Adam state and batch buffers */
+
+/* params (HOST, TNMC_NN_PARAMS floats) or NULL for the default
+ * initialisation from seed (W ~ N(0, 2/(9 c_in)), b = 0). */
+tnmc_status tnmc_nn_create(const float* params, uint64_t seed, tnmc_nn** out);
+tnmc_status tnmc_nn_free(tnmc_nn* nn);
+/* Parameters to / from a HOST buffer of TNMC_NN_PARAMS floats (synchronous);
+ * set also clears the Adam state. */
+tnmc_status tnmc_nn_get_params(tnmc_nn* nn, float* out);
+tnmc_status tnmc_nn_set_params(tnmc_nn* nn, const float* in);
+/* log q_theta(s_i | cond_i) for a batch (logq: DEVICE, n doubles). */
+tnmc_status tnmc_nn_logq(tnmc_nn* nn, const float* cond, const int8_t* s, int32_t n, int32_t Lx, int32_t Ly,
+                         double* logq, void* hip_stream);
+/* Mean of -log q_theta over the batch (*loss, HOST; synchronises) and its
+ * gradient with respect to the parameters (grad: DEVICE, TNMC_NN_PARAMS
+ * floats, or NULL); masked weights get 0, the clip passes no gradient where
+ * it is active. */
+tnmc_status tnmc_nn_loss_grad(tnmc_nn* nn, const float* cond, const int8_t* s, int32_t n, int32_t Lx, int32_t Ly,
+                              double* loss, float* grad, void* hip_stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+ * DEVICE gradient grad and learning rate lr. */
+tnmc_status tnmc_nn_adam_step(tnmc_nn* nn, const float* grad, double lr, void* hip_stream);
+/* epochs passes of minibatch Adam over the n pairs in their given order
+ * (minibatches of `batch` consecutive pairs, the last one possibly shorter);
+ * *last_loss (HOST, may be NULL) receives the loss of the last minibatch
+ * before its step (the call then synchronises). */
+tnmc_status tnmc_nn_train(tnmc_nn* nn, const float* cond, const int8_t* s, int64_t n, int32_t Lx, int32_t Ly,
+                          int32_t epochs, int32_t batch, double lr, double* last_loss, void* hip_stream);
+/* Training pairs from a lattice's current state: for every chain c and layer
+ * z, pair c*Lz + z = (condition channels of layer z, spins of layer z) into
+ * DEVICE buffers cond [n_chains*Lz][4][Ly][Lx] and s [n_chains*Lz][Ly][Lx]. */
+tnmc_status tnmc_nn_dataset(tnmc_lattice* lat, float* cond, int8_t* s, void* hip_stream);
+/* As tnmc_slice_propose / tnmc_slice_logq, with the learned proposal. */
+tnmc_status tnmc_nn_slice_propose(tnmc_lattice* lat, tnmc_nn* nn, int32_t chain, int32_t z, uint64_t sweep,
+                                  int8_t* s_new, double* logq_new, double* logq_old, double* dE, void* hip_stream);
+tnmc_status tnmc_nn_slice_logq(tnmc_lattice* lat, tnmc_nn* nn, int32_t chain, int32_t z, const int8_t* s,
+                               double* logq, void* hip_stream);
+/* As tnmc_sweep, each layer proposed by the learned proposal unless its
+ * fallback flag selects the tensor-network proposal (both are exact MH
+ * kernels).  The learned proposals of a lattice are counted per (chain, z). */
+tnmc_status tnmc_nn_sweep(tnmc_lattice* const* lats, int32_t n_lats, tnmc_nn* nn, int32_t n_sweeps,
+                          uint64_t sweep_offset, int32_t record, int32_t time_kernels, tnmc_stats* stats,
+                          void* hip_stream);
+/* Per-(chain, z) counts of learned proposals made and accepted since the
+ * last reset (HOST arrays [n_chains][Lz], either may be NULL). */
+tnmc_status tnmc_nn_counts(tnmc_lattice* lat, int64_t* proposed, int64_t* accepted);
+tnmc_status tnmc_nn_counts_reset(tnmc_lattice* lat);
+/* Fallback flags [n_chains][Lz] (HOST; 1 = tensor-network proposal); NULL
+ * clears them all. */
+tnmc_status tnmc_nn_set_fallback(tnmc_lattice* lat, const int8_t* flags);
+tnmc_status tnmc_nn_get_fallback(tnmc_lattice* lat, int8_t* flags);
+/* Freezes the fallback once, after a calibration window: every layer whose
+ * learned proposals were accepted at a rate below threshold switches to the
+ * tensor-network proposal (layers not yet proposed keep their flag);
+ * *n_fallback (may be NULL) receives the number of flagged layers.  Deciding
+ * once and then keeping each layer's kernel fixed keeps every later step an
+ * exact MH kernel. */
+tnmc_status tnmc_nn_calibrate_fallback(tnmc_lattice* lat, double threshold, int32_t* n_fallback);
+
 const char* tnmc_status_string(tnmc_status s);
 /* Text of the last failed HIP call (thread-local). */
 const char* tnmc_last_error(void);

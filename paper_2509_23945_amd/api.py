@@ -31,8 +31,13 @@ __all__ = [
     "tnmc_slice_logq", "tnmc_mh_accept", "tnmc_sweep", "tnmc_half_sweep", "tnmc_get_spins", "tnmc_set_spins",
     "tnmc_energy", "tnmc_timeseries", "tnmc_timeseries_reset", "tnmc_flop_model", "tnmc_debug_workspace", "tnmc_debug_set",
     "tnmc_status_string",
-    "tnmc_last_error", "Lattice", "TNMC_FP64", "TNMC_FP32",
+    "tnmc_last_error", "Lattice", "TNMC_FP64", "TNMC_FP32", "TNMC_NN_PARAMS", "Nn", "tnmc_nn_create", "tnmc_nn_free",
+    "tnmc_nn_get_params", "tnmc_nn_set_params", "tnmc_nn_logq", "tnmc_nn_loss_grad", "tnmc_nn_adam_step",
+    "tnmc_nn_train", "tnmc_nn_dataset", "tnmc_nn_slice_propose", "tnmc_nn_slice_logq", "tnmc_nn_sweep",
+    "tnmc_nn_counts", "tnmc_nn_counts_reset", "tnmc_nn_set_fallback", "tnmc_nn_get_fallback",
+    "tnmc_nn_calibrate_fallback",
 ]
+TNMC_NN_PARAMS = 38753
 
 
 class TnmcError(RuntimeError):
@@ -116,6 +121,29 @@ def load():
     lib.tnmc_status_string.restype = ctypes.c_char_p
     lib.tnmc_last_error.argtypes = []
     lib.tnmc_last_error.restype = ctypes.c_char_p
+    i32, u64, i64, dbl = ctypes.c_int32, ctypes.c_uint64, ctypes.c_int64, ctypes.c_double
+    nn_sigs = {
+        "tnmc_nn_create": [P(ctypes.c_float), u64, P(vp)],
+        "tnmc_nn_free": [vp],
+        "tnmc_nn_get_params": [vp, P(ctypes.c_float)],
+        "tnmc_nn_set_params": [vp, P(ctypes.c_float)],
+        "tnmc_nn_logq": [vp, vp, vp, i32, i32, i32, vp, vp],
+        "tnmc_nn_loss_grad": [vp, vp, vp, i32, i32, i32, P(dbl), vp, vp],
+        "tnmc_nn_adam_step": [vp, vp, dbl, vp],
+        "tnmc_nn_train": [vp, vp, vp, i64, i32, i32, i32, i32, dbl, P(dbl), vp],
+        "tnmc_nn_dataset": [vp, vp, vp, vp],
+        "tnmc_nn_slice_propose": [vp, vp, i32, i32, u64, P(ctypes.c_int8), P(dbl), P(dbl), P(dbl), vp],
+        "tnmc_nn_slice_logq": [vp, vp, i32, i32, P(ctypes.c_int8), P(dbl), vp],
+        "tnmc_nn_sweep": [P(vp), i32, vp, i32, u64, i32, i32, P(_Stats), vp],
+        "tnmc_nn_counts": [vp, P(i64), P(i64)],
+        "tnmc_nn_counts_reset": [vp],
+        "tnmc_nn_set_fallback": [vp, P(ctypes.c_int8)],
+        "tnmc_nn_get_fallback": [vp, P(ctypes.c_int8)],
+        "tnmc_nn_calibrate_fallback": [vp, dbl, P(i32)],
+    }
+    for name, sig in nn_sigs.items():
+        getattr(lib, name).argtypes = sig
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("tnmc_lattice_init", "tnmc_lattice_free", "tnmc_slice_propose", "tnmc_slice_logq",
                  "tnmc_mh_accept", "tnmc_sweep", "tnmc_half_sweep", "tnmc_get_spins", "tnmc_set_spins",
                  "tnmc_energy", "tnmc_timeseries", "tnmc_timeseries_reset", "tnmc_flop_model"):
@@ -294,3 +322,133 @@ def tnmc_flop_model(Lx: int, Ly: int, d: int, chi: int):
     a, b = ctypes.c_double(), ctypes.c_double()
     _check(load().tnmc_flop_model(Lx, Ly, d, chi, ctypes.byref(a), ctypes.byref(b)), "tnmc_flop_model")
     return a.value, b.value
+
+
+# ------------------------------------------------------------ learned proposal
+# Batched calls take device buffers as integer addresses (tensor.data_ptr()):
+# cond [n][4][Ly][Lx] float32, s [n][Ly][Lx] int8, logq [n] float64,
+# grad [TNMC_NN_PARAMS] float32.
+
+
+class Nn:
+    """Handle of a tnmc_nn."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.tnmc_nn_free(self.handle)
+            self.handle = None
+
+
+def tnmc_nn_create(params=None, seed: int = 0) -> Nn:
+    p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+    if p is not None and p.size != TNMC_NN_PARAMS:
+        raise ValueError(f"params need {TNMC_NN_PARAMS} entries")
+    h = ctypes.c_void_p()
+    _check(load().tnmc_nn_create(_ptr(p, ctypes.c_float), ctypes.c_uint64(seed), ctypes.byref(h)), "tnmc_nn_create")
+    return Nn(h)
+
+
+def tnmc_nn_free(nn: Nn) -> None:
+    if nn.handle:
+        _check(load().tnmc_nn_free(nn.handle), "tnmc_nn_free")
+        nn.handle = None
+
+
+def tnmc_nn_get_params(nn: Nn) -> np.ndarray:
+    out = np.zeros(TNMC_NN_PARAMS, dtype=np.float32)
+    _check(load().tnmc_nn_get_params(nn.handle, _ptr(out, ctypes.c_float)), "tnmc_nn_get_params")
+    return out
+
+
+def tnmc_nn_set_params(nn: Nn, params) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.size != TNMC_NN_PARAMS:
+        raise ValueError(f"params need {TNMC_NN_PARAMS} entries")
+    _check(load().tnmc_nn_set_params(nn.handle, _ptr(p, ctypes.c_float)), "tnmc_nn_set_params")
+
+
+def tnmc_nn_logq(nn: Nn, cond_ptr: int, s_ptr: int, n: int, Lx: int, Ly: int, logq_ptr: int, stream=None) -> None:
+    _check(load().tnmc_nn_logq(nn.handle, cond_ptr, s_ptr, n, Lx, Ly, logq_ptr, stream), "tnmc_nn_logq")
+
+
+def tnmc_nn_loss_grad(nn: Nn, cond_ptr: int, s_ptr: int, n: int, Lx: int, Ly: int, grad_ptr=None, stream=None) -> float:
+    loss = ctypes.c_double()
+    _check(load().tnmc_nn_loss_grad(nn.handle, cond_ptr, s_ptr, n, Lx, Ly, ctypes.byref(loss), grad_ptr, stream),
+           "tnmc_nn_loss_grad")
+    return loss.value
+
+
+def tnmc_nn_adam_step(nn: Nn, grad_ptr: int, lr: float, stream=None) -> None:
+    _check(load().tnmc_nn_adam_step(nn.handle, grad_ptr, lr, stream), "tnmc_nn_adam_step")
+
+
+def tnmc_nn_train(nn: Nn, cond_ptr: int, s_ptr: int, n: int, Lx: int, Ly: int, epochs: int, batch: int, lr: float,
+                  stream=None) -> float:
+    loss = ctypes.c_double()
+    _check(load().tnmc_nn_train(nn.handle, cond_ptr, s_ptr, n, Lx, Ly, epochs, batch, lr, ctypes.byref(loss), stream),
+           "tnmc_nn_train")
+    return loss.value
+
+
+def tnmc_nn_dataset(lat: Lattice, cond_ptr: int, s_ptr: int, stream=None) -> None:
+    _check(load().tnmc_nn_dataset(lat.handle, cond_ptr, s_ptr, stream), "tnmc_nn_dataset")
+
+
+def tnmc_nn_slice_propose(lat: Lattice, nn: Nn, chain: int, z: int, sweep: int = 0, stream=None):
+    """Returns (s_new [Ly, Lx] int8, logq_new, logq_old, dE, status)."""
+    s_new = np.zeros((lat.Ly, lat.Lx), dtype=np.int8)
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st = load().tnmc_nn_slice_propose(lat.handle, nn.handle, chain, z, ctypes.c_uint64(sweep),
+                                      _ptr(s_new, ctypes.c_int8), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                      stream)
+    _check(st, "tnmc_nn_slice_propose", allow=(TNMC_ERR_NUMERIC,))
+    return s_new, a.value, b.value, c.value, st
+
+
+def tnmc_nn_slice_logq(lat: Lattice, nn: Nn, chain: int, z: int, s, stream=None) -> float:
+    s = np.ascontiguousarray(s, dtype=np.int8).reshape(lat.Ly, lat.Lx)
+    out = ctypes.c_double()
+    _check(load().tnmc_nn_slice_logq(lat.handle, nn.handle, chain, z, _ptr(s, ctypes.c_int8), ctypes.byref(out),
+                                     stream), "tnmc_nn_slice_logq")
+    return out.value
+
+
+def tnmc_nn_sweep(lats, nn: Nn, n_sweeps: int, sweep_offset: int = 0, record: bool = False,
+                  time_kernels: bool = False, stream=None) -> dict:
+    arr, n = _handles(lats)
+    st = _Stats()
+    _check(load().tnmc_nn_sweep(arr, n, nn.handle, n_sweeps, ctypes.c_uint64(sweep_offset), int(record),
+                                int(time_kernels), ctypes.byref(st), stream), "tnmc_nn_sweep")
+    return st.as_dict()
+
+
+def tnmc_nn_counts(lat: Lattice):
+    """Returns (proposed, accepted), each [n_chains, Lz] int64."""
+    p = np.zeros((lat.n_chains, lat.Lz), dtype=np.int64)
+    a = np.zeros((lat.n_chains, lat.Lz), dtype=np.int64)
+    _check(load().tnmc_nn_counts(lat.handle, _ptr(p, ctypes.c_int64), _ptr(a, ctypes.c_int64)), "tnmc_nn_counts")
+    return p, a
+
+
+def tnmc_nn_counts_reset(lat: Lattice) -> None:
+    _check(load().tnmc_nn_counts_reset(lat.handle), "tnmc_nn_counts_reset")
+
+
+def tnmc_nn_set_fallback(lat: Lattice, flags=None) -> None:
+    f = None if flags is None else np.ascontiguousarray(flags, dtype=np.int8).reshape(lat.n_chains, lat.Lz)
+    _check(load().tnmc_nn_set_fallback(lat.handle, _ptr(f, ctypes.c_int8)), "tnmc_nn_set_fallback")
+
+
+def tnmc_nn_get_fallback(lat: Lattice) -> np.ndarray:
+    f = np.zeros((lat.n_chains, lat.Lz), dtype=np.int8)
+    _check(load().tnmc_nn_get_fallback(lat.handle, _ptr(f, ctypes.c_int8)), "tnmc_nn_get_fallback")
+    return f
+
+
+def tnmc_nn_calibrate_fallback(lat: Lattice, threshold: float) -> int:
+    n = ctypes.c_int32()
+    _check(load().tnmc_nn_calibrate_fallback(lat.handle, threshold, ctypes.byref(n)), "tnmc_nn_calibrate_fallback")
+    return n.value

@@ -15,6 +15,7 @@
 #include <tuple>
 #include <vector>
 
+#include "nn_internal.h"
 #include "tnmc.h"
 #include "tnmc_internal.h"
 
@@ -57,6 +58,11 @@ struct tnmc_lattice {
   double* dMrec = nullptr;
   double* dqrec = nullptr;
   double* dscal = nullptr;
+  // learned proposal: per-(chain, z) running counts of its proposals
+  // ([n_chains][Lz], kCounterStride long longs apart) and the frozen
+  // tensor-network fallback flags (1 = that layer uses the TN proposal)
+  long long* dnncnt = nullptr;
+  std::vector<int8_t> nn_fallback;
   size_t sites() const { return (size_t)Lx * Ly * Lz; }
   const float* J_of(int c) const { return dJ + (size_t)chain_instance[c] * 3 * sites(); }
   int8_t* spins_of(int c) const { return dspins + (size_t)c * sites(); }
@@ -83,6 +89,8 @@ struct Workspace {
   size_t bytes_cap = 0;
   double* gscr = nullptr;     // full contraction tile layout in global memory, per task (retry path)
   size_t gscr_cap = 0;
+  TaskDesc* nn_tasks = nullptr;   // descriptors of the learned-proposal tasks of a sweep
+  size_t nn_tasks_cap = 0;
 };
 Workspace g_ws;
 
@@ -454,7 +462,7 @@ tnmc_status tnmc_lattice_free(tnmc_lattice* L) {
   if (!L) return TNMC_ERR_ARG;
   (void)hipDeviceSynchronize();
   void* ptrs[] = {L->dJ, L->dspins, L->dpa, L->dpb, (void*)L->dJc, (void*)L->dSc,
-                  L->dErec, L->dMrec, L->dqrec, L->dscal};
+                  L->dErec, L->dMrec, L->dqrec, L->dscal, (void*)L->dnncnt};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete L;
@@ -721,6 +729,521 @@ tnmc_status tnmc_flop_model(int32_t Lx, int32_t Ly, int32_t d, int32_t chi, doub
     }
   }
   if (sample_flops) *sample_flops = total;
+  return TNMC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ learned proposal
+
+struct tnmc_nn {
+  float* theta = nullptr;   // parameters, the flat layout of include/tnmc.h
+  float* m = nullptr;       // Adam moments
+  float* v = nullptr;
+  float* grad = nullptr;
+  int64_t step = 0;         // Adam steps taken
+  // batch buffers (grow-only)
+  size_t cap_elems = 0;     // n * Ly * Lx of the buffers below
+  float* act = nullptr;     // 5 * 32 * elems
+  float* gbuf = nullptr;    // 2 * 32 * elems
+  float* logit = nullptr;   // elems
+  float* glogit = nullptr;  // elems
+  double* logq = nullptr;   // n
+  size_t cap_n = 0;
+  float* part = nullptr;    // kNnWeightParts * (32*32*9 + 32)
+};
+
+namespace {
+
+// Normal deviates for the default initialisation (splitmix64 + Box-Muller).
+struct InitRng {
+  uint64_t x;
+  uint64_t next() {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return ((double)(next() >> 11) + 0.5) * 0x1p-53; }
+  double normal() { return std::sqrt(-2.0 * std::log(uniform())) * std::cos(6.283185307179586 * uniform()); }
+};
+
+tnmc_status nn_batch(tnmc_nn* nn, const float* cond, const int8_t* s, int n, int Lx, int Ly, tnmc::NnBatch& B) {
+  const size_t elems = (size_t)n * Lx * Ly;
+  if (elems > nn->cap_elems) {
+    HIP_TRY(hipDeviceSynchronize());
+    float* bufs[] = {nn->act, nn->gbuf, nn->logit, nn->glogit};
+    for (float* p : bufs)
+      if (p) HIP_TRY(hipFree(p));
+    nn->act = nn->gbuf = nn->logit = nn->glogit = nullptr;
+    nn->cap_elems = 0;
+    HIP_TRY(hipMalloc((void**)&nn->act, 5 * tnmc::kNnChannels * elems * sizeof(float)));
+    HIP_TRY(hipMalloc((void**)&nn->gbuf, 2 * tnmc::kNnChannels * elems * sizeof(float)));
+    HIP_TRY(hipMalloc((void**)&nn->logit, elems * sizeof(float)));
+    HIP_TRY(hipMalloc((void**)&nn->glogit, elems * sizeof(float)));
+    nn->cap_elems = elems;
+  }
+  if ((size_t)n > nn->cap_n) {
+    HIP_TRY(hipDeviceSynchronize());
+    if (nn->logq) HIP_TRY(hipFree(nn->logq));
+    nn->logq = nullptr;
+    HIP_TRY(hipMalloc((void**)&nn->logq, (size_t)n * sizeof(double)));
+    nn->cap_n = n;
+  }
+  if (!nn->part)
+    HIP_TRY(hipMalloc((void**)&nn->part, (size_t)tnmc::kNnWeightParts * (32 * 32 * 9 + 32) * sizeof(float)));
+  B.n = n;
+  B.Lx = Lx;
+  B.Ly = Ly;
+  B.cond = cond;
+  B.s = s;
+  for (int l = 0; l < 5; ++l) B.act[l] = nn->act + (size_t)l * tnmc::kNnChannels * elems;
+  B.g[0] = nn->gbuf;
+  B.g[1] = nn->gbuf + (size_t)tnmc::kNnChannels * elems;
+  B.logit = nn->logit;
+  B.glogit = nn->glogit;
+  B.logq = nn->logq;
+  B.part = nn->part;
+  return TNMC_OK;
+}
+
+bool nn_shape_ok(int n, int Lx, int Ly) {
+  return n >= 1 && Lx >= 1 && Ly >= 1 && Lx <= tnmc::kNnLxMax && Ly <= kLyMax;
+}
+
+// The learned proposal runs on Ising lattices whose sampler fits in a CU's LDS.
+tnmc_status nn_lattice_ok(const tnmc_lattice* L) {
+  if (L->d != 2) return TNMC_ERR_UNSUPPORTED;
+  if (tnmc::nn_sample_lds_bytes(L->Lx, L->Ly) > 160 * 1024) return TNMC_ERR_UNSUPPORTED;
+  return TNMC_OK;
+}
+
+tnmc_status nn_counters(tnmc_lattice* L) {
+  if (L->dnncnt) return TNMC_OK;
+  const size_t n = (size_t)L->n_chains * L->Lz * tnmc::kCounterStride;
+  HIP_TRY(hipMalloc((void**)&L->dnncnt, n * sizeof(long long)));
+  HIP_TRY(hipMemset(L->dnncnt, 0, n * sizeof(long long)));
+  L->nn_fallback.assign((size_t)L->n_chains * L->Lz, 0);
+  return TNMC_OK;
+}
+
+TaskDesc nn_task(tnmc_lattice* L, int chain, int z) {
+  TaskDesc t;
+  std::memset(&t, 0, sizeof(t));
+  t.J = L->J_of(chain);
+  t.spins = L->spins_of(chain);
+  t.beta = L->beta[chain];
+  t.key0 = L->seed;
+  t.key1 = L->chain_key[chain];
+  t.Lx = L->Lx;
+  t.Ly = L->Ly;
+  t.Lz = L->Lz;
+  t.z = z;
+  t.d = L->d;
+  t.chi = L->chi;
+  t.chi_max = L->chi_max;
+  t.write_back = 1;
+  return t;
+}
+
+tnmc_status nn_single(tnmc_lattice* lat, tnmc_nn* nn, int chain, int z, uint64_t sweep, const int8_t* force_host,
+                      int8_t* s_new_host, double* rec_host, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  g_last_error.clear();
+  const size_t plane = (size_t)lat->Lx * lat->Ly;
+  if (grow(g_ws.bytes, g_ws.bytes_cap, 2 * plane) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.nn_tasks, g_ws.nn_tasks_cap, (size_t)1) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.dbl, g_ws.dbl_cap, (size_t)8) != TNMC_OK) return TNMC_ERR_OOM;
+  TaskDesc t = nn_task(lat, chain, z);
+  t.record = g_ws.dbl;
+  t.write_back = 0;
+  t.s_new_out = g_ws.bytes;
+  if (force_host) {
+    HIP_TRY(hipMemcpyAsync(g_ws.bytes + plane, force_host, plane, hipMemcpyHostToDevice, s));
+    t.force_new = g_ws.bytes + plane;
+  }
+  HIP_TRY(hipMemcpyAsync(g_ws.nn_tasks, &t, sizeof(TaskDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));   // the host copies above are released on return
+  HIP_TRY(tnmc::launch_nn_sample(g_ws.nn_tasks, 1, nn->theta, lat->Lx, lat->Ly, sweep, s));
+  if (s_new_host) HIP_TRY(hipMemcpyAsync(s_new_host, g_ws.bytes, plane, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(rec_host, g_ws.dbl, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return TNMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tnmc_status tnmc_nn_create(const float* params, uint64_t seed, tnmc_nn** out) {
+  if (!out) return TNMC_ERR_ARG;
+  std::vector<float> h(tnmc::kNnParams);
+  if (params) {
+    std::memcpy(h.data(), params, h.size() * sizeof(float));
+  } else {
+    // W ~ N(0, 2 / (9 c_in)), b = 0
+    InitRng rng{seed};
+    const int cin[6] = {5, 32, 32, 32, 32, 32}, cout[6] = {32, 32, 32, 32, 32, 1};
+    size_t o = 0;
+    for (int l = 0; l < 6; ++l) {
+      const double sd = std::sqrt(2.0 / (9.0 * cin[l]));
+      for (int i = 0; i < cout[l] * cin[l] * 9; ++i) h[o++] = (float)(sd * rng.normal());
+      for (int i = 0; i < cout[l]; ++i) h[o++] = 0.0f;
+    }
+  }
+  for (float x : h)
+    if (!std::isfinite(x)) return TNMC_ERR_ARG;
+  auto* nn = new tnmc_nn();
+  auto fail = [&](hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    tnmc_nn_free(nn);
+    return e == hipErrorOutOfMemory ? TNMC_ERR_OOM : TNMC_ERR_DEVICE;
+  };
+  const size_t bytes = tnmc::kNnParams * sizeof(float);
+  float** bufs[] = {&nn->theta, &nn->m, &nn->v, &nn->grad};
+  for (float** b : bufs) {
+    hipError_t e = hipMalloc((void**)b, bytes);
+    if (e != hipSuccess) return fail(e, "hipMalloc");
+    e = hipMemset(*b, 0, bytes);
+    if (e != hipSuccess) return fail(e, "hipMemset");
+  }
+  hipError_t e = hipMemcpy(nn->theta, h.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(e, "hipMemcpy");
+  *out = nn;
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_free(tnmc_nn* nn) {
+  if (!nn) return TNMC_ERR_ARG;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {nn->theta, nn->m, nn->v, nn->grad, nn->act, nn->gbuf, nn->logit, nn->glogit, nn->logq, nn->part};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete nn;
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_get_params(tnmc_nn* nn, float* out) {
+  if (!nn || !out) return TNMC_ERR_ARG;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(out, nn->theta, tnmc::kNnParams * sizeof(float), hipMemcpyDeviceToHost));
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_set_params(tnmc_nn* nn, const float* in) {
+  if (!nn || !in) return TNMC_ERR_ARG;
+  for (int i = 0; i < tnmc::kNnParams; ++i)
+    if (!std::isfinite(in[i])) return TNMC_ERR_ARG;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(nn->theta, in, tnmc::kNnParams * sizeof(float), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(nn->m, 0, tnmc::kNnParams * sizeof(float)));
+  HIP_TRY(hipMemset(nn->v, 0, tnmc::kNnParams * sizeof(float)));
+  nn->step = 0;
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_logq(tnmc_nn* nn, const float* cond, const int8_t* s, int32_t n, int32_t Lx, int32_t Ly,
+                         double* logq, void* stream) {
+  if (!nn || !cond || !s || !logq || !nn_shape_ok(n, Lx, Ly)) return TNMC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  tnmc::NnBatch B;
+  tnmc_status r = nn_batch(nn, cond, s, n, Lx, Ly, B);
+  if (r != TNMC_OK) return r;
+  HIP_TRY(tnmc::nn_forward(B, nn->theta, st));
+  HIP_TRY(hipMemcpyAsync(logq, B.logq, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_loss_grad(tnmc_nn* nn, const float* cond, const int8_t* s, int32_t n, int32_t Lx, int32_t Ly,
+                              double* loss, float* grad, void* stream) {
+  if (!nn || !cond || !s || !loss || !nn_shape_ok(n, Lx, Ly)) return TNMC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  tnmc::NnBatch B;
+  tnmc_status r = nn_batch(nn, cond, s, n, Lx, Ly, B);
+  if (r != TNMC_OK) return r;
+  HIP_TRY(tnmc::nn_forward(B, nn->theta, st));
+  HIP_TRY(tnmc::nn_backward(B, nn->theta, nn->grad, st));
+  if (grad) HIP_TRY(hipMemcpyAsync(grad, nn->grad, tnmc::kNnParams * sizeof(float), hipMemcpyDeviceToDevice, st));
+  std::vector<double> lq(n);
+  HIP_TRY(hipMemcpyAsync(lq.data(), B.logq, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double acc = 0.0;
+  for (double v : lq) acc -= v;
+  *loss = acc / n;
+  return std::isfinite(*loss) ? TNMC_OK : TNMC_ERR_NUMERIC;
+}
+
+tnmc_status tnmc_nn_adam_step(tnmc_nn* nn, const float* grad, double lr, void* stream) {
+  if (!nn || !grad || !(lr > 0.0) || !std::isfinite(lr)) return TNMC_ERR_ARG;
+  nn->step += 1;
+  HIP_TRY(tnmc::nn_adam(nn->theta, nn->m, nn->v, grad, nn->step, lr, (hipStream_t)stream));
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_train(tnmc_nn* nn, const float* cond, const int8_t* s, int64_t n, int32_t Lx, int32_t Ly,
+                          int32_t epochs, int32_t batch, double lr, double* last_loss, void* stream) {
+  if (!nn || !cond || !s || n < 1 || epochs < 0 || batch < 1 || !(lr > 0.0) || !std::isfinite(lr)) return TNMC_ERR_ARG;
+  if (!nn_shape_ok(batch, Lx, Ly)) return TNMC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t plane = (size_t)Lx * Ly;
+  tnmc::NnBatch B;
+  int last_n = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    for (int64_t i = 0; i < n; i += batch) {
+      const int bn = (int)std::min<int64_t>(batch, n - i);
+      tnmc_status r = nn_batch(nn, cond + (size_t)i * tnmc::kNnCond * plane, s + (size_t)i * plane, bn, Lx, Ly, B);
+      if (r != TNMC_OK) return r;
+      HIP_TRY(tnmc::nn_forward(B, nn->theta, st));
+      HIP_TRY(tnmc::nn_backward(B, nn->theta, nn->grad, st));
+      nn->step += 1;
+      HIP_TRY(tnmc::nn_adam(nn->theta, nn->m, nn->v, nn->grad, nn->step, lr, st));
+      last_n = bn;
+    }
+  }
+  if (last_loss) {
+    *last_loss = std::nan("");
+    if (last_n > 0) {
+      std::vector<double> lq(last_n);
+      HIP_TRY(hipMemcpyAsync(lq.data(), nn->logq, (size_t)last_n * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      double acc = 0.0;
+      for (double v : lq) acc -= v;
+      *last_loss = acc / last_n;
+      if (!std::isfinite(*last_loss)) return TNMC_ERR_NUMERIC;
+    }
+  }
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_dataset(tnmc_lattice* lat, float* cond, int8_t* s, void* stream) {
+  if (!lat || !cond || !s) return TNMC_ERR_ARG;
+  if (lat->d != 2) return TNMC_ERR_UNSUPPORTED;
+  HIP_TRY(tnmc::launch_nn_dataset(lat->dJc, lat->dSc, lat->n_chains, lat->Lx, lat->Ly, lat->Lz, cond, s,
+                                  (hipStream_t)stream));
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_slice_propose(tnmc_lattice* lat, tnmc_nn* nn, int32_t chain, int32_t z, uint64_t sweep,
+                                  int8_t* s_new, double* logq_new, double* logq_old, double* dE, void* stream) {
+  if (!lat || !nn || chain < 0 || chain >= lat->n_chains || z < 0 || z >= lat->Lz) return TNMC_ERR_ARG;
+  if (!s_new || !logq_new || !logq_old || !dE) return TNMC_ERR_ARG;
+  tnmc_status r = nn_lattice_ok(lat);
+  if (r != TNMC_OK) return r;
+  double rec[5];
+  r = nn_single(lat, nn, chain, z, sweep, nullptr, s_new, rec, (hipStream_t)stream);
+  if (r != TNMC_OK) return r;
+  *logq_new = rec[0];
+  *logq_old = rec[1];
+  *dE = rec[2];
+  if (rec[4] != 0.0 || !std::isfinite(rec[0]) || !std::isfinite(rec[1])) {
+    g_last_error = "non-finite logit (fault bits " + std::to_string((int)rec[4]) + ")";
+    return TNMC_ERR_NUMERIC;
+  }
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_slice_logq(tnmc_lattice* lat, tnmc_nn* nn, int32_t chain, int32_t z, const int8_t* s,
+                               double* logq, void* stream) {
+  if (!lat || !nn || chain < 0 || chain >= lat->n_chains || z < 0 || z >= lat->Lz || !s || !logq)
+    return TNMC_ERR_ARG;
+  tnmc_status r = nn_lattice_ok(lat);
+  if (r != TNMC_OK) return r;
+  const size_t plane = (size_t)lat->Lx * lat->Ly;
+  for (size_t i = 0; i < plane; ++i)
+    if (s[i] != 1 && s[i] != -1) return TNMC_ERR_ARG;
+  double rec[5];
+  r = nn_single(lat, nn, chain, z, 0, s, nullptr, rec, (hipStream_t)stream);
+  if (r != TNMC_OK) return r;
+  *logq = rec[0];
+  return std::isfinite(rec[0]) && rec[4] == 0.0 ? TNMC_OK : TNMC_ERR_NUMERIC;
+}
+
+tnmc_status tnmc_nn_sweep(tnmc_lattice* const* lats, int32_t n_lats, tnmc_nn* nn, int32_t n_sweeps,
+                          uint64_t sweep_offset, int32_t record, int32_t time_kernels, tnmc_stats* stats,
+                          void* stream) {
+  if (check_lats(lats, n_lats) != TNMC_OK || !nn || n_sweeps < 0) return TNMC_ERR_ARG;
+  for (int l = 0; l < n_lats; ++l) {
+    tnmc_status r = nn_lattice_ok(lats[l]);
+    if (r != TNMC_OK) return r;
+  }
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  hipStream_t s = (hipStream_t)stream;
+  for (int l = 0; l < n_lats; ++l) {
+    tnmc_status r = nn_counters(lats[l]);
+    if (r != TNMC_OK) return r;
+  }
+  // learned-proposal tasks per parity, and the layers frozen to the TN proposal
+  std::vector<TaskDesc> nd[2];
+  int lxm[2] = {1, 1}, lym[2] = {1, 1};
+  std::vector<Task> tn_tasks;
+  for (int p : {0, 1})
+    for (Task t : half_sweep_tasks(lats, n_lats, p)) {
+      tnmc_lattice* L = t.lat;
+      const size_t slot = (size_t)t.chain * L->Lz + t.z;
+      if (L->nn_fallback[slot]) {
+        t.key = p;
+        tn_tasks.push_back(t);
+      } else {
+        TaskDesc d = nn_task(L, t.chain, t.z);
+        d.counters = L->dnncnt + tnmc::kCounterStride * slot;
+        nd[p].push_back(d);
+        lxm[p] = std::max(lxm[p], L->Lx);
+        lym[p] = std::max(lym[p], L->Ly);
+      }
+    }
+  for (int p : {0, 1})   // lattices of different shapes share one launch per parity
+    if (!nd[p].empty() && tnmc::nn_sample_lds_bytes(lxm[p], lym[p]) > 160 * 1024) return TNMC_ERR_UNSUPPORTED;
+  const size_t n_nn = nd[0].size() + nd[1].size();
+  if (grow(g_ws.nn_tasks, g_ws.nn_tasks_cap, std::max<size_t>(n_nn, 1)) != TNMC_OK) return TNMC_ERR_OOM;
+  if (!nd[0].empty())
+    HIP_TRY(hipMemcpyAsync(g_ws.nn_tasks, nd[0].data(), nd[0].size() * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
+  if (!nd[1].empty())
+    HIP_TRY(hipMemcpyAsync(g_ws.nn_tasks + nd[0].size(), nd[1].data(), nd[1].size() * sizeof(TaskDesc),
+                           hipMemcpyHostToDevice, s));
+  Plan plan;
+  size_t n_tn = 0;
+  if (!tn_tasks.empty()) {
+    tnmc_status r = make_plan(tn_tasks, plan);
+    if (r != TNMC_OK) return r;
+    n_tn = plan.desc.size();
+    if (grow(g_ws.tasks, g_ws.tasks_cap, n_tn) != TNMC_OK) return TNMC_ERR_OOM;
+    HIP_TRY(hipMemcpyAsync(g_ws.tasks, plan.desc.data(), n_tn * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(g_ws.counters, 0, tnmc::kCounterStride * n_tn * sizeof(long long), s));
+  }
+  // counts before the sweeps, to report this call's proposals
+  std::vector<std::vector<long long>> before(n_lats);
+  if (stats) {
+    for (int l = 0; l < n_lats; ++l) {
+      before[l].resize((size_t)lats[l]->n_chains * lats[l]->Lz * tnmc::kCounterStride);
+      HIP_TRY(hipMemcpyAsync(before[l].data(), lats[l]->dnncnt, before[l].size() * sizeof(long long),
+                             hipMemcpyDeviceToHost, s));
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));   // host descriptors are released on return
+  Timer tm;
+  tm.on = (time_kernels != 0 && stats != nullptr);
+  for (int t = 0; t < n_sweeps; ++t) {
+    const uint64_t sw = sweep_offset + (uint64_t)t;
+    for (int p : {0, 1}) {
+      if (!nd[p].empty()) {
+        if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+        HIP_TRY(tnmc::launch_nn_sample(g_ws.nn_tasks + (p ? nd[0].size() : 0), (int)nd[p].size(), nn->theta, lxm[p],
+                                       lym[p], sw, s));
+        if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+        if (stats) stats->sample_launches += 1;
+      }
+      for (const auto& g : plan.groups) {
+        if (g.key != p) continue;
+        const TaskDesc* dt = g_ws.tasks + g.first;
+        if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+        HIP_TRY(tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, s));
+        if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+        if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+        HIP_TRY(tnmc::launch_sample(dt, g.count, g.d, g.chi_max, g.precision, g.lx_max, g.ly_max, sw, s));
+        if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+        if (stats) {
+          stats->contract_launches += 1;
+          stats->sample_launches += 1;
+        }
+      }
+    }
+    if (record) {
+      for (int l = 0; l < n_lats; ++l) {
+        tnmc_lattice* L = lats[l];
+        if (L->n_recorded >= L->record_capacity) continue;
+        const int64_t i = L->n_recorded++;
+        HIP_TRY(tnmc::launch_observables(L->dJc, L->dSc, L->n_chains, L->dpa, L->dpb, L->n_pairs, L->Lx, L->Ly,
+                                         L->Lz, L->d, L->dErec + i * L->n_chains, L->dMrec + i * L->n_chains,
+                                         L->dqrec + i * std::max(1, L->n_pairs), s));
+      }
+    }
+  }
+  if (stats) {
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int l = 0; l < n_lats; ++l) {
+      std::vector<long long> after(before[l].size());
+      HIP_TRY(hipMemcpy(after.data(), lats[l]->dnncnt, after.size() * sizeof(long long), hipMemcpyDeviceToHost));
+      for (size_t k = 0; k < after.size(); k += tnmc::kCounterStride) {
+        stats->proposed += after[k] - before[l][k];
+        stats->accepted += after[k + 1] - before[l][k + 1];
+        stats->numeric_faults += after[k + 2] - before[l][k + 2];
+      }
+    }
+    if (n_tn) {
+      tnmc_status r = read_counters(n_tn, stats);
+      if (r != TNMC_OK) return r;
+    }
+    tnmc_status r = finish_timer(tm, stats);
+    if (r != TNMC_OK) return r;
+  }
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_counts(tnmc_lattice* lat, int64_t* proposed, int64_t* accepted) {
+  if (!lat) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  tnmc_status r = nn_counters(lat);
+  if (r != TNMC_OK) return r;
+  const size_t n = (size_t)lat->n_chains * lat->Lz;
+  std::vector<long long> c(n * tnmc::kCounterStride);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(c.data(), lat->dnncnt, c.size() * sizeof(long long), hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < n; ++i) {
+    if (proposed) proposed[i] = c[i * tnmc::kCounterStride];
+    if (accepted) accepted[i] = c[i * tnmc::kCounterStride + 1];
+  }
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_counts_reset(tnmc_lattice* lat) {
+  if (!lat) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  tnmc_status r = nn_counters(lat);
+  if (r != TNMC_OK) return r;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemset(lat->dnncnt, 0, (size_t)lat->n_chains * lat->Lz * tnmc::kCounterStride * sizeof(long long)));
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_set_fallback(tnmc_lattice* lat, const int8_t* flags) {
+  if (!lat) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  tnmc_status r = nn_counters(lat);
+  if (r != TNMC_OK) return r;
+  const size_t n = (size_t)lat->n_chains * lat->Lz;
+  if (flags) {
+    for (size_t i = 0; i < n; ++i)
+      if (flags[i] != 0 && flags[i] != 1) return TNMC_ERR_ARG;
+    lat->nn_fallback.assign(flags, flags + n);
+  } else {
+    lat->nn_fallback.assign(n, 0);
+  }
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_get_fallback(tnmc_lattice* lat, int8_t* flags) {
+  if (!lat || !flags) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  tnmc_status r = nn_counters(lat);
+  if (r != TNMC_OK) return r;
+  std::memcpy(flags, lat->nn_fallback.data(), lat->nn_fallback.size());
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_nn_calibrate_fallback(tnmc_lattice* lat, double threshold, int32_t* n_fallback) {
+  if (!lat || !(threshold >= 0.0) || !(threshold <= 1.0)) return TNMC_ERR_ARG;
+  const size_t n = (size_t)lat->n_chains * lat->Lz;
+  std::vector<int64_t> prop(n), acc(n);
+  tnmc_status r = tnmc_nn_counts(lat, prop.data(), acc.data());
+  if (r != TNMC_OK) return r;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  int cnt = 0;
+  for (size_t i = 0; i < n; ++i) {
+    // a layer never proposed keeps its current kernel
+    if (prop[i] > 0) lat->nn_fallback[i] = ((double)acc[i] < threshold * (double)prop[i]) ? 1 : 0;
+    cnt += lat->nn_fallback[i];
+  }
+  if (n_fallback) *n_fallback = cnt;
   return TNMC_OK;
 }
 

@@ -1,0 +1,634 @@
+// Learned autoregressive slice proposal: a masked-convolution network
+// q_theta(s | cond) over the sites of a layer in the tensor-network sampler's
+// order (rows, then sites within a row), used as the proposal of the
+// Metropolis-Hastings slice update of main text Eq. 1 in place of the
+// boundary-MPS conditionals (any exactly normalised q with an exact log q
+// keeps the chain exact), and trained by minibatch Adam on (cond, s) pairs.
+//
+// Network (Ising layers): input = four condition channels (Jz(z-1) s(z-1),
+// Jz(z) s(z+1), Jx, Jy; 0 where a neighbour or bond does not exist) seen
+// through full 3x3 windows, plus the layer's spins seen through a mask that
+// hides the centre and later sites; five 3x3 layers of 32 channels with ReLU
+// (the last four masked to earlier sites and the centre); a 3x3 masked output
+// channel, the logit of P(s = +1), clipped to [-30, 30].  Zero padding at the
+// open edges.  Parameters: one flat FP32 vector, per layer W[c_out][c_in][3][3]
+// then b[c_out].  Arithmetic in FP32; probabilities, log q, dE and the MH test
+// in FP64.
+//
+// Kernels:
+//  * nn_sample_kernel - one slice task per workgroup of two wavefronts:
+//    wavefront 0 draws the new layer site by site, wavefront 1 evaluates the
+//    current layer with the same arithmetic (teacher forcing), then dE and MH.
+//    Each site needs the six layers at that site only: a layer's value at a
+//    site depends on earlier sites and on the previous layer at the same
+//    site, so each wavefront keeps, per layer, a ring of the last Lx + 2
+//    sites' activations in LDS and the masked weights once per workgroup.
+//  * nn_fwd / nn_loss / nn_bwd_data / nn_bwd_weight / nn_grad_reduce /
+//    nn_adam - batched training: one workgroup per (sample, row) for the
+//    convolutions, a two-stage deterministic reduction for weight gradients.
+#include <math.h>
+
+#include "device_common.h"
+#include "nn_internal.h"
+#include "tnmc_internal.h"
+
+namespace tnmc {
+
+namespace {
+
+constexpr int C = kNnChannels;   // hidden channels
+constexpr int NCOND = kNnCond;   // condition channels
+constexpr int NHID = 4;          // masked 32 -> 32 layers
+constexpr float CLIP = 30.0f;
+constexpr int NTS = 128;         // sampler: one wavefront per path
+
+// flat parameter offsets
+constexpr int OFF_W0 = 0;
+constexpr int OFF_B0 = OFF_W0 + C * (NCOND + 1) * 9;
+constexpr int HID = C * C * 9 + C;
+constexpr int OFF_H = OFF_B0 + C;
+constexpr int OFF_W5 = OFF_H + NHID * HID;
+constexpr int OFF_B5 = OFF_W5 + C * 9;
+static_assert(OFF_B5 + 1 == kNnParams, "parameter count");
+
+// Taps: k = ky * 3 + kx reads the site at (y + ky - 1, x + kx - 1).  Taps 0..3
+// are earlier sites (row above, left neighbour); tap 4 is the centre.
+__device__ __forceinline__ bool tap_kept(int layer, int ci, int k) {
+  if (layer == 0) return ci < NCOND || k < 4;
+  return k <= 4;
+}
+
+__device__ __forceinline__ double log_sigmoid(double t) { return -(fmax(-t, 0.0) + log1p(exp(-fabs(t)))); }
+
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Ordering of LDS accesses between the lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Condition channel c of site (y, x) of layer z (0 outside the layer).
+template <typename JP, typename SP>
+__device__ __forceinline__ float cond_value(JP J, SP spins, int Lx, int Ly, int Lz, int z, int c, int y, int x) {
+  if (y < 0 || y >= Ly || x < 0 || x >= Lx) return 0.0f;
+  const size_t plane = (size_t)Lx * Ly;
+  const size_t site = (size_t)y * Lx + x;
+  if (c == 0) return z > 0 ? J[2 * plane * Lz + (size_t)(z - 1) * plane + site] *
+                                 (float)(spins[(size_t)(z - 1) * plane + site] > 0 ? 1 : -1)
+                           : 0.0f;
+  if (c == 1) return z + 1 < Lz ? J[2 * plane * Lz + (size_t)z * plane + site] *
+                                      (float)(spins[(size_t)(z + 1) * plane + site] > 0 ? 1 : -1)
+                                : 0.0f;
+  if (c == 2) return J[(size_t)z * plane + site];
+  return J[plane * Lz + (size_t)z * plane + site];
+}
+
+// Sampler LDS layout (floats unless noted), shared by both paths:
+//   wc0 [C][NCOND][9]       layer 0, condition channels
+//   ws0 [C][4]              layer 0, spin channel, taps 0..3
+//   b0  [C]
+//   wh  [NHID][C][5][C]     hidden layers: [layer][c_out][tap][c_in]
+//   bh  [NHID][C]
+//   w5  [5][C], b5 (padded to 4)
+//   cp  [lx_max][C]         layer-0 pre-activation of the current row without the spin taps
+//   crow[3][NCOND][lx_max + 2]  condition channels of rows y-1, y, y+1, zero padded
+//   ring[2][NHID + 1][lx_max + 2][C]  per path, per layer output: the last lx + 2 sites
+//   uni [lx_max] doubles, then cfg [2][ly_max][lx_max] bytes (states: 0 = +1, 1 = -1)
+struct SampleLayout {
+  int wc0, ws0, b0, wh, bh, w5, b5, cp, crow, ring, uni_f, cfg_b, total_b;
+  __host__ __device__ SampleLayout(int lx_max, int ly_max) {
+    int o = 0;
+    wc0 = o; o += C * NCOND * 9;
+    ws0 = o; o += C * 4;
+    b0 = o; o += C;
+    wh = o; o += NHID * C * 5 * C;
+    bh = o; o += NHID * C;
+    w5 = o; o += 5 * C;
+    b5 = o; o += 4;
+    cp = o; o += lx_max * C;
+    crow = o; o += 3 * NCOND * (lx_max + 2);
+    o = (o + 3) & ~3;
+    ring = o; o += 2 * (NHID + 1) * (lx_max + 2) * C;
+    o = (o + 1) & ~1;
+    uni_f = o; o += 2 * lx_max;
+    cfg_b = o * 4;
+    total_b = cfg_b + 2 * lx_max * ly_max;
+  }
+};
+
+// dot product of 16 consecutive floats at a and b (16-byte aligned)
+__device__ __forceinline__ float dot16(const float* a, const float* b) {
+  const float4* a4 = reinterpret_cast<const float4*>(a);
+  const float4* b4 = reinterpret_cast<const float4*>(b);
+  float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 u = a4[q], v = b4[q];
+    s0 = fmaf(u.x, v.x, s0);
+    s1 = fmaf(u.y, v.y, s1);
+    s0 = fmaf(u.z, v.z, s0);
+    s1 = fmaf(u.w, v.w, s1);
+  }
+  return s0 + s1;
+}
+
+__global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restrict__ tasks,
+                                                        const float* __restrict__ theta_in, uint64_t sweep,
+                                                        int lx_max, int ly_max) {
+  extern __shared__ __align__(16) float lds[];
+  __shared__ double lq_sh[2];
+  __shared__ int fault_sh[2];
+  const TaskDesc& t = tasks[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int path = tid >> 6;   // 0: new layer (drawn), 1: current layer (forced)
+  const int lane = tid & 63;
+  const int Lx = t.Lx, Ly = t.Ly, Lz = t.Lz, z = t.z;
+  const double beta = t.beta;
+  const gptr<const float> J = gmem(t.J);
+  const gptr<int8_t> spins = gmem(t.spins);
+  const gptr<const float> theta = gmem(theta_in);
+  const size_t plane = (size_t)Lx * Ly;
+  const gptr<const int8_t> forced = (path == 1) ? gmem(static_cast<const int8_t*>(t.spins + (size_t)z * plane))
+                                                : gmem(t.force_new);
+  acquire_device();
+  const SampleLayout L(lx_max, ly_max);
+  float* wc0 = lds + L.wc0;
+  float* ws0 = lds + L.ws0;
+  float* b0 = lds + L.b0;
+  float* wh = lds + L.wh;
+  float* bh = lds + L.bh;
+  float* w5 = lds + L.w5;
+  float* cp = lds + L.cp;
+  float* crow = lds + L.crow;
+  const int RING = Lx + 2;
+  float* ring = lds + L.ring + (size_t)path * (NHID + 1) * (lx_max + 2) * C;
+  double* uni = reinterpret_cast<double*>(lds + L.uni_f);
+  int8_t* cfg = reinterpret_cast<int8_t*>(lds) + L.cfg_b;
+#define CFG(p, y, x) cfg[((size_t)(p) * ly_max + (y)) * lx_max + (x)]
+
+  // masked weights into LDS in the sampler's layout
+  for (int i = tid; i < C * NCOND * 9; i += NTS) {
+    const int co = i / (NCOND * 9), r = i % (NCOND * 9);
+    wc0[i] = theta[OFF_W0 + co * (NCOND + 1) * 9 + r];
+  }
+  for (int i = tid; i < C * 4; i += NTS) ws0[i] = theta[OFF_W0 + ((i >> 2) * (NCOND + 1) + NCOND) * 9 + (i & 3)];
+  for (int i = tid; i < C; i += NTS) b0[i] = theta[OFF_B0 + i];
+  for (int i = tid; i < NHID * C * 5 * C; i += NTS) {
+    const int l = i / (C * 5 * C), r = i % (C * 5 * C);
+    const int co = r / (5 * C), k = (r / C) % 5, ci = r % C;
+    wh[i] = theta[OFF_H + l * HID + (co * C + ci) * 9 + k];
+  }
+  for (int i = tid; i < NHID * C; i += NTS) bh[i] = theta[OFF_H + (i / C) * HID + C * C * 9 + (i % C)];
+  for (int i = tid; i < 5 * C; i += NTS) w5[i] = theta[OFF_W5 + (i % C) * 9 + i / C];
+  if (tid == 0) lds[L.b5] = theta[OFF_B5];
+  for (int i = tid; i < 2 * (NHID + 1) * (lx_max + 2) * C; i += NTS) lds[L.ring + i] = 0.0f;
+  // configuration tiles: the forced layers ahead of the walk
+  const bool have_forced = (path == 1) || (t.force_new != nullptr);
+  if (have_forced)
+    for (int i = lane; i < Ly * Lx; i += 64) CFG(path, i / Lx, i % Lx) = (int8_t)state_of<2>(forced[i]);
+  __syncthreads();
+
+  const int co = lane >> 1, h = lane & 1;
+  double logq = 0.0;
+  int fault = 0;
+  for (int y = 0; y < Ly; ++y) {
+    // condition channels of rows y-1..y+1 and the row's uniforms
+    for (int i = tid; i < 3 * NCOND * (Lx + 2); i += NTS) {
+      const int rr = i / (NCOND * (Lx + 2)), c = (i / (Lx + 2)) % NCOND, xx = i % (Lx + 2);
+      crow[(rr * NCOND + c) * (lx_max + 2) + xx] = cond_value(J, spins, Lx, Ly, Lz, z, c, y + rr - 1, xx - 1);
+    }
+    for (int x = tid; x < Lx; x += NTS) uni[x] = philox_uniform((uint64_t)(y * Lx + x), (uint64_t)z, sweep, 0ull, t.key0, t.key1);
+    __syncthreads();
+    // layer-0 pre-activations of the row without the spin taps
+    for (int i = tid; i < C * Lx; i += NTS) {
+      const int c_out = i & (C - 1), x = i / C;
+      float acc = b0[c_out];
+      const float* w = wc0 + c_out * NCOND * 9;
+#pragma unroll
+      for (int c = 0; c < NCOND; ++c)
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+          acc = fmaf(w[c * 9 + k], crow[((k / 3) * NCOND + c) * (lx_max + 2) + x + (k % 3)], acc);
+      cp[x * C + c_out] = acc;
+    }
+    __syncthreads();
+    for (int x = 0; x < Lx; ++x) {
+      const int f = y * Lx + x;
+      const int r = f % RING;
+      const bool up = y > 0, left = x > 0, right = x + 1 < Lx;
+      // ring slots of the taps 0..4: sites f - Lx - 1, f - Lx, f - Lx + 1, f - 1, f
+      const int rs0 = (r + RING - Lx - 1) % RING, rs1 = (r + RING - Lx) % RING, rs2 = (r + RING - Lx + 1) % RING;
+      const int rs3 = (r + RING - 1) % RING, rs4 = r;
+      // layer 0: spin taps
+      {
+        float a = cp[x * C + co];
+        if (up) {
+          if (left) a = fmaf(ws0[co * 4 + 0], 1.0f - 2.0f * CFG(path, y - 1, x - 1), a);
+          a = fmaf(ws0[co * 4 + 1], 1.0f - 2.0f * CFG(path, y - 1, x), a);
+          if (right) a = fmaf(ws0[co * 4 + 2], 1.0f - 2.0f * CFG(path, y - 1, x + 1), a);
+        }
+        if (left) a = fmaf(ws0[co * 4 + 3], 1.0f - 2.0f * CFG(path, y, x - 1), a);
+        if (h == 0) ring[(size_t)r * C + co] = fmaxf(a, 0.0f);
+      }
+      wave_sync();
+      // hidden layers
+#pragma unroll 1
+      for (int l = 0; l < NHID; ++l) {
+        const float* R = ring + (size_t)l * (lx_max + 2) * C + 16 * h;
+        const float* W = wh + ((size_t)l * C + co) * 5 * C + 16 * h;
+        float acc = 0.0f;
+        if (up) {
+          if (left) acc += dot16(W + 0 * C, R + rs0 * C);
+          acc += dot16(W + 1 * C, R + rs1 * C);
+          if (right) acc += dot16(W + 2 * C, R + rs2 * C);
+        }
+        if (left) acc += dot16(W + 3 * C, R + rs3 * C);
+        acc += dot16(W + 4 * C, R + rs4 * C);
+        acc += __shfl_xor(acc, 1, 64);
+        const float a = fmaxf(acc + bh[l * C + co], 0.0f);
+        if (h == 0) ring[((size_t)(l + 1) * (lx_max + 2) + r) * C + co] = a;
+        wave_sync();
+      }
+      // output logit: 5 taps x 32 channels over the wavefront
+      float part = 0.0f;
+      {
+        const float* R = ring + (size_t)NHID * (lx_max + 2) * C;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const int i = lane + 64 * q;
+          if (i < 5 * C) {
+            const int k = i / C, ci = i % C;
+            const bool ok = (k == 0) ? (up && left) : (k == 1) ? up : (k == 2) ? (up && right) : (k == 3) ? left : true;
+            const int rs = (k == 0) ? rs0 : (k == 1) ? rs1 : (k == 2) ? rs2 : (k == 3) ? rs3 : rs4;
+            if (ok) part = fmaf(w5[i], R[rs * C + ci], part);
+          }
+        }
+      }
+      const float logit = wave_sum_f(part) + lds[L.b5];
+      if (!(fabsf(logit) <= 3.0e38f)) fault |= 1;   // NaN or infinite
+      const float lc = fminf(fmaxf(logit, -CLIP), CLIP);
+      const double p_plus = 1.0 / (1.0 + exp(-(double)lc));
+      int st;
+      if (have_forced) {
+        st = CFG(path, y, x);
+      } else {
+        st = (uni[x] < p_plus) ? 0 : 1;
+      }
+      logq += log_sigmoid(st == 0 ? (double)lc : -(double)lc);
+      if (!have_forced && lane == 0) CFG(path, y, x) = (int8_t)st;
+      wave_sync();
+    }
+    __syncthreads();
+  }
+  if (lane == 0) {
+    lq_sh[path] = logq;
+    fault_sh[path] = fault;
+  }
+  __syncthreads();
+  if (path != 0) return;
+
+  // energy change E(new) - E(current): in-layer bonds and held-layer field
+  double dE = 0.0;
+  for (int i = lane; i < Ly * Lx; i += 64) {
+    const int y = i / Lx, x = i % Lx;
+    const int a = CFG(0, y, x), o = CFG(1, y, x);
+    double e = -(held_field<2>(J, spins, Lx, Ly, Lz, z, y, x, a) - held_field<2>(J, spins, Lx, Ly, Lz, z, y, x, o));
+    if (x + 1 < Lx) {
+      const double jx = (double)J[(size_t)z * plane + (size_t)y * Lx + x];
+      e -= jx * (sigma<2>(a, CFG(0, y, x + 1)) - sigma<2>(o, CFG(1, y, x + 1)));
+    }
+    if (y + 1 < Ly) {
+      const double jy = (double)J[plane * Lz + (size_t)z * plane + (size_t)y * Lx + x];
+      e -= jy * (sigma<2>(a, CFG(0, y + 1, x)) - sigma<2>(o, CFG(1, y + 1, x)));
+    }
+    dE += e;
+  }
+  dE = wave_sum(dE);
+  const double lq_new = lq_sh[0], lq_old = lq_sh[1];
+  const int any_fault = (fault_sh[0] | fault_sh[1]) ? 1 : 0;
+  const double lr = lq_old - lq_new - beta * dE;
+  const double Uacc = philox_uniform(0ull, (uint64_t)z, sweep, 1ull, t.key0, t.key1);
+  const int accepted = (!any_fault && Uacc < exp(fmin(0.0, lr))) ? 1 : 0;
+  if (t.s_new_out) {
+    for (int i = lane; i < Ly * Lx; i += 64) t.s_new_out[i] = spin_of<2>(CFG(0, i / Lx, i % Lx));
+  }
+  if (t.write_back && accepted) {
+    for (int i = lane; i < Ly * Lx; i += 64) spins[(size_t)z * plane + i] = spin_of<2>(CFG(0, i / Lx, i % Lx));
+  }
+#undef CFG
+  if (lane == 0) {
+    if (t.record) {
+      t.record[0] = lq_new;
+      t.record[1] = lq_old;
+      t.record[2] = dE;
+      t.record[3] = (double)accepted;
+      t.record[4] = (double)(fault_sh[0] | (fault_sh[1] << 2));
+    }
+    if (t.counters) {
+      add_device(t.counters + 0, 1);
+      add_device(t.counters + 1, accepted);
+      add_device(t.counters + 2, any_fault);
+    }
+  }
+  release_device();
+}
+
+// ---------------------------------------------------------------- training
+
+constexpr int NTT = 256;
+constexpr int LXT = kNnLxMax;
+
+template <int LAYER>
+struct LayerShape {
+  static constexpr int CIN = LAYER == 0 ? NCOND + 1 : C;
+  static constexpr int COUT = LAYER == 5 ? 1 : C;
+  static constexpr int OFF = LAYER == 0 ? OFF_W0 : LAYER == 5 ? OFF_W5 : OFF_H + (LAYER - 1) * HID;
+  static constexpr int NW = COUT * CIN * 9;
+};
+
+// Input x of layer LAYER at (sample b, channel ci, row y, column x), zero outside.
+template <int LAYER>
+__device__ __forceinline__ float layer_input(const float* act_prev, const float* cond, const int8_t* s, int b,
+                                             int ci, int y, int x, int Lx, int Ly) {
+  if (y < 0 || y >= Ly || x < 0 || x >= Lx) return 0.0f;
+  const size_t plane = (size_t)Lx * Ly;
+  const size_t site = (size_t)y * Lx + x;
+  if constexpr (LAYER == 0) {
+    if (ci < NCOND) return cond[((size_t)b * NCOND + ci) * plane + site];
+    return s[(size_t)b * plane + site] > 0 ? 1.0f : -1.0f;
+  } else {
+    return act_prev[((size_t)b * C + ci) * plane + site];
+  }
+}
+
+// out[b][co][y][x] = act(b_co + sum masked W x); ReLU for layers 0..4, the raw
+// logit for layer 5.  One workgroup per (sample, row).
+template <int LAYER>
+__global__ __launch_bounds__(NTT) void nn_fwd_kernel(const float* __restrict__ theta, const float* __restrict__ act_prev,
+                                                     const float* __restrict__ cond, const int8_t* __restrict__ s,
+                                                     float* __restrict__ out, int Lx, int Ly) {
+  using S = LayerShape<LAYER>;
+  __shared__ float wm[S::NW];
+  __shared__ float bs[S::COUT];
+  __shared__ float xs[S::CIN * 3 * (LXT + 2)];
+  const int b = blockIdx.x / Ly, y = blockIdx.x % Ly;
+  const int XS = Lx + 2;
+  for (int i = threadIdx.x; i < S::NW; i += NTT) {
+    const int ci = (i / 9) % S::CIN, k = i % 9;
+    wm[i] = tap_kept(LAYER, ci, k) ? theta[S::OFF + i] : 0.0f;
+  }
+  for (int i = threadIdx.x; i < S::COUT; i += NTT) bs[i] = theta[S::OFF + S::NW + i];
+  for (int i = threadIdx.x; i < S::CIN * 3 * XS; i += NTT) {
+    const int ci = i / (3 * XS), rr = (i / XS) % 3, xx = i % XS;
+    xs[i] = layer_input<LAYER>(act_prev, cond, s, b, ci, y + rr - 1, xx - 1, Lx, Ly);
+  }
+  __syncthreads();
+  const size_t plane = (size_t)Lx * Ly;
+  for (int e = threadIdx.x; e < S::COUT * Lx; e += NTT) {
+    const int c_out = e / Lx, x = e % Lx;
+    float acc = bs[c_out];
+    const float* w = wm + c_out * S::CIN * 9;
+    for (int ci = 0; ci < S::CIN; ++ci) {
+      const float* xr = xs + ci * 3 * XS + x;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc = fmaf(w[ci * 9 + k], xr[(k / 3) * XS + (k % 3)], acc);
+    }
+    out[((size_t)b * S::COUT + c_out) * plane + (size_t)y * Lx + x] = (LAYER < 5) ? fmaxf(acc, 0.0f) : acc;
+  }
+}
+
+// Per sample: log q (FP64) and d(mean -log q)/d logit (0 where the clip is active).
+__global__ __launch_bounds__(NTT) void nn_loss_kernel(const float* __restrict__ logit, const int8_t* __restrict__ s,
+                                                      double* __restrict__ logq, float* __restrict__ glogit,
+                                                      int plane, double inv_batch) {
+  __shared__ double red[NTT / 64];
+  const int b = blockIdx.x;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < plane; j += NTT) {
+    const size_t i = (size_t)b * plane + j;
+    const float l = logit[i];
+    const double sp = s[i] > 0 ? 1.0 : -1.0;
+    const double lc = (l != l) ? (double)l : (double)fminf(fmaxf(l, -CLIP), CLIP);
+    acc += log_sigmoid(sp * lc);
+    glogit[i] = (fabsf(l) < CLIP) ? (float)(-sp / (1.0 + exp(sp * lc)) * inv_batch) : 0.0f;
+  }
+  acc = block_sum<NTT>(acc, red);
+  if (threadIdx.x == 0) logq[b] = acc;
+}
+
+// gin[b][ci][y][x] = [act_prev > 0] sum_co sum_k Wm[co][ci][k] g[b][co][y - dy_k][x - dx_k]
+// (layers 1..5; act_prev is the layer's input, the previous layer's output).
+template <int LAYER>
+__global__ __launch_bounds__(NTT) void nn_bwd_data_kernel(const float* __restrict__ theta, const float* __restrict__ g,
+                                                          const float* __restrict__ act_prev,
+                                                          float* __restrict__ gin, int Lx, int Ly) {
+  using S = LayerShape<LAYER>;
+  static_assert(LAYER > 0, "no input gradient for the first layer");
+  __shared__ float wm[S::NW];
+  __shared__ float gs[S::COUT * 3 * (LXT + 2)];
+  const int b = blockIdx.x / Ly, y = blockIdx.x % Ly;
+  const int XS = Lx + 2;
+  const size_t plane = (size_t)Lx * Ly;
+  for (int i = threadIdx.x; i < S::NW; i += NTT) wm[i] = tap_kept(LAYER, (i / 9) % S::CIN, i % 9) ? theta[S::OFF + i] : 0.0f;
+  // rows y+1, y, y-1 of g (row rr holds y + 1 - rr), zero padded
+  for (int i = threadIdx.x; i < S::COUT * 3 * XS; i += NTT) {
+    const int co = i / (3 * XS), rr = (i / XS) % 3, xx = i % XS;
+    const int yy = y + 1 - rr, x = xx - 1;
+    gs[i] = (yy >= 0 && yy < Ly && x >= 0 && x < Lx) ? g[((size_t)b * S::COUT + co) * plane + (size_t)yy * Lx + x] : 0.0f;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < S::CIN * Lx; e += NTT) {
+    const int ci = e / Lx, x = e % Lx;
+    const size_t o = ((size_t)b * S::CIN + ci) * plane + (size_t)y * Lx + x;
+    float acc = 0.0f;
+    for (int co = 0; co < S::COUT; ++co) {
+      const float* w = wm + (co * S::CIN + ci) * 9;
+      const float* gr = gs + co * 3 * XS;
+      // tap k = ky*3 + kx reads g at (y - ky + 1, x - kx + 1): row slot ky, column x + 2 - kx (padded)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc = fmaf(w[k], gr[(k / 3) * XS + x + 2 - (k % 3)], acc);
+    }
+    gin[o] = act_prev[o] > 0.0f ? acc : 0.0f;
+  }
+}
+
+// Weight and bias gradient partials of layer LAYER: workgroup w sums over the
+// (sample, row) pairs w, w + G, ...; part[w][e] for e < NW + COUT.
+template <int LAYER>
+__global__ __launch_bounds__(NTT) void nn_bwd_weight_kernel(const float* __restrict__ g, const float* __restrict__ act_prev,
+                                                            const float* __restrict__ cond, const int8_t* __restrict__ s,
+                                                            float* __restrict__ part, int n_rows, int Lx, int Ly) {
+  using S = LayerShape<LAYER>;
+  constexpr int NE = S::NW + S::COUT;
+  constexpr int EPT = (NE + NTT - 1) / NTT;
+  __shared__ float xs[S::CIN * 3 * (LXT + 2)];
+  __shared__ float gs[S::COUT * LXT];
+  const int XS = Lx + 2;
+  const size_t plane = (size_t)Lx * Ly;
+  float acc[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) acc[q] = 0.0f;
+  for (int row = blockIdx.x; row < n_rows; row += gridDim.x) {
+    const int b = row / Ly, y = row % Ly;
+    __syncthreads();
+    for (int i = threadIdx.x; i < S::CIN * 3 * XS; i += NTT) {
+      const int ci = i / (3 * XS), rr = (i / XS) % 3, xx = i % XS;
+      xs[i] = layer_input<LAYER>(act_prev, cond, s, b, ci, y + rr - 1, xx - 1, Lx, Ly);
+    }
+    for (int i = threadIdx.x; i < S::COUT * Lx; i += NTT)
+      gs[i] = g[((size_t)b * S::COUT + i / Lx) * plane + (size_t)y * Lx + i % Lx];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + q * NTT;
+      if (e < S::NW) {
+        const int c_out = e / (S::CIN * 9), ci = (e / 9) % S::CIN, k = e % 9;
+        const float* gr = gs + c_out * Lx;
+        const float* xr = xs + (ci * 3 + k / 3) * XS + (k % 3);
+        float a = 0.0f;
+        for (int x = 0; x < Lx; ++x) a = fmaf(gr[x], xr[x], a);
+        acc[q] += a;
+      } else if (e < NE) {
+        const float* gr = gs + (e - S::NW) * Lx;
+        float a = 0.0f;
+        for (int x = 0; x < Lx; ++x) a += gr[x];
+        acc[q] += a;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + q * NTT;
+    if (e < NE) part[(size_t)blockIdx.x * NE + e] = acc[q];
+  }
+}
+
+// grad[OFF + e] = sum_w part[w][e] (FP64 sum), masked weights zeroed.
+template <int LAYER>
+__global__ __launch_bounds__(NTT) void nn_grad_reduce_kernel(const float* __restrict__ part, int n_parts,
+                                                             float* __restrict__ grad) {
+  using S = LayerShape<LAYER>;
+  constexpr int NE = S::NW + S::COUT;
+  const int e = blockIdx.x * NTT + threadIdx.x;
+  if (e >= NE) return;
+  double a = 0.0;
+  for (int w = 0; w < n_parts; ++w) a += (double)part[(size_t)w * NE + e];
+  const bool kept = e >= S::NW || tap_kept(LAYER, (e / 9) % S::CIN, e % 9);
+  grad[S::OFF + e] = kept ? (float)a : 0.0f;
+}
+
+__global__ __launch_bounds__(NTT) void nn_adam_kernel(float* __restrict__ theta, float* __restrict__ m,
+                                                      float* __restrict__ v, const float* __restrict__ grad, int n,
+                                                      float lr, float b1, float b2, float c1, float c2, float eps) {
+  const int i = blockIdx.x * NTT + threadIdx.x;
+  if (i >= n) return;
+  const float gi = grad[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+template <int LAYER>
+hipError_t bwd_weight(const NnBatch& B, const float* g, const float* act_prev, float* grad, hipStream_t s) {
+  using S = LayerShape<LAYER>;
+  constexpr int NE = S::NW + S::COUT;
+  const int n_rows = B.n * B.Ly;
+  const int G = std::min(n_rows, kNnWeightParts);
+  hipLaunchKernelGGL(nn_bwd_weight_kernel<LAYER>, dim3(G), dim3(NTT), 0, s, g, act_prev, B.cond, B.s, B.part, n_rows,
+                     B.Lx, B.Ly);
+  hipLaunchKernelGGL(nn_grad_reduce_kernel<LAYER>, dim3((NE + NTT - 1) / NTT), dim3(NTT), 0, s, B.part, G, grad);
+  return hipGetLastError();
+}
+
+// Condition channels and current layer of every (chain, z) of a lattice:
+// sample i = chain * Lz + z.
+__global__ __launch_bounds__(NTT) void nn_dataset_kernel(const float* const* __restrict__ Jc,
+                                                         int8_t* const* __restrict__ spins, int Lx, int Ly, int Lz,
+                                                         float* __restrict__ cond, int8_t* __restrict__ s) {
+  acquire_device();
+  const int i = blockIdx.x;
+  const int c = i / Lz, z = i % Lz;
+  const gptr<const float> J = gmem(Jc[c]);
+  const gptr<const int8_t> sp = gmem(static_cast<const int8_t*>(spins[c]));
+  const size_t plane = (size_t)Lx * Ly;
+  for (int j = threadIdx.x; j < (int)plane; j += NTT) {
+    const int y = j / Lx, x = j % Lx;
+#pragma unroll
+    for (int ch = 0; ch < NCOND; ++ch)
+      cond[((size_t)i * NCOND + ch) * plane + j] = cond_value(J, sp, Lx, Ly, Lz, z, ch, y, x);
+    s[(size_t)i * plane + j] = sp[(size_t)z * plane + j] > 0 ? 1 : -1;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_nn_dataset(const float* const* Jc, int8_t* const* spins, int n_chains, int Lx, int Ly, int Lz,
+                             float* cond, int8_t* s, hipStream_t st) {
+  hipLaunchKernelGGL(nn_dataset_kernel, dim3(n_chains * Lz), dim3(NTT), 0, st, Jc, spins, Lx, Ly, Lz, cond, s);
+  return hipGetLastError();
+}
+
+size_t nn_sample_lds_bytes(int lx_max, int ly_max) { return (size_t)SampleLayout(lx_max, ly_max).total_b; }
+
+hipError_t launch_nn_sample(const TaskDesc* tasks, int n, const float* theta, int lx_max, int ly_max, uint64_t sweep,
+                            hipStream_t s) {
+  const size_t bytes = nn_sample_lds_bytes(lx_max, ly_max);
+  static size_t attr_bytes = 0;
+  if (bytes > attr_bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)nn_sample_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)bytes);
+    if (e != hipSuccess) return e;
+    attr_bytes = bytes;
+  }
+  hipLaunchKernelGGL(nn_sample_kernel, dim3(n), dim3(NTS), bytes, s, tasks, theta, sweep, lx_max, ly_max);
+  return hipGetLastError();
+}
+
+hipError_t nn_forward(const NnBatch& B, const float* theta, hipStream_t s) {
+  const dim3 grid(B.n * B.Ly), blk(NTT);
+  hipLaunchKernelGGL(nn_fwd_kernel<0>, grid, blk, 0, s, theta, nullptr, B.cond, B.s, B.act[0], B.Lx, B.Ly);
+  hipLaunchKernelGGL(nn_fwd_kernel<1>, grid, blk, 0, s, theta, B.act[0], nullptr, nullptr, B.act[1], B.Lx, B.Ly);
+  hipLaunchKernelGGL(nn_fwd_kernel<2>, grid, blk, 0, s, theta, B.act[1], nullptr, nullptr, B.act[2], B.Lx, B.Ly);
+  hipLaunchKernelGGL(nn_fwd_kernel<3>, grid, blk, 0, s, theta, B.act[2], nullptr, nullptr, B.act[3], B.Lx, B.Ly);
+  hipLaunchKernelGGL(nn_fwd_kernel<4>, grid, blk, 0, s, theta, B.act[3], nullptr, nullptr, B.act[4], B.Lx, B.Ly);
+  hipLaunchKernelGGL(nn_fwd_kernel<5>, grid, blk, 0, s, theta, B.act[4], nullptr, nullptr, B.logit, B.Lx, B.Ly);
+  hipLaunchKernelGGL(nn_loss_kernel, dim3(B.n), blk, 0, s, B.logit, B.s, B.logq, B.glogit, B.Lx * B.Ly,
+                     1.0 / (double)B.n);
+  return hipGetLastError();
+}
+
+hipError_t nn_backward(const NnBatch& B, const float* theta, float* grad, hipStream_t s) {
+  const dim3 grid(B.n * B.Ly), blk(NTT);
+  hipError_t e;
+  // layer 5: g = dlogit; input act[4]
+  if ((e = bwd_weight<5>(B, B.glogit, B.act[4], grad, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(nn_bwd_data_kernel<5>, grid, blk, 0, s, theta, B.glogit, B.act[4], B.g[0], B.Lx, B.Ly);
+  if ((e = bwd_weight<4>(B, B.g[0], B.act[3], grad, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(nn_bwd_data_kernel<4>, grid, blk, 0, s, theta, B.g[0], B.act[3], B.g[1], B.Lx, B.Ly);
+  if ((e = bwd_weight<3>(B, B.g[1], B.act[2], grad, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(nn_bwd_data_kernel<3>, grid, blk, 0, s, theta, B.g[1], B.act[2], B.g[0], B.Lx, B.Ly);
+  if ((e = bwd_weight<2>(B, B.g[0], B.act[1], grad, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(nn_bwd_data_kernel<2>, grid, blk, 0, s, theta, B.g[0], B.act[1], B.g[1], B.Lx, B.Ly);
+  if ((e = bwd_weight<1>(B, B.g[1], B.act[0], grad, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(nn_bwd_data_kernel<1>, grid, blk, 0, s, theta, B.g[1], B.act[0], B.g[0], B.Lx, B.Ly);
+  if ((e = bwd_weight<0>(B, B.g[0], nullptr, grad, s)) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t nn_adam(float* theta, float* m, float* v, const float* grad, int64_t step, double lr, hipStream_t s) {
+  const double c1 = 1.0 / (1.0 - std::pow(kNnAdamB1, (double)step));
+  const double c2 = 1.0 / (1.0 - std::pow(kNnAdamB2, (double)step));
+  hipLaunchKernelGGL(nn_adam_kernel, dim3((kNnParams + NTT - 1) / NTT), dim3(NTT), 0, s, theta, m, v, grad, kNnParams,
+                     (float)lr, (float)kNnAdamB1, (float)kNnAdamB2, (float)c1, (float)c2, (float)kNnAdamEps);
+  return hipGetLastError();
+}
+
+}  // namespace tnmc

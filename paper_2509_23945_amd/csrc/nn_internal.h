@@ -1,0 +1,48 @@
+// Internal declarations of the learned autoregressive proposal (nn.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "tnmc_internal.h"
+
+namespace tnmc {
+
+constexpr int kNnChannels = 32;
+constexpr int kNnCond = 4;
+constexpr int kNnLayers = 6;
+constexpr int kNnParams = 38753;   // (5*32*9 + 32) + 4 (32*32*9 + 32) + (32*9 + 1)
+constexpr int kNnLxMax = 64;       // widest layer of the batched training kernels
+constexpr int kNnWeightParts = 256;   // workgroups of the weight-gradient partial sums
+constexpr double kNnAdamB1 = 0.9, kNnAdamB2 = 0.999, kNnAdamEps = 1e-8;
+
+// Device buffers of one training / evaluation batch of n layers of Lx x Ly.
+struct NnBatch {
+  int n = 0, Lx = 0, Ly = 0;
+  const float* cond = nullptr;   // [n][4][Ly][Lx]
+  const int8_t* s = nullptr;     // [n][Ly][Lx], +1 / -1
+  float* act[5] = {};            // outputs of layers 0..4 after ReLU, [n][32][Ly][Lx]
+  float* logit = nullptr;        // [n][Ly][Lx], before the clip
+  float* glogit = nullptr;       // d(mean -log q)/d logit
+  float* g[2] = {};              // back-propagated gradients, [n][32][Ly][Lx]
+  double* logq = nullptr;        // [n]
+  float* part = nullptr;         // [kNnWeightParts][32*32*9 + 32]
+};
+
+size_t nn_sample_lds_bytes(int lx_max, int ly_max);
+hipError_t launch_nn_sample(const TaskDesc* tasks, int n, const float* theta, int lx_max, int ly_max, uint64_t sweep,
+                            hipStream_t s);
+// Forward pass of a batch: activations, logits, log q per layer and the logit gradient of the mean loss.
+hipError_t nn_forward(const NnBatch& B, const float* theta, hipStream_t s);
+// Parameter gradient of the mean -log q of the batch after nn_forward.
+hipError_t nn_backward(const NnBatch& B, const float* theta, float* grad, hipStream_t s);
+// Adam step number `step` (from 1).
+hipError_t nn_adam(float* theta, float* m, float* v, const float* grad, int64_t step, double lr, hipStream_t s);
+// Condition channels [n_chains * Lz][4][Ly][Lx] and layers of a lattice's current state.
+hipError_t launch_nn_dataset(const float* const* Jc, int8_t* const* spins, int n_chains, int Lx, int Ly, int Lz,
+                             float* cond, int8_t* s, hipStream_t st);
+
+}  // namespace tnmc

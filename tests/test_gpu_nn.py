@@ -1,0 +1,284 @@
+"""The learned proposal's HIP kernels against the FP64 oracle (oracle.nn).
+
+The network runs in FP32 on the GPU and in FP64 in the oracle, so values are
+compared within tolerances derived from FP32 rounding (log q and logits 1e-4
+relative, the gradient 1e-4 of its largest entry); decisions taken by floating
+point (a site's spin) are checked for consistency with the oracle's
+probability at that site, except within 1e-5 of a tie.  dE is exact."""
+import math
+
+import numpy as np
+import pytest
+
+import bruteforce as bf
+import gpu_helpers as gh
+import paper_2509_23945_amd as tn
+import synth
+from oracle import model
+from oracle import nn as onn
+from oracle import philox
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = onn.layer_shapes()
+TIE = 1e-5
+
+
+def torch_dev():
+    import torch
+    return torch
+
+
+def to_dev(a):
+    torch = torch_dev()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def make_pairs(Lx, Ly, Lz, n, seed):
+    """n (cond, s) pairs from random +-J lattices (layer z = i % Lz of lattice i // Lz)."""
+    conds, spins = [], []
+    for i in range(n):
+        J = synth.couplings_pm_j(Lx, Ly, Lz, seed + i)
+        s = synth.spins_random(Lx, Ly, Lz, 100 * seed + i, 2)
+        z = i % Lz
+        conds.append(onn.cond_channels(J, s, z))
+        spins.append(s[z])
+    return np.stack(conds).astype(np.float32), np.stack(spins).astype(np.int8)
+
+
+def params(seed, scale=1.0):
+    return synth.nn_params(seed, SHAPES, scale)
+
+
+def close(a, b, rel=1e-4):
+    return abs(a - b) <= rel * max(1.0, abs(a), abs(b))
+
+
+@pytest.mark.parametrize("Lx,Ly,n,scale", [(7, 5, 3, 1.0), (8, 8, 2, 2.0), (33, 3, 2, 1.0), (32, 32, 2, 1.0)])
+def test_nn_logq_batch(Lx, Ly, n, scale):
+    torch = torch_dev()
+    gh.announce(f"nn logq batch {Lx}x{Ly} n={n}")
+    th = params(1, scale)
+    cond, s = make_pairs(Lx, Ly, 4, n, 7)
+    net = tn.tnmc_nn_create(th)
+    dc, ds = to_dev(cond), to_dev(s)
+    out = torch.zeros(n, dtype=torch.float64, device="cuda")
+    tn.tnmc_nn_logq(net, dc.data_ptr(), ds.data_ptr(), n, Lx, Ly, out.data_ptr())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for i in range(n):
+        ref = onn.logq(th.astype(np.float64), cond[i], s[i])
+        assert close(got[i], ref), (i, got[i], ref)
+
+
+@pytest.mark.parametrize("Lx,Ly,Lz,z,scale", [(6, 5, 4, 1, 1.0), (9, 7, 3, 0, 2.0), (5, 6, 3, 2, 1.0),
+                                               (16, 12, 4, 2, 1.0), (32, 32, 4, 1, 1.0)])
+def test_nn_slice_propose(Lx, Ly, Lz, z, scale):
+    gh.announce(f"nn propose {Lx}x{Ly}x{Lz} z={z}")
+    th = params(2, scale)
+    lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, 2, 4, kind="pmj", beta=1.0, seed=4)
+    net = tn.tnmc_nn_create(th)
+    th64 = th.astype(np.float64)
+    cond = onn.cond_channels(J[0], spins[0], z)
+    for sweep in (0, 5):
+        s_new, lq_new, lq_old, dE, st = tn.tnmc_nn_slice_propose(lat, net, 0, z, sweep)
+        assert st == 0
+        # every site's choice is the one the oracle's probability gives, up to ties
+        logits = onn.forward(th64, cond, s_new)
+        U = onn.site_uniforms(12345, 0, sweep, z, Ly, Lx)
+        p_plus = 1.0 / (1.0 + np.exp(-logits))
+        want_plus = U < p_plus
+        mismatch = (s_new > 0) != want_plus
+        assert np.all(np.abs(U - p_plus)[mismatch] < TIE), np.argwhere(mismatch)
+        assert close(lq_new, onn.logq(th64, cond, s_new))
+        assert close(lq_old, onn.logq(th64, cond, spins[0][z]))
+        after = spins[0].copy()
+        after[z] = s_new
+        assert dE == model.energy(J[0], after, 2) - model.energy(J[0], spins[0], 2)
+        # the forced evaluation runs the same arithmetic as the drawing walk
+        assert tn.tnmc_nn_slice_logq(lat, net, 0, z, s_new) == lq_new
+
+
+def test_nn_slice_propose_matches_oracle_draws():
+    """Small layer: the GPU's drawn layer equals the oracle sampler's (no tie
+    within 1e-5 on these seeds)."""
+    gh.announce("nn propose vs oracle sampler 5x4x3")
+    th = params(3, 2.0)
+    lat, J, spins, _ = gh.make_lattice(5, 4, 3, 2, 4, kind="gauss", beta=0.7, seed=6)
+    net = tn.tnmc_nn_create(th)
+    th64 = th.astype(np.float64)
+    for z in range(3):
+        rec = onn.propose(th64, J[0], spins[0], z, seed=12345, chain_key=0, sweep=3)
+        s_new, lq_new, lq_old, dE, st = tn.tnmc_nn_slice_propose(lat, net, 0, z, 3)
+        assert st == 0
+        U = onn.site_uniforms(12345, 0, 3, z, 4, 5)
+        if np.min(np.abs(U - rec["p_plus"])) > TIE:
+            assert np.array_equal(s_new, rec["s_new"])
+        assert close(lq_new, rec["logq_new"]) and close(lq_old, rec["logq_old"])
+        assert dE == rec["dE"]
+
+
+def test_nn_dataset_matches_oracle():
+    torch = torch_dev()
+    gh.announce("nn dataset 6x5x4")
+    lat, J, spins, _ = gh.make_lattice(6, 5, 4, 2, 4, kind="gauss", seed=2, n_chains=3)
+    n = 3 * 4
+    cond = torch.zeros((n, 4, 5, 6), dtype=torch.float32, device="cuda")
+    s = torch.zeros((n, 5, 6), dtype=torch.int8, device="cuda")
+    tn.tnmc_nn_dataset(lat, cond.data_ptr(), s.data_ptr())
+    torch.cuda.synchronize()
+    cond, s = cond.cpu().numpy(), s.cpu().numpy()
+    for c in range(3):
+        for z in range(4):
+            assert np.array_equal(cond[c * 4 + z], onn.cond_channels(J[c], spins[c], z).astype(np.float32))
+            assert np.array_equal(s[c * 4 + z], spins[c][z])
+
+
+@pytest.mark.parametrize("Lx,Ly,n", [(6, 5, 3), (33, 4, 2)])
+def test_nn_gradient(Lx, Ly, n):
+    torch = torch_dev()
+    gh.announce(f"nn gradient {Lx}x{Ly} n={n}")
+    th = params(4, 1.5)
+    cond, s = make_pairs(Lx, Ly, 3, n, 11)
+    net = tn.tnmc_nn_create(th)
+    dc, ds = to_dev(cond), to_dev(s)
+    g = torch.zeros(tn.TNMC_NN_PARAMS, dtype=torch.float32, device="cuda")
+    loss = tn.tnmc_nn_loss_grad(net, dc.data_ptr(), ds.data_ptr(), n, Lx, Ly, g.data_ptr())
+    torch.cuda.synchronize()
+    ref_loss, ref_g = onn.loss_and_grad(th.astype(np.float64), cond, s)
+    assert close(loss, ref_loss, 1e-5), (loss, ref_loss)
+    got = g.cpu().numpy().astype(np.float64)
+    scale = np.abs(ref_g).max()
+    assert np.all(np.abs(got - ref_g) <= 1e-4 * scale + 1e-7), np.abs(got - ref_g).max() / scale
+    assert np.array_equal(got == 0, ref_g == 0) or np.all(got[ref_g == 0] == 0)
+
+
+def test_nn_adam_and_train():
+    torch = torch_dev()
+    gh.announce("nn adam / train 6x5")
+    Lx, Ly = 6, 5
+    th = params(5, 1.0)
+    cond, s = make_pairs(Lx, Ly, 3, 4, 13)
+    th64 = th.astype(np.float64)
+    dc, ds = to_dev(cond), to_dev(s)
+    # one explicit step: Adam on the GPU's gradient against the oracle's Adam on the same gradient
+    net = tn.tnmc_nn_create(th)
+    g = torch.zeros(tn.TNMC_NN_PARAMS, dtype=torch.float32, device="cuda")
+    tn.tnmc_nn_loss_grad(net, dc.data_ptr(), ds.data_ptr(), 4, Lx, Ly, g.data_ptr())
+    tn.tnmc_nn_adam_step(net, g.data_ptr(), 1e-3)
+    torch.cuda.synchronize()
+    g64 = g.cpu().numpy().astype(np.float64)
+    ref, _, _ = onn.adam_step(th64, np.zeros_like(th64), np.zeros_like(th64), g64, 1, 1e-3)
+    got = tn.tnmc_nn_get_params(net).astype(np.float64)
+    assert np.abs(got - ref).max() < 2e-6
+    # two minibatch steps of train() against the oracle's train()
+    net2 = tn.tnmc_nn_create(th)
+    last = tn.tnmc_nn_train(net2, dc.data_ptr(), ds.data_ptr(), 4, Lx, Ly, 1, 2, 1e-2)
+    ref_th, ref_loss = onn.train(th64, cond, s, 1, 2, 1e-2)
+    got2 = tn.tnmc_nn_get_params(net2).astype(np.float64)
+    # Adam's step is lr g / |g| to first order: FP32 rounding of the gradient only
+    # shows where |g| is near zero, so nearly every parameter agrees closely
+    diff = np.abs(got2 - ref_th)
+    assert np.mean(diff < 1e-5) > 0.99 and diff.max() <= 2 * 2 * 1e-2 + 1e-6
+    assert close(last, ref_loss, 1e-5)
+
+
+def test_nn_training_lowers_the_loss():
+    torch = torch_dev()
+    gh.announce("nn training 8x8")
+    lat, J, spins, _ = gh.make_lattice(8, 8, 8, 2, 4, kind="pmj", beta=1.0, seed=1, n_chains=8)
+    n = 8 * 8
+    cond = torch.zeros((n, 4, 8, 8), dtype=torch.float32, device="cuda")
+    s = torch.zeros((n, 8, 8), dtype=torch.int8, device="cuda")
+    tn.tnmc_nn_dataset(lat, cond.data_ptr(), s.data_ptr())
+    net = tn.tnmc_nn_create(None, seed=3)
+    l0 = tn.tnmc_nn_loss_grad(net, cond.data_ptr(), s.data_ptr(), n, 8, 8)
+    l1 = tn.tnmc_nn_train(net, cond.data_ptr(), s.data_ptr(), n, 8, 8, 30, 16, 3e-3)
+    l2 = tn.tnmc_nn_loss_grad(net, cond.data_ptr(), s.data_ptr(), n, 8, 8)
+    assert math.isfinite(l1) and l2 < 0.8 * l0, (l0, l2)
+
+
+def test_nn_chain_averages_match_enumeration():
+    """64 independent chains on 2x2x4 +-J instances with an untrained (random)
+    learned proposal (acceptance well below 1): each chain's averages of E and
+    M^2 over sweeps 50..399 against exact enumeration, deviations with mean
+    zero within four standard errors."""
+    gh.announce("nn chain averages 2x2x4")
+    Lx, Ly, Lz, beta, n_chains, n_sweeps = 2, 2, 4, 1.0, 64, 400
+    lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, 2, 1, kind="pmj", beta=beta, seed=3, n_chains=n_chains,
+                                       record_capacity=n_sweeps)
+    net = tn.tnmc_nn_create(params(6, 1.0))
+    st = tn.tnmc_nn_sweep([lat], net, n_sweeps, record=True)
+    assert st["numeric_faults"] == 0 and 0 < st["accepted"] < st["proposed"]
+    assert st["proposed"] == n_chains * Lz * n_sweeps
+    E, M, _ = tn.tnmc_timeseries(lat)
+    devs_E, devs_M2 = [], []
+    for c in range(n_chains):
+        states, En = bf.lattice_states(J[c], Lx, Ly, Lz, 2)
+        w = np.exp(-beta * (En - En.min()))
+        w /= w.sum()
+        Mn = np.sum(1 - 2 * states, axis=(1, 2, 3)) / 16.0
+        devs_E.append(E[50:, c].mean() - float(np.sum(w * En)))
+        devs_M2.append((M[50:, c] ** 2).mean() - float(np.sum(w * Mn * Mn)))
+    for devs in (np.array(devs_E), np.array(devs_M2)):
+        err = devs.std(ddof=1) / math.sqrt(len(devs))
+        assert abs(devs.mean()) < 4 * err + 1e-12, (devs.mean(), err)
+
+
+def test_nn_sweep_step_matches_oracle_update():
+    """One learned-proposal half-sweep step of a layer equals the oracle's slice
+    update (the MH uniform of purpose 1): same decision, same new state."""
+    gh.announce("nn sweep step vs oracle 5x4x2")
+    th = params(7, 1.0)
+    lat, J, spins, _ = gh.make_lattice(5, 4, 2, 2, 4, kind="pmj", beta=0.5, seed=9, n_chains=2)
+    net = tn.tnmc_nn_create(th)
+    th64 = th.astype(np.float64)
+    tn.tnmc_nn_sweep([lat], net, 1, sweep_offset=4)
+    for c in range(2):
+        ref = spins[c].copy()
+        for z in (0, 1):   # even layers, then odd layers
+            onn.slice_update(th64, J[c], ref, z, 0.5, seed=12345, chain_key=c, sweep=4)
+        assert np.array_equal(tn.tnmc_get_spins(lat, c), ref)
+
+
+def test_nn_fallback_routing():
+    gh.announce("nn fallback 4x4x4")
+    lat, J, spins, _ = gh.make_lattice(4, 4, 4, 2, 4, kind="pmj", beta=1.0, seed=5, n_chains=2)
+    net = tn.tnmc_nn_create(params(8, 1.0))
+    flags = np.zeros((2, 4), dtype=np.int8)
+    flags[0, 1] = flags[1, 2] = 1
+    tn.tnmc_nn_set_fallback(lat, flags)
+    assert np.array_equal(tn.tnmc_nn_get_fallback(lat), flags)
+    st = tn.tnmc_nn_sweep([lat], net, 3)
+    prop, acc = tn.tnmc_nn_counts(lat)
+    assert np.array_equal(prop, np.where(flags == 1, 0, 3))
+    assert st["proposed"] == 2 * 4 * 3 and st["contract_launches"] > 0
+    # calibration: threshold 0 flags nothing new; threshold 1 flags every proposed
+    # layer with a rejection; layers never proposed keep their flag
+    assert tn.tnmc_nn_calibrate_fallback(lat, 0.0) == 2
+    n = tn.tnmc_nn_calibrate_fallback(lat, 1.0)
+    want = np.where(prop > 0, (acc < prop).astype(np.int8), flags)
+    assert n == int(want.sum()) and np.array_equal(tn.tnmc_nn_get_fallback(lat), want)
+    tn.tnmc_nn_counts_reset(lat)
+    st = tn.tnmc_nn_sweep([lat], net, 2)
+    assert np.array_equal(tn.tnmc_nn_counts(lat)[0], np.where(want == 1, 0, 2)) and st["proposed"] == 2 * 4 * 2
+    with pytest.raises(tn.TnmcError):
+        tn.tnmc_nn_calibrate_fallback(lat, 1.5)
+    tn.tnmc_nn_set_fallback(lat, None)
+    assert np.all(tn.tnmc_nn_get_fallback(lat) == 0)
+
+
+def test_nn_invalid_calls():
+    gh.announce("nn invalid calls")
+    net = tn.tnmc_nn_create(None, seed=1)
+    potts, _, _, _ = gh.make_lattice(4, 4, 3, 3, 4, kind="ferro", beta=0.5, seed=1)
+    with pytest.raises(tn.TnmcError) as e:
+        tn.tnmc_nn_slice_propose(potts, net, 0, 1)
+    assert e.value.status == tn.api.TNMC_ERR_UNSUPPORTED
+    wide, _, _, _ = gh.make_lattice(64, 8, 3, 2, 4, kind="pmj", seed=1)
+    with pytest.raises(tn.TnmcError) as e:
+        tn.tnmc_nn_sweep([wide], net, 1)
+    assert e.value.status == tn.api.TNMC_ERR_UNSUPPORTED
+    bad = np.full(tn.TNMC_NN_PARAMS, np.nan, dtype=np.float32)
+    with pytest.raises(tn.TnmcError):
+        tn.tnmc_nn_set_params(net, bad)
