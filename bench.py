@@ -203,6 +203,100 @@ def cpu_baseline(name: str, per_worker: int = 6):
                       f"{np.sum(per):.1f} s of CPU work, mean {np.mean(per):.2f} s per update per core"}
 
 
+NN_FLOPS_PER_SITE = 2 * 9 * (5 * 32 + 4 * 32 * 32 + 32)   # dense 3x3 forward, as the training kernels run it
+FP32_PEAK_TFLOPS = 157.3
+
+
+def learned_form(tn, lat, group, args, stream, fp64_value):
+    """The learned proposal on the same chains: a training set of (condition,
+    layer) pairs taken after each of a number of further FP64 TN sweeps (each
+    layer then is a fresh draw of the TN proposal given its neighbours),
+    minibatch Adam, a calibration window that freezes the TN fallback of layers
+    whose acceptance stays below 5%, then timed sweeps."""
+    import torch
+    L = group["L"]
+    n_chains = len(group["inst"])
+    per_sweep = n_chains * L
+    sweep0 = args.warmup + args.steps
+    K = args.learned_data_sweeps
+    n = K * per_sweep
+    cond = torch.empty((n, 4, L, L), dtype=torch.float32, device="cuda")
+    spins = torch.empty((n, L, L), dtype=torch.int8, device="cuda")
+    print(f"[bench] learned proposal: {K} TN sweeps -> {n} training pairs", file=sys.stderr, flush=True)
+    for k in range(K):
+        tn.tnmc_sweep([lat], 1, sweep_offset=sweep0 + k, stream=stream)
+        tn.tnmc_nn_dataset(lat, cond.data_ptr() + k * per_sweep * 4 * L * L * 4,
+                           spins.data_ptr() + k * per_sweep * L * L, stream=stream)
+    torch.cuda.synchronize()
+    # shuffle the pairs once (seeded): minibatches then mix sweeps, chains and layers
+    perm = torch.from_numpy(np.random.Generator(np.random.PCG64(5)).permutation(n)).cuda()
+    cond, spins = cond[perm].contiguous(), spins[perm].contiguous()
+    net = tn.tnmc_nn_create(None, seed=1)
+    batch = 256
+    loss0 = tn.tnmc_nn_loss_grad(net, cond.data_ptr(), spins.data_ptr(), batch, L, L, stream=stream)
+    print(f"[bench] learned proposal: training {args.learned_epochs} epochs", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = tn.tnmc_nn_train(net, cond.data_ptr(), spins.data_ptr(), n, L, L, args.learned_epochs, batch, 1e-3,
+                            stream=stream)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    train_flops = 3.0 * NN_FLOPS_PER_SITE * L * L * n * args.learned_epochs
+    del cond, spins
+    # every layer on the learned proposal: its own rate and acceptance; these
+    # sweeps are also the calibration window of the fallback
+    sw = sweep0 + K
+    tn.tnmc_nn_set_fallback(lat, None)
+    tn.tnmc_nn_counts_reset(lat)
+    print(f"[bench] learned proposal: timing {args.steps} sweeps, every layer learned", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_nn = tn.tnmc_nn_sweep([lat], net, args.steps, sweep_offset=sw, time_kernels=True, stream=stream)
+    torch.cuda.synchronize()
+    secs_nn = time.perf_counter() - t0
+    sw += args.steps
+    n_fb = tn.tnmc_nn_calibrate_fallback(lat, 0.05)
+    print(f"[bench] learned proposal: timing {args.steps} sweeps ({n_fb} of {per_sweep} layers on the TN fallback)",
+          file=sys.stderr, flush=True)
+    tn.tnmc_nn_counts_reset(lat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = tn.tnmc_nn_sweep([lat], net, args.steps, sweep_offset=sw, time_kernels=True, stream=stream)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    prop, acc = tn.tnmc_nn_counts(lat)
+    nn_prop = int(prop.sum())
+    value = args.steps * per_sweep / secs
+    # log q gap on the current layers of a few (chain, layer) pairs: log q_TN - log q_theta
+    gaps = []
+    cur = [tn.tnmc_get_spins(lat, c) for c in range(min(n_chains, 4))]
+    for c, sc in enumerate(cur):
+        for z in range(0, L, 4):
+            gaps.append(tn.tnmc_slice_logq(lat, c, z, sc[z]) - tn.tnmc_nn_slice_logq(lat, net, c, z, sc[z]))
+    return {
+        "form": "masked-conv autoregressive proposal (6 layers, 32 channels, FP32) with exact log q, "
+                "MH per main text Eq. 1, TN fallback frozen after a calibration window (the learned-only sweeps; acceptance < 5%)",
+        "value": value, "unit": "slice updates/s", "ms_per_step": secs / args.steps * 1e3,
+        "vs_fp64": value / fp64_value,
+        "acceptance": st["accepted"] / max(1, st["proposed"]),
+        "acceptance_learned": float(acc.sum()) / max(1, nn_prop),
+        "learned_updates_per_step": nn_prop / args.steps, "fallback_layers": n_fb,
+        "learned_only": {"value": args.steps * per_sweep / secs_nn, "unit": "slice updates/s",
+                         "ms_per_step": secs_nn / args.steps * 1e3,
+                         "acceptance": st_nn["accepted"] / max(1, st_nn["proposed"]),
+                         "sampler_ms_per_launch": st_nn["sample_ms"] / max(1, st_nn["sample_launches"]),
+                         "tasks_per_launch": per_sweep // 2},
+        "sample_ms_per_step": st["sample_ms"] / args.steps, "contract_ms_per_step": st["contract_ms"] / args.steps,
+        "logq_gap_tn_minus_learned": {"mean": float(np.mean(gaps)), "median": float(np.median(gaps)),
+                                      "layers": len(gaps)},
+        "training": {"pairs": n, "epochs": args.learned_epochs, "batch": batch, "lr": 1e-3, "seconds": train_s,
+                     "loss_first_batch_nats": loss0, "loss_last_batch_nats": last,
+                     "tflops": train_flops / train_s / 1e12,
+                     "frac_fp32_peak": train_flops / train_s / 1e12 / FP32_PEAK_TFLOPS},
+        "numeric_faults": st["numeric_faults"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +305,10 @@ def main():
     ap.add_argument("--workload", default="ea32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true", help="skip the FP32-environment form")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal form")
+    ap.add_argument("--learned-data-sweeps", type=int, default=24,
+                    help="TN sweeps whose layers form the training set of the learned proposal")
+    ap.add_argument("--learned-epochs", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -313,6 +411,8 @@ def main():
             "sample_ms_per_step": st32["sample_ms"] / args.steps}
         for lat in lats32:
             tn.tnmc_lattice_free(lat)
+    if not args.no_learned and len(lats) == 1:
+        out["learned_proposal"] = learned_form(tn, lats[0], groups[0], args, stream, value)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload)
