@@ -237,8 +237,8 @@ def learned_form(tn, lat, group, args, stream, fp64_value):
     print(f"[bench] learned proposal: training {args.learned_epochs} epochs", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    last = tn.tnmc_nn_train(net, cond.data_ptr(), spins.data_ptr(), n, L, L, args.learned_epochs, batch, 1e-3,
-                            stream=stream)
+    last = tn.tnmc_nn_train(net, cond.data_ptr(), spins.data_ptr(), n, L, L, args.learned_epochs, batch,
+                            args.learned_lr, stream=stream)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     train_flops = 3.0 * NN_FLOPS_PER_SITE * L * L * n * args.learned_epochs
@@ -289,7 +289,7 @@ def learned_form(tn, lat, group, args, stream, fp64_value):
         "sample_ms_per_step": st["sample_ms"] / args.steps, "contract_ms_per_step": st["contract_ms"] / args.steps,
         "logq_gap_tn_minus_learned": {"mean": float(np.mean(gaps)), "median": float(np.median(gaps)),
                                       "layers": len(gaps)},
-        "training": {"pairs": n, "epochs": args.learned_epochs, "batch": batch, "lr": 1e-3, "seconds": train_s,
+        "training": {"pairs": n, "epochs": args.learned_epochs, "batch": batch, "lr": args.learned_lr, "seconds": train_s,
                      "loss_first_batch_nats": loss0, "loss_last_batch_nats": last,
                      "tflops": train_flops / train_s / 1e12,
                      "frac_fp32_peak": train_flops / train_s / 1e12 / FP32_PEAK_TFLOPS},
@@ -306,9 +306,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true", help="skip the FP32-environment form")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal form")
-    ap.add_argument("--learned-data-sweeps", type=int, default=24,
+    ap.add_argument("--learned-data-sweeps", type=int, default=48,
                     help="TN sweeps whose layers form the training set of the learned proposal")
-    ap.add_argument("--learned-epochs", type=int, default=2)
+    ap.add_argument("--learned-epochs", type=int, default=5)
+    ap.add_argument("--learned-lr", type=float, default=2e-3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
