@@ -141,7 +141,7 @@ __device__ __forceinline__ double recip(double v) { return (v > 1e-300) ? rcp_nr
 // The next site tensor is read from global memory into registers while the
 // current one is used, so each step waits on LDS only.  ET: storage type of
 // the environments (double or float); the walk itself is FP64.
-template <typename ET, int DP, int CHIM>
+template <typename ET, int DP, int CHIM, bool SB>
 __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict__ tasks, uint64_t sweep, int lx_max,
                                                      int ly_max) {
   __shared__ SampleShared<DP, CHIM> sh;
@@ -168,13 +168,14 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
   const bool contract_fault = contract_status != 0;
   double* Rp = dyn + (size_t)path * (lx_max + 1) * CHIM * DP;
   double* sAb = dyn + (size_t)2 * (lx_max + 1) * CHIM * DP;
-  int8_t* cfg = reinterpret_cast<int8_t*>(sAb + 2 * SITEL);
+  constexpr int NBUF = SB ? 1 : 2;              // site tiles in LDS (SB: one, reused after a barrier)
+  int8_t* cfg = reinterpret_cast<int8_t*>(sAb + NBUF * SITEL);
 #define RENV(x, al, u) Rp[((size_t)(x) * CHIM + (al)) * DP + (u)]
 #define CFG(p, y, x) cfg[((size_t)(p) * ly_max + (y)) * lx_max + (x)]
 
   // the site tiles start at zero: entries outside a site's corner then hold
   // finite values only (zeros, or an earlier site's entries)
-  for (int i = tid; i < 2 * SITEL; i += NTS) sAb[i] = 0.0;
+  for (int i = tid; i < NBUF * SITEL; i += NTS) sAb[i] = 0.0;
   __syncthreads();
   double pf[PF];
   int buf = 0;
@@ -254,8 +255,13 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
 #pragma unroll
         for (int tt = 0; tt < DP; ++tt) RENV(x, lane, tt) = rt[tt] * inv;
       }
-      site_commit<DP, CHIM, PF>(sAb + (buf ^ 1) * SITEL, pf, ncl, ncr, tid);
-      buf ^= 1;
+      if constexpr (SB) {
+        __syncthreads();   // every lane is done with the tile before it is overwritten
+        site_commit<DP, CHIM, PF>(sAb, pf, ncl, ncr, tid);
+      } else {
+        site_commit<DP, CHIM, PF>(sAb + (buf ^ 1) * SITEL, pf, ncl, ncr, tid);
+        buf ^= 1;
+      }
       __syncthreads();
     }
     // draws, x = 0 .. Lx-1
@@ -360,9 +366,14 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
         inv = (lm > 0.0 && isfinite(lm)) ? recip(lm) : 1.0;
       }
       if (lane < CHIM) sh.l[path][lb ^ 1][lane] = (lane < cr) ? lv * inv : 0.0;
-      if (gn) {
-        site_commit<DP, CHIM, PF>(sAb + (buf ^ 1) * SITEL, pf, ncl, ncr, tid);
-        buf ^= 1;
+      if (gn) {   // uniform over the workgroup
+        if constexpr (SB) {
+          __syncthreads();
+          site_commit<DP, CHIM, PF>(sAb, pf, ncl, ncr, tid);
+        } else {
+          site_commit<DP, CHIM, PF>(sAb + (buf ^ 1) * SITEL, pf, ncl, ncr, tid);
+          buf ^= 1;
+        }
       }
       lb ^= 1;
       prev = s;
@@ -428,23 +439,43 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
 
 // Dynamic LDS of a sampler workgroup for layers of at most Lx_max x Ly_max sites.
 template <int DP, int CHIM>
-size_t sample_dyn_bytes(int Lx_max, int Ly_max) {
-  return sizeof(double) * (2 * (size_t)(Lx_max + 1) * CHIM * DP + 2 * (size_t)site_lds<DP, CHIM>()) +
+size_t sample_dyn_bytes(int Lx_max, int Ly_max, bool single) {
+  return sizeof(double) * (2 * (size_t)(Lx_max + 1) * CHIM * DP + (single ? 1 : 2) * (size_t)site_lds<DP, CHIM>()) +
          2 * (size_t)Lx_max * Ly_max;
 }
+// The double-buffered layout when it fits a CU's LDS, else one site tile.
+template <int DP, int CHIM>
+bool sample_single(int Lx_max, int Ly_max) {
+  return sizeof(SampleShared<DP, CHIM>) + sample_dyn_bytes<DP, CHIM>(Lx_max, Ly_max, false) > 160 * 1024;
+}
+template <int DP, int CHIM>
+size_t sample_total_bytes(int Lx_max, int Ly_max) {
+  return sizeof(SampleShared<DP, CHIM>) +
+         sample_dyn_bytes<DP, CHIM>(Lx_max, Ly_max, sample_single<DP, CHIM>(Lx_max, Ly_max));
+}
 
-template <typename ET, int DP, int CHIM>
-hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep, hipStream_t s) {
-  const size_t bytes = sample_dyn_bytes<DP, CHIM>(Lx_max, Ly_max);
+template <typename ET, int DP, int CHIM, bool SB>
+hipError_t launch_sample_v(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep, hipStream_t s) {
+  const size_t bytes = sample_dyn_bytes<DP, CHIM>(Lx_max, Ly_max, SB);
   static size_t attr_bytes = 0;
   if (bytes > 48 * 1024 && bytes > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)sample_kernel<ET, DP, CHIM>,
+    hipError_t e = hipFuncSetAttribute((const void*)sample_kernel<ET, DP, CHIM, SB>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
     attr_bytes = bytes;
   }
-  hipLaunchKernelGGL((sample_kernel<ET, DP, CHIM>), dim3(n), dim3(NTS), bytes, s, tasks, sweep, Lx_max, Ly_max);
+  hipLaunchKernelGGL((sample_kernel<ET, DP, CHIM, SB>), dim3(n), dim3(NTS), bytes, s, tasks, sweep, Lx_max, Ly_max);
   return hipGetLastError();
+}
+
+// Only Potts at chi_max = 32 on rows longer than 59 sites needs the single tile.
+template <typename ET, int DP, int CHIM>
+hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep, hipStream_t s) {
+  if constexpr (DP == 3 && CHIM == 32) {
+    if (sample_single<DP, CHIM>(Lx_max, Ly_max))
+      return launch_sample_v<ET, DP, CHIM, true>(tasks, n, Lx_max, Ly_max, sweep, s);
+  }
+  return launch_sample_v<ET, DP, CHIM, false>(tasks, n, Lx_max, Ly_max, sweep, s);
 }
 
 // Full-lattice energy of one configuration, FP64: one workgroup of 256.
@@ -551,17 +582,17 @@ hipError_t launch_sample_et(const TaskDesc* tasks, int n, int d, int chi_max, in
 size_t sample_lds_bytes(int d, int chi_max, int Lx, int Ly) {
   if (d == 2) {
     switch (chi_max) {
-      case 4: return sizeof(SampleShared<2, 4>) + sample_dyn_bytes<2, 4>(Lx, Ly);
-      case 8: return sizeof(SampleShared<2, 8>) + sample_dyn_bytes<2, 8>(Lx, Ly);
-      case 16: return sizeof(SampleShared<2, 16>) + sample_dyn_bytes<2, 16>(Lx, Ly);
-      case 32: return sizeof(SampleShared<2, 32>) + sample_dyn_bytes<2, 32>(Lx, Ly);
+      case 4: return sample_total_bytes<2, 4>(Lx, Ly);
+      case 8: return sample_total_bytes<2, 8>(Lx, Ly);
+      case 16: return sample_total_bytes<2, 16>(Lx, Ly);
+      case 32: return sample_total_bytes<2, 32>(Lx, Ly);
     }
   } else if (d == 3) {
     switch (chi_max) {
-      case 4: return sizeof(SampleShared<3, 4>) + sample_dyn_bytes<3, 4>(Lx, Ly);
-      case 8: return sizeof(SampleShared<3, 8>) + sample_dyn_bytes<3, 8>(Lx, Ly);
-      case 16: return sizeof(SampleShared<3, 16>) + sample_dyn_bytes<3, 16>(Lx, Ly);
-      case 32: return sizeof(SampleShared<3, 32>) + sample_dyn_bytes<3, 32>(Lx, Ly);
+      case 4: return sample_total_bytes<3, 4>(Lx, Ly);
+      case 8: return sample_total_bytes<3, 8>(Lx, Ly);
+      case 16: return sample_total_bytes<3, 16>(Lx, Ly);
+      case 32: return sample_total_bytes<3, 32>(Lx, Ly);
     }
   }
   return 0;

@@ -38,6 +38,8 @@ CASES = [
     (8, 6, 3, 3, "ferro", 0.55, 14, 1),    # Potts, compact, truncating after an LQ of more than 32 rows
     (5, 4, 3, 3, "ferro", 0.55, 20, 1),    # Potts, chi_max = 32 (every tile in global memory), exact
     (7, 7, 3, 3, "ferro", 0.55, 24, 1),    # Potts, chi_max = 32, truncating
+    (64, 6, 3, 3, "ferro", 0.55, 24, 1),   # Potts, chi_max = 32, 64-site rows: the sampler's single-tile layout
+    (64, 5, 2, 3, "ferro", 0.55, 32, 0),   # the same with one held neighbour
 ]
 
 
@@ -189,11 +191,13 @@ def test_invalid_calls_are_rejected():
         assert ei.value.status == tn.api.TNMC_ERR_ARG
     with pytest.raises(tn.TnmcError):
         tn.tnmc_slice_logq(lat, 0, 0, np.zeros((4, 4), np.int8))
-    # chi above 32, and Potts chi = 32 rows too long for the sampler's LDS, are not built
-    for (Lx, Ly, d, chi) in ((8, 2, 2, 40), (64, 64, 3, 32)):
-        with pytest.raises(tn.TnmcError) as ei:
-            gh.make_lattice(Lx, Ly, 2, d, chi, kind="ferro", seed=1)
-        assert ei.value.status == tn.api.TNMC_ERR_UNSUPPORTED
+    # chi above 32 is not built
+    with pytest.raises(tn.TnmcError) as ei:
+        gh.make_lattice(8, 2, 2, 2, 40, kind="ferro", seed=1)
+    assert ei.value.status == tn.api.TNMC_ERR_UNSUPPORTED
+    # the largest layers are: 64 x 64 Potts at chi = 32 (single-tile sampler layout) and Ising
+    for d in (2, 3):
+        gh.make_lattice(64, 64, 2, d, 32, kind="ferro", seed=1)
 
 
 def test_heterogeneous_batch_like_c3():
