@@ -39,6 +39,9 @@ WORKLOADS = {
     # heterogeneous batch: Gaussian couplings, chain k has L = Ls[k % 3],
     # chi = chis[(k // 3) % 3] and beta drawn uniformly in [0.5, 1.5]; chains of
     # the chi = 64 class are left out (that tile size is not built)
+    # 3-state Potts, 64^3, uniform J = 1 at beta = 0.5505 (near the transition), chi = 32: 4 chains
+    # started ordered (all state 0) and 4 from uniform random states
+    "potts64": dict(potts=True, L=64, chi=32, beta=0.5505, n_ordered=4, n_random=4),
     "c3": dict(mixed=True, n_chains=512, Ls=(16, 24, 32), chis=(16, 32, 64), built_chis=(16, 32),
                beta_range=(0.5, 1.5)),
 }
@@ -95,6 +98,13 @@ def build_inputs(name: str):
 def build_groups(name: str):
     """The workload as a list of lattices: dicts with L, chi, J, spins, inst, pairs, betas."""
     cfg = WORKLOADS[name]
+    if cfg.get("potts"):
+        L = cfg["L"]
+        n = cfg["n_ordered"] + cfg["n_random"]
+        spins = np.stack([synth.spins_ordered(L, L, L, 3)] * cfg["n_ordered"] +
+                         [synth.spins_random(L, L, L, 1000 + c, 3) for c in range(cfg["n_random"])])
+        return [dict(L=L, chi=cfg["chi"], d=3, J=synth.couplings_uniform(L, L, L)[None], spins=spins,
+                     inst=np.zeros(n, dtype=np.int32), pairs=None, betas=np.full(n, cfg["beta"]))]
     if not cfg.get("mixed"):
         _, J, spins, inst, pairs, betas = build_inputs(name)
         return [dict(L=cfg["L"], chi=cfg["chi"], J=J, spins=spins, inst=inst, pairs=pairs, betas=betas)]
@@ -127,7 +137,8 @@ def make_lattice(name: str, record_capacity: int = 0):
 def make_lattices(name: str, record_capacity: int = 0, precision: int = 0):
     import paper_2509_23945_amd as tn
     groups = build_groups(name)
-    lats = [tn.tnmc_lattice_init(Lx=g["L"], Ly=g["L"], Lz=g["L"], d=2, chi=g["chi"], J=g["J"], beta=g["betas"],
+    lats = [tn.tnmc_lattice_init(Lx=g["L"], Ly=g["L"], Lz=g["L"], d=g.get("d", 2), chi=g["chi"], J=g["J"],
+                                 beta=g["betas"],
                                  spins=g["spins"], chain_instance=g["inst"], seed=PHILOX_SEED, pairs=g["pairs"],
                                  record_capacity=record_capacity, precision=precision) for g in groups]
     return lats, groups
@@ -171,7 +182,7 @@ def _oracle_task(args):
     g = _worker_inputs(name)[gi]
     with threadpool_limits(1):
         t = time.perf_counter()
-        ochain.propose(g["J"][g["inst"][chain]], g["spins"][chain], z, g["betas"][chain], g["chi"], 2,
+        ochain.propose(g["J"][g["inst"][chain]], g["spins"][chain], z, g["betas"][chain], g["chi"], g.get("d", 2),
                        seed=PHILOX_SEED, chain=chain, sweep=0)
         return time.perf_counter() - t
 
@@ -339,8 +350,8 @@ def main():
     avg_launch_s = st["contract_ms"] / 1e3 / launches
     flops_per_launch = st["contract_flops"] / launches
     achieved = flops_per_launch / avg_launch_s / 1e12
-    kernels = sorted({g["chi"] if g["chi"] > 16 else 16 for g in groups})
-    flops_model = sum(tn.tnmc_flop_model(g["L"], g["L"], 2, g["chi"])[0] * len(g["inst"]) * g["L"]
+    kernels = sorted({(g.get("d", 2), g["chi"] if g["chi"] > 16 else 16) for g in groups})
+    flops_model = sum(tn.tnmc_flop_model(g["L"], g["L"], g.get("d", 2), g["chi"])[0] * len(g["inst"]) * g["L"]
                       for g in groups) / tasks_per_sweep
     # launches of different layer classes run concurrently on four streams: the
     # per-launch rate (flops of a launch / its duration) is the roofline figure,
@@ -348,7 +359,7 @@ def main():
     achieved_chip = st["contract_flops"] / secs / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(args.workload),
-                "kernel": " + ".join(f"contract_kernel<2,{c}>" for c in kernels),
+                "kernel": " + ".join(f"contract_kernel<{d},{c}>" for d, c in kernels),
                 "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
                 "achieved_chip": achieved_chip, "frac_chip": achieved_chip / FP64_PEAK_TFLOPS,
                 "flops_per_task": st["contract_flops"] / (args.steps * tasks_per_sweep),
@@ -362,7 +373,11 @@ def main():
         if q.shape[0] >= 100 and q.shape[1] > 0:
             indep, tau, _ = analysis.independent_samples_per_second(q, secs / args.steps)
 
-    if cfg.get("mixed"):
+    if cfg.get("potts"):
+        desc = (f"3D 3-state Potts {cfg['L']}^3 open BC, J=1, beta={cfg['beta']}, chi={cfg['chi']}, "
+                f"{cfg['n_ordered']} chains started ordered + {cfg['n_random']} from random states")
+        data = "synthetic (uniform couplings, ordered and seeded random initial states)"
+    elif cfg.get("mixed"):
         desc = (f"heterogeneous batch, Gaussian J (2^-20 grid), open BC: chain k of {cfg['n_chains']} has "
                 f"L={list(cfg['Ls'])}[k%3], chi={list(cfg['chis'])}[(k//3)%3], beta uniform in "
                 f"{list(cfg['beta_range'])}; the chi=64 class ({cfg['n_chains'] - n_chains} chains) left out")
@@ -412,11 +427,11 @@ def main():
             "sample_ms_per_step": st32["sample_ms"] / args.steps}
         for lat in lats32:
             tn.tnmc_lattice_free(lat)
-    if not args.no_learned and len(lats) == 1:
+    if not args.no_learned and len(lats) == 1 and groups[0].get("d", 2) == 2:
         out["learned_proposal"] = learned_form(tn, lats[0], groups[0], args, stream, value)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload)
+        out["cpu_baseline"] = cpu_baseline(args.workload, per_worker=1 if cfg.get("potts") else 6)
     print(json.dumps(out), flush=True)
 
 
