@@ -189,8 +189,10 @@ tnmc_status tnmc_debug_set(int32_t what, int32_t value);
  * Convolutions run in FP32; probabilities, log q, dE and the MH test in FP64.
  * Site j of a drawn layer takes +1 when its uniform (Philox counter
  * (y*Lx+x, z, sweep, 0), as for the TN sampler) is below P(s_j = +1).
- * Ising lattices (d = 2) only; layers up to 64 sites wide whose sampler fits
- * in 160 KB of LDS (TNMC_ERR_UNSUPPORTED otherwise).
+ * Ising lattices (d = 2) only.  The batched calls take layers up to 64 sites
+ * wide (TNMC_ERR_ARG beyond); the sampler behind propose / logq / sweeps keeps
+ * the masked weights and per-layer activation rings in LDS, which limits rows
+ * to about 48 sites (TNMC_ERR_UNSUPPORTED beyond).
  * Batched entry points take DEVICE pointers: cond [n][4][Ly][Lx] float,
  * s [n][Ly][Lx] int8; they are stream-ordered on hip_stream. */
 enum { TNMC_NN_PARAMS = 38753 };

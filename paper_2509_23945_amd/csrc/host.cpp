@@ -807,6 +807,8 @@ tnmc_status nn_batch(tnmc_nn* nn, const float* cond, const int8_t* s, int n, int
   return TNMC_OK;
 }
 
+constexpr size_t kNnStaticLds = 64;   // the sampler's static LDS (log q and fault slots), rounded up
+
 bool nn_shape_ok(int n, int Lx, int Ly) {
   return n >= 1 && Lx >= 1 && Ly >= 1 && Lx <= tnmc::kNnLxMax && Ly <= kLyMax;
 }
@@ -814,7 +816,7 @@ bool nn_shape_ok(int n, int Lx, int Ly) {
 // The learned proposal runs on Ising lattices whose sampler fits in a CU's LDS.
 tnmc_status nn_lattice_ok(const tnmc_lattice* L) {
   if (L->d != 2) return TNMC_ERR_UNSUPPORTED;
-  if (tnmc::nn_sample_lds_bytes(L->Lx, L->Ly) > 160 * 1024) return TNMC_ERR_UNSUPPORTED;
+  if (tnmc::nn_sample_lds_bytes(L->Lx, L->Ly) + kNnStaticLds > 160 * 1024) return TNMC_ERR_UNSUPPORTED;
   return TNMC_OK;
 }
 
@@ -1092,7 +1094,8 @@ tnmc_status tnmc_nn_sweep(tnmc_lattice* const* lats, int32_t n_lats, tnmc_nn* nn
       }
     }
   for (int p : {0, 1})   // lattices of different shapes share one launch per parity
-    if (!nd[p].empty() && tnmc::nn_sample_lds_bytes(lxm[p], lym[p]) > 160 * 1024) return TNMC_ERR_UNSUPPORTED;
+    if (!nd[p].empty() && tnmc::nn_sample_lds_bytes(lxm[p], lym[p]) + kNnStaticLds > 160 * 1024)
+      return TNMC_ERR_UNSUPPORTED;
   const size_t n_nn = nd[0].size() + nd[1].size();
   if (grow(g_ws.nn_tasks, g_ws.nn_tasks_cap, std::max<size_t>(n_nn, 1)) != TNMC_OK) return TNMC_ERR_OOM;
   if (!nd[0].empty())
