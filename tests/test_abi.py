@@ -82,3 +82,26 @@ def test_flop_model(lib):
     assert tn.tnmc_flop_model(16, 16, 2, 32)[0] > tn.tnmc_flop_model(16, 16, 2, 16)[0]
     with pytest.raises(tn.TnmcError):
         tn.tnmc_flop_model(0, 4, 2, 4)
+
+
+def test_learned_proposal_arguments_checked_on_host(lib):
+    """The learned-proposal entry points reject bad arguments before any device work."""
+    import ctypes
+    ARG = tn.api.TNMC_ERR_ARG
+    h = ctypes.c_void_p()
+    assert lib.tnmc_nn_create(None, 0, None) == ARG
+    bad = np.full(tn.TNMC_NN_PARAMS, np.nan, dtype=np.float32)
+    assert lib.tnmc_nn_create(bad.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 0, ctypes.byref(h)) == ARG
+    assert not h.value
+    assert lib.tnmc_nn_free(None) == ARG
+    assert lib.tnmc_nn_logq(None, None, None, 1, 4, 4, None, None) == ARG
+    loss = ctypes.c_double()
+    assert lib.tnmc_nn_loss_grad(None, None, None, 1, 4, 4, ctypes.byref(loss), None, None) == ARG
+    assert lib.tnmc_nn_adam_step(None, None, 1e-3, None) == ARG
+    assert lib.tnmc_nn_train(None, None, None, 1, 4, 4, 1, 1, 1e-3, None, None) == ARG
+    assert lib.tnmc_nn_dataset(None, None, None, None) == ARG
+    assert lib.tnmc_nn_sweep(None, 0, None, 1, 0, 0, 0, None, None) == ARG
+    assert lib.tnmc_nn_counts(None, None, None) == ARG
+    assert lib.tnmc_nn_set_fallback(None, None) == ARG
+    assert lib.tnmc_nn_calibrate_fallback(None, 0.05, None) == ARG
+    assert lib.tnmc_nn_slice_logq(None, None, 0, 0, None, None, None) == ARG
