@@ -36,6 +36,8 @@ WORKLOADS = {
     "ea32": dict(L=32, chi=32, beta=1.0, n_inst=16, n_rep=2),
     "ea16": dict(L=16, chi=32, beta=1.0, n_inst=64, n_rep=2),
     "ea8": dict(L=8, chi=16, beta=0.5, n_inst=1, n_rep=1),
+    # small layers where the learned proposal is accepted: 8^3 +-J, beta = 1.0, 32 instances x 2 replicas
+    "ea8b": dict(L=8, chi=16, beta=1.0, n_inst=32, n_rep=2),
     # heterogeneous batch: Gaussian couplings, chain k has L = Ls[k % 3],
     # chi = chis[(k // 3) % 3] and beta drawn uniformly in [0.5, 1.5]; chains of
     # the chi = 64 class are left out (that tile size is not built)
@@ -214,6 +216,18 @@ def cpu_baseline(name: str, per_worker: int = 6):
                       f"{np.sum(per):.1f} s of CPU work, mean {np.mean(per):.2f} s per update per core"}
 
 
+def indep_of(lat, sweep_s):
+    """(independent samples/s, tau_int of the overlap q) from the lattice's record, or Nones when it is
+    shorter than 100 sweeps or has no replica pairs."""
+    import paper_2509_23945_amd as tn
+    from paper_2509_23945_amd import analysis
+    _, _, q = tn.tnmc_timeseries(lat)
+    if q.shape[0] < 100 or q.shape[1] == 0:
+        return None, None
+    indep, tau, _ = analysis.independent_samples_per_second(q, sweep_s)
+    return indep, tau
+
+
 NN_FLOPS_PER_SITE = 2 * 9 * (5 * 32 + 4 * 32 * 32 + 32)   # dense 3x3 forward, as the training kernels run it
 FP32_PEAK_TFLOPS = 157.3
 
@@ -259,22 +273,26 @@ def learned_form(tn, lat, group, args, stream, fp64_value):
     sw = sweep0 + K
     tn.tnmc_nn_set_fallback(lat, None)
     tn.tnmc_nn_counts_reset(lat)
+    tn.tnmc_timeseries_reset(lat)
     print(f"[bench] learned proposal: timing {args.steps} sweeps, every layer learned", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st_nn = tn.tnmc_nn_sweep([lat], net, args.steps, sweep_offset=sw, time_kernels=True, stream=stream)
+    st_nn = tn.tnmc_nn_sweep([lat], net, args.steps, sweep_offset=sw, record=True, time_kernels=True, stream=stream)
     torch.cuda.synchronize()
     secs_nn = time.perf_counter() - t0
+    indep_nn = indep_of(lat, secs_nn / args.steps)
     sw += args.steps
     n_fb = tn.tnmc_nn_calibrate_fallback(lat, 0.05)
     print(f"[bench] learned proposal: timing {args.steps} sweeps ({n_fb} of {per_sweep} layers on the TN fallback)",
           file=sys.stderr, flush=True)
     tn.tnmc_nn_counts_reset(lat)
+    tn.tnmc_timeseries_reset(lat)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = tn.tnmc_nn_sweep([lat], net, args.steps, sweep_offset=sw, time_kernels=True, stream=stream)
+    st = tn.tnmc_nn_sweep([lat], net, args.steps, sweep_offset=sw, record=True, time_kernels=True, stream=stream)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
+    indep = indep_of(lat, secs / args.steps)
     prop, acc = tn.tnmc_nn_counts(lat)
     nn_prop = int(prop.sum())
     value = args.steps * per_sweep / secs
@@ -292,10 +310,12 @@ def learned_form(tn, lat, group, args, stream, fp64_value):
         "acceptance": st["accepted"] / max(1, st["proposed"]),
         "acceptance_learned": float(acc.sum()) / max(1, nn_prop),
         "learned_updates_per_step": nn_prop / args.steps, "fallback_layers": n_fb,
+        "tau_int_q": indep[1], "indep_samples_per_s": indep[0],
         "learned_only": {"value": args.steps * per_sweep / secs_nn, "unit": "slice updates/s",
                          "ms_per_step": secs_nn / args.steps * 1e3,
                          "acceptance": st_nn["accepted"] / max(1, st_nn["proposed"]),
                          "sampler_ms_per_launch": st_nn["sample_ms"] / max(1, st_nn["sample_launches"]),
+                         "tau_int_q": indep_nn[1], "indep_samples_per_s": indep_nn[0],
                          "tasks_per_launch": per_sweep // 2},
         "sample_ms_per_step": st["sample_ms"] / args.steps, "contract_ms_per_step": st["contract_ms"] / args.steps,
         "logq_gap_tn_minus_learned": {"mean": float(np.mean(gaps)), "median": float(np.median(gaps)),

@@ -283,3 +283,32 @@ def test_nn_invalid_calls():
     bad = np.full(tn.TNMC_NN_PARAMS, np.nan, dtype=np.float32)
     with pytest.raises(tn.TnmcError):
         tn.tnmc_nn_set_params(net, bad)
+
+
+def test_training_gains_acceptance():
+    """What training buys: on 8x8 layers of 8^3 +-J lattices at beta = 1 (64 chains,
+    chi = 16), the untrained network's proposals are essentially never accepted;
+    after 10 epochs of Adam on 20 480 (condition, layer) pairs taken from TN sweeps
+    of the same chains, more than 15% are."""
+    torch = torch_dev()
+    gh.announce("nn training gain 8^3")
+    L, n_chains, K = 8, 64, 40
+    lat, _, _, _ = gh.make_lattice(L, L, L, 2, 16, kind="pmj", beta=1.0, seed=21, n_chains=n_chains)
+    tn.tnmc_sweep([lat], 10)
+    per = n_chains * L
+    cond = torch.empty((K * per, 4, L, L), dtype=torch.float32, device="cuda")
+    s = torch.empty((K * per, L, L), dtype=torch.int8, device="cuda")
+    for k in range(K):
+        tn.tnmc_sweep([lat], 1, sweep_offset=10 + k)
+        tn.tnmc_nn_dataset(lat, cond.data_ptr() + k * per * 4 * L * L * 4, s.data_ptr() + k * per * L * L)
+    torch.cuda.synchronize()
+    perm = torch.from_numpy(np.random.Generator(np.random.PCG64(5)).permutation(K * per)).cuda()
+    cond, s = cond[perm].contiguous(), s[perm].contiguous()
+    net = tn.tnmc_nn_create(None, seed=1)
+    st0 = tn.tnmc_nn_sweep([lat], net, 2, sweep_offset=100)
+    tn.tnmc_nn_train(net, cond.data_ptr(), s.data_ptr(), K * per, L, L, 10, 256, 2e-3)
+    st1 = tn.tnmc_nn_sweep([lat], net, 5, sweep_offset=102)
+    a0 = st0["accepted"] / st0["proposed"]
+    a1 = st1["accepted"] / st1["proposed"]
+    print(f"acceptance untrained {a0:.4f}, trained {a1:.4f}")
+    assert a0 < 0.01 and a1 > 0.15 and st1["numeric_faults"] == 0
