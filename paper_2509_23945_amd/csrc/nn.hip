@@ -41,6 +41,7 @@ constexpr int NCOND = kNnCond;   // condition channels
 constexpr int NHID = 4;          // masked 32 -> 32 layers
 constexpr float CLIP = 30.0f;
 constexpr int NTS = 128;         // sampler: one wavefront per path
+constexpr int WCO = 5 * C + 4;   // sampler: LDS row of one output channel's hidden-layer weights
 
 // flat parameter offsets
 constexpr int OFF_W0 = 0;
@@ -60,10 +61,27 @@ __device__ __forceinline__ bool tap_kept(int layer, int ci, int k) {
 
 __device__ __forceinline__ double log_sigmoid(double t) { return -(fmax(-t, 0.0) + log1p(exp(-fabs(t)))); }
 
+// Cross-lane moves of a float through DPP.  dpp_f: every lane reads its
+// partner; dpp_f_rows: lanes outside the enabled rows read zero.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f_rows(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, false));
+}
+// Wavefront sum: butterflies within rows of 16 lanes, then row_bcast15 and
+// row_bcast31 carry the row sums to lane 63, read once; every lane gets the
+// same bits.
 __device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f<0xB1>(v);    // lane ^ 1
+  v += dpp_f<0x4E>(v);    // lane ^ 2
+  v += dpp_f<0x141>(v);   // half-row mirror
+  v += dpp_f<0x140>(v);   // row mirror
+  v += dpp_f_rows<0x142, 0xa>(v);
+  v += dpp_f_rows<0x143, 0xc>(v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
 // Ordering of LDS accesses between the lanes of one wavefront.
@@ -93,7 +111,8 @@ __device__ __forceinline__ float cond_value(JP J, SP spins, int Lx, int Ly, int 
 //   wc0 [C][NCOND][9]       layer 0, condition channels
 //   ws0 [C][4]              layer 0, spin channel, taps 0..3
 //   b0  [C]
-//   wh  [NHID][C][5][C]     hidden layers: [layer][c_out][tap][c_in]
+//   wh  [NHID][C][WCO]      hidden layers: [layer][c_out][tap * C + c_in], rows of WCO = 5 C + 4 floats
+//                           (the padding spreads the lanes of different c_out over the LDS banks)
 //   bh  [NHID][C]
 //   w5  [5][C], b5 (padded to 4)
 //   cp  [lx_max][C]         layer-0 pre-activation of the current row without the spin taps
@@ -107,7 +126,7 @@ struct SampleLayout {
     wc0 = o; o += C * NCOND * 9;
     ws0 = o; o += C * 4;
     b0 = o; o += C;
-    wh = o; o += NHID * C * 5 * C;
+    wh = o; o += NHID * C * WCO;
     bh = o; o += NHID * C;
     w5 = o; o += 5 * C;
     b5 = o; o += 4;
@@ -182,7 +201,7 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
   for (int i = tid; i < NHID * C * 5 * C; i += NTS) {
     const int l = i / (C * 5 * C), r = i % (C * 5 * C);
     const int co = r / (5 * C), k = (r / C) % 5, ci = r % C;
-    wh[i] = theta[OFF_H + l * HID + (co * C + ci) * 9 + k];
+    wh[(l * C + co) * WCO + k * C + ci] = theta[OFF_H + l * HID + (co * C + ci) * 9 + k];
   }
   for (int i = tid; i < NHID * C; i += NTS) bh[i] = theta[OFF_H + (i / C) * HID + C * C * 9 + (i % C)];
   for (int i = tid; i < 5 * C; i += NTS) w5[i] = theta[OFF_W5 + (i % C) * 9 + i / C];
@@ -241,7 +260,7 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
 #pragma unroll 1
       for (int l = 0; l < NHID; ++l) {
         const float* R = ring + (size_t)l * (lx_max + 2) * C + 16 * h;
-        const float* W = wh + ((size_t)l * C + co) * 5 * C + 16 * h;
+        const float* W = wh + ((size_t)l * C + co) * WCO + 16 * h;
         float acc = 0.0f;
         if (up) {
           if (left) acc += dot16(W + 0 * C, R + rs0 * C);
@@ -250,7 +269,7 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
         }
         if (left) acc += dot16(W + 3 * C, R + rs3 * C);
         acc += dot16(W + 4 * C, R + rs4 * C);
-        acc += __shfl_xor(acc, 1, 64);
+        acc += dpp_f<0xB1>(acc);   // the other half of the input channels
         const float a = fmaxf(acc + bh[l * C + co], 0.0f);
         if (h == 0) ring[((size_t)(l + 1) * (lx_max + 2) + r) * C + co] = a;
         wave_sync();
