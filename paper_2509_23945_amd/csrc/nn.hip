@@ -23,9 +23,12 @@
 //    site depends on earlier sites and on the previous layer at the same
 //    site, so each wavefront keeps, per layer, a ring of the last Lx + 2
 //    sites' activations in LDS and the masked weights once per workgroup.
-//  * nn_fwd / nn_loss / nn_bwd_data / nn_bwd_weight / nn_grad_reduce /
-//    nn_adam - batched training: one workgroup per (sample, row) for the
-//    convolutions, a two-stage deterministic reduction for weight gradients.
+//  * batched training: the four hidden 32 -> 32 layers' forward, input
+//    gradient and weight gradient are implicit GEMMs on MFMA in FP32
+//    (nn_conv32, nn_wgrad32); the thin first and last layers run on the
+//    vector ALU (nn_fwd, nn_bwd_data, nn_bwd_weight); weight gradients are
+//    reduced from per-wavefront partials in a fixed order (nn_grad_reduce);
+//    then nn_loss and nn_adam.
 #include <math.h>
 
 #include "device_common.h"
@@ -422,6 +425,169 @@ __global__ __launch_bounds__(NTT) void nn_fwd_kernel(const float* __restrict__ t
   }
 }
 
+// Hidden layers (32 -> 32 channels) on MFMA: the convolution of one output
+// row is a 32 x Lx x 160 product (K = 32 input channels x the 5 taps a
+// type-B mask keeps), done as 80 steps of V_MFMA_F32_32X32X2_F32 per 32
+// columns in FP32.  Operand layout of that instruction: lane l supplies
+// A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator r of lane l is
+// C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+//  * forward (BWD = false): out = ReLU(b + sum_{c, k} W[m][c][k] x[c][y + ky - 1][x + kx - 1]), taps k = 0..4;
+//  * input gradient (BWD = true): out[m] = [mask > 0] sum_{c, k'} W[c][m][8 - k'] g[c][y + ky' - 1][x + kx' - 1],
+//    taps k' = 4..8 (the flipped kept taps).
+// One workgroup of four wavefronts per (sample, four rows); the input rows
+// y0 - 1 .. y0 + 4 and the weights in MFMA operand order sit in LDS.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+constexpr int MROWS = 4;
+constexpr int WA = 5 * 16 * 64;   // weights in operand order: [tap][channel pair][lane]
+
+__host__ __device__ inline size_t conv32_lds_floats(int Lx) { return (size_t)WA + (size_t)C * (MROWS + 2) * (Lx + 2); }
+
+template <bool BWD>
+__global__ __launch_bounds__(256) void nn_conv32_kernel(const float* __restrict__ theta, int off,
+                                                        const float* __restrict__ in,
+                                                        const float* __restrict__ mask_src, float* __restrict__ out,
+                                                        int Lx, int Ly) {
+  extern __shared__ __align__(16) float cl[];
+  float* wa = cl;
+  float* xs = cl + WA;
+  const int nyb = (Ly + MROWS - 1) / MROWS;
+  const int b = blockIdx.x / nyb, y0 = (blockIdx.x % nyb) * MROWS;
+  const int XS = Lx + 2;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const size_t plane = (size_t)Lx * Ly;
+  for (int i = tid; i < WA; i += 256) {
+    const int ks = i >> 6, l = i & 63, tt = ks >> 4, kk = ks & 15;
+    const int m = l & 31, c = 2 * kk + (l >> 5);
+    wa[i] = BWD ? theta[off + (c * C + m) * 9 + (4 - tt)] : theta[off + (m * C + c) * 9 + tt];
+  }
+  // rows (channel, row slot) over the four wavefronts, columns over the lanes
+  for (int ri = tid >> 6; ri < C * (MROWS + 2); ri += 4) {
+    const int c = ri / (MROWS + 2), yy = y0 + ri % (MROWS + 2) - 1;
+    const bool rok = yy >= 0 && yy < Ly;
+    const float* src = in + ((size_t)b * C + c) * plane + (size_t)(rok ? yy : 0) * Lx;
+    for (int xx = lane; xx < XS; xx += 64) {
+      const int x = xx - 1;
+      xs[ri * XS + xx] = (rok && x >= 0 && x < Lx) ? src[x] : 0.0f;
+    }
+  }
+  __syncthreads();
+  const int y = y0 + w;
+  if (y >= Ly) return;   // no barrier follows
+  for (int x0 = 0; x0 < Lx; x0 += 32) {
+    const int xl = x0 + (lane & 31);
+    const int xr = min(xl, Lx - 1);   // columns past the row read a valid entry and are not written
+    floatx16 acc = {};
+#pragma unroll
+    for (int tt = 0; tt < 5; ++tt) {
+      const int t = BWD ? 4 + tt : tt;
+      const float* xb = xs + ((lane >> 5) * (MROWS + 2) + w + t / 3) * XS + xr + t % 3;
+      const float* wb = wa + tt * 16 * 64 + lane;
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk)
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wb[kk * 64], xb[2 * kk * (MROWS + 2) * XS], acc, 0, 0, 0);
+    }
+    if (xl < Lx) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const size_t o = ((size_t)b * C + m) * plane + (size_t)y * Lx + xl;
+        out[o] = BWD ? (mask_src[o] > 0.0f ? acc[r] : 0.0f) : fmaxf(acc[r] + theta[off + C * C * 9 + m], 0.0f);
+      }
+    }
+  }
+}
+
+template <bool BWD>
+hipError_t conv32(const float* theta, int layer, const float* in, const float* mask_src, float* out, int n, int Lx,
+                  int Ly, hipStream_t s) {
+  const size_t bytes = conv32_lds_floats(Lx) * sizeof(float);
+  static size_t attr_bytes = 0;
+  if (bytes > 48 * 1024 && bytes > attr_bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)nn_conv32_kernel<BWD>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)bytes);
+    if (e != hipSuccess) return e;
+    attr_bytes = bytes;
+  }
+  const int nyb = (Ly + MROWS - 1) / MROWS;
+  hipLaunchKernelGGL(nn_conv32_kernel<BWD>, dim3(n * nyb), dim3(256), bytes, s, theta, OFF_H + (layer - 1) * HID, in,
+                     mask_src, out, Lx, Ly);
+  return hipGetLastError();
+}
+
+// Weight and bias gradient partials of a hidden layer on MFMA: for each kept
+// tap k, dW_k[co][ci] = sum over positions of g[co][pos] x[ci][pos + offset_k],
+// a 32 x 32 product whose K runs over the positions, two per MFMA step.  Each
+// wavefront takes one (sample, row) per pass of its workgroup over the rows
+// and keeps the five tap accumulators in registers; wavefront p of the grid
+// writes part[p][e] (e < 32*32*9 + 32; masked taps are not written and are
+// zeroed by the reduction).
+constexpr int WROWS = 4;
+__host__ __device__ inline size_t wgrad_lds_floats(int Lx) {
+  return (size_t)WROWS * ((size_t)C * (Lx + 2) + (size_t)C * 3 * (Lx + 3));
+}
+
+__global__ __launch_bounds__(256) void nn_wgrad32_kernel(const float* __restrict__ g, const float* __restrict__ act_prev,
+                                                         float* __restrict__ part, int n_rows, int Lx, int Ly) {
+  extern __shared__ __align__(16) float wl[];
+  constexpr int NE = C * C * 9 + C;
+  const int GS = Lx + 2, XS = Lx + 3;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const size_t per = (size_t)C * GS + (size_t)C * 3 * XS;
+  const float* gs = wl + w * per;      // this wavefront's row: g [C][GS], zero past Lx
+  const float* xs = gs + (size_t)C * GS;   // input rows y-1..y+1 [C][3][XS], zero padded
+  const size_t plane = (size_t)Lx * Ly;
+  const int steps = (Lx + 1) / 2;
+  floatx16 acc[5];
+#pragma unroll
+  for (int t = 0; t < 5; ++t) acc[t] = floatx16{};
+  float bsum = 0.0f;
+  for (int row0 = blockIdx.x * WROWS; row0 < n_rows; row0 += gridDim.x * WROWS) {
+    __syncthreads();
+    for (int q = 0; q < WROWS; ++q) {
+      const int row = row0 + q;
+      const bool ok = row < n_rows;
+      const int b = ok ? row / Ly : 0, y = ok ? row % Ly : 0;
+      float* gq = wl + q * per;
+      float* xq = gq + (size_t)C * GS;
+      for (int c = tid >> 6; c < C; c += 4) {
+        const float* src = g + ((size_t)b * C + c) * plane + (size_t)y * Lx;
+        for (int x = lane; x < GS; x += 64) gq[c * GS + x] = (ok && x < Lx) ? src[x] : 0.0f;
+      }
+      for (int ri = tid >> 6; ri < C * 3; ri += 4) {
+        const int c = ri / 3, yy = y + ri % 3 - 1;
+        const bool rok = ok && yy >= 0 && yy < Ly;
+        const float* src = act_prev + ((size_t)b * C + c) * plane + (size_t)(rok ? yy : 0) * Lx;
+        for (int xx = lane; xx < XS; xx += 64) {
+          const int x = xx - 1;
+          xq[ri * XS + xx] = (rok && x >= 0 && x < Lx) ? src[x] : 0.0f;
+        }
+      }
+    }
+    __syncthreads();
+    if (row0 + w < n_rows) {
+      // A[co][pos] = g[co = lane % 32][x = 2 st + lane / 32]; B[pos][ci] = x[ci = lane % 32][row ky][x + kx] (padded)
+      const float* ga = gs + (lane & 31) * GS + (lane >> 5);
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        const float* xb = xs + ((lane & 31) * 3 + t / 3) * XS + (lane >> 5) + t % 3;
+        for (int st = 0; st < steps; ++st)
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(ga[2 * st], xb[2 * st], acc[t], 0, 0, 0);
+      }
+      if (lane < 32)
+        for (int x = 0; x < Lx; ++x) bsum += gs[lane * GS + x];
+    }
+  }
+  const size_t p = ((size_t)blockIdx.x * WROWS + w) * NE;
+#pragma unroll
+  for (int t = 0; t < 5; ++t)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int co = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), ci = lane & 31;
+      part[p + (size_t)(co * C + ci) * 9 + t] = acc[t][r];
+    }
+  if (lane < 32) part[p + C * C * 9 + lane] = bsum;
+}
+
 // Per sample: log q (FP64) and d(mean -log q)/d logit (0 where the clip is active).
 __global__ __launch_bounds__(NTT) void nn_loss_kernel(const float* __restrict__ logit, const int8_t* __restrict__ s,
                                                       double* __restrict__ logq, float* __restrict__ glogit,
@@ -528,18 +694,40 @@ __global__ __launch_bounds__(NTT) void nn_bwd_weight_kernel(const float* __restr
   }
 }
 
-// grad[OFF + e] = sum_w part[w][e] (FP64 sum), masked weights zeroed.
+// grad[OFF + e] = sum_w part[w][e] (FP64 sum), masked weights zeroed.  A
+// workgroup takes 32 consecutive entries; its 8 groups of 32 threads sum the
+// partials w = j, j + 8, ... (j = group), which are then added in group
+// order: the same order on every run.
 template <int LAYER>
 __global__ __launch_bounds__(NTT) void nn_grad_reduce_kernel(const float* __restrict__ part, int n_parts,
                                                              float* __restrict__ grad) {
   using S = LayerShape<LAYER>;
   constexpr int NE = S::NW + S::COUT;
-  const int e = blockIdx.x * NTT + threadIdx.x;
-  if (e >= NE) return;
+  __shared__ double red[NTT];
+  const int el = threadIdx.x & 31, j = threadIdx.x >> 5;
+  const int e = blockIdx.x * 32 + el;
   double a = 0.0;
-  for (int w = 0; w < n_parts; ++w) a += (double)part[(size_t)w * NE + e];
-  const bool kept = e >= S::NW || tap_kept(LAYER, (e / 9) % S::CIN, e % 9);
-  grad[S::OFF + e] = kept ? (float)a : 0.0f;
+  if (e < NE) {
+    int w = j;
+    for (; w + 24 < n_parts; w += 32) {
+      const float v0 = part[(size_t)w * NE + e], v1 = part[(size_t)(w + 8) * NE + e];
+      const float v2 = part[(size_t)(w + 16) * NE + e], v3 = part[(size_t)(w + 24) * NE + e];
+      a += (double)v0;
+      a += (double)v1;
+      a += (double)v2;
+      a += (double)v3;
+    }
+    for (; w < n_parts; w += 8) a += (double)part[(size_t)w * NE + e];
+  }
+  red[threadIdx.x] = a;
+  __syncthreads();
+  if (j == 0 && e < NE) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < NTT / 32; ++q) t += red[q * 32 + el];
+    const bool kept = e >= S::NW || tap_kept(LAYER, (e / 9) % S::CIN, e % 9);
+    grad[S::OFF + e] = kept ? (float)t : 0.0f;
+  }
 }
 
 __global__ __launch_bounds__(NTT) void nn_adam_kernel(float* __restrict__ theta, float* __restrict__ m,
@@ -560,11 +748,27 @@ hipError_t bwd_weight(const NnBatch& B, const float* g, const float* act_prev, f
   using S = LayerShape<LAYER>;
   constexpr int NE = S::NW + S::COUT;
   const int n_rows = B.n * B.Ly;
-  const int G = std::min(n_rows, kNnWeightParts);
-  hipLaunchKernelGGL(nn_bwd_weight_kernel<LAYER>, dim3(G), dim3(NTT), 0, s, g, act_prev, B.cond, B.s, B.part, n_rows,
-                     B.Lx, B.Ly);
-  hipLaunchKernelGGL(nn_grad_reduce_kernel<LAYER>, dim3((NE + NTT - 1) / NTT), dim3(NTT), 0, s, B.part, G, grad);
-  return hipGetLastError();
+  if constexpr (LAYER >= 1 && LAYER <= 4) {
+    const int wgs = std::min((n_rows + WROWS - 1) / WROWS, kNnWeightParts / WROWS);
+    const size_t bytes = wgrad_lds_floats(B.Lx) * sizeof(float);
+    static size_t attr_bytes = 0;
+    if (bytes > 48 * 1024 && bytes > attr_bytes) {
+      hipError_t e = hipFuncSetAttribute((const void*)nn_wgrad32_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)bytes);
+      if (e != hipSuccess) return e;
+      attr_bytes = bytes;
+    }
+    hipLaunchKernelGGL(nn_wgrad32_kernel, dim3(wgs), dim3(NTT), bytes, s, g, act_prev, B.part, n_rows, B.Lx, B.Ly);
+    hipLaunchKernelGGL(nn_grad_reduce_kernel<LAYER>, dim3((NE + 31) / 32), dim3(NTT), 0, s, B.part, wgs * WROWS,
+                       grad);
+    return hipGetLastError();
+  } else {
+    const int G = std::min(n_rows, kNnWeightParts);
+    hipLaunchKernelGGL(nn_bwd_weight_kernel<LAYER>, dim3(G), dim3(NTT), 0, s, g, act_prev, B.cond, B.s, B.part, n_rows,
+                       B.Lx, B.Ly);
+    hipLaunchKernelGGL(nn_grad_reduce_kernel<LAYER>, dim3((NE + 31) / 32), dim3(NTT), 0, s, B.part, G, grad);
+    return hipGetLastError();
+  }
 }
 
 // Condition channels and current layer of every (chain, z) of a lattice:
@@ -614,10 +818,10 @@ hipError_t launch_nn_sample(const TaskDesc* tasks, int n, const float* theta, in
 hipError_t nn_forward(const NnBatch& B, const float* theta, hipStream_t s) {
   const dim3 grid(B.n * B.Ly), blk(NTT);
   hipLaunchKernelGGL(nn_fwd_kernel<0>, grid, blk, 0, s, theta, nullptr, B.cond, B.s, B.act[0], B.Lx, B.Ly);
-  hipLaunchKernelGGL(nn_fwd_kernel<1>, grid, blk, 0, s, theta, B.act[0], nullptr, nullptr, B.act[1], B.Lx, B.Ly);
-  hipLaunchKernelGGL(nn_fwd_kernel<2>, grid, blk, 0, s, theta, B.act[1], nullptr, nullptr, B.act[2], B.Lx, B.Ly);
-  hipLaunchKernelGGL(nn_fwd_kernel<3>, grid, blk, 0, s, theta, B.act[2], nullptr, nullptr, B.act[3], B.Lx, B.Ly);
-  hipLaunchKernelGGL(nn_fwd_kernel<4>, grid, blk, 0, s, theta, B.act[3], nullptr, nullptr, B.act[4], B.Lx, B.Ly);
+  for (int l = 1; l <= 4; ++l) {
+    hipError_t e = conv32<false>(theta, l, B.act[l - 1], nullptr, B.act[l], B.n, B.Lx, B.Ly, s);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(nn_fwd_kernel<5>, grid, blk, 0, s, theta, B.act[4], nullptr, nullptr, B.logit, B.Lx, B.Ly);
   hipLaunchKernelGGL(nn_loss_kernel, dim3(B.n), blk, 0, s, B.logit, B.s, B.logq, B.glogit, B.Lx * B.Ly,
                      1.0 / (double)B.n);
@@ -631,13 +835,13 @@ hipError_t nn_backward(const NnBatch& B, const float* theta, float* grad, hipStr
   if ((e = bwd_weight<5>(B, B.glogit, B.act[4], grad, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(nn_bwd_data_kernel<5>, grid, blk, 0, s, theta, B.glogit, B.act[4], B.g[0], B.Lx, B.Ly);
   if ((e = bwd_weight<4>(B, B.g[0], B.act[3], grad, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(nn_bwd_data_kernel<4>, grid, blk, 0, s, theta, B.g[0], B.act[3], B.g[1], B.Lx, B.Ly);
+  if ((e = conv32<true>(theta, 4, B.g[0], B.act[3], B.g[1], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
   if ((e = bwd_weight<3>(B, B.g[1], B.act[2], grad, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(nn_bwd_data_kernel<3>, grid, blk, 0, s, theta, B.g[1], B.act[2], B.g[0], B.Lx, B.Ly);
+  if ((e = conv32<true>(theta, 3, B.g[1], B.act[2], B.g[0], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
   if ((e = bwd_weight<2>(B, B.g[0], B.act[1], grad, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(nn_bwd_data_kernel<2>, grid, blk, 0, s, theta, B.g[0], B.act[1], B.g[1], B.Lx, B.Ly);
+  if ((e = conv32<true>(theta, 2, B.g[0], B.act[1], B.g[1], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
   if ((e = bwd_weight<1>(B, B.g[1], B.act[0], grad, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(nn_bwd_data_kernel<1>, grid, blk, 0, s, theta, B.g[1], B.act[0], B.g[0], B.Lx, B.Ly);
+  if ((e = conv32<true>(theta, 1, B.g[1], B.act[0], B.g[0], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
   if ((e = bwd_weight<0>(B, B.g[0], nullptr, grad, s)) != hipSuccess) return e;
   return hipGetLastError();
 }
