@@ -460,15 +460,12 @@ __global__ __launch_bounds__(256) void nn_conv32_kernel(const float* __restrict_
     const int m = l & 31, c = 2 * kk + (l >> 5);
     wa[i] = BWD ? theta[off + (c * C + m) * 9 + (4 - tt)] : theta[off + (m * C + c) * 9 + tt];
   }
-  // rows (channel, row slot) over the four wavefronts, columns over the lanes
-  for (int ri = tid >> 6; ri < C * (MROWS + 2); ri += 4) {
-    const int c = ri / (MROWS + 2), yy = y0 + ri % (MROWS + 2) - 1;
-    const bool rok = yy >= 0 && yy < Ly;
-    const float* src = in + ((size_t)b * C + c) * plane + (size_t)(rok ? yy : 0) * Lx;
-    for (int xx = lane; xx < XS; xx += 64) {
-      const int x = xx - 1;
-      xs[ri * XS + xx] = (rok && x >= 0 && x < Lx) ? src[x] : 0.0f;
-    }
+  // flat over all threads; the quotient by the row length through an exact float reciprocal
+  const float inv_xs = 1.0f / (float)XS;
+  for (int i = tid; i < C * (MROWS + 2) * XS; i += 256) {
+    const int ri = fquot(i, inv_xs), xx = i - ri * XS;
+    const int c = ri / (MROWS + 2), yy = y0 + ri % (MROWS + 2) - 1, x = xx - 1;
+    xs[i] = (yy >= 0 && yy < Ly && x >= 0 && x < Lx) ? in[((size_t)b * C + c) * plane + (size_t)yy * Lx + x] : 0.0f;
   }
   __syncthreads();
   const int y = y0 + w;
@@ -537,6 +534,7 @@ __global__ __launch_bounds__(256) void nn_wgrad32_kernel(const float* __restrict
   const float* xs = gs + (size_t)C * GS;   // input rows y-1..y+1 [C][3][XS], zero padded
   const size_t plane = (size_t)Lx * Ly;
   const int steps = (Lx + 1) / 2;
+  const float inv_gs = 1.0f / (float)GS, inv_xs = 1.0f / (float)XS;
   floatx16 acc[5];
 #pragma unroll
   for (int t = 0; t < 5; ++t) acc[t] = floatx16{};
@@ -549,18 +547,15 @@ __global__ __launch_bounds__(256) void nn_wgrad32_kernel(const float* __restrict
       const int b = ok ? row / Ly : 0, y = ok ? row % Ly : 0;
       float* gq = wl + q * per;
       float* xq = gq + (size_t)C * GS;
-      for (int c = tid >> 6; c < C; c += 4) {
-        const float* src = g + ((size_t)b * C + c) * plane + (size_t)y * Lx;
-        for (int x = lane; x < GS; x += 64) gq[c * GS + x] = (ok && x < Lx) ? src[x] : 0.0f;
+      for (int i = tid; i < C * GS; i += 256) {
+        const int c = fquot(i, inv_gs), x = i - c * GS;
+        gq[i] = (ok && x < Lx) ? g[((size_t)b * C + c) * plane + (size_t)y * Lx + x] : 0.0f;
       }
-      for (int ri = tid >> 6; ri < C * 3; ri += 4) {
-        const int c = ri / 3, yy = y + ri % 3 - 1;
-        const bool rok = ok && yy >= 0 && yy < Ly;
-        const float* src = act_prev + ((size_t)b * C + c) * plane + (size_t)(rok ? yy : 0) * Lx;
-        for (int xx = lane; xx < XS; xx += 64) {
-          const int x = xx - 1;
-          xq[ri * XS + xx] = (rok && x >= 0 && x < Lx) ? src[x] : 0.0f;
-        }
+      for (int i = tid; i < C * 3 * XS; i += 256) {
+        const int ri = fquot(i, inv_xs), xx = i - ri * XS;
+        const int c = ri / 3, yy = y + ri % 3 - 1, x = xx - 1;
+        xq[i] = (ok && yy >= 0 && yy < Ly && x >= 0 && x < Lx)
+                    ? act_prev[((size_t)b * C + c) * plane + (size_t)yy * Lx + x] : 0.0f;
       }
     }
     __syncthreads();
