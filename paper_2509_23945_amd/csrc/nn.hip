@@ -565,6 +565,7 @@ __global__ __launch_bounds__(256) void nn_wgrad32_kernel(const float* __restrict
 #pragma unroll
       for (int t = 0; t < 5; ++t) {
         const float* xb = xs + ((lane & 31) * 3 + t / 3) * XS + (lane >> 5) + t % 3;
+#pragma unroll 4
         for (int st = 0; st < steps; ++st)
           acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(ga[2 * st], xb[2 * st], acc[t], 0, 0, 0);
       }
@@ -758,7 +759,7 @@ hipError_t bwd_weight(const NnBatch& B, const float* g, const float* act_prev, f
                        grad);
     return hipGetLastError();
   } else {
-    const int G = std::min(n_rows, kNnWeightParts);
+    const int G = std::min(n_rows, kNnWeightParts / 2);
     hipLaunchKernelGGL(nn_bwd_weight_kernel<LAYER>, dim3(G), dim3(NTT), 0, s, g, act_prev, B.cond, B.s, B.part, n_rows,
                        B.Lx, B.Ly);
     hipLaunchKernelGGL(nn_grad_reduce_kernel<LAYER>, dim3((NE + 31) / 32), dim3(NTT), 0, s, B.part, G, grad);

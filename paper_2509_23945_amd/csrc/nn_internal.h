@@ -16,7 +16,7 @@ constexpr int kNnCond = 4;
 constexpr int kNnLayers = 6;
 constexpr int kNnParams = 38753;   // (5*32*9 + 32) + 4 (32*32*9 + 32) + (32*9 + 1)
 constexpr int kNnLxMax = 64;       // widest layer of the batched training kernels
-constexpr int kNnWeightParts = 1024;  // partial sums of a weight gradient (workgroups, or wavefronts on MFMA)
+constexpr int kNnWeightParts = 2048;  // partial sums of a weight gradient (workgroups, or wavefronts on MFMA)
 constexpr double kNnAdamB1 = 0.9, kNnAdamB2 = 0.999, kNnAdamEps = 1e-8;
 
 // Device buffers of one training / evaluation batch of n layers of Lx x Ly.
