@@ -446,12 +446,11 @@ template <bool BWD>
 __global__ __launch_bounds__(256) void nn_conv32_kernel(const float* __restrict__ theta, int off,
                                                         const float* __restrict__ in,
                                                         const float* __restrict__ mask_src, float* __restrict__ out,
-                                                        int Lx, int Ly) {
+                                                        int n_groups, int Lx, int Ly) {
   extern __shared__ __align__(16) float cl[];
   float* wa = cl;
   float* xs = cl + WA;
   const int nyb = (Ly + MROWS - 1) / MROWS;
-  const int b = blockIdx.x / nyb, y0 = (blockIdx.x % nyb) * MROWS;
   const int XS = Lx + 2;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const size_t plane = (size_t)Lx * Ly;
@@ -462,33 +461,38 @@ __global__ __launch_bounds__(256) void nn_conv32_kernel(const float* __restrict_
   }
   // flat over all threads; the quotient by the row length through an exact float reciprocal
   const float inv_xs = 1.0f / (float)XS;
-  for (int i = tid; i < C * (MROWS + 2) * XS; i += 256) {
-    const int ri = fquot(i, inv_xs), xx = i - ri * XS;
-    const int c = ri / (MROWS + 2), yy = y0 + ri % (MROWS + 2) - 1, x = xx - 1;
-    xs[i] = (yy >= 0 && yy < Ly && x >= 0 && x < Lx) ? in[((size_t)b * C + c) * plane + (size_t)yy * Lx + x] : 0.0f;
-  }
-  __syncthreads();
-  const int y = y0 + w;
-  if (y >= Ly) return;   // no barrier follows
-  for (int x0 = 0; x0 < Lx; x0 += 32) {
-    const int xl = x0 + (lane & 31);
-    const int xr = min(xl, Lx - 1);   // columns past the row read a valid entry and are not written
-    floatx16 acc = {};
-#pragma unroll
-    for (int tt = 0; tt < 5; ++tt) {
-      const int t = BWD ? 4 + tt : tt;
-      const float* xb = xs + ((lane >> 5) * (MROWS + 2) + w + t / 3) * XS + xr + t % 3;
-      const float* wb = wa + tt * 16 * 64 + lane;
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk)
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wb[kk * 64], xb[2 * kk * (MROWS + 2) * XS], acc, 0, 0, 0);
+  // the workgroup walks the (sample, four-row group) pairs blockIdx.x, + gridDim.x, ...
+  for (int gi = blockIdx.x; gi < n_groups; gi += gridDim.x) {
+    const int b = gi / nyb, y0 = (gi % nyb) * MROWS;
+    __syncthreads();   // the previous group's reads of xs are done
+    for (int i = tid; i < C * (MROWS + 2) * XS; i += 256) {
+      const int ri = fquot(i, inv_xs), xx = i - ri * XS;
+      const int c = ri / (MROWS + 2), yy = y0 + ri % (MROWS + 2) - 1, x = xx - 1;
+      xs[i] = (yy >= 0 && yy < Ly && x >= 0 && x < Lx) ? in[((size_t)b * C + c) * plane + (size_t)yy * Lx + x] : 0.0f;
     }
-    if (xl < Lx) {
+    __syncthreads();
+    const int y = y0 + w;
+    if (y >= Ly) continue;   // the next group starts with a barrier every wavefront reaches
+    for (int x0 = 0; x0 < Lx; x0 += 32) {
+      const int xl = x0 + (lane & 31);
+      const int xr = min(xl, Lx - 1);   // columns past the row read a valid entry and are not written
+      floatx16 acc = {};
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const size_t o = ((size_t)b * C + m) * plane + (size_t)y * Lx + xl;
-        out[o] = BWD ? (mask_src[o] > 0.0f ? acc[r] : 0.0f) : fmaxf(acc[r] + theta[off + C * C * 9 + m], 0.0f);
+      for (int tt = 0; tt < 5; ++tt) {
+        const int t = BWD ? 4 + tt : tt;
+        const float* xb = xs + ((lane >> 5) * (MROWS + 2) + w + t / 3) * XS + xr + t % 3;
+        const float* wb = wa + tt * 16 * 64 + lane;
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(wb[kk * 64], xb[2 * kk * (MROWS + 2) * XS], acc, 0, 0, 0);
+      }
+      if (xl < Lx) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const size_t o = ((size_t)b * C + m) * plane + (size_t)y * Lx + xl;
+          out[o] = BWD ? (mask_src[o] > 0.0f ? acc[r] : 0.0f) : fmaxf(acc[r] + theta[off + C * C * 9 + m], 0.0f);
+        }
       }
     }
   }
@@ -505,9 +509,9 @@ hipError_t conv32(const float* theta, int layer, const float* in, const float* m
     if (e != hipSuccess) return e;
     attr_bytes = bytes;
   }
-  const int nyb = (Ly + MROWS - 1) / MROWS;
-  hipLaunchKernelGGL(nn_conv32_kernel<BWD>, dim3(n * nyb), dim3(256), bytes, s, theta, OFF_H + (layer - 1) * HID, in,
-                     mask_src, out, Lx, Ly);
+  const int n_groups = n * ((Ly + MROWS - 1) / MROWS);
+  hipLaunchKernelGGL(nn_conv32_kernel<BWD>, dim3(std::min(n_groups, 1024)), dim3(256), bytes, s, theta,
+                     OFF_H + (layer - 1) * HID, in, mask_src, out, n_groups, Lx, Ly);
   return hipGetLastError();
 }
 
