@@ -39,7 +39,8 @@ typedef enum {
   TNMC_ERR_OOM = -2,         /* device allocation failed */
   TNMC_ERR_DEVICE = -3,      /* a HIP call failed (message: tnmc_last_error) */
   TNMC_ERR_NUMERIC = -4,     /* non-finite result in a proposal */
-  TNMC_ERR_UNSUPPORTED = -5  /* (d, chi, precision) combination not built */
+  TNMC_ERR_UNSUPPORTED = -5, /* (d, chi, precision) combination not built */
+  TNMC_ERR_IO = -6           /* checkpoint file unreadable / unwritable, or of another lattice */
 } tnmc_status;
 
 enum { TNMC_FP64 = 0, TNMC_FP32 = 1 };   /* storage precision of the boundary-MPS environments */
@@ -144,6 +145,21 @@ tnmc_status tnmc_energy(tnmc_lattice* lat, int32_t chain, double* E);
 tnmc_status tnmc_timeseries(tnmc_lattice* lat, double* E, double* M, double* q, int64_t* n);
 /* Drop the recorded observables. */
 tnmc_status tnmc_timeseries_reset(tnmc_lattice* lat);
+/* Couplings as given at init: HOST [n_instances][3][Lz][Ly][Lx] (synchronous). */
+tnmc_status tnmc_get_couplings(tnmc_lattice* lat, float* out);
+
+/* Checkpoint / resume (synchronous).  save writes the chains' spins, the
+ * recorded observables, the learned-proposal counts and fallback flags, and
+ * the caller's next sweep counter to the file at path.  load restores them
+ * into a lattice created with the same description (shape, d, chi,
+ * precision, chains, instances, betas, pairs, Philox seed and keys, and the
+ * same couplings, checked by a hash); *next_sweep (may be NULL) receives the
+ * saved counter.  Random numbers are a pure function of (seed, key, sweep,
+ * layer, site), so sweeps run after a load with that counter reproduce an
+ * uninterrupted run.  Errors: TNMC_ERR_IO (message: tnmc_last_error); the
+ * lattice is unchanged unless TNMC_OK. */
+tnmc_status tnmc_checkpoint_save(tnmc_lattice* lat, uint64_t next_sweep, const char* path);
+tnmc_status tnmc_checkpoint_load(tnmc_lattice* lat, const char* path, uint64_t* next_sweep);
 
 /* Algorithmic FP64 flop count of one slice update of an Lx x Ly layer with
  * bond dimension chi, split into the boundary-MPS contraction (textbook

@@ -23,6 +23,7 @@ TNMC_ERR_OOM = -2
 TNMC_ERR_DEVICE = -3
 TNMC_ERR_NUMERIC = -4
 TNMC_ERR_UNSUPPORTED = -5
+TNMC_ERR_IO = -6
 TNMC_FP64 = 0
 TNMC_FP32 = 1
 
@@ -35,7 +36,7 @@ __all__ = [
     "tnmc_nn_get_params", "tnmc_nn_set_params", "tnmc_nn_logq", "tnmc_nn_loss_grad", "tnmc_nn_adam_step",
     "tnmc_nn_train", "tnmc_nn_dataset", "tnmc_nn_slice_propose", "tnmc_nn_slice_logq", "tnmc_nn_sweep",
     "tnmc_nn_counts", "tnmc_nn_counts_reset", "tnmc_nn_set_fallback", "tnmc_nn_get_fallback",
-    "tnmc_nn_calibrate_fallback",
+    "tnmc_nn_calibrate_fallback", "tnmc_get_couplings", "tnmc_checkpoint_save", "tnmc_checkpoint_load",
 ]
 TNMC_NN_PARAMS = 38753
 
@@ -140,6 +141,9 @@ def load():
         "tnmc_nn_set_fallback": [vp, P(ctypes.c_int8)],
         "tnmc_nn_get_fallback": [vp, P(ctypes.c_int8)],
         "tnmc_nn_calibrate_fallback": [vp, dbl, P(i32)],
+        "tnmc_get_couplings": [vp, P(ctypes.c_float)],
+        "tnmc_checkpoint_save": [vp, u64, ctypes.c_char_p],
+        "tnmc_checkpoint_load": [vp, ctypes.c_char_p, P(u64)],
     }
     for name, sig in nn_sigs.items():
         getattr(lib, name).argtypes = sig
@@ -214,7 +218,9 @@ def tnmc_lattice_init(*, Lx, Ly, Lz, d, chi, J, beta, spins, chain_instance=None
                  _ptr(pr, ctypes.c_int32) if pr.shape[0] else None, record_capacity)
     h = ctypes.c_void_p()
     _check(lib.tnmc_lattice_init(ctypes.byref(desc), ctypes.byref(h)), "tnmc_lattice_init")
-    return Lattice(h, Lx, Ly, Lz, d, chi, n_chains, pr.shape[0], record_capacity)
+    lat = Lattice(h, Lx, Ly, Lz, d, chi, n_chains, pr.shape[0], record_capacity)
+    lat.n_instances = n_inst
+    return lat
 
 
 def tnmc_lattice_free(lat: Lattice):
@@ -452,3 +458,22 @@ def tnmc_nn_calibrate_fallback(lat: Lattice, threshold: float) -> int:
     n = ctypes.c_int32()
     _check(load().tnmc_nn_calibrate_fallback(lat.handle, threshold, ctypes.byref(n)), "tnmc_nn_calibrate_fallback")
     return n.value
+
+
+def tnmc_get_couplings(lat: Lattice) -> np.ndarray:
+    """Returns J [n_instances, 3, Lz, Ly, Lx]."""
+    out = np.zeros((lat.n_instances, 3, lat.Lz, lat.Ly, lat.Lx), dtype=np.float32)
+    _check(load().tnmc_get_couplings(lat.handle, _ptr(out, ctypes.c_float)), "tnmc_get_couplings")
+    return out
+
+
+def tnmc_checkpoint_save(lat: Lattice, next_sweep: int, path: str) -> None:
+    _check(load().tnmc_checkpoint_save(lat.handle, ctypes.c_uint64(next_sweep), os.fsencode(path)),
+           "tnmc_checkpoint_save")
+
+
+def tnmc_checkpoint_load(lat: Lattice, path: str) -> int:
+    """Returns the saved next sweep counter."""
+    nxt = ctypes.c_uint64()
+    _check(load().tnmc_checkpoint_load(lat.handle, os.fsencode(path), ctypes.byref(nxt)), "tnmc_checkpoint_load")
+    return nxt.value

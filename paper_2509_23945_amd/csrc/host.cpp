@@ -48,6 +48,7 @@ struct tnmc_lattice {
   std::vector<double> beta;
   std::vector<uint64_t> chain_key;
   std::vector<int> pairs;
+  uint64_t J_hash = 0;      // FNV-1a of the couplings given at init (checkpoints are tied to them)
   float* dJ = nullptr;
   int8_t* dspins = nullptr;
   int* dpa = nullptr;
@@ -353,6 +354,7 @@ const char* tnmc_status_string(tnmc_status s) {
     case TNMC_ERR_DEVICE: return "HIP error";
     case TNMC_ERR_NUMERIC: return "numeric fault";
     case TNMC_ERR_UNSUPPORTED: return "unsupported configuration";
+    case TNMC_ERR_IO: return "checkpoint file error";
   }
   return "unknown status";
 }
@@ -423,6 +425,12 @@ tnmc_status tnmc_lattice_init(const tnmc_lattice_desc* ds, tnmc_lattice** out) {
       return fail(e_ == hipErrorOutOfMemory ? TNMC_ERR_OOM : TNMC_ERR_DEVICE); \
     }                                                                    \
   } while (0)
+  {
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(ds->J);
+    for (size_t i = 0; i < (size_t)ds->n_instances * 3 * n * sizeof(float); ++i) h = (h ^ p[i]) * 1099511628211ull;
+    L->J_hash = h;
+  }
   INIT_TRY(hipMalloc((void**)&L->dJ, (size_t)ds->n_instances * 3 * n * sizeof(float)));
   INIT_TRY(hipMemcpy(L->dJ, ds->J, (size_t)ds->n_instances * 3 * n * sizeof(float), hipMemcpyHostToDevice));
   INIT_TRY(hipMalloc((void**)&L->dspins, (size_t)ds->n_chains * n));
@@ -1247,6 +1255,153 @@ tnmc_status tnmc_nn_calibrate_fallback(tnmc_lattice* lat, double threshold, int3
     cnt += lat->nn_fallback[i];
   }
   if (n_fallback) *n_fallback = cnt;
+  return TNMC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ checkpoints
+
+namespace {
+
+constexpr char kCkptMagic[8] = {'T', 'N', 'M', 'C', 'C', 'K', 'P', '1'};
+
+struct CkptHeader {
+  char magic[8];
+  int32_t Lx, Ly, Lz, d, chi, precision, n_chains, n_instances, n_pairs, record_capacity;
+  uint64_t seed, J_hash, next_sweep;
+  int64_t n_recorded;
+  int32_t has_nn, pad;
+};
+
+struct File {
+  FILE* f = nullptr;
+  ~File() {
+    if (f) fclose(f);
+  }
+};
+
+tnmc_status io_fail(const std::string& what) {
+  g_last_error = what;
+  return TNMC_ERR_IO;
+}
+
+}  // namespace
+
+extern "C" {
+
+tnmc_status tnmc_get_couplings(tnmc_lattice* L, float* out) {
+  if (!L || !out) return TNMC_ERR_ARG;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(out, L->dJ, (size_t)L->n_instances * 3 * L->sites() * sizeof(float), hipMemcpyDeviceToHost));
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_checkpoint_save(tnmc_lattice* L, uint64_t next_sweep, const char* path) {
+  if (!L || !path) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  HIP_TRY(hipDeviceSynchronize());
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.Lx = L->Lx; h.Ly = L->Ly; h.Lz = L->Lz; h.d = L->d; h.chi = L->chi; h.precision = L->precision;
+  h.n_chains = L->n_chains; h.n_instances = L->n_instances; h.n_pairs = L->n_pairs;
+  h.record_capacity = L->record_capacity;
+  h.seed = L->seed; h.J_hash = L->J_hash; h.next_sweep = next_sweep; h.n_recorded = L->n_recorded;
+  h.has_nn = L->dnncnt ? 1 : 0;
+  const size_t nc = L->n_chains, k = (size_t)L->n_recorded, np = L->n_pairs;
+  std::vector<double> E(k * nc), M(k * nc), q(k * np);
+  std::vector<int8_t> spins(nc * L->sites());
+  if (k) {
+    HIP_TRY(hipMemcpy(E.data(), L->dErec, E.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(M.data(), L->dMrec, M.size() * sizeof(double), hipMemcpyDeviceToHost));
+    if (np) HIP_TRY(hipMemcpy(q.data(), L->dqrec, q.size() * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  HIP_TRY(hipMemcpy(spins.data(), L->dspins, spins.size(), hipMemcpyDeviceToHost));
+  std::vector<long long> cnt;
+  if (h.has_nn) {
+    cnt.resize(nc * L->Lz * tnmc::kCounterStride);
+    HIP_TRY(hipMemcpy(cnt.data(), L->dnncnt, cnt.size() * sizeof(long long), hipMemcpyDeviceToHost));
+  }
+  File f;
+  f.f = fopen(path, "wb");
+  if (!f.f) return io_fail(std::string("cannot open ") + path + " for writing");
+  bool ok = fwrite(&h, sizeof(h), 1, f.f) == 1;
+  ok = ok && fwrite(L->chain_key.data(), sizeof(uint64_t), nc, f.f) == nc;
+  ok = ok && fwrite(L->beta.data(), sizeof(double), nc, f.f) == nc;
+  ok = ok && fwrite(L->chain_instance.data(), sizeof(int), nc, f.f) == nc;
+  ok = ok && (np == 0 || fwrite(L->pairs.data(), sizeof(int), 2 * np, f.f) == 2 * np);
+  ok = ok && (k == 0 || fwrite(E.data(), sizeof(double), E.size(), f.f) == E.size());
+  ok = ok && (k == 0 || fwrite(M.data(), sizeof(double), M.size(), f.f) == M.size());
+  ok = ok && (k * np == 0 || fwrite(q.data(), sizeof(double), q.size(), f.f) == q.size());
+  ok = ok && fwrite(spins.data(), 1, spins.size(), f.f) == spins.size();
+  if (h.has_nn) {
+    ok = ok && fwrite(L->nn_fallback.data(), 1, L->nn_fallback.size(), f.f) == L->nn_fallback.size();
+    ok = ok && fwrite(cnt.data(), sizeof(long long), cnt.size(), f.f) == cnt.size();
+  }
+  ok = ok && fflush(f.f) == 0;
+  if (!ok) return io_fail(std::string("short write to ") + path);
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_checkpoint_load(tnmc_lattice* L, const char* path, uint64_t* next_sweep) {
+  if (!L || !path) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  File f;
+  f.f = fopen(path, "rb");
+  if (!f.f) return io_fail(std::string("cannot open ") + path);
+  CkptHeader h;
+  if (fread(&h, sizeof(h), 1, f.f) != 1 || std::memcmp(h.magic, kCkptMagic, 8) != 0)
+    return io_fail(std::string(path) + " is not a checkpoint");
+  if (h.Lx != L->Lx || h.Ly != L->Ly || h.Lz != L->Lz || h.d != L->d || h.chi != L->chi ||
+      h.precision != L->precision || h.n_chains != L->n_chains || h.n_instances != L->n_instances ||
+      h.n_pairs != L->n_pairs || h.seed != L->seed || h.J_hash != L->J_hash)
+    return io_fail("checkpoint belongs to another lattice (shape, chi, precision, chains, seed or couplings differ)");
+  if (h.n_recorded < 0 || h.n_recorded > L->record_capacity)
+    return io_fail("checkpoint holds more recorded sweeps than this lattice's record capacity");
+  const size_t nc = L->n_chains, k = (size_t)h.n_recorded, np = L->n_pairs;
+  std::vector<uint64_t> keys(nc);
+  std::vector<double> beta(nc), E(k * nc), M(k * nc), q(k * np);
+  std::vector<int> inst(nc), pairs(2 * np);
+  std::vector<int8_t> spins(nc * L->sites());
+  bool ok = fread(keys.data(), sizeof(uint64_t), nc, f.f) == nc;
+  ok = ok && fread(beta.data(), sizeof(double), nc, f.f) == nc;
+  ok = ok && fread(inst.data(), sizeof(int), nc, f.f) == nc;
+  ok = ok && (np == 0 || fread(pairs.data(), sizeof(int), 2 * np, f.f) == 2 * np);
+  if (!ok || keys != L->chain_key || beta != L->beta || inst != L->chain_instance || pairs != L->pairs)
+    return io_fail("checkpoint belongs to another lattice (chain keys, betas, instances or pairs differ)");
+  ok = (k == 0 || fread(E.data(), sizeof(double), E.size(), f.f) == E.size());
+  ok = ok && (k == 0 || fread(M.data(), sizeof(double), M.size(), f.f) == M.size());
+  ok = ok && (k * np == 0 || fread(q.data(), sizeof(double), q.size(), f.f) == q.size());
+  ok = ok && fread(spins.data(), 1, spins.size(), f.f) == spins.size();
+  std::vector<int8_t> flags;
+  std::vector<long long> cnt;
+  if (ok && h.has_nn) {
+    flags.resize(nc * L->Lz);
+    cnt.resize(nc * L->Lz * tnmc::kCounterStride);
+    ok = fread(flags.data(), 1, flags.size(), f.f) == flags.size();
+    ok = ok && fread(cnt.data(), sizeof(long long), cnt.size(), f.f) == cnt.size();
+  }
+  if (!ok) return io_fail(std::string(path) + " is truncated");
+  for (int8_t v : spins)
+    if (L->d == 2 ? (v != 1 && v != -1) : (v < 0 || v >= L->d)) return io_fail("checkpoint holds invalid spins");
+  for (int8_t v : flags)
+    if (v != 0 && v != 1) return io_fail("checkpoint holds invalid fallback flags");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(L->dspins, spins.data(), spins.size(), hipMemcpyHostToDevice));
+  if (k) {
+    HIP_TRY(hipMemcpy(L->dErec, E.data(), E.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(L->dMrec, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (np) HIP_TRY(hipMemcpy(L->dqrec, q.data(), q.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  L->n_recorded = h.n_recorded;
+  if (h.has_nn) {
+    tnmc_status r = nn_counters(L);
+    if (r != TNMC_OK) return r;
+    L->nn_fallback = flags;
+    HIP_TRY(hipMemcpy(L->dnncnt, cnt.data(), cnt.size() * sizeof(long long), hipMemcpyHostToDevice));
+  }
+  if (next_sweep) *next_sweep = h.next_sweep;
   return TNMC_OK;
 }
 

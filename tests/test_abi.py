@@ -105,3 +105,10 @@ def test_learned_proposal_arguments_checked_on_host(lib):
     assert lib.tnmc_nn_set_fallback(None, None) == ARG
     assert lib.tnmc_nn_calibrate_fallback(None, 0.05, None) == ARG
     assert lib.tnmc_nn_slice_logq(None, None, 0, 0, None, None, None) == ARG
+
+
+def test_checkpoint_arguments_checked_on_host(lib):
+    assert tn.tnmc_status_string(-6) == "checkpoint file error"
+    assert lib.tnmc_checkpoint_save(None, 0, b"/tmp/x") == tn.api.TNMC_ERR_ARG
+    assert lib.tnmc_checkpoint_load(None, b"/tmp/x", None) == tn.api.TNMC_ERR_ARG
+    assert lib.tnmc_get_couplings(None, None) == tn.api.TNMC_ERR_ARG
