@@ -217,8 +217,16 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
   __syncthreads();
 
   const int co = lane >> 1, h = lane & 1;
+  // this lane's output channel: spin-tap weights and biases in registers
+  float w0s[4], bias[NHID];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w0s[k] = ws0[co * 4 + k];
+#pragma unroll
+  for (int l = 0; l < NHID; ++l) bias[l] = bh[l * C + co];
+  const float b_out = lds[L.b5];
   double logq = 0.0;
   int fault = 0;
+  int r = 0;   // ring slot of the current site, (y Lx + x) mod (Lx + 2)
   for (int y = 0; y < Ly; ++y) {
     // condition channels of rows y-1..y+1 and the row's uniforms
     for (int i = tid; i < 3 * NCOND * (Lx + 2); i += NTS) {
@@ -241,26 +249,27 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
     }
     __syncthreads();
     for (int x = 0; x < Lx; ++x) {
-      const int f = y * Lx + x;
-      const int r = f % RING;
       const bool up = y > 0, left = x > 0, right = x + 1 < Lx;
-      // ring slots of the taps 0..4: sites f - Lx - 1, f - Lx, f - Lx + 1, f - 1, f
-      const int rs0 = (r + RING - Lx - 1) % RING, rs1 = (r + RING - Lx) % RING, rs2 = (r + RING - Lx + 1) % RING;
-      const int rs3 = (r + RING - 1) % RING, rs4 = r;
+      // ring slots of the taps 0..4: sites f - Lx - 1, f - Lx, f - Lx + 1, f - 1, f of f = y Lx + x, i.e.
+      // f + 1, f + 2, f + 3, f - 1, f modulo Lx + 2 (the slot of the up-right tap is used only when Lx > 1)
+      const int rs0 = (r + 1 < RING) ? r + 1 : r + 1 - RING;
+      const int rs1 = (r + 2 < RING) ? r + 2 : r + 2 - RING;
+      const int rs2 = (r + 3 < RING) ? r + 3 : r + 3 - RING;
+      const int rs3 = (r > 0) ? r - 1 : RING - 1, rs4 = r;
       // layer 0: spin taps
       {
         float a = cp[x * C + co];
         if (up) {
-          if (left) a = fmaf(ws0[co * 4 + 0], 1.0f - 2.0f * CFG(path, y - 1, x - 1), a);
-          a = fmaf(ws0[co * 4 + 1], 1.0f - 2.0f * CFG(path, y - 1, x), a);
-          if (right) a = fmaf(ws0[co * 4 + 2], 1.0f - 2.0f * CFG(path, y - 1, x + 1), a);
+          if (left) a = fmaf(w0s[0], 1.0f - 2.0f * CFG(path, y - 1, x - 1), a);
+          a = fmaf(w0s[1], 1.0f - 2.0f * CFG(path, y - 1, x), a);
+          if (right) a = fmaf(w0s[2], 1.0f - 2.0f * CFG(path, y - 1, x + 1), a);
         }
-        if (left) a = fmaf(ws0[co * 4 + 3], 1.0f - 2.0f * CFG(path, y, x - 1), a);
+        if (left) a = fmaf(w0s[3], 1.0f - 2.0f * CFG(path, y, x - 1), a);
         if (h == 0) ring[(size_t)r * C + co] = fmaxf(a, 0.0f);
       }
       wave_sync();
       // hidden layers
-#pragma unroll 1
+#pragma unroll
       for (int l = 0; l < NHID; ++l) {
         const float* R = ring + (size_t)l * (lx_max + 2) * C + 16 * h;
         const float* W = wh + ((size_t)l * C + co) * WCO + 16 * h;
@@ -273,7 +282,7 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
         if (left) acc += dot16(W + 3 * C, R + rs3 * C);
         acc += dot16(W + 4 * C, R + rs4 * C);
         acc += dpp_f<0xB1>(acc);   // the other half of the input channels
-        const float a = fmaxf(acc + bh[l * C + co], 0.0f);
+        const float a = fmaxf(acc + bias[l], 0.0f);
         if (h == 0) ring[((size_t)(l + 1) * (lx_max + 2) + r) * C + co] = a;
         wave_sync();
       }
@@ -292,18 +301,24 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
           }
         }
       }
-      const float logit = wave_sum_f(part) + lds[L.b5];
+      const float logit = wave_sum_f(part) + b_out;
       if (!(fabsf(logit) <= 3.0e38f)) fault |= 1;   // NaN or infinite
       const float lc = fminf(fmaxf(logit, -CLIP), CLIP);
-      const double p_plus = 1.0 / (1.0 + exp(-(double)lc));
+      // one exponential: e = exp(-|l|), P(+1) = 1 / (1 + e) for l >= 0 and e / (1 + e) below,
+      // log P(s) = -(max(-s l, 0) + log1p(e))
+      const double dl = (double)lc;
+      const double e = exp(-fabs(dl));
+      const double inv = 1.0 / (1.0 + e);
+      const double p_plus = (dl >= 0.0) ? inv : e * inv;
       int st;
       if (have_forced) {
         st = CFG(path, y, x);
       } else {
         st = (uni[x] < p_plus) ? 0 : 1;
       }
-      logq += log_sigmoid(st == 0 ? (double)lc : -(double)lc);
+      logq -= fmax(st == 0 ? -dl : dl, 0.0) + log1p(e);
       if (!have_forced && lane == 0) CFG(path, y, x) = (int8_t)st;
+      r = (r + 1 < RING) ? r + 1 : 0;
       wave_sync();
     }
     __syncthreads();
