@@ -208,7 +208,7 @@ tnmc_status tnmc_debug_set(int32_t what, int32_t value);
  * Ising lattices (d = 2) only.  The batched calls take layers up to 64 sites
  * wide (TNMC_ERR_ARG beyond); the sampler behind propose / logq / sweeps keeps
  * the masked weights and per-layer activation rings in LDS, which limits rows
- * to about 48 sites (TNMC_ERR_UNSUPPORTED beyond).
+ * to 47 sites (TNMC_ERR_UNSUPPORTED beyond).
  * Batched entry points take DEVICE pointers: cond [n][4][Ly][Lx] float,
  * s [n][Ly][Lx] int8; they are stream-ordered on hip_stream. */
 enum { TNMC_NN_PARAMS = 38753 };

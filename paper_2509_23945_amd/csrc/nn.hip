@@ -121,9 +121,11 @@ __device__ __forceinline__ float cond_value(JP J, SP spins, int Lx, int Ly, int 
 //   cp  [lx_max][C]         layer-0 pre-activation of the current row without the spin taps
 //   crow[3][NCOND][lx_max + 2]  condition channels of rows y-1, y, y+1, zero padded
 //   ring[2][NHID + 1][lx_max + 2][C]  per path, per layer output: the last lx + 2 sites
-//   uni [lx_max] doubles, then cfg [2][ly_max][lx_max] bytes (states: 0 = +1, 1 = -1)
+//   lcr [2][lx_max]         per path, the clipped logits of the current row
+//   uni [lx_max] doubles: logit of the row's uniforms, log U - log(1 - U); then
+//   cfg [2][ly_max][lx_max] bytes (states: 0 = +1, 1 = -1)
 struct SampleLayout {
-  int wc0, ws0, b0, wh, bh, w5, b5, cp, crow, ring, uni_f, cfg_b, total_b;
+  int wc0, ws0, b0, wh, bh, w5, b5, cp, crow, ring, lcr, uni_f, cfg_b, total_b;
   __host__ __device__ SampleLayout(int lx_max, int ly_max) {
     int o = 0;
     wc0 = o; o += C * NCOND * 9;
@@ -137,6 +139,7 @@ struct SampleLayout {
     crow = o; o += 3 * NCOND * (lx_max + 2);
     o = (o + 3) & ~3;
     ring = o; o += 2 * (NHID + 1) * (lx_max + 2) * C;
+    lcr = o; o += 2 * lx_max;
     o = (o + 1) & ~1;
     uni_f = o; o += 2 * lx_max;
     cfg_b = o * 4;
@@ -191,6 +194,7 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
   const int RING = Lx + 2;
   float* ring = lds + L.ring + (size_t)path * (NHID + 1) * (lx_max + 2) * C;
   double* uni = reinterpret_cast<double*>(lds + L.uni_f);
+  float* lcr = lds + L.lcr + path * lx_max;
   int8_t* cfg = reinterpret_cast<int8_t*>(lds) + L.cfg_b;
 #define CFG(p, y, x) cfg[((size_t)(p) * ly_max + (y)) * lx_max + (x)]
 
@@ -233,7 +237,12 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
       const int rr = i / (NCOND * (Lx + 2)), c = (i / (Lx + 2)) % NCOND, xx = i % (Lx + 2);
       crow[(rr * NCOND + c) * (lx_max + 2) + xx] = cond_value(J, spins, Lx, Ly, Lz, z, c, y + rr - 1, xx - 1);
     }
-    for (int x = tid; x < Lx; x += NTS) uni[x] = philox_uniform((uint64_t)(y * Lx + x), (uint64_t)z, sweep, 0ull, t.key0, t.key1);
+    // U < P(+1) = 1 / (1 + exp(-l)) exactly when log U - log(1 - U) < l (0 < U < 1): the draw then
+    // needs no transcendental on the site-by-site chain
+    for (int x = tid; x < Lx; x += NTS) {
+      const double U = philox_uniform((uint64_t)(y * Lx + x), (uint64_t)z, sweep, 0ull, t.key0, t.key1);
+      uni[x] = log(U) - log1p(-U);
+    }
     __syncthreads();
     // layer-0 pre-activations of the row without the spin taps
     for (int i = tid; i < C * Lx; i += NTS) {
@@ -304,22 +313,22 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
       const float logit = wave_sum_f(part) + b_out;
       if (!(fabsf(logit) <= 3.0e38f)) fault |= 1;   // NaN or infinite
       const float lc = fminf(fmaxf(logit, -CLIP), CLIP);
-      // one exponential: e = exp(-|l|), P(+1) = 1 / (1 + e) for l >= 0 and e / (1 + e) below,
-      // log P(s) = -(max(-s l, 0) + log1p(e))
-      const double dl = (double)lc;
-      const double e = exp(-fabs(dl));
-      const double inv = 1.0 / (1.0 + e);
-      const double p_plus = (dl >= 0.0) ? inv : e * inv;
-      int st;
-      if (have_forced) {
-        st = CFG(path, y, x);
-      } else {
-        st = (uni[x] < p_plus) ? 0 : 1;
+      if (!have_forced) {
+        const int st = (uni[x] < (double)lc) ? 0 : 1;
+        if (lane == 0) CFG(path, y, x) = (int8_t)st;
       }
-      logq -= fmax(st == 0 ? -dl : dl, 0.0) + log1p(e);
-      if (!have_forced && lane == 0) CFG(path, y, x) = (int8_t)st;
+      if (lane == 0) lcr[x] = lc;
       r = (r + 1 < RING) ? r + 1 : 0;
       wave_sync();
+    }
+    // log q of the row: log P(s) = -(max(-s l, 0) + log1p(exp(-|l|))) per site, one site per lane
+    {
+      double term = 0.0;
+      for (int x = lane; x < Lx; x += 64) {
+        const double dl = (double)lcr[x];
+        term -= fmax(CFG(path, y, x) == 0 ? -dl : dl, 0.0) + log1p(exp(-fabs(dl)));
+      }
+      logq += wave_sum(term);
     }
     __syncthreads();
   }
