@@ -312,3 +312,23 @@ def test_training_gains_acceptance():
     a1 = st1["accepted"] / st1["proposed"]
     print(f"acceptance untrained {a0:.4f}, trained {a1:.4f}")
     assert a0 < 0.01 and a1 > 0.15 and st1["numeric_faults"] == 0
+
+
+def test_nn_sweep_over_lattices_of_different_shapes():
+    """One learned-proposal sweep over two lattices of different (Lx, Ly, Lz) in
+    one call (each parity is one launch sized for the widest and tallest
+    layer) equals the oracle's slice updates of each lattice."""
+    gh.announce("nn sweep two lattices")
+    th = params(9, 1.5)
+    th64 = th.astype(np.float64)
+    net = tn.tnmc_nn_create(th)
+    a, Ja, sa, _ = gh.make_lattice(6, 5, 4, 2, 4, kind="gauss", beta=0.7, seed=12, n_chains=2)
+    b, Jb, sb, _ = gh.make_lattice(3, 8, 3, 2, 4, kind="pmj", beta=1.2, seed=13, n_chains=1)
+    tn.tnmc_nn_sweep([a, b], net, 1, sweep_offset=2)
+    for lat, J, s0, beta, nch in ((a, Ja, sa, 0.7, 2), (b, Jb, sb, 1.2, 1)):
+        Lz = s0.shape[1]
+        for c in range(nch):
+            ref = s0[c].copy()
+            for z in list(range(0, Lz, 2)) + list(range(1, Lz, 2)):
+                onn.slice_update(th64, J[c], ref, z, beta, seed=12345, chain_key=c, sweep=2)
+            assert np.array_equal(tn.tnmc_get_spins(lat, c), ref)
