@@ -127,6 +127,20 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
                        uint64_t sweep_offset, int32_t record, int32_t time_kernels,
                        tnmc_stats* stats, void* hip_stream);
 
+/* As tnmc_sweep, with the slices taken perpendicular to axis `direction`
+ * (0: z, identical to tnmc_sweep; 1: y; 2: x), so that chains can cycle the
+ * slice direction between sweeps.  A y-slice is the layer of sites with one
+ * y, its held neighbours the y-1 and y+1 layers; the sites of a slice are
+ * drawn in the order (z, x) for y-slices and (z, y) for x-slices (row index
+ * first); the Philox sweep counter of sweep t is sweep_offset + t +
+ * direction * 2^56, and the layer counter is the slice index.  The slice's
+ * shape must be supported as a layer (TNMC_ERR_UNSUPPORTED otherwise).  Each
+ * sweep reorders the spins into the direction's layout and back (two L^3
+ * byte copies), and builds its task list on the host. */
+tnmc_status tnmc_sweep_direction(tnmc_lattice* const* lats, int32_t n_lats, int32_t direction, int32_t n_sweeps,
+                                 uint64_t sweep_offset, int32_t record, int32_t time_kernels, tnmc_stats* stats,
+                                 void* hip_stream);
+
 /* One half-sweep (parity 0: even layers, 1: odd layers) of every chain in
  * lats, as inside tnmc_sweep.  trace (DEVICE pointer or NULL) receives, for
  * task t in the order lattice-major, chain, layer z = parity, parity+2, ...:

@@ -104,3 +104,51 @@ def run_chain(J, spins, beta: float, chi: int, d: int, n_sweeps: int, *, seed: i
         E[t] = model.energy(J, spins, d)
         M[t] = model.magnetisation(spins, d)
     return E, M, acc
+
+
+# Direction cycling: slices perpendicular to y or x are z-slices of the lattice
+# with its axes permuted.  Direction 0 is z (no change), 1 is y, 2 is x.  Each
+# direction draws from its own range of Philox sweep counters.
+DIRECTION_STRIDE = 2 ** 56
+
+
+def to_direction(J, spins, direction: int):
+    """(J', spins') of the lattice seen as z-slices perpendicular to axis
+    `direction`: direction 1 maps site (z, y, x) to (y, z, x), direction 2 to
+    (x, z, y); the coupling components follow their bonds (x-, y-, z-bond of
+    the permuted lattice)."""
+    J = np.asarray(J)
+    s = np.asarray(spins)
+    if direction == 0:
+        return J.copy(), s.copy()
+    if direction == 1:
+        perm = (1, 0, 2)
+        comps = (0, 2, 1)     # x' = x, y' = z, z' = y
+    elif direction == 2:
+        perm = (2, 0, 1)
+        comps = (1, 2, 0)     # x' = y, y' = z, z' = x
+    else:
+        raise ValueError("direction is 0, 1 or 2")
+    Jp = np.stack([J[c].transpose(perm) for c in comps])
+    return np.ascontiguousarray(Jp), np.ascontiguousarray(s.transpose(perm))
+
+
+def from_direction(spins_p, direction: int):
+    """Inverse of the spin permutation of to_direction."""
+    s = np.asarray(spins_p)
+    if direction == 0:
+        return s.copy()
+    if direction == 1:
+        return np.ascontiguousarray(s.transpose(1, 0, 2))
+    return np.ascontiguousarray(s.transpose(1, 2, 0))
+
+
+def sweep_direction(J, spins, beta: float, chi: int, d: int, direction: int, *, seed: int, chain: int,
+                    sweep_index: int):
+    """One sweep with slices perpendicular to axis `direction` (in place),
+    using sweep counter sweep_index + direction * DIRECTION_STRIDE.  Returns the
+    number of accepted updates."""
+    Jp, sp = to_direction(J, spins, direction)
+    n = sweep(Jp, sp, beta, chi, d, seed=seed, chain=chain, sweep_index=sweep_index + direction * DIRECTION_STRIDE)
+    spins[...] = from_direction(sp, direction)
+    return n

@@ -37,6 +37,7 @@ __all__ = [
     "tnmc_nn_train", "tnmc_nn_dataset", "tnmc_nn_slice_propose", "tnmc_nn_slice_logq", "tnmc_nn_sweep",
     "tnmc_nn_counts", "tnmc_nn_counts_reset", "tnmc_nn_set_fallback", "tnmc_nn_get_fallback",
     "tnmc_nn_calibrate_fallback", "tnmc_get_couplings", "tnmc_checkpoint_save", "tnmc_checkpoint_load",
+    "tnmc_sweep_direction",
 ]
 TNMC_NN_PARAMS = 38753
 
@@ -144,6 +145,7 @@ def load():
         "tnmc_get_couplings": [vp, P(ctypes.c_float)],
         "tnmc_checkpoint_save": [vp, u64, ctypes.c_char_p],
         "tnmc_checkpoint_load": [vp, ctypes.c_char_p, P(u64)],
+        "tnmc_sweep_direction": [P(vp), i32, i32, i32, u64, i32, i32, P(_Stats), vp],
     }
     for name, sig in nn_sigs.items():
         getattr(lib, name).argtypes = sig
@@ -266,6 +268,15 @@ def tnmc_sweep(lats, n_sweeps: int, sweep_offset: int = 0, record: bool = False,
     st = _Stats()
     _check(load().tnmc_sweep(arr, n, n_sweeps, ctypes.c_uint64(sweep_offset), int(record), int(time_kernels),
                              ctypes.byref(st), stream), "tnmc_sweep")
+    return st.as_dict()
+
+
+def tnmc_sweep_direction(lats, direction: int, n_sweeps: int, sweep_offset: int = 0, record: bool = False,
+                         time_kernels: bool = False, stream=None) -> dict:
+    arr, n = _handles(lats)
+    st = _Stats()
+    _check(load().tnmc_sweep_direction(arr, n, direction, n_sweeps, ctypes.c_uint64(sweep_offset), int(record),
+                                       int(time_kernels), ctypes.byref(st), stream), "tnmc_sweep_direction")
     return st.as_dict()
 
 

@@ -64,6 +64,9 @@ struct tnmc_lattice {
   // tensor-network fallback flags (1 = that layer uses the TN proposal)
   long long* dnncnt = nullptr;
   std::vector<int8_t> nn_fallback;
+  // slice-direction views (index 1: y-slices, 2: x-slices): the lattice with
+  // permuted axes and coupling components, built on first use
+  tnmc_lattice* view[3] = {nullptr, nullptr, nullptr};
   size_t sites() const { return (size_t)Lx * Ly * Lz; }
   const float* J_of(int c) const { return dJ + (size_t)chain_instance[c] * 3 * sites(); }
   int8_t* spins_of(int c) const { return dspins + (size_t)c * sites(); }
@@ -469,6 +472,8 @@ tnmc_status tnmc_lattice_init(const tnmc_lattice_desc* ds, tnmc_lattice** out) {
 tnmc_status tnmc_lattice_free(tnmc_lattice* L) {
   if (!L) return TNMC_ERR_ARG;
   (void)hipDeviceSynchronize();
+  for (tnmc_lattice* v : L->view)
+    if (v) tnmc_lattice_free(v);
   void* ptrs[] = {L->dJ, L->dspins, L->dpa, L->dpb, (void*)L->dJc, (void*)L->dSc,
                   L->dErec, L->dMrec, L->dqrec, L->dscal, (void*)L->dnncnt};
   for (void* p : ptrs)
@@ -1402,6 +1407,120 @@ tnmc_status tnmc_checkpoint_load(tnmc_lattice* L, const char* path, uint64_t* ne
     HIP_TRY(hipMemcpy(L->dnncnt, cnt.data(), cnt.size() * sizeof(long long), hipMemcpyHostToDevice));
   }
   if (next_sweep) *next_sweep = h.next_sweep;
+  return TNMC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ slice directions
+
+namespace tnmc {
+hipError_t launch_permute_spins(int8_t* const* lat_spins, int8_t* const* view_spins, int n_chains, int Lx, int Ly,
+                                int Lz, int dir, int to_view, hipStream_t s);
+}
+
+namespace {
+
+constexpr uint64_t kDirectionStride = 1ull << 56;
+
+// The lattice seen with slices perpendicular to axis dir (1: y, 2: x) as
+// z-slices: dir 1 maps site (z, y, x) to (y, z, x) with bond components
+// (x, z, y), dir 2 maps it to (x, z, y) with components (y, z, x).
+tnmc_status make_view(tnmc_lattice* L, int dir, tnmc_lattice** out) {
+  const int Lx = L->Lx, Ly = L->Ly, Lz = L->Lz;
+  const int nx = (dir == 1) ? Lx : Ly, ny = Lz, nz = (dir == 1) ? Ly : Lx;
+  if (nx > kLxMax || ny > kLyMax) return TNMC_ERR_UNSUPPORTED;
+  if (tnmc::sample_lds_bytes(L->d, L->chi_max, nx, ny) > 160 * 1024) return TNMC_ERR_UNSUPPORTED;
+  const size_t n = L->sites();
+  std::vector<float> J((size_t)L->n_instances * 3 * n), Jp(J.size());
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(J.data(), L->dJ, J.size() * sizeof(float), hipMemcpyDeviceToHost));
+  const int comp[2][3] = {{0, 2, 1}, {1, 2, 0}};   // source component of the view's x-, y- and z-bonds
+  for (int i = 0; i < L->n_instances; ++i)
+    for (int c = 0; c < 3; ++c) {
+      const float* src = J.data() + ((size_t)i * 3 + comp[dir - 1][c]) * n;
+      float* dst = Jp.data() + ((size_t)i * 3 + c) * n;
+      for (int z = 0; z < Lz; ++z)
+        for (int y = 0; y < Ly; ++y)
+          for (int x = 0; x < Lx; ++x) {
+            const size_t j = (dir == 1) ? ((size_t)y * Lz + z) * Lx + x : ((size_t)x * Lz + z) * Ly + y;
+            dst[j] = src[((size_t)z * Ly + y) * Lx + x];
+          }
+    }
+  auto* V = new tnmc_lattice();
+  V->Lx = nx;
+  V->Ly = ny;
+  V->Lz = nz;
+  V->d = L->d;
+  V->chi = L->chi;
+  V->chi_max = L->chi_max;
+  V->precision = L->precision;
+  V->n_chains = L->n_chains;
+  V->n_instances = L->n_instances;
+  V->seed = L->seed;
+  V->chain_instance = L->chain_instance;
+  V->beta = L->beta;
+  V->chain_key = L->chain_key;
+  auto fail = [&](hipError_t e) {
+    g_last_error = std::string("slice-direction view: ") + hipGetErrorString(e);
+    tnmc_lattice_free(V);
+    return e == hipErrorOutOfMemory ? TNMC_ERR_OOM : TNMC_ERR_DEVICE;
+  };
+  hipError_t e;
+  if ((e = hipMalloc((void**)&V->dJ, Jp.size() * sizeof(float))) != hipSuccess) return fail(e);
+  if ((e = hipMemcpy(V->dJ, Jp.data(), Jp.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc((void**)&V->dspins, (size_t)L->n_chains * n)) != hipSuccess) return fail(e);
+  std::vector<const float*> jc(L->n_chains);
+  std::vector<int8_t*> sc(L->n_chains);
+  for (int c = 0; c < L->n_chains; ++c) {
+    jc[c] = V->J_of(c);
+    sc[c] = V->spins_of(c);
+  }
+  if ((e = hipMalloc((void**)&V->dJc, L->n_chains * sizeof(float*))) != hipSuccess) return fail(e);
+  if ((e = hipMemcpy(V->dJc, jc.data(), L->n_chains * sizeof(float*), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  if ((e = hipMalloc((void**)&V->dSc, L->n_chains * sizeof(int8_t*))) != hipSuccess) return fail(e);
+  if ((e = hipMemcpy(V->dSc, sc.data(), L->n_chains * sizeof(int8_t*), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  *out = V;
+  return TNMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tnmc_status tnmc_sweep_direction(tnmc_lattice* const* lats, int32_t n_lats, int32_t direction, int32_t n_sweeps,
+                                 uint64_t sweep_offset, int32_t record, int32_t time_kernels, tnmc_stats* stats,
+                                 void* stream) {
+  if (direction == 0) return tnmc_sweep(lats, n_lats, n_sweeps, sweep_offset, record, time_kernels, stats, stream);
+  if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0 || direction < 0 || direction > 2) return TNMC_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<tnmc_lattice*> views(n_lats);
+  for (int l = 0; l < n_lats; ++l) {
+    tnmc_lattice* L = lats[l];
+    if (!L->view[direction]) {
+      tnmc_status r = make_view(L, direction, &L->view[direction]);
+      if (r != TNMC_OK) return r;
+    }
+    views[l] = L->view[direction];
+  }
+  for (int t = 0; t < n_sweeps; ++t) {
+    for (int l = 0; l < n_lats; ++l)
+      HIP_TRY(tnmc::launch_permute_spins(lats[l]->dSc, views[l]->dSc, lats[l]->n_chains, lats[l]->Lx, lats[l]->Ly,
+                                         lats[l]->Lz, direction, 1, s));
+    tnmc_status r = tnmc_sweep(views.data(), n_lats, 1, sweep_offset + (uint64_t)t + direction * kDirectionStride, 0,
+                               time_kernels, stats, stream);
+    if (r != TNMC_OK) return r;
+    for (int l = 0; l < n_lats; ++l) {
+      tnmc_lattice* L = lats[l];
+      HIP_TRY(tnmc::launch_permute_spins(L->dSc, views[l]->dSc, L->n_chains, L->Lx, L->Ly, L->Lz, direction, 0, s));
+      if (record && L->n_recorded < L->record_capacity) {
+        const int64_t i = L->n_recorded++;
+        HIP_TRY(tnmc::launch_observables(L->dJc, L->dSc, L->n_chains, L->dpa, L->dpb, L->n_pairs, L->Lx, L->Ly,
+                                         L->Lz, L->d, L->dErec + i * L->n_chains, L->dMrec + i * L->n_chains,
+                                         L->dqrec + i * std::max(1, L->n_pairs), s));
+      }
+    }
+  }
   return TNMC_OK;
 }
 

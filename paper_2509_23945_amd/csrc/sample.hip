@@ -15,6 +15,8 @@
 // Weights are clamped at 0, normalised, floored at 1e-12 and normalised again;
 // the state is the first u with U < p(0)+...+p(u).
 
+#include <algorithm>
+
 #include "device_common.h"
 #include "tnmc_internal.h"
 
@@ -608,6 +610,38 @@ hipError_t launch_energy(const float* J, const int8_t* spins, int Lx, int Ly, in
                          hipStream_t s) {
   if (d == 2) hipLaunchKernelGGL(energy_kernel<2>, dim3(1), dim3(256), 0, s, J, spins, Lx, Ly, Lz, out);
   else hipLaunchKernelGGL(energy_kernel<3>, dim3(1), dim3(256), 0, s, J, spins, Lx, Ly, Lz, out);
+  return hipGetLastError();
+}
+
+namespace {
+// Spins of every chain between the lattice's layout [z][y][x] and the layout
+// whose z-slices are the slices perpendicular to axis dir: dir 1 maps site
+// (z, y, x) to (y, z, x), dir 2 to (x, z, y).  to_view: lattice -> view, else back.
+__global__ __launch_bounds__(256) void permute_spins_kernel(int8_t* const* __restrict__ lat_spins,
+                                                            int8_t* const* __restrict__ view_spins, int Lx, int Ly,
+                                                            int Lz, int dir, int to_view) {
+  acquire_device();
+  const int c = blockIdx.y;
+  const size_t n = (size_t)Lx * Ly * Lz;
+  const gptr<int8_t> a = gmem(lat_spins[c]);
+  const gptr<int8_t> v = gmem(view_spins[c]);
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const int x = (int)(i % Lx), y = (int)((i / Lx) % Ly), z = (int)(i / ((size_t)Lx * Ly));
+    const size_t j = (dir == 1) ? ((size_t)y * Lz + z) * Lx + x : ((size_t)x * Lz + z) * Ly + y;
+    if (to_view) v[j] = a[i];
+    else a[i] = v[j];
+  }
+  release_device();
+}
+}  // namespace
+
+hipError_t launch_permute_spins(int8_t* const* lat_spins, int8_t* const* view_spins, int n_chains, int Lx, int Ly,
+                                int Lz, int dir, int to_view, hipStream_t s) {
+  if (n_chains <= 0) return hipSuccess;
+  const size_t n = (size_t)Lx * Ly * Lz;
+  const int bx = (int)std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(permute_spins_kernel, dim3(bx, n_chains), dim3(256), 0, s, lat_spins, view_spins, Lx, Ly, Lz, dir,
+                     to_view);
   return hipGetLastError();
 }
 

@@ -118,3 +118,41 @@ def test_chain_averages_match_enumeration(chi, seed):
         err = math.sqrt(2 * max(tau, 0.5) * np.var(series) / len(series))
         assert abs(series.mean() - exact) < 4 * err + 1e-12
     assert acc <= 4 * n
+
+
+@pytest.mark.parametrize("direction", [1, 2])
+def test_direction_views_keep_the_hamiltonian(direction):
+    """The permuted lattice of a slice direction has the same energy as the
+    original for every configuration (a wrong coupling component or axis fails),
+    its open boundaries stay open, and the spin permutation round-trips."""
+    rng = np.random.default_rng(direction)
+    J = synth.couplings_gauss(5, 4, 3, 7)
+    for d in (2, 3):
+        for _ in range(5):
+            s = synth.spins_random(5, 4, 3, int(rng.integers(1 << 30)), d)
+            Jp, sp = chain.to_direction(J, s, direction)
+            assert model.energy(Jp, sp, d) == model.energy(J, s, d)
+            assert np.array_equal(chain.from_direction(sp, direction), s)
+    Jp, _ = chain.to_direction(J, s, direction)
+    assert np.all(Jp[0, :, :, -1] == 0) and np.all(Jp[1, :, -1, :] == 0) and np.all(Jp[2, -1, :, :] == 0)
+
+
+def test_direction_cycled_chain_matches_enumeration():
+    """Sweeps cycling z, y, x slices on 2x2x3 +-J lattices at chi = 1 (truncated):
+    averages of E over many chains agree with exact enumeration."""
+    Lx, Ly, Lz, beta = 2, 2, 3, 1.0
+    devs = []
+    for inst in range(24):
+        J = synth.couplings_pm_j(Lx, Ly, Lz, 100 + inst)
+        s = synth.spins_random(Lx, Ly, Lz, 200 + inst)
+        states, En = bf.lattice_states(J, Lx, Ly, Lz, 2)
+        w = np.exp(-beta * (En - En.min()))
+        w /= w.sum()
+        Es = []
+        for t in range(90):
+            chain.sweep_direction(J, s, beta, 1, 2, t % 3, seed=9, chain=inst, sweep_index=t)
+            if t >= 15:
+                Es.append(model.energy(J, s, 2))
+        devs.append(np.mean(Es) - float(np.sum(w * En)))
+    devs = np.array(devs)
+    assert abs(devs.mean()) < 4 * devs.std(ddof=1) / math.sqrt(len(devs)) + 1e-12
