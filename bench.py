@@ -155,7 +155,16 @@ def time_form(tn, lats, warmup: int, steps: int, stream):
         tn.tnmc_timeseries_reset(lat)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = tn.tnmc_sweep(lats, steps, sweep_offset=warmup, record=True, time_kernels=True, stream=stream)
+    # long runs go in chunks of 500 sweeps with a progress line after each
+    st = None
+    done = 0
+    while done < steps:
+        k = min(500, steps - done)
+        part = tn.tnmc_sweep(lats, k, sweep_offset=warmup + done, record=True, time_kernels=True, stream=stream)
+        st = part if st is None else {key: st[key] + part[key] for key in st}
+        done += k
+        if steps > 500:
+            print(f"[bench] {done}/{steps} sweeps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     return time.perf_counter() - t0, st
 
