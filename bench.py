@@ -451,9 +451,14 @@ def main():
             "form": "environments stored in FP32, rank cut-off 1e-6; factorisations, log q, dE, MH in FP64",
             "value": v32, "unit": "slice updates/s", "ms_per_step": secs32 / args.steps * 1e3,
             "vs_fp64": v32 / value, "acceptance": st32["accepted"] / max(1, st32["proposed"]),
+            "tau_int_q": None, "indep_samples_per_s": None,
             "numeric_faults": st32["numeric_faults"],
             "contract_ms_per_step": st32["contract_ms"] / args.steps,
             "sample_ms_per_step": st32["sample_ms"] / args.steps}
+        if len(lats32) == 1:
+            i32, t32 = indep_of(lats32[0], secs32 / args.steps)
+            out["reduced_precision"]["tau_int_q"] = t32
+            out["reduced_precision"]["indep_samples_per_s"] = i32
         for lat in lats32:
             tn.tnmc_lattice_free(lat)
     if not args.no_learned and len(lats) == 1 and groups[0].get("d", 2) == 2:
