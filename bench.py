@@ -440,6 +440,12 @@ def main():
         "indep_samples_per_s": indep,
         "roofline": roofline,
     }
+    # the layout autotuner's choice for the headline class (timed on the first sweep)
+    for d_, c_ in sorted({(g.get("d", 2), g["chi"]) for g in groups}):
+        lay, ms_c, ms_f = tn.tnmc_layout_choice(d_, c_)
+        if lay >= 0:
+            out.setdefault("autotune", []).append({"d": d_, "chi": c_, "layout": "full" if lay else "compact",
+                                                   "trial_ms_compact": ms_c, "trial_ms_full": ms_f})
     if not args.no_reduced:
         # the reduced-precision form on the same inputs: FP32 environments, rank
         # cut-off at FP32 resolution, FP64 factorisations, log q and MH

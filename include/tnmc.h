@@ -190,12 +190,13 @@ tnmc_status tnmc_flop_model(int32_t Lx, int32_t Ly, int32_t d, int32_t chi, doub
  * ints, 3 R factors [Lx][(d chi_max)^2] doubles, 4 log scales [Ly] doubles. */
 tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes);
 
-/* Test hook: what = 0 sends every slice task of the configurations that use
- * the compact two-per-CU contraction layout through its overflow path (a
- * second launch with the full tile layout in LDS, one task per CU), so that
- * path can be checked against the oracle; value 1 = on, 0 = off (default).
- * Results are the same either way.  Process-wide, not per handle.  Returns
- * TNMC_ERR_ARG for an unknown what. */
+/* Test hooks, process-wide.  what = 0: send every slice task of the
+ * configurations that use the compact two-per-CU contraction layout through
+ * its overflow path (a second launch with the full tile layout in LDS, one
+ * task per CU), so that path can be checked against the oracle; value 1 = on,
+ * 0 = off (default).  what = 1: the layout autotuner (value 1 = on, the
+ * default; 0 = off, which also drops its choices).  Results are the same
+ * either way.  Returns TNMC_ERR_ARG for an unknown what. */
 tnmc_status tnmc_debug_set(int32_t what, int32_t value);
 
 /* ------------------------------------------------------------------------
@@ -284,6 +285,17 @@ tnmc_status tnmc_nn_get_fallback(tnmc_lattice* lat, int8_t* flags);
  * once and then keeping each layer's kernel fixed keeps every later step an
  * exact MH kernel. */
 tnmc_status tnmc_nn_calibrate_fallback(tnmc_lattice* lat, double threshold, int32_t* n_fallback);
+
+/* Layout autotuner (batching): the (d, chi) classes that can run either the
+ * compact contraction layout (two tasks per CU, with a full-layout redo of the
+ * tasks whose rank outgrows it) or the full layout (one task per CU) are timed
+ * once with each, on the tasks of the first tnmc_sweep that contains them,
+ * and the faster is kept for the process (both give the same results).
+ * *layout receives -1 (not tuned yet, or no choice), 0 (compact) or 1 (full);
+ * ms_compact / ms_full (may be NULL) the trial durations of the contraction
+ * launch. */
+tnmc_status tnmc_layout_choice(int32_t d, int32_t chi, int32_t precision, int32_t* layout, double* ms_compact,
+                               double* ms_full);
 
 const char* tnmc_status_string(tnmc_status s);
 /* Text of the last failed HIP call (thread-local). */

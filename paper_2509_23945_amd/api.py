@@ -37,7 +37,7 @@ __all__ = [
     "tnmc_nn_train", "tnmc_nn_dataset", "tnmc_nn_slice_propose", "tnmc_nn_slice_logq", "tnmc_nn_sweep",
     "tnmc_nn_counts", "tnmc_nn_counts_reset", "tnmc_nn_set_fallback", "tnmc_nn_get_fallback",
     "tnmc_nn_calibrate_fallback", "tnmc_get_couplings", "tnmc_checkpoint_save", "tnmc_checkpoint_load",
-    "tnmc_sweep_direction",
+    "tnmc_sweep_direction", "tnmc_layout_choice",
 ]
 TNMC_NN_PARAMS = 38753
 
@@ -146,6 +146,7 @@ def load():
         "tnmc_checkpoint_save": [vp, u64, ctypes.c_char_p],
         "tnmc_checkpoint_load": [vp, ctypes.c_char_p, P(u64)],
         "tnmc_sweep_direction": [P(vp), i32, i32, i32, u64, i32, i32, P(_Stats), vp],
+        "tnmc_layout_choice": [i32, i32, i32, P(i32), P(dbl), P(dbl)],
     }
     for name, sig in nn_sigs.items():
         getattr(lib, name).argtypes = sig
@@ -488,3 +489,12 @@ def tnmc_checkpoint_load(lat: Lattice, path: str) -> int:
     nxt = ctypes.c_uint64()
     _check(load().tnmc_checkpoint_load(lat.handle, os.fsencode(path), ctypes.byref(nxt)), "tnmc_checkpoint_load")
     return nxt.value
+
+
+def tnmc_layout_choice(d: int, chi: int, precision: int = TNMC_FP64):
+    """Returns (layout, ms_compact, ms_full): layout -1 (not tuned / no choice), 0 compact, 1 full."""
+    lay = ctypes.c_int32()
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(load().tnmc_layout_choice(d, chi, precision, ctypes.byref(lay), ctypes.byref(a), ctypes.byref(b)),
+           "tnmc_layout_choice")
+    return lay.value, a.value, b.value

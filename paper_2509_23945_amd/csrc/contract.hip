@@ -6,8 +6,36 @@
 namespace tnmc {
 
 int g_force_retry = 0;
+int g_layout_full[2][2] = {{0, 0}, {0, 0}};
 
 void set_force_retry(int on) { g_force_retry = on; }
+
+// Whether a (d, chi_max) class runs the compact layout (two tasks per CU)
+// by default: the same test as launch_contract_t's.
+template <int DP, int CHIM>
+constexpr bool has_compact() {
+  return sizeof(double) * Layout<DP, CHIM, false>::total > kHalfLds &&
+         sizeof(double) * Layout<DP, CHIM, true>::total <= kHalfLds;
+}
+bool contract_has_compact(int d, int chi_max) {
+  if (d == 2) {
+    switch (chi_max) {
+      case 4: return has_compact<2, 4>();
+      case 8: return has_compact<2, 8>();
+      case 16: return has_compact<2, 16>();
+      case 32: return has_compact<2, 32>();
+    }
+  } else if (d == 3) {
+    switch (chi_max) {
+      case 4: return has_compact<3, 4>();
+      case 8: return has_compact<3, 8>();
+      case 16: return has_compact<3, 16>();
+      case 32: return has_compact<3, 32>();
+    }
+  }
+  return false;
+}
+void set_layout_full(int d, int precision, int full) { g_layout_full[d == 3][precision == kPrecF32] = full ? 1 : 0; }
 
 // Bytes of the full tile layout: the LDS of a full-layout workgroup, and the
 // per-task global scratch of the retry path (and of d = 3, chi = 32, whose

@@ -29,6 +29,10 @@
 namespace tnmc {
 
 extern int g_force_retry;   // test hook: every compact-layout task takes the retry path
+// Layout chosen by the host's autotuner for the (d, chi_max) classes that
+// have a compact layout: g_layout_full[d == 3][FP32 storage] = 1 runs them
+// with the full layout instead (same results).
+extern int g_layout_full[2][2];
 
 namespace {
 
@@ -1396,6 +1400,8 @@ hipError_t launch_contract_t(const TaskDesc* tasks, int n, hipStream_t s) {
     // in the task's global scratch
     return launch_contract_k<ET, DP, CHIM, false, true>(tasks, n, 0, s);
   } else if constexpr (use_compact) {
+    if (!g_force_retry && g_layout_full[DP == 3][sizeof(ET) == sizeof(float)])
+      return launch_contract_k<ET, DP, CHIM, false>(tasks, n, 0, s);
     // every task in the compact layout (two per CU), then the few whose left
     // rank outgrew it, from the row where they stopped, with the full layout
     // in LDS (one per CU; the launch starts once the compact one has ended, so

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -20,6 +21,11 @@
 #include "tnmc_internal.h"
 
 using tnmc::TaskDesc;
+
+namespace tnmc {
+bool contract_has_compact(int d, int chi_max);
+void set_layout_full(int d, int precision, int full);
+}
 
 namespace {
 
@@ -95,6 +101,8 @@ struct Workspace {
   size_t gscr_cap = 0;
   TaskDesc* nn_tasks = nullptr;   // descriptors of the learned-proposal tasks of a sweep
   size_t nn_tasks_cap = 0;
+  TaskDesc* tune_tasks = nullptr;   // descriptors of the layout trials
+  size_t tune_tasks_cap = 0;
 };
 Workspace g_ws;
 
@@ -299,6 +307,73 @@ tnmc_status finish_timer(Timer& tm, tnmc_stats* st) {
   tnmc_status r = sum(tm.c_ev, st->contract_ms);
   if (r != TNMC_OK) return r;
   return sum(tm.s_ev, st->sample_ms);
+}
+
+// Layout autotuner.  The (d, chi_max) classes with a compact layout (two
+// tasks per CU, with a full-layout redo of the tasks that outgrow it) can also
+// run every task in the full layout (one per CU); both give the same results.
+// Before the second sweep of such a class and storage precision, the
+// contraction of that sweep's tasks runs once with each layout untimed, then
+// once more timed (descriptors without counters, so the statistics see only
+// the real launch, which follows and rewrites the same workspace), and the
+// faster layout is kept for the process.
+struct TuneResult {
+  int full = -1;
+  double ms_compact = 0.0, ms_full = 0.0;
+};
+std::map<std::tuple<int, int, int>, TuneResult> g_tune;
+std::map<std::tuple<int, int, int>, int> g_tune_seen;   // sweeps run per class before its trial
+bool g_autotune = true;
+
+// Trials for the classes of the plan that have run one sweep already: the
+// first sweep from a prepared (often random) configuration meets larger ranks
+// than the chain sees afterwards and would favour the full layout.
+tnmc_status autotune_groups(const Plan& plan, hipStream_t s) {
+  if (!g_autotune) return TNMC_OK;
+  for (const auto& g : plan.groups) {
+    const auto key = std::make_tuple(g.d, g.chi_max, g.precision);
+    if (!tnmc::contract_has_compact(g.d, g.chi_max) || g_tune.count(key)) continue;
+    if (g_tune_seen[key] < 1) continue;
+    std::vector<TaskDesc> trial(plan.desc.begin() + g.first, plan.desc.begin() + g.first + g.count);
+    for (auto& t : trial) {
+      t.counters = nullptr;
+      t.record = nullptr;
+    }
+    if (grow(g_ws.tune_tasks, g_ws.tune_tasks_cap, trial.size()) != TNMC_OK) return TNMC_ERR_OOM;
+    HIP_TRY(hipMemcpyAsync(g_ws.tune_tasks, trial.data(), trial.size() * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // one untimed pass of each layout first: a kernel's first launch in a
+    // process also pays for loading its code, which would decide the trial
+    for (int full : {0, 1}) {
+      tnmc::set_layout_full(g.d, g.precision, full);
+      HIP_TRY(tnmc::launch_contract(g_ws.tune_tasks, g.count, g.d, g.chi_max, g.precision, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    double ms[2] = {0.0, 0.0};
+    for (int full : {0, 1}) {
+      hipEvent_t e0, e1;
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      tnmc::set_layout_full(g.d, g.precision, full);
+      hipError_t e = hipEventRecord(e0, s);
+      if (e == hipSuccess) e = tnmc::launch_contract(g_ws.tune_tasks, g.count, g.d, g.chi_max, g.precision, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float t = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      HIP_TRY(e);
+      ms[full] = t;
+    }
+    TuneResult r;
+    r.full = (ms[1] < ms[0]) ? 1 : 0;
+    r.ms_compact = ms[0];
+    r.ms_full = ms[1];
+    tnmc::set_layout_full(g.d, g.precision, r.full);
+    g_tune[key] = r;
+  }
+  return TNMC_OK;
 }
 
 // One task run with optional forced layer; used by propose / logq.
@@ -582,6 +657,8 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
   tm.on = (time_kernels != 0 && stats != nullptr);
   for (int t = 0; t < n_sweeps; ++t) {
     const uint64_t sw = sweep_offset + (uint64_t)t;
+    r = autotune_groups(plan, s);
+    if (r != TNMC_OK) return r;
     for (const auto& g : plan.groups) {
       const TaskDesc* dt = g_ws.tasks + g.first;
       if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
@@ -594,6 +671,11 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
         stats->contract_launches += 1;
         stats->sample_launches += 1;
       }
+    }
+    {
+      std::set<std::tuple<int, int, int>> swept;
+      for (const auto& g : plan.groups) swept.insert(std::make_tuple(g.d, g.chi_max, g.precision));
+      for (const auto& k : swept) g_tune_seen[k] += 1;
     }
     if (record) {
       for (int l = 0; l < n_lats; ++l) {
@@ -617,9 +699,35 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
 }
 
 tnmc_status tnmc_debug_set(int32_t what, int32_t value) {
-  if (what != 0 || (value != 0 && value != 1)) return TNMC_ERR_ARG;
+  if ((what != 0 && what != 1) || (value != 0 && value != 1)) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
-  tnmc::set_force_retry(value);
+  if (what == 0) {
+    tnmc::set_force_retry(value);
+  } else {
+    // autotuner off: forget its choices and run the default (compact) layouts
+    g_autotune = value != 0;
+    if (!g_autotune) {
+      for (const auto& kv : g_tune) tnmc::set_layout_full(std::get<0>(kv.first), std::get<2>(kv.first), 0);
+      g_tune.clear();
+      g_tune_seen.clear();
+    }
+  }
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_layout_choice(int32_t d, int32_t chi, int32_t precision, int32_t* layout, double* ms_compact,
+                               double* ms_full) {
+  if (!layout || (d != 2 && d != 3) || chi < 1) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  const int cm = tnmc::chi_bucket(chi);
+  *layout = -1;
+  if (ms_compact) *ms_compact = 0.0;
+  if (ms_full) *ms_full = 0.0;
+  auto it = g_tune.find(std::make_tuple((int)d, cm, (int)precision));
+  if (it == g_tune.end()) return TNMC_OK;
+  *layout = it->second.full;
+  if (ms_compact) *ms_compact = it->second.ms_compact;
+  if (ms_full) *ms_full = it->second.ms_full;
   return TNMC_OK;
 }
 
