@@ -112,3 +112,16 @@ def test_checkpoint_arguments_checked_on_host(lib):
     assert lib.tnmc_checkpoint_save(None, 0, b"/tmp/x") == tn.api.TNMC_ERR_ARG
     assert lib.tnmc_checkpoint_load(None, b"/tmp/x", None) == tn.api.TNMC_ERR_ARG
     assert lib.tnmc_get_couplings(None, None) == tn.api.TNMC_ERR_ARG
+
+
+def test_direction_and_layout_arguments_checked_on_host(lib):
+    import ctypes
+    ARG = tn.api.TNMC_ERR_ARG
+    lay = ctypes.c_int32()
+    assert lib.tnmc_layout_choice(4, 32, 0, ctypes.byref(lay), None, None) == ARG
+    assert lib.tnmc_layout_choice(2, 0, 0, ctypes.byref(lay), None, None) == ARG
+    assert lib.tnmc_layout_choice(2, 32, 0, None, None, None) == ARG
+    # untuned class: -1
+    assert lib.tnmc_layout_choice(2, 32, 1, ctypes.byref(lay), None, None) == 0 and lay.value == -1
+    assert lib.tnmc_sweep_direction(None, 1, 1, 1, 0, 0, 0, None, None) == ARG
+    assert lib.tnmc_debug_set(2, 1) == ARG and lib.tnmc_debug_set(1, 2) == ARG

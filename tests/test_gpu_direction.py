@@ -42,3 +42,11 @@ def test_cycled_sweeps_and_record():
     for c in range(2):
         assert np.array_equal(tn.tnmc_get_spins(lat, c), ref[c])
         assert E[-1, c] == model.energy(J[c], ref[c], 2)
+
+
+def test_direction_argument_checked():
+    lat, _, _, _ = gh.make_lattice(4, 4, 4, 2, 4, seed=1)
+    for bad in (-1, 3):
+        with pytest.raises(tn.TnmcError) as e:
+            tn.tnmc_sweep_direction([lat], bad, 1)
+        assert e.value.status == tn.api.TNMC_ERR_ARG
