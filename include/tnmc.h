@@ -195,8 +195,8 @@ tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes);
  * its overflow path (a second launch with the full tile layout in LDS, one
  * task per CU), so that path can be checked against the oracle; value 1 = on,
  * 0 = off (default).  what = 1: the layout autotuner (value 1 = on, the
- * default; 0 = off, which also drops its choices).  Results are the same
- * either way.  Returns TNMC_ERR_ARG for an unknown what. */
+ * default; 0 = off, which also drops its choices).  Results agree within
+ * the parity bar either way.  Returns TNMC_ERR_ARG for an unknown what. */
 tnmc_status tnmc_debug_set(int32_t what, int32_t value);
 
 /* ------------------------------------------------------------------------
@@ -290,7 +290,8 @@ tnmc_status tnmc_nn_calibrate_fallback(tnmc_lattice* lat, double threshold, int3
  * compact contraction layout (two tasks per CU, with a full-layout redo of the
  * tasks whose rank outgrows it) or the full layout (one task per CU) are timed
  * once with each, on the tasks of the first tnmc_sweep that contains them,
- * and the faster is kept for the process (both give the same results).
+ * and the faster is kept for the process (the two agree within the FP64
+ * parity bar, and the chains they produce in the tests are identical).
  * *layout receives -1 (not tuned yet, or no choice), 0 (compact) or 1 (full);
  * ms_compact / ms_full (may be NULL) the trial durations of the contraction
  * launch. */

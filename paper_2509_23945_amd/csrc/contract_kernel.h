@@ -31,7 +31,7 @@ namespace tnmc {
 extern int g_force_retry;   // test hook: every compact-layout task takes the retry path
 // Layout chosen by the host's autotuner for the (d, chi_max) classes that
 // have a compact layout: g_layout_full[d == 3][FP32 storage] = 1 runs them
-// with the full layout instead (same results).
+// with the full layout instead (equal within the FP64 parity bar).
 extern int g_layout_full[2][2];
 
 namespace {

@@ -311,7 +311,8 @@ tnmc_status finish_timer(Timer& tm, tnmc_stats* st) {
 
 // Layout autotuner.  The (d, chi_max) classes with a compact layout (two
 // tasks per CU, with a full-layout redo of the tasks that outgrow it) can also
-// run every task in the full layout (one per CU); both give the same results.
+// run every task in the full layout (one per CU); the two agree within the
+// FP64 parity bar.
 // Before the second sweep of such a class and storage precision, the
 // contraction of that sweep's tasks runs once with each layout untimed, then
 // once more timed (descriptors without counters, so the statistics see only
