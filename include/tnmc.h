@@ -195,8 +195,11 @@ tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes);
  * its overflow path (a second launch with the full tile layout in LDS, one
  * task per CU), so that path can be checked against the oracle; value 1 = on,
  * 0 = off (default).  what = 1: the layout autotuner (value 1 = on, the
- * default; 0 = off, which also drops its choices).  Results agree within
- * the parity bar either way.  Returns TNMC_ERR_ARG for an unknown what. */
+ * default; 0 = off, which also drops its choices).  what = 2: two
+ * learned-proposal tasks per workgroup in tnmc_nn_sweep launches that allow
+ * it (value 1 = on, the default; 0 = off).  Results agree within the parity
+ * bar either way (what = 2: bit for bit).  Returns TNMC_ERR_ARG for an
+ * unknown what. */
 tnmc_status tnmc_debug_set(int32_t what, int32_t value);
 
 /* ------------------------------------------------------------------------

@@ -325,6 +325,7 @@ struct TuneResult {
 std::map<std::tuple<int, int, int>, TuneResult> g_tune;
 std::map<std::tuple<int, int, int>, int> g_tune_seen;   // sweeps run per class before its trial
 bool g_autotune = true;
+bool g_nn_pairing = true;   // two learned-proposal tasks per workgroup where a launch allows it
 
 // Trials for the classes of the plan that have run one sweep already: the
 // first sweep from a prepared (often random) configuration meets larger ranks
@@ -700,10 +701,12 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
 }
 
 tnmc_status tnmc_debug_set(int32_t what, int32_t value) {
-  if ((what != 0 && what != 1) || (value != 0 && value != 1)) return TNMC_ERR_ARG;
+  if (what < 0 || what > 2 || (value != 0 && value != 1)) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
   if (what == 0) {
     tnmc::set_force_retry(value);
+  } else if (what == 2) {
+    g_nn_pairing = value != 0;
   } else {
     // autotuner off: forget its choices and run the default (compact) layouts
     g_autotune = value != 0;
@@ -1218,6 +1221,17 @@ tnmc_status tnmc_nn_sweep(tnmc_lattice* const* lats, int32_t n_lats, tnmc_nn* nn
   for (int p : {0, 1})   // lattices of different shapes share one launch per parity
     if (!nd[p].empty() && tnmc::nn_sample_lds_bytes(lxm[p], lym[p]) + kNnStaticLds > 160 * 1024)
       return TNMC_ERR_UNSUPPORTED;
+  // Two tasks per workgroup share the weights in LDS, which halves the rounds
+  // of a launch with more tasks than CUs; only where every task of the
+  // launch has one layer shape (both halves of a workgroup then pass the
+  // same barriers) and their count is even.
+  bool paired[2] = {false, false};
+  for (int p : {0, 1}) {
+    bool one_shape = true;
+    for (const auto& d : nd[p]) one_shape = one_shape && d.Lx == nd[p][0].Lx && d.Ly == nd[p][0].Ly;
+    paired[p] = g_nn_pairing && one_shape && nd[p].size() > 256 && nd[p].size() % 2 == 0 &&
+                tnmc::nn_sample_lds_bytes(lxm[p], lym[p], 2) + kNnStaticLds <= 160 * 1024;
+  }
   const size_t n_nn = nd[0].size() + nd[1].size();
   if (grow(g_ws.nn_tasks, g_ws.nn_tasks_cap, std::max<size_t>(n_nn, 1)) != TNMC_OK) return TNMC_ERR_OOM;
   if (!nd[0].empty())
@@ -1253,7 +1267,7 @@ tnmc_status tnmc_nn_sweep(tnmc_lattice* const* lats, int32_t n_lats, tnmc_nn* nn
       if (!nd[p].empty()) {
         if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
         HIP_TRY(tnmc::launch_nn_sample(g_ws.nn_tasks + (p ? nd[0].size() : 0), (int)nd[p].size(), nn->theta, lxm[p],
-                                       lym[p], sw, s));
+                                       lym[p], sw, s, paired[p]));
         if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
         if (stats) stats->sample_launches += 1;
       }

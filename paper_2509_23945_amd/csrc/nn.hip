@@ -124,9 +124,11 @@ __device__ __forceinline__ float cond_value(JP J, SP spins, int Lx, int Ly, int 
 //   lcr [2][lx_max]         per path, the clipped logits of the current row
 //   uni [lx_max] doubles: logit of the row's uniforms, log U - log(1 - U); then
 //   cfg [2][ly_max][lx_max] bytes (states: 0 = +1, 1 = -1)
+// With nslot = 2 a workgroup runs two tasks of one shape: the weights are
+// shared, the rest (from cp on) is per task, slot s at offset s * slot_f.
 struct SampleLayout {
-  int wc0, ws0, b0, wh, bh, w5, b5, cp, crow, ring, lcr, uni_f, cfg_b, total_b;
-  __host__ __device__ SampleLayout(int lx_max, int ly_max) {
+  int wc0, ws0, b0, wh, bh, w5, b5, cp, crow, ring, lcr, uni_f, cfg_b, slot_f, total_b;
+  __host__ __device__ SampleLayout(int lx_max, int ly_max, int nslot = 1) {
     int o = 0;
     wc0 = o; o += C * NCOND * 9;
     ws0 = o; o += C * 4;
@@ -135,6 +137,7 @@ struct SampleLayout {
     bh = o; o += NHID * C;
     w5 = o; o += 5 * C;
     b5 = o; o += 4;
+    const int s0 = o;
     cp = o; o += lx_max * C;
     crow = o; o += 3 * NCOND * (lx_max + 2);
     o = (o + 3) & ~3;
@@ -143,7 +146,10 @@ struct SampleLayout {
     o = (o + 1) & ~1;
     uni_f = o; o += 2 * lx_max;
     cfg_b = o * 4;
-    total_b = cfg_b + 2 * lx_max * ly_max;
+    o += (2 * lx_max * ly_max + 3) / 4;
+    o = (o + 3) & ~3;
+    slot_f = o - s0;
+    total_b = (s0 + nslot * slot_f) * 4;
   }
 };
 
@@ -163,14 +169,24 @@ __device__ __forceinline__ float dot16(const float* a, const float* b) {
   return s0 + s1;
 }
 
-__global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restrict__ tasks,
-                                                        const float* __restrict__ theta_in, uint64_t sweep,
-                                                        int lx_max, int ly_max) {
+template <int NSLOT>
+__global__ __launch_bounds__(NTS * NSLOT) void nn_sample_kernel(const TaskDesc* __restrict__ tasks,
+                                                                const float* __restrict__ theta_in, uint64_t sweep,
+                                                                int lx_max, int ly_max) {
   extern __shared__ __align__(16) float lds[];
-  __shared__ double lq_sh[2];
-  __shared__ int fault_sh[2];
-  const TaskDesc& t = tasks[blockIdx.x];
-  const int tid = threadIdx.x;
+  __shared__ double lq_sh[NSLOT][2];
+  __shared__ int fault_sh[NSLOT][2];
+  const int gtid = threadIdx.x;
+  const int slot = (NSLOT == 2) ? (gtid >> 7) : 0;   // task of this half of the workgroup
+  if constexpr (NSLOT == 2) {
+    // both halves pass the same barriers only if their layers have one shape:
+    // otherwise the whole workgroup leaves before the first barrier
+    const TaskDesc& a = tasks[2 * blockIdx.x];
+    const TaskDesc& b = tasks[2 * blockIdx.x + 1];
+    if (a.Lx != b.Lx || a.Ly != b.Ly) return;
+  }
+  const TaskDesc& t = tasks[blockIdx.x * NSLOT + slot];
+  const int tid = gtid & (NTS - 1);   // thread within the task's half
   const int path = tid >> 6;   // 0: new layer (drawn), 1: current layer (forced)
   const int lane = tid & 63;
   const int Lx = t.Lx, Ly = t.Ly, Lz = t.Lz, z = t.z;
@@ -182,38 +198,40 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
   const gptr<const int8_t> forced = (path == 1) ? gmem(static_cast<const int8_t*>(t.spins + (size_t)z * plane))
                                                 : gmem(t.force_new);
   acquire_device();
-  const SampleLayout L(lx_max, ly_max);
+  const SampleLayout L(lx_max, ly_max, NSLOT);
+  float* const sl = lds + (size_t)slot * L.slot_f;   // this task's region (offsets from cp on)
   float* wc0 = lds + L.wc0;
   float* ws0 = lds + L.ws0;
   float* b0 = lds + L.b0;
   float* wh = lds + L.wh;
   float* bh = lds + L.bh;
   float* w5 = lds + L.w5;
-  float* cp = lds + L.cp;
-  float* crow = lds + L.crow;
+  float* cp = sl + L.cp;
+  float* crow = sl + L.crow;
   const int RING = Lx + 2;
-  float* ring = lds + L.ring + (size_t)path * (NHID + 1) * (lx_max + 2) * C;
-  double* uni = reinterpret_cast<double*>(lds + L.uni_f);
-  float* lcr = lds + L.lcr + path * lx_max;
-  int8_t* cfg = reinterpret_cast<int8_t*>(lds) + L.cfg_b;
+  float* ring = sl + L.ring + (size_t)path * (NHID + 1) * (lx_max + 2) * C;
+  double* uni = reinterpret_cast<double*>(sl + L.uni_f);
+  float* lcr = sl + L.lcr + path * lx_max;
+  int8_t* cfg = reinterpret_cast<int8_t*>(sl) + L.cfg_b;
 #define CFG(p, y, x) cfg[((size_t)(p) * ly_max + (y)) * lx_max + (x)]
 
-  // masked weights into LDS in the sampler's layout
-  for (int i = tid; i < C * NCOND * 9; i += NTS) {
+  // masked weights into LDS in the sampler's layout (shared by the workgroup's tasks)
+  constexpr int NT = NTS * NSLOT;
+  for (int i = gtid; i < C * NCOND * 9; i += NT) {
     const int co = i / (NCOND * 9), r = i % (NCOND * 9);
     wc0[i] = theta[OFF_W0 + co * (NCOND + 1) * 9 + r];
   }
-  for (int i = tid; i < C * 4; i += NTS) ws0[i] = theta[OFF_W0 + ((i >> 2) * (NCOND + 1) + NCOND) * 9 + (i & 3)];
-  for (int i = tid; i < C; i += NTS) b0[i] = theta[OFF_B0 + i];
-  for (int i = tid; i < NHID * C * 5 * C; i += NTS) {
+  for (int i = gtid; i < C * 4; i += NT) ws0[i] = theta[OFF_W0 + ((i >> 2) * (NCOND + 1) + NCOND) * 9 + (i & 3)];
+  for (int i = gtid; i < C; i += NT) b0[i] = theta[OFF_B0 + i];
+  for (int i = gtid; i < NHID * C * 5 * C; i += NT) {
     const int l = i / (C * 5 * C), r = i % (C * 5 * C);
     const int co = r / (5 * C), k = (r / C) % 5, ci = r % C;
     wh[(l * C + co) * WCO + k * C + ci] = theta[OFF_H + l * HID + (co * C + ci) * 9 + k];
   }
-  for (int i = tid; i < NHID * C; i += NTS) bh[i] = theta[OFF_H + (i / C) * HID + C * C * 9 + (i % C)];
-  for (int i = tid; i < 5 * C; i += NTS) w5[i] = theta[OFF_W5 + (i % C) * 9 + i / C];
-  if (tid == 0) lds[L.b5] = theta[OFF_B5];
-  for (int i = tid; i < 2 * (NHID + 1) * (lx_max + 2) * C; i += NTS) lds[L.ring + i] = 0.0f;
+  for (int i = gtid; i < NHID * C; i += NT) bh[i] = theta[OFF_H + (i / C) * HID + C * C * 9 + (i % C)];
+  for (int i = gtid; i < 5 * C; i += NT) w5[i] = theta[OFF_W5 + (i % C) * 9 + i / C];
+  if (gtid == 0) lds[L.b5] = theta[OFF_B5];
+  for (int i = tid; i < 2 * (NHID + 1) * (lx_max + 2) * C; i += NTS) sl[L.ring + i] = 0.0f;
   // configuration tiles: the forced layers ahead of the walk
   const bool have_forced = (path == 1) || (t.force_new != nullptr);
   if (have_forced)
@@ -333,8 +351,8 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
     __syncthreads();
   }
   if (lane == 0) {
-    lq_sh[path] = logq;
-    fault_sh[path] = fault;
+    lq_sh[slot][path] = logq;
+    fault_sh[slot][path] = fault;
   }
   __syncthreads();
   if (path != 0) return;
@@ -356,8 +374,8 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
     dE += e;
   }
   dE = wave_sum(dE);
-  const double lq_new = lq_sh[0], lq_old = lq_sh[1];
-  const int any_fault = (fault_sh[0] | fault_sh[1]) ? 1 : 0;
+  const double lq_new = lq_sh[slot][0], lq_old = lq_sh[slot][1];
+  const int any_fault = (fault_sh[slot][0] | fault_sh[slot][1]) ? 1 : 0;
   const double lr = lq_old - lq_new - beta * dE;
   const double Uacc = philox_uniform(0ull, (uint64_t)z, sweep, 1ull, t.key0, t.key1);
   const int accepted = (!any_fault && Uacc < exp(fmin(0.0, lr))) ? 1 : 0;
@@ -374,7 +392,7 @@ __global__ __launch_bounds__(NTS) void nn_sample_kernel(const TaskDesc* __restri
       t.record[1] = lq_old;
       t.record[2] = dE;
       t.record[3] = (double)accepted;
-      t.record[4] = (double)(fault_sh[0] | (fault_sh[1] << 2));
+      t.record[4] = (double)(fault_sh[slot][0] | (fault_sh[slot][1] << 2));
     }
     if (t.counters) {
       add_device(t.counters + 0, 1);
@@ -823,20 +841,31 @@ hipError_t launch_nn_dataset(const float* const* Jc, int8_t* const* spins, int n
   return hipGetLastError();
 }
 
-size_t nn_sample_lds_bytes(int lx_max, int ly_max) { return (size_t)SampleLayout(lx_max, ly_max).total_b; }
+size_t nn_sample_lds_bytes(int lx_max, int ly_max, int nslot) {
+  return (size_t)SampleLayout(lx_max, ly_max, nslot).total_b;
+}
 
-hipError_t launch_nn_sample(const TaskDesc* tasks, int n, const float* theta, int lx_max, int ly_max, uint64_t sweep,
-                            hipStream_t s) {
-  const size_t bytes = nn_sample_lds_bytes(lx_max, ly_max);
+template <int NSLOT>
+hipError_t launch_nn_sample_t(const TaskDesc* tasks, int n_groups, const float* theta, int lx_max, int ly_max,
+                              uint64_t sweep, hipStream_t s) {
+  const size_t bytes = nn_sample_lds_bytes(lx_max, ly_max, NSLOT);
   static size_t attr_bytes = 0;
   if (bytes > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)nn_sample_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)bytes);
+    hipError_t e = hipFuncSetAttribute((const void*)nn_sample_kernel<NSLOT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
     attr_bytes = bytes;
   }
-  hipLaunchKernelGGL(nn_sample_kernel, dim3(n), dim3(NTS), bytes, s, tasks, theta, sweep, lx_max, ly_max);
+  hipLaunchKernelGGL(nn_sample_kernel<NSLOT>, dim3(n_groups), dim3(NTS * NSLOT), bytes, s, tasks, theta, sweep, lx_max,
+                     ly_max);
   return hipGetLastError();
+}
+
+// paired: n is even and consecutive tasks 2k, 2k + 1 share one layer shape.
+hipError_t launch_nn_sample(const TaskDesc* tasks, int n, const float* theta, int lx_max, int ly_max, uint64_t sweep,
+                            hipStream_t s, bool paired) {
+  if (paired) return launch_nn_sample_t<2>(tasks, n / 2, theta, lx_max, ly_max, sweep, s);
+  return launch_nn_sample_t<1>(tasks, n, theta, lx_max, ly_max, sweep, s);
 }
 
 hipError_t nn_forward(const NnBatch& B, const float* theta, hipStream_t s) {

@@ -32,9 +32,11 @@ struct NnBatch {
   float* part = nullptr;         // [kNnWeightParts][32*32*9 + 32]
 };
 
-size_t nn_sample_lds_bytes(int lx_max, int ly_max);
+// Dynamic LDS of a sampler workgroup running nslot (1 or 2) tasks of layers up to lx_max x ly_max.
+size_t nn_sample_lds_bytes(int lx_max, int ly_max, int nslot = 1);
+// paired: two tasks per workgroup (n even, tasks 2k and 2k + 1 of one layer shape), sharing the weights in LDS.
 hipError_t launch_nn_sample(const TaskDesc* tasks, int n, const float* theta, int lx_max, int ly_max, uint64_t sweep,
-                            hipStream_t s);
+                            hipStream_t s, bool paired = false);
 // Forward pass of a batch: activations, logits, log q per layer and the logit gradient of the mean loss.
 hipError_t nn_forward(const NnBatch& B, const float* theta, hipStream_t s);
 // Parameter gradient of the mean -log q of the batch after nn_forward.

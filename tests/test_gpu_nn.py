@@ -332,3 +332,25 @@ def test_nn_sweep_over_lattices_of_different_shapes():
             for z in list(range(0, Lz, 2)) + list(range(1, Lz, 2)):
                 onn.slice_update(th64, J[c], ref, z, beta, seed=12345, chain_key=c, sweep=2)
             assert np.array_equal(tn.tnmc_get_spins(lat, c), ref)
+
+
+def test_paired_sampler_launch_equals_single_task_workgroups():
+    """More than 256 learned-proposal tasks of one shape run two per workgroup
+    (sharing the weights in LDS); the chain equals the one-task-per-workgroup
+    launch bit for bit."""
+    gh.announce("nn paired launch 8x8x10, 64 chains")
+    th = params(10, 1.5)
+    runs = []
+    try:
+        for pairing in (1, 0):
+            tn.tnmc_debug_set(2, pairing)
+            lat, _, _, _ = gh.make_lattice(8, 8, 10, 2, 4, kind="pmj", beta=1.0, seed=51, n_chains=64)
+            net = tn.tnmc_nn_create(th)
+            st = tn.tnmc_nn_sweep([lat], net, 2, sweep_offset=1)
+            assert st["proposed"] == 64 * 10 * 2 and st["numeric_faults"] == 0
+            runs.append((st["accepted"], [tn.tnmc_get_spins(lat, c) for c in range(64)]))
+    finally:
+        tn.tnmc_debug_set(2, 1)
+    assert runs[0][0] == runs[1][0] > 0
+    for a, b in zip(runs[0][1], runs[1][1]):
+        assert np.array_equal(a, b)
