@@ -124,4 +124,4 @@ def test_direction_and_layout_arguments_checked_on_host(lib):
     # untuned class: -1
     assert lib.tnmc_layout_choice(2, 32, 1, ctypes.byref(lay), None, None) == 0 and lay.value == -1
     assert lib.tnmc_sweep_direction(None, 1, 1, 1, 0, 0, 0, None, None) == ARG
-    assert lib.tnmc_debug_set(2, 1) == ARG and lib.tnmc_debug_set(1, 2) == ARG
+    assert lib.tnmc_debug_set(3, 1) == ARG and lib.tnmc_debug_set(1, 2) == ARG
