@@ -611,7 +611,6 @@ __global__ __launch_bounds__(256) void nn_wgrad32_kernel(const float* __restrict
 #pragma unroll
       for (int t = 0; t < 5; ++t) {
         const float* xb = xs + ((lane & 31) * 3 + t / 3) * XS + (lane >> 5) + t % 3;
-#pragma unroll 4
         for (int st = 0; st < steps; ++st)
           acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(ga[2 * st], xb[2 * st], acc[t], 0, 0, 0);
       }
