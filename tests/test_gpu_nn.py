@@ -354,3 +354,18 @@ def test_paired_sampler_launch_equals_single_task_workgroups():
     assert runs[0][0] == runs[1][0] > 0
     for a, b in zip(runs[0][1], runs[1][1]):
         assert np.array_equal(a, b)
+
+
+def test_nn_sweep_with_every_layer_on_the_fallback_is_the_tn_sweep():
+    """All layers flagged for the TN proposal (here on a reduced-precision
+    lattice): a learned-proposal sweep is then the plain TN sweep, spin for spin."""
+    gh.announce("nn sweep all fallback, fp32 lattice")
+    net = tn.tnmc_nn_create(params(11, 1.0))
+    lats = [gh.make_lattice(6, 5, 4, 2, 4, kind="gauss", beta=0.9, seed=61, n_chains=2, precision=tn.TNMC_FP32)[0]
+            for _ in range(2)]
+    tn.tnmc_nn_set_fallback(lats[0], np.ones((2, 4), dtype=np.int8))
+    st = tn.tnmc_nn_sweep([lats[0]], net, 2, sweep_offset=5)
+    tn.tnmc_sweep([lats[1]], 2, sweep_offset=5)
+    assert st["proposed"] == 2 * 4 * 2 and np.all(tn.tnmc_nn_counts(lats[0])[0] == 0)
+    for c in range(2):
+        assert np.array_equal(tn.tnmc_get_spins(lats[0], c), tn.tnmc_get_spins(lats[1], c))
