@@ -50,3 +50,23 @@ def test_direction_argument_checked():
         with pytest.raises(tn.TnmcError) as e:
             tn.tnmc_sweep_direction([lat], bad, 1)
         assert e.value.status == tn.api.TNMC_ERR_ARG
+
+
+@pytest.mark.parametrize("direction", [1, 2])
+def test_direction_sweep_is_the_z_sweep_of_the_permuted_lattice(direction):
+    """On a reduced-precision lattice (no bit-exact oracle there): a sweep along
+    `direction` equals a plain z-slice sweep of a second lattice built from the
+    permuted couplings and spins, with the direction's sweep counter."""
+    gh.announce(f"direction vs permuted lattice dir={direction}")
+    Lx, Ly, Lz, chi, beta = 5, 4, 6, 4, 0.8
+    lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, 2, chi, kind="gauss", beta=beta, seed=33, n_chains=2,
+                                       precision=tn.TNMC_FP32)
+    perm = [ochain.to_direction(J[c], spins[c], direction) for c in range(2)]
+    nz, ny, nx = perm[0][1].shape
+    view = tn.tnmc_lattice_init(Lx=nx, Ly=ny, Lz=nz, d=2, chi=chi, J=np.stack([p[0] for p in perm]),
+                                beta=np.full(2, beta), spins=np.stack([p[1] for p in perm]),
+                                chain_instance=np.arange(2, dtype=np.int32), seed=12345, precision=tn.TNMC_FP32)
+    tn.tnmc_sweep_direction([lat], direction, 1, sweep_offset=2)
+    tn.tnmc_sweep([view], 1, sweep_offset=2 + direction * ochain.DIRECTION_STRIDE)
+    for c in range(2):
+        assert np.array_equal(tn.tnmc_get_spins(lat, c), ochain.from_direction(tn.tnmc_get_spins(view, c), direction))
