@@ -92,6 +92,22 @@ tnmc_status tnmc_slice_propose(tnmc_lattice* lat, int32_t chain, int32_t z, uint
                                int8_t* s_new, double* logq_new, double* logq_old, double* dE,
                                void* hip_stream);
 
+/* As tnmc_slice_propose, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): this call makes no device allocation of any kind.  The slice
+ * task's workspace lives in a static device array of 24 MiB that each GPU the
+ * library runs on holds until the process ends; layers whose workspace
+ * (environments of Ly*Lx*d*chi_max^2 values, R factors, tiles) does not fit
+ * it return TNMC_ERR_ARG with the sizes in tnmc_last_error (FP64 Ising layers
+ * up to 32x32 at chi <= 32 fit).  Results equal tnmc_slice_propose's.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (other host threads, or other streams before this call has returned) race
+ * and must not be made.  Outputs are HOST pointers as for tnmc_slice_propose;
+ * the call synchronises hip_stream. */
+tnmc_status tnmc_slice_propose_static(tnmc_lattice* lat, int32_t chain, int32_t z, uint64_t sweep,
+                                      int8_t* s_new, double* logq_new, double* logq_old, double* dE,
+                                      void* hip_stream);
+
 /* log q of an arbitrary configuration s [Ly][Lx] (HOST) of layer z given the
  * current held layers (SM S1.C: product of the conditionals along the
  * sampling order, with the spins projected on their states). */

@@ -37,7 +37,7 @@ __all__ = [
     "tnmc_nn_train", "tnmc_nn_dataset", "tnmc_nn_slice_propose", "tnmc_nn_slice_logq", "tnmc_nn_sweep",
     "tnmc_nn_counts", "tnmc_nn_counts_reset", "tnmc_nn_set_fallback", "tnmc_nn_get_fallback",
     "tnmc_nn_calibrate_fallback", "tnmc_get_couplings", "tnmc_checkpoint_save", "tnmc_checkpoint_load",
-    "tnmc_sweep_direction", "tnmc_layout_choice",
+    "tnmc_sweep_direction", "tnmc_layout_choice", "tnmc_slice_propose_static",
 ]
 TNMC_NN_PARAMS = 38753
 
@@ -103,6 +103,7 @@ def load():
     lib.tnmc_lattice_free.argtypes = [vp]
     lib.tnmc_slice_propose.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, P(ctypes.c_int8),
                                        P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double), vp]
+    lib.tnmc_slice_propose_static.argtypes = lib.tnmc_slice_propose.argtypes
     lib.tnmc_slice_logq.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int8), P(ctypes.c_double), vp]
     lib.tnmc_mh_accept.argtypes = [ctypes.c_double] * 5 + [P(ctypes.c_int32)]
     lib.tnmc_sweep.argtypes = [P(vp), ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
@@ -240,6 +241,17 @@ def tnmc_slice_propose(lat: Lattice, chain: int, z: int, sweep: int = 0, stream=
     st = lib.tnmc_slice_propose(lat.handle, chain, z, ctypes.c_uint64(sweep), _ptr(s_new, ctypes.c_int8),
                                 ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), stream)
     _check(st, "tnmc_slice_propose", allow=(TNMC_ERR_NUMERIC,))
+    return s_new, a.value, b.value, c.value, st
+
+
+def tnmc_slice_propose_static(lat: Lattice, chain: int, z: int, sweep: int = 0, stream=None):
+    """As tnmc_slice_propose, through the allocation-free entry point (static device scratch)."""
+    lib = load()
+    s_new = np.zeros((lat.Ly, lat.Lx), dtype=np.int8)
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st = lib.tnmc_slice_propose_static(lat.handle, chain, z, ctypes.c_uint64(sweep), _ptr(s_new, ctypes.c_int8),
+                                       ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), stream)
+    _check(st, "tnmc_slice_propose_static", allow=(TNMC_ERR_NUMERIC,))
     return s_new, a.value, b.value, c.value, st
 
 

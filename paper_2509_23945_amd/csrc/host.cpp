@@ -106,6 +106,7 @@ struct Workspace {
 };
 Workspace g_ws;
 
+
 template <typename T>
 tnmc_status grow(T*& p, size_t& cap, size_t need) {
   if (need <= cap) return TNMC_OK;
@@ -795,6 +796,127 @@ tnmc_status tnmc_timeseries(tnmc_lattice* L, double* E, double* M, double* q, in
 tnmc_status tnmc_timeseries_reset(tnmc_lattice* L) {
   if (!L) return TNMC_ERR_ARG;
   L->n_recorded = 0;
+  return TNMC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ allocation-free proposal
+// Static device scratch of the allocation-free entry point: the workspace of
+// one slice task (descriptor, environments, R factors, global tile scratch,
+// bond dimensions, log scales, record, drawn layer).  Each GPU the library
+// runs on holds its own copy for the life of the process.  In host code the
+// array's name is only a stand-in: its device address comes from
+// hipGetSymbolAddress, once per device.
+namespace {
+
+constexpr size_t kStaticScratchBytes = (size_t)24 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch (looked up on the first call on it).
+tnmc_status static_scratch(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    g_last_error = "device index beyond the static scratch table";
+    return TNMC_ERR_DEVICE;
+  }
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+      g_last_error = "hipGetSymbolAddress returned no address for the static scratch";
+      return TNMC_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TNMC_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+tnmc_status tnmc_slice_propose_static(tnmc_lattice* lat, int32_t chain, int32_t z, uint64_t sweep, int8_t* s_new,
+                                      double* logq_new, double* logq_old, double* dE, void* stream) {
+  if (!lat || chain < 0 || chain >= lat->n_chains || z < 0 || z >= lat->Lz) return TNMC_ERR_ARG;
+  if (!s_new || !logq_new || !logq_old || !dE) return TNMC_ERR_ARG;
+  g_last_error.clear();
+  const int Lx = lat->Lx, Ly = lat->Ly, d = lat->d, cm = lat->chi_max;
+  const size_t plane = (size_t)Lx * Ly;
+  // scratch layout, every region on a 256-byte boundary
+  const bool glob = tnmc::contract_uses_global(d, cm);
+  const size_t o_desc = 0;
+  const size_t o_env = o_desc + align256(sizeof(TaskDesc));
+  const size_t o_rscr = o_env + align256(tnmc::env_doubles(Lx, Ly, d, cm, lat->precision) * sizeof(double));
+  const size_t o_gscr = o_rscr + align256(tnmc::rscr_doubles(Lx, d, cm) * sizeof(double));
+  const size_t o_ints = o_gscr + (glob ? align256(tnmc::contract_lds_bytes(d, cm)) : 0);
+  const size_t o_dbl = o_ints + align256((plane + 1) * sizeof(int));
+  const size_t o_bytes = o_dbl + align256(((size_t)Ly + 5) * sizeof(double));
+  const size_t need = o_bytes + align256(plane);
+  if (need > kStaticScratchBytes) {
+    g_last_error = "tnmc_slice_propose_static: this layer needs " + std::to_string(need) +
+                   " bytes of workspace, more than the " + std::to_string(kStaticScratchBytes) +
+                   " bytes of static scratch";
+    return TNMC_ERR_ARG;
+  }
+  void* base = nullptr;
+  tnmc_status r = static_scratch(&base);
+  if (r != TNMC_OK) return r;
+  unsigned char* sb = static_cast<unsigned char*>(base);
+  TaskDesc t;
+  std::memset(&t, 0, sizeof(t));
+  t.J = lat->J_of(chain);
+  t.spins = lat->spins_of(chain);
+  t.env = sb + o_env;
+  t.rscr = reinterpret_cast<double*>(sb + o_rscr);
+  t.gscr = glob ? reinterpret_cast<double*>(sb + o_gscr) : nullptr;
+  t.bond = reinterpret_cast<int*>(sb + o_ints);
+  t.status = t.bond + plane;
+  t.logscale = reinterpret_cast<double*>(sb + o_dbl);
+  t.record = t.logscale + Ly;
+  t.s_new_out = reinterpret_cast<int8_t*>(sb + o_bytes);
+  t.counters = nullptr;
+  t.force_new = nullptr;
+  t.beta = lat->beta[chain];
+  t.rank_tol = (lat->precision == TNMC_FP32) ? tnmc::kRankTolF32 : tnmc::kRankTolF64;
+  t.key0 = lat->seed;
+  t.key1 = lat->chain_key[chain];
+  t.Lx = Lx;
+  t.Ly = Ly;
+  t.Lz = lat->Lz;
+  t.z = z;
+  t.chi = lat->chi;
+  t.d = d;
+  t.chi_max = cm;
+  t.write_back = 0;
+  hipStream_t s = (hipStream_t)stream;
+  TaskDesc* dt = reinterpret_cast<TaskDesc*>(sb + o_desc);
+  // the descriptor is copied from this frame: wait for the copy before
+  // returning (and before the kernels read it, which stream order gives)
+  HIP_TRY(hipMemcpyAsync(dt, &t, sizeof(TaskDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(tnmc::launch_contract(dt, 1, d, cm, lat->precision, s));
+  HIP_TRY(tnmc::launch_sample(dt, 1, d, cm, lat->precision, Lx, Ly, sweep, s));
+  double rec[5];
+  HIP_TRY(hipMemcpyAsync(s_new, t.s_new_out, plane, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(rec, t.record, sizeof(rec), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *logq_new = rec[0];
+  *logq_old = rec[1];
+  *dE = rec[2];
+  if (rec[4] != 0.0 || !std::isfinite(rec[0]) || !std::isfinite(rec[1])) {
+    g_last_error = "numeric fault bits " + std::to_string((int)rec[4]) +
+                   " (1-2: new path, 4-8: current path, 16-64: contraction)";
+    return TNMC_ERR_NUMERIC;
+  }
   return TNMC_OK;
 }
 
