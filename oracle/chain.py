@@ -57,12 +57,14 @@ def propose(J, spins, z: int, beta: float, chi: int, d: int, *, seed: int = 0,
     }
 
 
-def slice_logq(J, spins, z: int, layer_spins, beta: float, chi: int, d: int) -> float:
-    """log q of an arbitrary configuration of layer z given the held layers."""
+def slice_logq(J, spins, z: int, layer_spins, beta: float, chi: int, d: int, site_probs=None) -> float:
+    """log q of an arbitrary configuration of layer z given the held layers.
+    With ``site_probs`` a list, it receives each site's conditional p(u) along
+    the forced walk (rows, then sites within a row)."""
     F = model.slice_field(J, spins, z, d)
     envs, _ = bmps.environments(J, F, z, beta, chi, d)
     _, lq, _ = sampler.sample_layer(envs, J, F, z, beta, d,
-                                    forced=model.to_states(layer_spins, d))
+                                    forced=model.to_states(layer_spins, d), site_probs=site_probs)
     return lq
 
 

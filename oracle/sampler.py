@@ -57,13 +57,16 @@ def draw(p: np.ndarray, U: float) -> int:
 
 
 def sample_layer(envs, J, F, z: int, beta: float, d: int, *, forced=None,
-                 seed: int = 0, chain: int = 0, sweep: int = 0, margins=None):
+                 seed: int = 0, chain: int = 0, sweep: int = 0, margins=None, site_probs=None):
     """Draw a layer configuration (state indices [y, x]) and its log q.
 
     With ``forced`` given, the draws are replaced by the given states
     (teacher forcing) and the result is log q(forced).  If ``margins`` is a
     list, the distance of every draw's uniform to the nearest cumulative
-    threshold is appended to it (to recognise near-ties).
+    threshold is appended to it (to recognise near-ties).  If ``site_probs``
+    is a list, every site's final probabilities p(u) are appended to it in
+    visiting order (drawn or forced), so a caller can check which state each
+    site's uniform selects under these conditionals.
     Returns (states, logq, fault)."""
     Ly, Lx, _ = F.shape
     sig = sig_table(d)
@@ -99,6 +102,8 @@ def sample_layer(envs, J, F, z: int, beta: float, d: int, *, forced=None,
             w = np.exp(loc) * np.einsum("ub,bu->u", mvec, R[x + 1])
             p, f = site_probabilities(w)
             fault |= f
+            if site_probs is not None:
+                site_probs.append(p.copy())
             if forced is not None:
                 u = int(forced[y, x])
             else:

@@ -38,3 +38,25 @@ def pytest_collection_finish(session):
         except ImportError:  # pragma: no cover
             return
         torch.cuda.is_available()
+
+
+def pytest_terminal_summary(terminalreporter):
+    """After GPU parity runs: the largest observed FP64 log q discrepancies
+    (absolute and relative) and the reduced form's per-site draw margins."""
+    gh = sys.modules.get("gpu_helpers")
+    if gh is None:
+        return
+    rows = getattr(gh, "OBSERVED_LOGQ", [])
+    if rows:
+        a = max(rows, key=lambda r: r[2])
+        r = max(rows, key=lambda r: r[3])
+        terminalreporter.write_line(f"[parity] fp64 log q over {len(rows)} comparisons: max |d| = {a[2]:.3e} "
+                                    f"({a[0]}, case {a[1]}); max |d|/max(1,|log q|) = {r[3]:.3e} ({r[0]}, case {r[1]})")
+    rows = getattr(gh, "OBSERVED_MARGINS", [])
+    if rows:
+        bad = sum(r[3] for r in rows)
+        worst = max(r[4] for r in rows)
+        closest = min(r[5] for r in rows)
+        terminalreporter.write_line(f"[parity] reduced-form draws over {len(rows)} layers: {bad} sites differ from the "
+                                    f"FP64 oracle's pick (largest margin among them {worst:.3e}); smallest margin "
+                                    f"of any site {closest:.3e}")

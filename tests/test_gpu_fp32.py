@@ -7,6 +7,12 @@ oracle's draws.  What is checked, on the GPU's own proposals:
 
 * log q of the current layer and of the drawn layer within 1e-4 relative of
   the FP64 oracle's log q of the same configurations (forced evaluation);
+* the draws themselves, site by site: every site of a drawn layer holds the
+  state that the FP64 oracle's conditional at that site (given the GPU's own
+  earlier sites) selects for the site's Philox uniform, except where the
+  uniform lies within a tie window of a cumulative threshold (SM S1.C:
+  ancestral sampling defines q, so MH is exact only if s is drawn from the q
+  whose log q is reported);
 * dE exact (a full-lattice energy difference of the oracle's model);
 * the Markov chain stays exact: with a truncated (chi = 1) proposal on a
   2x2x4 lattice, chain averages of E and M^2 over independent GPU chains match
@@ -37,7 +43,10 @@ def test_fp32_logq_of_own_proposals(case):
         s_new, lq_new, lq_old, dE, st = tn.tnmc_slice_propose(lat, 0, z, sweep)
         assert st == 0
         assert gh.logq_close_reduced(lq_old, lq_cur), (lq_old, lq_cur)
-        o_new = ochain.slice_logq(J[0], spins[0], z, s_new, beta, chi, d)
+        o_new, bad, worst, closest = gh.sitewise_draw_check(J[0], spins[0], z, s_new, beta, chi, d, seed=12345,
+                                                            chain=0, sweep=sweep)
+        gh.record_margin("fp32 sitewise", case, sweep, bad, worst, closest)
+        assert bad == 0 or worst < gh.TIE_REDUCED, (bad, worst)
         assert gh.logq_close_reduced(lq_new, o_new), (lq_new, o_new)
         after = spins[0].copy()
         after[z] = s_new

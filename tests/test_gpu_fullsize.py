@@ -2,9 +2,11 @@
 one even half-sweep of the 3D +-J workload (32^3, chi = 32, 16 instances x 2
 replicas, FP64) as a single batched launch.
 
-The oracle (about half a second per slice at this size) checks a sample of the
-512 tasks one by one: edge layers (one held neighbour, the largest bonds) and
-interior ones.  Every task is checked through properties that hold at any
+The oracle (a fraction of a second per slice at this size, run in worker
+processes) checks every one of the 512 tasks: log q of the current layer, and
+for each task the proposal visible in the result (the written-back layer if
+accepted), dE, log q of the proposal and the MH decision on the shared
+uniform.  Every task is also checked through properties that hold at any
 size: finite log q <= 0, and per chain the energy change of the half-sweep
 equals the sum of dE over its accepted proposals (layers of one parity do not
 interact)."""
@@ -13,14 +15,13 @@ import pytest
 
 import bench
 import gpu_helpers as gh
+import oracle_pool
 import paper_2509_23945_amd as tn
 from oracle import chain as ochain
 from oracle import model
 from oracle.philox import PURPOSE_MH, uniform
 
 pytestmark = pytest.mark.gpu
-
-SAMPLE = [(0, 0), (9, 0), (31, 0), (3, 14), (16, 2), (30, 30)]   # (chain, z)
 
 
 def test_half_sweep_full_size():
@@ -48,14 +49,17 @@ def test_half_sweep_full_size():
         for z in range(1, L, 2):
             assert np.array_equal(after[c][z], spins[c][z])
 
-    for (c, z) in SAMPLE:
-        k = tasks.index((c, z))
-        gh.announce(f"  oracle chain {c} z {z}")
-        ref, margins = gh.oracle_propose(J[inst[c]], spins[c], z, betas[c], chi, 2, seed=bench.PHILOX_SEED,
-                                         chain=c, sweep=0)
+    gh.announce(f"  oracle on all {len(tasks)} tasks")
+    refs = oracle_pool.propose_many(J, spins, [(int(inst[c]), c, z, float(betas[c]), chi, 2, bench.PHILOX_SEED, c, 0)
+                                               for (c, z) in tasks])
+    checked = 0
+    for k, (c, z) in enumerate(tasks):
+        ref = refs[k]
         lq_new, lq_old, dE, acc, _ = tr[k]
-        assert gh.logq_close(lq_old, ref["logq_old"]), (c, z, lq_old, ref["logq_old"])
-        tie = bool(margins) and min(margins) < gh.TIE
+        label = f"fullsize c{c} z{z}"
+        assert gh.logq_close(lq_old, ref["logq_old"], "fp64 fullsize logq_old", (c, z)), (c, z, lq_old,
+                                                                                          ref["logq_old"])
+        tie = ref["min_margin"] < gh.TIE
         if acc == 1.0:
             if not np.array_equal(after[c][z], ref["new"]):
                 assert tie, (c, z)   # a uniform on a cumulative threshold: both draws are correct
@@ -64,7 +68,10 @@ def test_half_sweep_full_size():
             assert np.array_equal(after[c][z], spins[c][z])
             if tie:
                 continue             # the proposal itself is not visible after a rejection
-        assert dE == ref["dE"], (c, z)
-        assert gh.logq_close(lq_new, ref["logq_new"]), (c, z, lq_new, ref["logq_new"])
+        assert dE == ref["dE"], label
+        assert gh.logq_close(lq_new, ref["logq_new"], "fp64 fullsize logq_new", (c, z)), (c, z, lq_new,
+                                                                                          ref["logq_new"])
         u = uniform(bench.PHILOX_SEED, c, 0, z, PURPOSE_MH, 0)
         assert bool(acc) == ochain.mh_accept(ref["logq_old"], ref["logq_new"], betas[c], ref["dE"], u)
+        checked += 1
+    assert checked >= len(tasks) - 4

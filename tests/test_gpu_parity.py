@@ -52,7 +52,7 @@ def test_propose_matches_oracle(case):
         gpu = tn.tnmc_slice_propose(lat, 0, z, sweep)
         assert gpu[4] == 0
         ref, margins = gh.oracle_propose(J[0], spins[0], z, beta, chi, d, seed=12345, chain=0, sweep=sweep)
-        diff = gh.compare_proposal(gpu, ref, margins)
+        diff = gh.compare_proposal(gpu, ref, margins, case=case)
         assert not diff or diff.get("spins", ("",))[0] == "near-tie", diff
 
 
