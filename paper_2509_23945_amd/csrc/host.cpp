@@ -103,9 +103,27 @@ struct Workspace {
   size_t nn_tasks_cap = 0;
   TaskDesc* tune_tasks = nullptr;   // descriptors of the layout trials
   size_t tune_tasks_cap = 0;
+  // Device-side end of the last call that used this workspace, on whatever
+  // stream it ran: the next call's stream waits for it, so calls made on
+  // different streams never overwrite descriptors or workspace that kernels
+  // of an earlier call still read.
+  hipEvent_t done = nullptr;
+  bool done_recorded = false;
 };
 Workspace g_ws;
 
+// Orders one workspace-using call after the previous one (whatever stream
+// either ran on) and marks its own end.  Taken with g_ws.mu held.
+struct WsOrder {
+  hipStream_t s;
+  explicit WsOrder(hipStream_t st) : s(st) {
+    if (!g_ws.done && hipEventCreateWithFlags(&g_ws.done, hipEventDisableTiming) != hipSuccess) g_ws.done = nullptr;
+    if (g_ws.done && g_ws.done_recorded) (void)hipStreamWaitEvent(s, g_ws.done, 0);
+  }
+  ~WsOrder() {
+    if (g_ws.done && hipEventRecord(g_ws.done, s) == hipSuccess) g_ws.done_recorded = true;
+  }
+};
 
 template <typename T>
 tnmc_status grow(T*& p, size_t& cap, size_t need) {
@@ -383,6 +401,7 @@ tnmc_status autotune_groups(const Plan& plan, hipStream_t s) {
 tnmc_status run_single(tnmc_lattice* lat, int chain, int z, uint64_t sweep, const int8_t* force_host,
                        int8_t* s_new_host, double* rec_host, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_ws.mu);
+  WsOrder order(s);
   g_last_error.clear();
   std::vector<Task> tasks{{lat, chain, z}};
   Plan plan;
@@ -599,6 +618,7 @@ tnmc_status tnmc_half_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t p
   if (check_lats(lats, n_lats) != TNMC_OK || (parity != 0 && parity != 1)) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
   hipStream_t s = (hipStream_t)stream;
+  WsOrder order(s);
   auto tasks = half_sweep_tasks(lats, n_lats, parity);
   Plan plan;
   tnmc_status r = make_plan(tasks, plan);
@@ -633,6 +653,7 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
   if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
   hipStream_t s = (hipStream_t)stream;
+  WsOrder order(s);
   // Every task of both parities with a workspace of its own; one launch pair
   // (contraction, sampler) per (parity, d, chi_max), longest task first, all
   // on the caller's stream.  Launches are kept strictly in order: launches of
@@ -1098,6 +1119,7 @@ TaskDesc nn_task(tnmc_lattice* L, int chain, int z) {
 tnmc_status nn_single(tnmc_lattice* lat, tnmc_nn* nn, int chain, int z, uint64_t sweep, const int8_t* force_host,
                       int8_t* s_new_host, double* rec_host, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_ws.mu);
+  WsOrder order(s);
   g_last_error.clear();
   const size_t plane = (size_t)lat->Lx * lat->Ly;
   if (grow(g_ws.bytes, g_ws.bytes_cap, 2 * plane) != TNMC_OK) return TNMC_ERR_OOM;
@@ -1317,6 +1339,7 @@ tnmc_status tnmc_nn_sweep(tnmc_lattice* const* lats, int32_t n_lats, tnmc_nn* nn
   }
   std::lock_guard<std::mutex> lk(g_ws.mu);
   hipStream_t s = (hipStream_t)stream;
+  WsOrder order(s);
   for (int l = 0; l < n_lats; ++l) {
     tnmc_status r = nn_counters(lats[l]);
     if (r != TNMC_OK) return r;
