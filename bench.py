@@ -198,12 +198,23 @@ def _oracle_task(args):
         return time.perf_counter() - t
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(name: str, per_worker: int = 6):
     """The FP64 oracle on the host cores over a bounded sample of the workload's slice updates
     (spread over its lattices in proportion to their share of slice updates)."""
     import multiprocessing as mp
     groups = build_groups(name)
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores = max(1, len(os.sched_getaffinity(0)))
     n = cores * per_worker
     weights = np.array([len(g["inst"]) * g["L"] for g in groups], dtype=float)
     counts = np.floor(weights / weights.sum() * n).astype(int)
@@ -220,6 +231,7 @@ def cpu_baseline(name: str, per_worker: int = 6):
         wall = time.perf_counter() - t0
     shapes = ", ".join(f"L={g['L']} chi={g['chi']}: {c}" for g, c in zip(groups, counts) if c)
     return {"value": len(tasks) / wall, "unit": "slice updates/s", "cores": cores, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
             "sample": f"{len(tasks)} slice updates of the {name} workload ({shapes}), "
                       f"{per_worker} per worker process, numpy single-threaded; wall {wall:.1f} s, "
                       f"{np.sum(per):.1f} s of CPU work, mean {np.mean(per):.2f} s per update per core"}
@@ -237,11 +249,15 @@ def indep_of(lat, sweep_s):
     return indep, tau
 
 
-NN_FLOPS_PER_SITE = 2 * 9 * (5 * 32 + 4 * 32 * 32 + 32)   # dense 3x3 forward, as the training kernels run it
+# forward flops per site on the taps the masks keep: the first layer sees the 4
+# condition channels through all 9 taps and the spin channel through the 4 taps
+# of the type-A mask; the four hidden 32 -> 32 layers and the 32 -> 1 output
+# keep 5 taps (type-B mask).  Training = forward + input gradient + weight gradient.
+NN_FLOPS_PER_SITE = 2 * (32 * (4 * 9 + 1 * 4) + 4 * 32 * 32 * 5 + 32 * 5)
 FP32_PEAK_TFLOPS = 157.3
 
 
-def learned_form(tn, lat, group, args, stream, fp64_value):
+def learned_form(tn, lat, group, args, stream, fp64_value, sweep0, tau_on, fp64_indep):
     """The learned proposal on the same chains: a training set of (condition,
     layer) pairs taken after each of a number of further FP64 TN sweeps (each
     layer then is a fresh draw of the TN proposal given its neighbours),
@@ -251,7 +267,6 @@ def learned_form(tn, lat, group, args, stream, fp64_value):
     L = group["L"]
     n_chains = len(group["inst"])
     per_sweep = n_chains * L
-    sweep0 = args.warmup + args.steps
     K = args.learned_data_sweeps
     n = K * per_sweep
     cond = torch.empty((n, 4, L, L), dtype=torch.float32, device="cuda")
@@ -302,6 +317,7 @@ def learned_form(tn, lat, group, args, stream, fp64_value):
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     indep = indep_of(lat, secs / args.steps)
+    sw += args.steps
     prop, acc = tn.tnmc_nn_counts(lat)
     nn_prop = int(prop.sum())
     value = args.steps * per_sweep / secs
@@ -311,6 +327,12 @@ def learned_form(tn, lat, group, args, stream, fp64_value):
     for c, sc in enumerate(cur):
         for z in range(0, L, 4):
             gaps.append(tn.tnmc_slice_logq(lat, c, z, sc[z]) - tn.tnmc_nn_slice_logq(lat, net, c, z, sc[z]))
+    leg = None
+    if tau_on:
+        leg = tau_leg(tn, lat, lambda k, off: tn.tnmc_nn_sweep([lat], net, k, sweep_offset=sw + off, record=True,
+                                                               stream=stream),
+                      "learned", args.tau_seconds, args.tau_sweeps)
+        indep = (leg["indep_samples_per_s"], leg["tau_int_q"])
     return {
         "form": "masked-conv autoregressive proposal (6 layers, 32 channels, FP32) with exact log q, "
                 "MH per main text Eq. 1, TN fallback frozen after a calibration window (the learned-only sweeps; acceptance < 5%)",
@@ -319,7 +341,8 @@ def learned_form(tn, lat, group, args, stream, fp64_value):
         "acceptance": st["accepted"] / max(1, st["proposed"]),
         "acceptance_learned": float(acc.sum()) / max(1, nn_prop),
         "learned_updates_per_step": nn_prop / args.steps, "fallback_layers": n_fb,
-        "tau_int_q": indep[1], "indep_samples_per_s": indep[0],
+        "tau_int_q": indep[1], "indep_samples_per_s": indep[0], "tau_leg": leg,
+        "indep_vs_fp64": (indep[0] / fp64_indep) if (indep[0] and fp64_indep) else None,
         "learned_only": {"value": args.steps * per_sweep / secs_nn, "unit": "slice updates/s",
                          "ms_per_step": secs_nn / args.steps * 1e3,
                          "acceptance": st_nn["accepted"] / max(1, st_nn["proposed"]),
@@ -337,6 +360,53 @@ def learned_form(tn, lat, group, args, stream, fp64_value):
     }
 
 
+def copy_probe() -> None:
+    """A plain device-to-device copy of 64 MiB, three times: profiled with
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, it scales those counters to bytes
+    (each dispatch reads and writes exactly 64 MiB)."""
+    import torch
+    n = 64 * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied", a.numel() * 8, "bytes x 3", flush=True)
+
+
+def tau_leg(tn, lat, run, label: str, budget_s: float, max_sweeps: int, chunk: int = 100):
+    """Runs the form's own sweeps (run(k, offset) does k recorded sweeps) for
+    about budget_s seconds (at most max_sweeps), then estimates tau_int of the
+    replica overlap q (SM S3; Sokal window) from the recorded series and the
+    independent samples per second n_pairs / (tau * t_s) (main text: t_int =
+    tau_int * t_s)."""
+    import torch
+    from paper_2509_23945_amd import analysis
+    tn.tnmc_timeseries_reset(lat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < max_sweeps:
+        k = min(chunk, max_sweeps - done)
+        run(k, done)
+        done += k
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if done % 500 == 0 or el > budget_s:
+            print(f"[bench] tau leg ({label}): {done} sweeps, {el:.0f} s", file=sys.stderr, flush=True)
+        if el > budget_s:
+            break
+    secs = time.perf_counter() - t0
+    _, _, q = tn.tnmc_timeseries(lat)
+    out = {"sweeps": done, "seconds": secs, "ms_per_sweep": secs / max(1, done) * 1e3, "tau_int_q": None,
+           "window": None, "sweeps_per_tau": None, "tau_converged": False, "indep_samples_per_s": None}
+    if q.shape[0] >= 20 and q.shape[1] > 0:
+        tau, W = analysis.tau_int(q.T)
+        out.update(tau_int_q=tau, window=W, sweeps_per_tau=q.shape[0] / tau, tau_converged=q.shape[0] >= 50 * tau,
+                   indep_samples_per_s=q.shape[1] / (tau * secs / done))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,11 +416,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true", help="skip the FP32-environment form")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal form")
-    ap.add_argument("--learned-data-sweeps", type=int, default=48,
+    ap.add_argument("--learned-data-sweeps", type=int, default=98,
                     help="TN sweeps whose layers form the training set of the learned proposal")
     ap.add_argument("--learned-epochs", type=int, default=5)
     ap.add_argument("--learned-lr", type=float, default=2e-3)
+    ap.add_argument("--tau-sweeps", type=int, default=1500,
+                    help="sweeps per form of the tau_int leg (the same for every form; 0 skips the leg)")
+    ap.add_argument("--tau-seconds", type=float, default=120.0,
+                    help="wall-time cap per form of the tau_int leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 64 MiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
               "design only: chains are independent, so each GPU would run its own share of them", file=sys.stderr)
@@ -362,7 +441,10 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
-    lats, groups = make_lattices(args.workload, record_capacity=args.steps)
+    tau_on = args.tau_sweeps > 0
+    cap = max(args.steps, args.tau_sweeps if tau_on else 0)
+    lats, groups = make_lattices(args.workload, record_capacity=cap)
+    tau_on = tau_on and len(lats) == 1 and groups[0]["pairs"] is not None
     cfg = WORKLOADS[args.workload]
     n_chains = sum(len(g["inst"]) for g in groups)
     updates_per_sweep = sum(len(g["inst"]) * g["L"] for g in groups)
@@ -395,12 +477,17 @@ def main():
                 "flops_per_task_fixed_chi": flops_model,
                 "tasks_per_launch": args.steps * tasks_per_sweep / launches}
 
-    indep = None
-    tau = None
-    if len(lats) == 1:
-        _, _, q = tn.tnmc_timeseries(lats[0])
-        if q.shape[0] >= 100 and q.shape[1] > 0:
-            indep, tau, _ = analysis.independent_samples_per_second(q, secs / args.steps)
+    next_sweep = args.warmup + args.steps   # sweep counters are never reused on a chain
+    tau_fp64 = None
+    if tau_on:
+        # the FP64 chains go on: tau_int of the overlap and independent samples/s
+        base = next_sweep
+        tau_fp64 = tau_leg(tn, lats[0], lambda k, off: tn.tnmc_sweep(lats, k, sweep_offset=base + off, record=True,
+                                                                      stream=stream),
+                           "FP64", args.tau_seconds, args.tau_sweeps)
+        next_sweep += tau_fp64["sweeps"]
+    indep = tau_fp64["indep_samples_per_s"] if tau_fp64 else None
+    tau = tau_fp64["tau_int_q"] if tau_fp64 else None
 
     if cfg.get("potts"):
         desc = (f"3D 3-state Potts {cfg['L']}^3 open BC, J=1, beta={cfg['beta']}, chi={cfg['chi']}, "
@@ -438,6 +525,7 @@ def main():
         "sample_ms_per_step": st["sample_ms"] / args.steps,
         "tau_int_q": tau,
         "indep_samples_per_s": indep,
+        "tau_leg": tau_fp64,
         "roofline": roofline,
     }
     # the layout autotuner's choice for the headline class (timed on the first sweep)
@@ -450,7 +538,7 @@ def main():
         # the reduced-precision form on the same inputs: FP32 environments, rank
         # cut-off at FP32 resolution, FP64 factorisations, log q and MH
         print(f"[bench] reduced-precision form: timing {args.steps} sweeps", file=sys.stderr, flush=True)
-        lats32, _ = make_lattices(args.workload, record_capacity=args.steps, precision=tn.TNMC_FP32)
+        lats32, _ = make_lattices(args.workload, record_capacity=cap, precision=tn.TNMC_FP32)
         secs32, st32 = time_form(tn, lats32, args.warmup, args.steps, stream)
         v32 = args.steps * updates_per_sweep / secs32
         out["reduced_precision"] = {
@@ -461,14 +549,20 @@ def main():
             "numeric_faults": st32["numeric_faults"],
             "contract_ms_per_step": st32["contract_ms"] / args.steps,
             "sample_ms_per_step": st32["sample_ms"] / args.steps}
-        if len(lats32) == 1:
-            i32, t32 = indep_of(lats32[0], secs32 / args.steps)
-            out["reduced_precision"]["tau_int_q"] = t32
-            out["reduced_precision"]["indep_samples_per_s"] = i32
+        if tau_on:
+            base32 = args.warmup + args.steps
+            leg = tau_leg(tn, lats32[0], lambda k, off: tn.tnmc_sweep(lats32, k, sweep_offset=base32 + off,
+                                                                       record=True, stream=stream),
+                          "reduced", args.tau_seconds, args.tau_sweeps)
+            out["reduced_precision"].update(tau_int_q=leg["tau_int_q"], indep_samples_per_s=leg["indep_samples_per_s"],
+                                            tau_leg=leg)
+            if indep and leg["indep_samples_per_s"]:
+                out["reduced_precision"]["indep_vs_fp64"] = leg["indep_samples_per_s"] / indep
         for lat in lats32:
             tn.tnmc_lattice_free(lat)
     if not args.no_learned and len(lats) == 1 and groups[0].get("d", 2) == 2:
-        out["learned_proposal"] = learned_form(tn, lats[0], groups[0], args, stream, value)
+        out["learned_proposal"] = learned_form(tn, lats[0], groups[0], args, stream, value, next_sweep,
+                                               tau_on, indep)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, per_worker=1 if cfg.get("potts") else 6)
