@@ -147,10 +147,12 @@ def make_lattices(name: str, record_capacity: int = 0, precision: int = 0):
 
 
 def time_form(tn, lats, warmup: int, steps: int, stream):
-    """Warm up, then time `steps` sweeps of every lattice; returns (seconds, stats)."""
+    """Warm up, tune the contraction on the warmed-up states (untimed), then
+    time `steps` sweeps of every lattice; returns (seconds, stats)."""
     import torch
     if warmup:
         tn.tnmc_sweep(lats, warmup, sweep_offset=0, stream=stream)
+    tn.tnmc_autotune_now(lats, stream=stream)
     for lat in lats:
         tn.tnmc_timeseries_reset(lat)
     torch.cuda.synchronize()
@@ -360,6 +362,19 @@ def learned_form(tn, lat, group, args, stream, fp64_value, sweep0, tau_on, fp64_
     }
 
 
+def autotune_report(tn, groups, precision):
+    """The contraction autotuner's choice per (d, chi) class of the workload
+    (product engine and tile layout) with the median trial durations."""
+    rep = []
+    for d_, c_ in sorted({(g.get("d", 2), g["chi"]) for g in groups}):
+        lay, eng, ms = tn.tnmc_autotune_choice(d_, c_, precision)
+        if eng >= 0:
+            rep.append({"d": d_, "chi": c_, "engine": "mfma" if eng else "valu", "layout": "full" if lay else "compact",
+                        "trial_ms": {"valu_compact": ms[0], "valu_full": ms[1], "mfma_compact": ms[2],
+                                     "mfma_full": ms[3]}})
+    return rep
+
+
 def copy_probe() -> None:
     """A plain device-to-device copy of 64 MiB, three times: profiled with
     rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, it scales those counters to bytes
@@ -424,6 +439,8 @@ def main():
                     help="sweeps per form of the tau_int leg (the same for every form; 0 skips the leg)")
     ap.add_argument("--tau-seconds", type=float, default=120.0,
                     help="wall-time cap per form of the tau_int leg")
+    ap.add_argument("--engine", choices=("auto", "valu", "mfma"), default="auto",
+                    help="contraction products: chosen by the autotuner (default) or pinned")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 64 MiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -441,6 +458,8 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
+    if args.engine != "auto":
+        tn.tnmc_autotune_pin(-1, 1 if args.engine == "mfma" else 0)
     tau_on = args.tau_sweeps > 0
     cap = max(args.steps, args.tau_sweeps if tau_on else 0)
     lats, groups = make_lattices(args.workload, record_capacity=cap)
@@ -528,12 +547,7 @@ def main():
         "tau_leg": tau_fp64,
         "roofline": roofline,
     }
-    # the layout autotuner's choice for the headline class (timed on the first sweep)
-    for d_, c_ in sorted({(g.get("d", 2), g["chi"]) for g in groups}):
-        lay, ms_c, ms_f = tn.tnmc_layout_choice(d_, c_)
-        if lay >= 0:
-            out.setdefault("autotune", []).append({"d": d_, "chi": c_, "layout": "full" if lay else "compact",
-                                                   "trial_ms_compact": ms_c, "trial_ms_full": ms_f})
+    out["autotune"] = autotune_report(tn, groups, tn.TNMC_FP64)
     if not args.no_reduced:
         # the reduced-precision form on the same inputs: FP32 environments, rank
         # cut-off at FP32 resolution, FP64 factorisations, log q and MH
@@ -542,7 +556,9 @@ def main():
         secs32, st32 = time_form(tn, lats32, args.warmup, args.steps, stream)
         v32 = args.steps * updates_per_sweep / secs32
         out["reduced_precision"] = {
-            "form": "environments stored in FP32, rank cut-off 1e-6; factorisations, log q, dE, MH in FP64",
+            "form": "environments stored in FP32, rank cut-off 1e-6; products M, AT, C, Y on the engine the autotuner "
+                    "picks (FP32 MFMA operands and accumulation, or FP64 VALU); factorisations, log q, dE, MH in FP64",
+            "autotune": autotune_report(tn, groups, tn.TNMC_FP32),
             "value": v32, "unit": "slice updates/s", "ms_per_step": secs32 / args.steps * 1e3,
             "vs_fp64": v32 / value, "acceptance": st32["accepted"] / max(1, st32["proposed"]),
             "tau_int_q": None, "indep_samples_per_s": None,

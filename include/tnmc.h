@@ -210,7 +210,7 @@ tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes);
  * configurations that use the compact two-per-CU contraction layout through
  * its overflow path (a second launch with the full tile layout in LDS, one
  * task per CU), so that path can be checked against the oracle; value 1 = on,
- * 0 = off (default).  what = 1: the layout autotuner (value 1 = on, the
+ * 0 = off (default).  what = 1: the contraction autotuner (value 1 = on, the
  * default; 0 = off, which also drops its choices).  what = 2: two
  * learned-proposal tasks per workgroup in tnmc_nn_sweep launches that allow
  * it (value 1 = on, the default; 0 = off).  Results agree within the parity
@@ -305,17 +305,45 @@ tnmc_status tnmc_nn_get_fallback(tnmc_lattice* lat, int8_t* flags);
  * exact MH kernel. */
 tnmc_status tnmc_nn_calibrate_fallback(tnmc_lattice* lat, double threshold, int32_t* n_fallback);
 
-/* Layout autotuner (batching): the (d, chi) classes that can run either the
- * compact contraction layout (two tasks per CU, with a full-layout redo of the
- * tasks whose rank outgrows it) or the full layout (one task per CU) are timed
- * once with each, on the tasks of the first tnmc_sweep that contains them,
- * and the faster is kept for the process (the two agree within the FP64
- * parity bar, and the chains they produce in the tests are identical).
- * *layout receives -1 (not tuned yet, or no choice), 0 (compact) or 1 (full);
- * ms_compact / ms_full (may be NULL) the trial durations of the contraction
- * launch. */
+/* Autotuner of the contraction (batching).  A launch group of slice tasks is
+ * keyed by (d, chi bucket, precision, row length, row count, number of
+ * tasks); its candidates are the engine of the products M, AT, C and Y
+ * (0: FP64 on the vector ALU; 1: the matrix cores, V_MFMA_F64_16X16X4_F64
+ * for FP64 environments, V_MFMA_F32_16X16X4_F32 with FP32 operands and
+ * accumulation for FP32 ones) and, where the class has the compact tile layout
+ * (two tasks per CU, with a full-layout redo of the tasks whose rank outgrows
+ * it), the layout (0: compact, 1: full, one task per CU).  Before a group's
+ * second sweep each candidate's contraction of that sweep is timed three
+ * times with HIP events and the smallest median is kept for the process.
+ * All candidates are correct contractions and agree within the parity bar of
+ * the storage precision, not bit for bit: pin them (tnmc_autotune_pin) for
+ * runs that must reproduce bit for bit across processes.  Single-task calls
+ * (tnmc_slice_propose, tnmc_slice_logq and their learned / static variants)
+ * use the pins, else engine 0 and the compact layout.
+ *
+ * tnmc_layout_choice: *layout receives -1 (no tuned class of this (d, chi,
+ * precision), or no layout choice) or the chosen layout; ms_compact / ms_full
+ * (may be NULL) the median trial durations of the two layouts with the chosen
+ * engine (-1 if not tried).
+ * tnmc_autotune_choice: the most recently tuned class of this (d, chi,
+ * precision): *layout and *engine (-1 if none); ms (may be NULL, 4 doubles)
+ * the median trial durations [engine 0 compact, engine 0 full, engine 1
+ * compact, engine 1 full] (-1 where not a candidate).
+ * tnmc_autotune_pin: fixes the layout and / or the engine for every later
+ * launch (-1 leaves that dimension to the autotuner); drops earlier choices.
+ * TNMC_ERR_ARG for values outside -1..1. */
 tnmc_status tnmc_layout_choice(int32_t d, int32_t chi, int32_t precision, int32_t* layout, double* ms_compact,
                                double* ms_full);
+tnmc_status tnmc_autotune_choice(int32_t d, int32_t chi, int32_t precision, int32_t* layout, int32_t* engine,
+                                 double* ms);
+tnmc_status tnmc_autotune_pin(int32_t layout, int32_t engine);
+/* Runs the trials now, on the current states of the chains of lats (the
+ * tasks of one sweep of them, both parities), for every launch group, and
+ * replaces earlier choices for those groups; the chains are not changed.  A
+ * caller that warms its chains up first can tune on representative states
+ * (the automatic trial at a group's second sweep may still see the larger
+ * bond ranks of a random start).  Synchronises hip_stream. */
+tnmc_status tnmc_autotune_now(tnmc_lattice* const* lats, int32_t n_lats, void* hip_stream);
 
 const char* tnmc_status_string(tnmc_status s);
 /* Text of the last failed HIP call (thread-local). */

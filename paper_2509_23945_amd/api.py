@@ -37,7 +37,8 @@ __all__ = [
     "tnmc_nn_train", "tnmc_nn_dataset", "tnmc_nn_slice_propose", "tnmc_nn_slice_logq", "tnmc_nn_sweep",
     "tnmc_nn_counts", "tnmc_nn_counts_reset", "tnmc_nn_set_fallback", "tnmc_nn_get_fallback",
     "tnmc_nn_calibrate_fallback", "tnmc_get_couplings", "tnmc_checkpoint_save", "tnmc_checkpoint_load",
-    "tnmc_sweep_direction", "tnmc_layout_choice", "tnmc_slice_propose_static",
+    "tnmc_sweep_direction", "tnmc_layout_choice", "tnmc_slice_propose_static", "tnmc_autotune_choice",
+    "tnmc_autotune_pin", "tnmc_autotune_now",
 ]
 TNMC_NN_PARAMS = 38753
 
@@ -148,6 +149,9 @@ def load():
         "tnmc_checkpoint_load": [vp, ctypes.c_char_p, P(u64)],
         "tnmc_sweep_direction": [P(vp), i32, i32, i32, u64, i32, i32, P(_Stats), vp],
         "tnmc_layout_choice": [i32, i32, i32, P(i32), P(dbl), P(dbl)],
+        "tnmc_autotune_choice": [i32, i32, i32, P(i32), P(i32), P(dbl)],
+        "tnmc_autotune_pin": [i32, i32],
+        "tnmc_autotune_now": [P(vp), i32, vp],
     }
     for name, sig in nn_sigs.items():
         getattr(lib, name).argtypes = sig
@@ -510,3 +514,24 @@ def tnmc_layout_choice(d: int, chi: int, precision: int = TNMC_FP64):
     _check(load().tnmc_layout_choice(d, chi, precision, ctypes.byref(lay), ctypes.byref(a), ctypes.byref(b)),
            "tnmc_layout_choice")
     return lay.value, a.value, b.value
+
+
+def tnmc_autotune_choice(d: int, chi: int, precision: int = TNMC_FP64):
+    """Returns (layout, engine, ms[4]) of the most recently tuned class of (d, chi, precision):
+    -1 where not tuned; ms = median trial ms [VALU compact, VALU full, MFMA compact, MFMA full], -1 if not tried."""
+    lay, eng = ctypes.c_int32(), ctypes.c_int32()
+    ms = (ctypes.c_double * 4)()
+    _check(load().tnmc_autotune_choice(d, chi, precision, ctypes.byref(lay), ctypes.byref(eng), ms),
+           "tnmc_autotune_choice")
+    return lay.value, eng.value, list(ms)
+
+
+def tnmc_autotune_pin(layout: int = -1, engine: int = -1) -> None:
+    """Fix the contraction layout (0 compact, 1 full) and / or product engine (0 VALU, 1 MFMA); -1 = tuned."""
+    _check(load().tnmc_autotune_pin(layout, engine), "tnmc_autotune_pin")
+
+
+def tnmc_autotune_now(lats, stream=None) -> None:
+    """Time the contraction candidates now on the chains' current states (replaces earlier choices)."""
+    arr, n = _handles(lats)
+    _check(load().tnmc_autotune_now(arr, n, stream), "tnmc_autotune_now")

@@ -12,7 +12,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtnmc.so")
-SOURCES = ["contract.hip", "contract_f32.hip", "sample.hip", "nn.hip", "host.cpp"]
+SOURCES = ["contract.hip", "contract_f32.hip", "contract_mf.hip", "contract_f32_mf.hip", "sample.hip", "nn.hip",
+           "host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

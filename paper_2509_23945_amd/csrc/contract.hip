@@ -1,41 +1,35 @@
 // Boundary-MPS contraction (SM S1.B): the kernels are in contract_kernel.h;
-// this unit instantiates them for FP64 environments and holds the dispatch.
+// this unit instantiates them for FP64 environments with the products on the
+// vector ALU, and holds the dispatch over storage precision and product engine
+// (the other instantiations are in units of their own, which compile in
+// parallel).
 
 #include "contract_kernel.h"
 
 namespace tnmc {
 
 int g_force_retry = 0;
-int g_layout_full[2][2] = {{0, 0}, {0, 0}};
 
 void set_force_retry(int on) { g_force_retry = on; }
 
-// Whether a (d, chi_max) class runs the compact layout (two tasks per CU)
-// by default: the same test as launch_contract_t's.
-template <int DP, int CHIM>
-constexpr bool has_compact() {
-  return sizeof(double) * Layout<DP, CHIM, false>::total > kHalfLds &&
-         sizeof(double) * Layout<DP, CHIM, true>::total <= kHalfLds;
-}
 bool contract_has_compact(int d, int chi_max) {
   if (d == 2) {
     switch (chi_max) {
-      case 4: return has_compact<2, 4>();
-      case 8: return has_compact<2, 8>();
-      case 16: return has_compact<2, 16>();
-      case 32: return has_compact<2, 32>();
+      case 4: return layout_has_compact<2, 4>();
+      case 8: return layout_has_compact<2, 8>();
+      case 16: return layout_has_compact<2, 16>();
+      case 32: return layout_has_compact<2, 32>();
     }
   } else if (d == 3) {
     switch (chi_max) {
-      case 4: return has_compact<3, 4>();
-      case 8: return has_compact<3, 8>();
-      case 16: return has_compact<3, 16>();
-      case 32: return has_compact<3, 32>();
+      case 4: return layout_has_compact<3, 4>();
+      case 8: return layout_has_compact<3, 8>();
+      case 16: return layout_has_compact<3, 16>();
+      case 32: return layout_has_compact<3, 32>();
     }
   }
   return false;
 }
-void set_layout_full(int d, int precision, int full) { g_layout_full[d == 3][precision == kPrecF32] = full ? 1 : 0; }
 
 // Bytes of the full tile layout: the LDS of a full-layout workgroup, and the
 // per-task global scratch of the retry path (and of d = 3, chi = 32, whose
@@ -73,9 +67,17 @@ int chi_bucket(int chi) {
   return 0;
 }
 
-hipError_t launch_contract(const TaskDesc* tasks, int n, int d, int chi_max, int precision, hipStream_t s) {
-  if (precision == kPrecF32) return launch_contract_f32(tasks, n, d, chi_max, s);
-  return launch_contract_et<double>(tasks, n, d, chi_max, s);
+hipError_t launch_contract_f64(const TaskDesc* tasks, int n, int d, int chi_max, int full, hipStream_t s) {
+  return launch_contract_et<double, false>(tasks, n, d, chi_max, full, s);
+}
+
+hipError_t launch_contract(const TaskDesc* tasks, int n, int d, int chi_max, int precision, ContractCfg cfg,
+                           hipStream_t s) {
+  if (precision == kPrecF32)
+    return cfg.mfma ? launch_contract_f32_mf(tasks, n, d, chi_max, cfg.full, s)
+                    : launch_contract_f32(tasks, n, d, chi_max, cfg.full, s);
+  return cfg.mfma ? launch_contract_f64_mf(tasks, n, d, chi_max, cfg.full, s)
+                  : launch_contract_f64(tasks, n, d, chi_max, cfg.full, s);
 }
 
 }  // namespace tnmc

@@ -1,13 +1,13 @@
-// Boundary-MPS contraction with environments stored in FP32 (the
-// reduced-precision form): the kernels of contract_kernel.h instantiated for
-// float storage, in a unit of their own so that the two forms compile in parallel.
+// Boundary-MPS contraction: the kernels of contract_kernel.h instantiated
+// with environments stored in FP32 (the reduced-precision form) and the
+// products on the vector ALU, in a unit of their own so that the instantiations compile in parallel.
 
 #include "contract_kernel.h"
 
 namespace tnmc {
 
-hipError_t launch_contract_f32(const TaskDesc* tasks, int n, int d, int chi_max, hipStream_t s) {
-  return launch_contract_et<float>(tasks, n, d, chi_max, s);
+hipError_t launch_contract_f32(const TaskDesc* tasks, int n, int d, int chi_max, int full, hipStream_t s) {
+  return launch_contract_et<float, false>(tasks, n, d, chi_max, full, s);
 }
 
 }  // namespace tnmc

@@ -29,10 +29,6 @@
 namespace tnmc {
 
 extern int g_force_retry;   // test hook: every compact-layout task takes the retry path
-// Layout chosen by the host's autotuner for the (d, chi_max) classes that
-// have a compact layout: g_layout_full[d == 3][FP32 storage] = 1 runs them
-// with the full layout instead (equal within the FP64 parity bar).
-extern int g_layout_full[2][2];
 
 namespace {
 
@@ -69,6 +65,82 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+}
+
+// Matrix-core tiles of the contraction's products.  One wavefront computes a
+// 16 x 16 tile of A B with K in steps of 4 (V_MFMA_F64_16X16X4_F64 on the
+// FP64 path, V_MFMA_F32_16X16X4_F32 with FP32 operands and accumulation on the
+// reduced-precision one).  Both take A[row l % 16][k0 + l / 16] and
+// B[k0 + l / 16][col l % 16] from lane l; element r of lane l's result is
+// row (l / 16) + 4 r (FP64) or 4 (l / 16) + r (FP32), column l % 16.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+template <typename CT>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  using V = mfma_d4;
+  static __device__ __forceinline__ V zero() { return V{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+  using V = mfma_f4;
+  static __device__ __forceinline__ V zero() { return V{0.0f, 0.0f, 0.0f, 0.0f}; }
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// NB products at once for this lane's (row, column) of a tile: acc[j] = sum
+// over k < K of fa(k, j) fb(k, j), j < NB (K <= KMAX, the same on every
+// lane).  fa / fb return this lane's A / B operand for index k (its row /
+// column are fixed by the caller, which also zeroes rows or columns outside
+// the tile's extent); they are called for every lane with k < K, so a lane
+// past K reads index K - 1 and its value is replaced by zero.  Loads are
+// unconditional and the trip count is a compile-time bound with a uniform exit,
+// so no lane-divergent branch is needed.  Each product runs as two MFMA chains
+// (even and odd steps of 4 along K) interleaved with the other products' chains.
+template <typename CT, int KMAX, int NB, typename FA, typename FB>
+__device__ __forceinline__ void mfma_multi(typename Mfma<CT>::V (&acc)[NB], int K, int lane, FA fa, FB fb) {
+  constexpr int S = (KMAX + 3) / 4;
+  const int kq = lane >> 4;
+  typename Mfma<CT>::V odd[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    acc[j] = Mfma<CT>::zero();
+    odd[j] = Mfma<CT>::zero();
+  }
+#pragma unroll
+  for (int s = 0; s < S; s += 2) {
+    if (4 * s >= K) continue;   // uniform: the rest of the steps are past K
+    CT a[2][NB], b[2][NB];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int kk = 4 * (s + h) + kq;
+      const bool ok = kk < K;
+      const int kc = ok ? kk : K - 1;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const CT va = (CT)fa(kc, j);
+        const CT vb = (CT)fb(kc, j);
+        a[h][j] = ok ? va : CT(0);
+        b[h][j] = ok ? vb : CT(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = Mfma<CT>::mma(a[0][j], b[0][j], acc[j]);
+    if (4 * (s + 1) < K) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) odd[j] = Mfma<CT>::mma(a[1][j], b[1][j], odd[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] += odd[j];
 }
 
 // Householder QR of the m x n row-major matrix M (leading dim ld) in LDS, R
@@ -746,7 +818,10 @@ __device__ inline double svd_count(double m, double n) {
 // C[i][r*k + k'] = sum_b G[r][b] sum_al R~[i][al*d+b] AT[al][b][k'] with
 // R~[i][al*d+b] = sum_a R[i][al*d+a] H[a][b], for i < rR (rows of R, row
 // stride LD) and k' < k: written transposed to Ct (leading dimension CTLD)
-// when to_ct, and as C (leading dimension LDC) when to_c.
+// when to_ct, and as C (leading dimension LDC) when to_c.  On the matrix
+// cores: for each b the rR x k product of R (columns kk2 = al*d + a) with
+// H[a][b] AT[al][b][k'], K = cl*d, in 16 x 16 tiles spread over the NW
+// wavefronts; the d products of a tile are combined with G in registers.
 template <int DP, int CHIM, int NTK, int LD, int CTLD, int LDC>
 __device__ __attribute__((always_inline)) void form_c(const double* sR, const double* sAT, const double* Hx,
                                                       const double* Gx, double* sCt, double* sC, int rR, int k,
@@ -794,6 +869,47 @@ __device__ __attribute__((always_inline)) void form_c(const double* sR, const do
       for (int b = 0; b < DP; ++b) c = fma(Gx[r * DP + b], z[b], c);
       if (to_ct) sCt[(r * k + kk) * CTLD + i] = c;
       if (to_c) sC[i * LDC + r * k + kk] = c;
+    }
+  }
+}
+
+template <typename CT, int DP, int CHIM, int NW, int LD, int RROWS, int CTLD, int LDC>
+__device__ __attribute__((always_inline)) void form_c_mfma(const double* sR, const double* sAT, const double* Hx,
+                                                           const double* Gx, double* sCt, double* sC, int rR, int k,
+                                                           int cl, int lane, int wv, bool to_ct, bool to_c) {
+  const int K = cl * DP;
+  const int tj_n = (k + 15) >> 4, tij = ((rR + 15) >> 4) * tj_n;
+  for (int tt = wv; tt < tij; tt += NW) {
+    const int ti = tt / tj_n, tj = tt - ti * tj_n;
+    const int i = ti * 16 + (lane & 15), kk = tj * 16 + (lane & 15);
+    const bool ri = i < rR, ck = kk < k;
+    const double* Ri = sR + min(i, RROWS - 1) * LD;
+    const double* ATk = sAT + min(kk, CHIM - 1);
+    typename Mfma<CT>::V acc[DP];
+    mfma_multi<CT, DP * CHIM, DP>(
+        acc, K, lane,
+        [&](int kk2, int) {
+          const double v = Ri[kk2];
+          return ri ? v : 0.0;
+        },
+        [&](int kk2, int b) {
+          const int al = kk2 / DP, a = kk2 - al * DP;
+          const double v = Hx[a * DP + b] * ATk[(al * DP + b) * CHIM];
+          return ck ? v : 0.0;
+        });
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = ti * 16 + Mfma<CT>::row(lane, q);
+      if (row < rR && ck) {
+#pragma unroll
+        for (int r = 0; r < DP; ++r) {
+          double c = 0.0;
+#pragma unroll
+          for (int b = 0; b < DP; ++b) c = fma(Gx[r * DP + b], (double)acc[b][q], c);
+          if (to_ct) sCt[(r * k + kk) * CTLD + row] = c;
+          if (to_c) sC[row * LDC + r * k + kk] = c;
+        }
+      }
     }
   }
 }
@@ -863,8 +979,11 @@ struct Layout {
 // GM: the tiles live in the task's global scratch instead of LDS (for the
 // full layouts that exceed a CU's LDS).
 // ET: storage type of the environments (double, or float for the
-// reduced-precision form); all arithmetic is FP64.
-template <typename ET, int DP, int CHIM, bool CMP, bool GM = false>
+// reduced-precision form).  The factorisations are FP64; the products M, AT,
+// C and Y run on the vector ALU in FP64 (MF = false) or on the matrix cores
+// (MF = true) in FP64 (ET = double) or with FP32 operands and accumulation
+// (ET = float).
+template <typename ET, int DP, int CHIM, bool CMP, bool GM = false, bool MF = false>
 __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(const TaskDesc* __restrict__ tasks,
                                                                             int retry) {
   using Lay = Layout<DP, CHIM, CMP>;
@@ -875,6 +994,8 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
   extern __shared__ __align__(16) double lds[];
   const TaskDesc& t = tasks[blockIdx.x];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = NTK / 64;   // wavefronts of the workgroup
   acquire_device();
   if (retry < 0) {   // test hook: leave every task to the retry launch
     if (tid == 0) *t.status = 8 | ((t.Ly - 1) << 8);
@@ -954,40 +1075,78 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         const double* Hx = sH + x * DP * DP;
         const double* Gx = sG + x * DP * DP;
         {
-          const int nb = DP * cr;
-          const float inv_nb = 1.0f / (float)nb, inv_cr = 1.0f / (float)cr;
-          for (int w = tid; w < rR * nb; w += NTK) {
-            const int i = fquot(w, inv_nb);
-            const int rem = w - i * nb;
-            const int b = fquot(rem, inv_cr), be = rem - b * cr;
-            double hb[DP];
-#pragma unroll
-            for (int a = 0; a < DP; ++a) hb[a] = Hx[a * DP + b];
-            double s = 0.0;
-            const double* Ri = sR + i * LD;
-            const double* Ab = sA + b * CHIM * CHIM + be;
-            for (int al0 = 0; al0 < cl; al0 += 4) {
-              // four values of al per group, loads first (indices clamped into the tiles)
-              double rv[4][DP], av[4];
+          if constexpr (MF) {
+            // matrix cores: for each b, the rR x cr product of R (rows i, columns
+            // kk = al*na + a) with B_b[kk][be] = H[a][b] A_b[al][be], K = cl*na;
+            // 16 x 16 tiles spread over the wavefronts, the d products of a
+            // tile computed together
+            const int K = cl * na;
+            const int tj_n = (cr + 15) >> 4, tij = ((rR + 15) >> 4) * tj_n;
+            for (int tt = wv; tt < tij; tt += NW) {
+              const int ti = tt / tj_n, tj = tt - ti * tj_n;
+              const int i = ti * 16 + (lane & 15), be = tj * 16 + (lane & 15);
+              const double* Ri = sR + min(i, Lay::RROWS - 1) * LD;
+              const double* Ab = sA + min(be, CHIM - 1);
+              const bool ri = i < rR, cb = be < cr;
+              typename Mfma<ET>::V acc[DP];
+              mfma_multi<ET, Lay::D, DP>(
+                  acc, K, lane,
+                  [&](int kk, int) {
+                    const double v = Ri[kk];
+                    return ri ? v : 0.0;
+                  },
+                  [&](int kk, int b) {
+                    const int al = (na == 1) ? kk : kk / DP, a = kk - al * na;
+                    const double v = Hx[a * DP + b] * Ab[(b * CHIM + al) * CHIM];
+                    return cb ? v : 0.0;
+                  });
 #pragma unroll
               for (int q = 0; q < 4; ++q) {
-                const int al = (al0 + q < CHIM) ? al0 + q : CHIM - 1;
+                const int row = ti * 16 + Mfma<ET>::row(lane, q);
+                if (row < rR && cb) {
 #pragma unroll
-                for (int a = 0; a < DP; ++a) rv[q][a] = (a < na) ? Ri[al * na + a] : 0.0;
-                av[q] = Ab[al * CHIM];
-              }
+                  for (int r = 0; r < DP; ++r)
 #pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                if (al0 + q < cl) {
-                  double rt = 0.0;
-#pragma unroll
-                  for (int a = 0; a < DP; ++a) rt = fma(rv[q][a], hb[a], rt);
-                  s = fma(rt, av[q], s);
+                    for (int b = 0; b < DP; ++b) sM[(row * DP + r) * LD + be * DP + b] = Gx[r * DP + b] * (double)acc[b][q];
                 }
               }
             }
+          } else {
+            const int nb = DP * cr;
+            const float inv_nb = 1.0f / (float)nb, inv_cr = 1.0f / (float)cr;
+            for (int w = tid; w < rR * nb; w += NTK) {
+              const int i = fquot(w, inv_nb);
+              const int rem = w - i * nb;
+              const int b = fquot(rem, inv_cr), be = rem - b * cr;
+              double hb[DP];
 #pragma unroll
-            for (int r = 0; r < DP; ++r) sM[(i * DP + r) * LD + be * DP + b] = Gx[r * DP + b] * s;
+              for (int a = 0; a < DP; ++a) hb[a] = Hx[a * DP + b];
+              double s = 0.0;
+              const double* Ri = sR + i * LD;
+              const double* Ab = sA + b * CHIM * CHIM + be;
+              for (int al0 = 0; al0 < cl; al0 += 4) {
+                // four values of al per group, loads first (indices clamped into the tiles)
+                double rv[4][DP], av[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  const int al = (al0 + q < CHIM) ? al0 + q : CHIM - 1;
+#pragma unroll
+                  for (int a = 0; a < DP; ++a) rv[q][a] = (a < na) ? Ri[al * na + a] : 0.0;
+                  av[q] = Ab[al * CHIM];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                  if (al0 + q < cl) {
+                    double rt = 0.0;
+#pragma unroll
+                    for (int a = 0; a < DP; ++a) rt = fma(rv[q][a], hb[a], rt);
+                    s = fma(rt, av[q], s);
+                  }
+                }
+              }
+#pragma unroll
+              for (int r = 0; r < DP; ++r) sM[(i * DP + r) * LD + be * DP + b] = Gx[r * DP + b] * s;
+            }
           }
         }
         __syncthreads();
@@ -1111,8 +1270,52 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
             for (int a = 0; a < DP; ++a) pr[q][a] = gR[(size_t)i * D + al * DP + a];
           }
         }
-        // AT[al][b][k'] = sum_be A[b][al][be] T[be*d + b][k']  (b summed later at the edge)
-        {
+        // AT[al][b][k'] = sum_be A[b][al][be] T[be*d + b][k']  (b summed later at the edge):
+        // for each b a cl x k product with K = cr (on the matrix cores with MF)
+        if (MF && !last) {
+          const int tj_n = (k + 15) >> 4, tij = ((cl + 15) >> 4) * tj_n;
+          for (int tt = wv; tt < tij; tt += NW) {
+            const int ti = tt / tj_n, tj = tt - ti * tj_n;
+            const int al = ti * 16 + (lane & 15), kk = tj * 16 + (lane & 15);
+            const bool ra = al < cl, ck = kk < k;
+            const int alc = min(al, CHIM - 1), kkc = min(kk, CHIM - 1);
+            const double* Tk = sT + kkc;
+            typename Mfma<ET>::V acc[DP];
+            if constexpr (CMP) {
+              const gptr<const ET> Arow = envY + (size_t)x * SITE + alc * CHIM;
+              mfma_multi<ET, CHIM, DP>(
+                  acc, cr, lane,
+                  [&](int be, int b) {
+                    const ET v = Arow[b * CHIM * CHIM + be];
+                    return ra ? v : ET(0);
+                  },
+                  [&](int be, int b) {
+                    const double v = Tk[(be * DP + b) * CHIM];
+                    return ck ? v : 0.0;
+                  });
+            } else {
+              const double* Arow = sA + alc * CHIM;
+              mfma_multi<ET, CHIM, DP>(
+                  acc, cr, lane,
+                  [&](int be, int b) {
+                    const double v = Arow[b * CHIM * CHIM + be];
+                    return ra ? v : 0.0;
+                  },
+                  [&](int be, int b) {
+                    const double v = Tk[(be * DP + b) * CHIM];
+                    return ck ? v : 0.0;
+                  });
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = ti * 16 + Mfma<ET>::row(lane, q);
+              if (row < cl && ck) {
+#pragma unroll
+                for (int b = 0; b < DP; ++b) sAT[(row * DP + b) * CHIM + kk] = (double)acc[b][q];
+              }
+            }
+          }
+        } else {
           const int nb = DP * k;
           const float inv_nb = 1.0f / (float)nb, inv_k = 1.0f / (float)k;
           for (int w = tid; w < cl * nb; w += NTK) {
@@ -1174,7 +1377,11 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         // R~[i][al*d+b] = sum_a R[i][al*d+a] H[a][b]; stored transposed for
         // the LQ (to_ct), and as C (to_c) when the LQ may not take the
         // register path
-        form_c<DP, CHIM, NTK, LD, Lay::CTLD, Lay::LDC>(sR, sAT, Hx, Gx, sCt, sC, rR, k, cl, tid, true, !lq_reg);
+        if constexpr (MF)
+          form_c_mfma<ET, DP, CHIM, NW, LD, Lay::RROWS, Lay::CTLD, Lay::LDC>(sR, sAT, Hx, Gx, sCt, sC, rR, k, cl, lane,
+                                                                          wv, true, !lq_reg);
+        else
+          form_c<DP, CHIM, NTK, LD, Lay::CTLD, Lay::LDC>(sR, sAT, Hx, Gx, sCt, sC, rR, k, cl, tid, true, !lq_reg);
         __syncthreads();
         // right singular vectors of C.  When the rank of C does not exceed chi
         // nothing is truncated and any orthonormal basis of its row space is
@@ -1228,7 +1435,11 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
             // again: R_{x-1} and AT are intact (Q is not formed when the LQ
             // stops at chi + 1 steps)
             if constexpr (CMP) {
-              form_c<DP, CHIM, NTK, LD, Lay::CTLD, Lay::LDC>(sR, sAT, Hx, Gx, sCt, sC, rR, k, cl, tid, false, true);
+              if constexpr (MF)
+                form_c_mfma<ET, DP, CHIM, NW, LD, Lay::RROWS, Lay::CTLD, Lay::LDC>(sR, sAT, Hx, Gx, sCt, sC, rR, k, cl,
+                                                                                lane, wv, false, true);
+              else
+                form_c<DP, CHIM, NTK, LD, Lay::CTLD, Lay::LDC>(sR, sAT, Hx, Gx, sCt, sC, rR, k, cl, tid, false, true);
             } else {
               for (int w = tid; w < nC * rR; w += NTK) {
                 const int c = w / rR, i = w % rR;
@@ -1298,7 +1509,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
           flops += 2.0 * DP * cl * cr * k + 2.0 * rR * DP * cl * k + 2.0 * rR * DP * DP * k + 2.0 * kx * DP * DP * k +
                    2.0 * cl * DP * kx * k + 2.0 * cl * DP * DP * kx;
         // V rows (normalised) -> new environment site x, and V~[rho][b][k'] = sum_r G[r][b] V[rho][r*k+k']
-        const float inv_k = 1.0f / (float)k, inv_kx = 1.0f / (float)kx, inv_dkx = 1.0f / (float)(DP * kx);
+        const float inv_k = 1.0f / (float)k, inv_kx = 1.0f / (float)kx;
         for (int w = tid; w < kx * k; w += NTK) {
           const int rho = fquot(w, inv_k), kk = w - rho * k;
           const int i = min(max(sIdx[rho], 0), D - 1);
@@ -1320,13 +1531,45 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
           }
         }
         __syncthreads();
-        // Y[al][b][rho] = sum_k' AT[al][b][k'] V~[rho][b][k']
-        for (int w = tid; w < cl * DP * kx; w += NTK) {
-          const int al = fquot(w, inv_dkx);
-          const int rem = w - al * DP * kx;
-          const int b = fquot(rem, inv_kx), rho = rem - b * kx;
-          const double s = lds_dot<CHIM>(sAT + (al * DP + b) * CHIM, 1, sVt + (rho * DP + b) * CHIM, 1, k);
-          sY[(al * DP + b) * CHIM + rho] = s;
+        // Y[al][b][rho] = sum_k' AT[al][b][k'] V~[rho][b][k']: for each b a cl x kx
+        // product with K = k (on the matrix cores with MF)
+        if constexpr (MF) {
+          const int tj_n = (kx + 15) >> 4, tij = ((cl + 15) >> 4) * tj_n;
+          for (int tt = wv; tt < tij; tt += NW) {
+            const int ti = tt / tj_n, tj = tt - ti * tj_n;
+            const int al = ti * 16 + (lane & 15), rho = tj * 16 + (lane & 15);
+            const bool ra = al < cl, cr2 = rho < kx;
+            const double* Aa = sAT + min(al, CHIM - 1) * DP * CHIM;
+            const double* Vr = sVt + min(rho, CHIM - 1) * DP * CHIM;
+            typename Mfma<ET>::V acc[DP];
+            mfma_multi<ET, CHIM, DP>(
+                acc, k, lane,
+                [&](int kk, int b) {
+                  const double v = Aa[b * CHIM + kk];
+                  return ra ? v : 0.0;
+                },
+                [&](int kk, int b) {
+                  const double v = Vr[b * CHIM + kk];
+                  return cr2 ? v : 0.0;
+                });
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int row = ti * 16 + Mfma<ET>::row(lane, q);
+              if (row < cl && cr2) {
+#pragma unroll
+                for (int b = 0; b < DP; ++b) sY[(row * DP + b) * CHIM + rho] = (double)acc[b][q];
+              }
+            }
+          }
+        } else {
+          const float inv_dkx = 1.0f / (float)(DP * kx);
+          for (int w = tid; w < cl * DP * kx; w += NTK) {
+            const int al = fquot(w, inv_dkx);
+            const int rem = w - al * DP * kx;
+            const int b = fquot(rem, inv_kx), rho = rem - b * kx;
+            const double s = lds_dot<CHIM>(sAT + (al * DP + b) * CHIM, 1, sVt + (rho * DP + b) * CHIM, 1, k);
+            sY[(al * DP + b) * CHIM + rho] = s;
+          }
         }
         __syncthreads();
         // T_x[al*d + a][rho] = sum_b H[a][b] Y[al][b][rho], then normalise
@@ -1371,18 +1614,18 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
 }
 
 
-template <typename ET, int DP, int CHIM, bool CMP, bool GM = false>
+template <typename ET, int DP, int CHIM, bool CMP, bool GM, bool MF>
 hipError_t launch_contract_k(const TaskDesc* tasks, int n, int retry, hipStream_t s) {
   using Lay = Layout<DP, CHIM, CMP>;
   const size_t bytes = GM ? 0 : sizeof(double) * Lay::total;
   static bool attr_set = false;
   if (!attr_set && bytes > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)contract_kernel<ET, DP, CHIM, CMP, GM>,
+    hipError_t e = hipFuncSetAttribute((const void*)contract_kernel<ET, DP, CHIM, CMP, GM, MF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((contract_kernel<ET, DP, CHIM, CMP, GM>), dim3(n), dim3(Lay::NTH), bytes, s, tasks, retry);
+  hipLaunchKernelGGL((contract_kernel<ET, DP, CHIM, CMP, GM, MF>), dim3(n), dim3(Lay::NTH), bytes, s, tasks, retry);
   return hipGetLastError();
 }
 
@@ -1390,47 +1633,53 @@ hipError_t launch_contract_k(const TaskDesc* tasks, int n, int retry, hipStream_
 constexpr size_t kHalfLds = 80 * 1024;
 constexpr size_t kCuLds = 160 * 1024;
 
-template <typename ET, int DP, int CHIM>
-hipError_t launch_contract_t(const TaskDesc* tasks, int n, hipStream_t s) {
-  constexpr bool use_compact = sizeof(double) * Layout<DP, CHIM, false>::total > kHalfLds &&
-                               sizeof(double) * Layout<DP, CHIM, true>::total <= kHalfLds;
+template <int DP, int CHIM>
+constexpr bool layout_has_compact() {
+  return sizeof(double) * Layout<DP, CHIM, false>::total > kHalfLds &&
+         sizeof(double) * Layout<DP, CHIM, true>::total <= kHalfLds;
+}
+
+// full: run a class that has the compact layout with the full one instead.
+template <typename ET, int DP, int CHIM, bool MF>
+hipError_t launch_contract_t(const TaskDesc* tasks, int n, int full, hipStream_t s) {
+  constexpr bool use_compact = layout_has_compact<DP, CHIM>();
   constexpr bool use_global = !use_compact && sizeof(double) * Layout<DP, CHIM, false>::total > kCuLds;
   if constexpr (use_global) {
     // the full tile layout exceeds a CU's LDS (d = 3, chi = 32): every tile
     // in the task's global scratch
-    return launch_contract_k<ET, DP, CHIM, false, true>(tasks, n, 0, s);
+    return launch_contract_k<ET, DP, CHIM, false, true, MF>(tasks, n, 0, s);
   } else if constexpr (use_compact) {
-    if (!g_force_retry && g_layout_full[DP == 3][sizeof(ET) == sizeof(float)])
-      return launch_contract_k<ET, DP, CHIM, false>(tasks, n, 0, s);
+    if (!g_force_retry && full) return launch_contract_k<ET, DP, CHIM, false, false, MF>(tasks, n, 0, s);
     // every task in the compact layout (two per CU), then the few whose left
     // rank outgrew it, from the row where they stopped, with the full layout
     // in LDS (one per CU; the launch starts once the compact one has ended, so
     // the whole chip is free for them)
-    hipError_t e = launch_contract_k<ET, DP, CHIM, true>(tasks, n, g_force_retry ? -1 : 0, s);
+    hipError_t e = launch_contract_k<ET, DP, CHIM, true, false, MF>(tasks, n, g_force_retry ? -1 : 0, s);
     if (e != hipSuccess) return e;
-    return launch_contract_k<ET, DP, CHIM, false>(tasks, n, 1, s);
+    return launch_contract_k<ET, DP, CHIM, false, false, MF>(tasks, n, 1, s);
   } else {
-    return launch_contract_k<ET, DP, CHIM, false>(tasks, n, 0, s);
+    return launch_contract_k<ET, DP, CHIM, false, false, MF>(tasks, n, 0, s);
   }
 }
 
-// One (d, chi_max) instantiation per supported pair, for environments stored as ET.
-template <typename ET>
-hipError_t launch_contract_et(const TaskDesc* tasks, int n, int d, int chi_max, hipStream_t s) {
+// One (d, chi_max) instantiation per supported pair, for environments stored
+// as ET and products on the engine MF.
+template <typename ET, bool MF>
+hipError_t launch_contract_et(const TaskDesc* tasks, int n, int d, int chi_max, int full, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (d == 2) {
     switch (chi_max) {
-      case 4: return launch_contract_t<ET, 2, 4>(tasks, n, s);
-      case 8: return launch_contract_t<ET, 2, 8>(tasks, n, s);
-      case 16: return launch_contract_t<ET, 2, 16>(tasks, n, s);
-      case 32: return launch_contract_t<ET, 2, 32>(tasks, n, s);
+      case 4: return launch_contract_t<ET, 2, 4, MF>(tasks, n, full, s);
+      case 8: return launch_contract_t<ET, 2, 8, MF>(tasks, n, full, s);
+      case 16: return launch_contract_t<ET, 2, 16, MF>(tasks, n, full, s);
+      case 32: return launch_contract_t<ET, 2, 32, MF>(tasks, n, full, s);
     }
   } else if (d == 3) {
     switch (chi_max) {
-      case 4: return launch_contract_t<ET, 3, 4>(tasks, n, s);
-      case 8: return launch_contract_t<ET, 3, 8>(tasks, n, s);
-      case 16: return launch_contract_t<ET, 3, 16>(tasks, n, s);
-      case 32: return launch_contract_t<ET, 3, 32>(tasks, n, s);
+      case 4: return launch_contract_t<ET, 3, 4, MF>(tasks, n, full, s);
+      case 8: return launch_contract_t<ET, 3, 8, MF>(tasks, n, full, s);
+      case 16: return launch_contract_t<ET, 3, 16, MF>(tasks, n, full, s);
+      case 32: return launch_contract_t<ET, 3, 32, MF>(tasks, n, full, s);
     }
   }
   return hipErrorInvalidValue;

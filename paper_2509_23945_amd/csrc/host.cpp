@@ -22,10 +22,6 @@
 
 using tnmc::TaskDesc;
 
-namespace tnmc {
-bool contract_has_compact(int d, int chi_max);
-void set_layout_full(int d, int precision, int full);
-}
 
 namespace {
 
@@ -264,12 +260,14 @@ struct Timer {
   }
 };
 
+tnmc::ContractCfg contract_cfg(const Plan::Group& g);   // the autotuner's choice for a launch group (below)
+
 // Launch the contraction and sampling kernels of a plan whose descriptors are at dtasks.
 tnmc_status launch_plan(const Plan& plan, const TaskDesc* dtasks, uint64_t sweep, hipStream_t s, Timer* tm,
                         tnmc_stats* st) {
   for (const auto& g : plan.groups) {
     if (tm && tm->on && tm->mark(tm->c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
-    HIP_TRY(tnmc::launch_contract(dtasks + g.first, g.count, g.d, g.chi_max, g.precision, s));
+    HIP_TRY(tnmc::launch_contract(dtasks + g.first, g.count, g.d, g.chi_max, g.precision, contract_cfg(g), s));
     if (tm && tm->on && tm->mark(tm->c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
     if (st) st->contract_launches += 1;
   }
@@ -328,71 +326,128 @@ tnmc_status finish_timer(Timer& tm, tnmc_stats* st) {
   return sum(tm.s_ev, st->sample_ms);
 }
 
-// Layout autotuner.  The (d, chi_max) classes with a compact layout (two
-// tasks per CU, with a full-layout redo of the tasks that outgrow it) can also
-// run every task in the full layout (one per CU); the two agree within the
-// FP64 parity bar.
-// Before the second sweep of such a class and storage precision, the
-// contraction of that sweep's tasks runs once with each layout untimed, then
-// once more timed (descriptors without counters, so the statistics see only
-// the real launch, which follows and rewrites the same workspace), and the
-// faster layout is kept for the process.
+// Autotuner of the contraction (batching).  A class of slice tasks is keyed
+// by (d, chi_max, storage precision, row length, row count, tasks in the
+// launch).  Its candidates are the product engines (vector ALU, matrix cores)
+// times, where the class has a compact layout (two tasks per CU, with a
+// full-layout redo of the tasks that outgrow it), the two tile layouts.
+// Every candidate is a correct contraction; they agree within the parity bar
+// of the storage precision (not bit for bit, so pin them for bit-for-bit
+// reproducible runs across processes).  Before the second sweep of a class,
+// the contraction of that sweep's tasks runs once per candidate untimed (a
+// kernel's first launch also loads its code), then three times per candidate
+// timed with HIP events (descriptors without counters, so the statistics see
+// only the real launch, which follows and rewrites the same workspace); the
+// candidate of the smallest median is kept for the process.  The first sweep
+// from a prepared (often random) configuration meets larger ranks than the
+// chain sees afterwards and would bias the choice.
 struct TuneResult {
-  int full = -1;
-  double ms_compact = 0.0, ms_full = 0.0;
+  tnmc::ContractCfg cfg;
+  double ms[2][2] = {{-1.0, -1.0}, {-1.0, -1.0}};   // median ms per [engine][layout], -1: not a candidate
 };
-std::map<std::tuple<int, int, int>, TuneResult> g_tune;
-std::map<std::tuple<int, int, int>, int> g_tune_seen;   // sweeps run per class before its trial
+using TuneKey = std::tuple<int, int, int, int, int, int>;
+std::map<TuneKey, TuneResult> g_tune;
+std::map<TuneKey, int> g_tune_seen;   // sweeps run per class before its trial
+TuneKey g_tune_last{};                // most recent key tuned (reported by tnmc_layout_choice)
+bool g_tune_any = false;
 bool g_autotune = true;
+int g_pin_layout = -1, g_pin_engine = -1;   // -1: tuned; 0 / 1: fixed by tnmc_autotune_pin
 bool g_nn_pairing = true;   // two learned-proposal tasks per workgroup where a launch allows it
 
-// Trials for the classes of the plan that have run one sweep already: the
-// first sweep from a prepared (often random) configuration meets larger ranks
-// than the chain sees afterwards and would favour the full layout.
-tnmc_status autotune_groups(const Plan& plan, hipStream_t s) {
+TuneKey tune_key(const Plan::Group& g) {
+  return std::make_tuple(g.d, g.chi_max, g.precision, g.lx_max, g.ly_max, g.count);
+}
+
+// Configuration used for a launch group: the pins, then the tuned choice,
+// then the defaults (compact layout where it exists, vector-ALU products).
+tnmc::ContractCfg contract_cfg(const Plan::Group& g) {
+  tnmc::ContractCfg c;
+  auto it = g_tune.find(tune_key(g));
+  if (it != g_tune.end()) c = it->second.cfg;
+  if (g_pin_layout >= 0) c.full = g_pin_layout;
+  if (g_pin_engine >= 0) c.mfma = g_pin_engine;
+  return c;
+}
+
+tnmc_status time_launch(const TaskDesc* dt, const Plan::Group& g, tnmc::ContractCfg cfg, hipStream_t s, double* ms) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    HIP_TRY(e);
+  }
+  e = hipEventRecord(e0, s);
+  if (e == hipSuccess) e = tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, cfg, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_TRY(e);
+  *ms = t;
+  return TNMC_OK;
+}
+
+// Trials for the classes of the plan that have run one sweep already (every
+// class of the plan with force, replacing earlier choices).
+tnmc_status autotune_groups(const Plan& plan, hipStream_t s, bool force = false) {
   if (!g_autotune) return TNMC_OK;
+  std::set<TuneKey> done;
   for (const auto& g : plan.groups) {
-    const auto key = std::make_tuple(g.d, g.chi_max, g.precision);
-    if (!tnmc::contract_has_compact(g.d, g.chi_max) || g_tune.count(key)) continue;
-    if (g_tune_seen[key] < 1) continue;
-    std::vector<TaskDesc> trial(plan.desc.begin() + g.first, plan.desc.begin() + g.first + g.count);
-    for (auto& t : trial) {
-      t.counters = nullptr;
-      t.record = nullptr;
+    const TuneKey key = tune_key(g);
+    if (force) {
+      if (done.count(key)) continue;
+      done.insert(key);
+      g_tune.erase(key);
+    } else if (g_tune.count(key) || g_tune_seen[key] < 1) {
+      continue;
     }
-    if (grow(g_ws.tune_tasks, g_ws.tune_tasks_cap, trial.size()) != TNMC_OK) return TNMC_ERR_OOM;
-    HIP_TRY(hipMemcpyAsync(g_ws.tune_tasks, trial.data(), trial.size() * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    // one untimed pass of each layout first: a kernel's first launch in a
-    // process also pays for loading its code, which would decide the trial
-    for (int full : {0, 1}) {
-      tnmc::set_layout_full(g.d, g.precision, full);
-      HIP_TRY(tnmc::launch_contract(g_ws.tune_tasks, g.count, g.d, g.chi_max, g.precision, s));
-    }
-    HIP_TRY(hipStreamSynchronize(s));
-    double ms[2] = {0.0, 0.0};
-    for (int full : {0, 1}) {
-      hipEvent_t e0, e1;
-      HIP_TRY(hipEventCreate(&e0));
-      HIP_TRY(hipEventCreate(&e1));
-      tnmc::set_layout_full(g.d, g.precision, full);
-      hipError_t e = hipEventRecord(e0, s);
-      if (e == hipSuccess) e = tnmc::launch_contract(g_ws.tune_tasks, g.count, g.d, g.chi_max, g.precision, s);
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float t = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      HIP_TRY(e);
-      ms[full] = t;
-    }
+    std::vector<tnmc::ContractCfg> cands;
+    for (int mf : {0, 1})
+      for (int full : {0, 1}) {
+        if (full && !tnmc::contract_has_compact(g.d, g.chi_max)) continue;
+        if ((g_pin_layout >= 0 && full != g_pin_layout && tnmc::contract_has_compact(g.d, g.chi_max)) ||
+            (g_pin_engine >= 0 && mf != g_pin_engine))
+          continue;
+        tnmc::ContractCfg c;
+        c.full = full;
+        c.mfma = mf;
+        cands.push_back(c);
+      }
     TuneResult r;
-    r.full = (ms[1] < ms[0]) ? 1 : 0;
-    r.ms_compact = ms[0];
-    r.ms_full = ms[1];
-    tnmc::set_layout_full(g.d, g.precision, r.full);
+    r.cfg = contract_cfg(g);
+    if (cands.size() > 1) {
+      std::vector<TaskDesc> trial(plan.desc.begin() + g.first, plan.desc.begin() + g.first + g.count);
+      for (auto& t : trial) {
+        t.counters = nullptr;
+        t.record = nullptr;
+      }
+      if (grow(g_ws.tune_tasks, g_ws.tune_tasks_cap, trial.size()) != TNMC_OK) return TNMC_ERR_OOM;
+      HIP_TRY(hipMemcpyAsync(g_ws.tune_tasks, trial.data(), trial.size() * sizeof(TaskDesc), hipMemcpyHostToDevice,
+                             s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (const auto& c : cands) HIP_TRY(tnmc::launch_contract(g_ws.tune_tasks, g.count, g.d, g.chi_max, g.precision, c, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double best = 1e300;
+      for (const auto& c : cands) {
+        double t[3];
+        for (double& ti : t) {
+          tnmc_status st = time_launch(g_ws.tune_tasks, g, c, s, &ti);
+          if (st != TNMC_OK) return st;
+        }
+        std::sort(t, t + 3);
+        r.ms[c.mfma][c.full] = t[1];
+        if (t[1] < best) {
+          best = t[1];
+          r.cfg = c;
+        }
+      }
+    }
     g_tune[key] = r;
+    g_tune_last = key;
+    g_tune_any = true;
   }
   return TNMC_OK;
 }
@@ -686,7 +741,7 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
     for (const auto& g : plan.groups) {
       const TaskDesc* dt = g_ws.tasks + g.first;
       if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
-      HIP_TRY(tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, s));
+      HIP_TRY(tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, contract_cfg(g), s));
       if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
       if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
       HIP_TRY(tnmc::launch_sample(dt, g.count, g.d, g.chi_max, g.precision, g.lx_max, g.ly_max, sw, s));
@@ -697,8 +752,8 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
       }
     }
     {
-      std::set<std::tuple<int, int, int>> swept;
-      for (const auto& g : plan.groups) swept.insert(std::make_tuple(g.d, g.chi_max, g.precision));
+      std::set<TuneKey> swept;
+      for (const auto& g : plan.groups) swept.insert(tune_key(g));
       for (const auto& k : swept) g_tune_seen[k] += 1;
     }
     if (record) {
@@ -722,6 +777,23 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
   return TNMC_OK;
 }
 
+tnmc_status tnmc_autotune_now(tnmc_lattice* const* lats, int32_t n_lats, void* stream) {
+  if (check_lats(lats, n_lats) != TNMC_OK) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  hipStream_t s = (hipStream_t)stream;
+  WsOrder order(s);
+  std::vector<Task> tasks;
+  for (int p : {0, 1})
+    for (Task t : half_sweep_tasks(lats, n_lats, p)) {
+      t.key = p;
+      tasks.push_back(t);
+    }
+  Plan plan;
+  tnmc_status r = make_plan(tasks, plan);
+  if (r != TNMC_OK) return r;
+  return autotune_groups(plan, s, true);
+}
+
 tnmc_status tnmc_debug_set(int32_t what, int32_t value) {
   if (what < 0 || what > 2 || (value != 0 && value != 1)) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
@@ -730,30 +802,71 @@ tnmc_status tnmc_debug_set(int32_t what, int32_t value) {
   } else if (what == 2) {
     g_nn_pairing = value != 0;
   } else {
-    // autotuner off: forget its choices and run the default (compact) layouts
+    // autotuner off: forget its choices and run the defaults (or the pins)
     g_autotune = value != 0;
     if (!g_autotune) {
-      for (const auto& kv : g_tune) tnmc::set_layout_full(std::get<0>(kv.first), std::get<2>(kv.first), 0);
       g_tune.clear();
       g_tune_seen.clear();
+      g_tune_any = false;
     }
   }
   return TNMC_OK;
+}
+
+// The most recent tuned class with this (d, chi bucket, precision), if any.
+const TuneResult* find_tuned(int d, int chi, int precision) {
+  const int cm = tnmc::chi_bucket(chi);
+  const TuneResult* r = nullptr;
+  if (g_tune_any && std::get<0>(g_tune_last) == d && std::get<1>(g_tune_last) == cm &&
+      std::get<2>(g_tune_last) == precision)
+    return &g_tune.at(g_tune_last);
+  for (const auto& kv : g_tune)
+    if (std::get<0>(kv.first) == d && std::get<1>(kv.first) == cm && std::get<2>(kv.first) == precision)
+      r = &kv.second;
+  return r;
 }
 
 tnmc_status tnmc_layout_choice(int32_t d, int32_t chi, int32_t precision, int32_t* layout, double* ms_compact,
                                double* ms_full) {
   if (!layout || (d != 2 && d != 3) || chi < 1) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
-  const int cm = tnmc::chi_bucket(chi);
   *layout = -1;
   if (ms_compact) *ms_compact = 0.0;
   if (ms_full) *ms_full = 0.0;
-  auto it = g_tune.find(std::make_tuple((int)d, cm, (int)precision));
-  if (it == g_tune.end()) return TNMC_OK;
-  *layout = it->second.full;
-  if (ms_compact) *ms_compact = it->second.ms_compact;
-  if (ms_full) *ms_full = it->second.ms_full;
+  const TuneResult* r = find_tuned(d, chi, precision);
+  if (!r || !tnmc::contract_has_compact(d, tnmc::chi_bucket(chi))) return TNMC_OK;
+  *layout = r->cfg.full;
+  if (ms_compact) *ms_compact = r->ms[r->cfg.mfma][0];
+  if (ms_full) *ms_full = r->ms[r->cfg.mfma][1];
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_autotune_choice(int32_t d, int32_t chi, int32_t precision, int32_t* layout, int32_t* engine,
+                                 double* ms) {
+  if (!layout || !engine || (d != 2 && d != 3) || chi < 1) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  *layout = -1;
+  *engine = -1;
+  if (ms)
+    for (int i = 0; i < 4; ++i) ms[i] = -1.0;
+  const TuneResult* r = find_tuned(d, chi, precision);
+  if (!r) return TNMC_OK;
+  *layout = r->cfg.full;
+  *engine = r->cfg.mfma;
+  if (ms)
+    for (int e = 0; e < 2; ++e)
+      for (int l = 0; l < 2; ++l) ms[2 * e + l] = r->ms[e][l];
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_autotune_pin(int32_t layout, int32_t engine) {
+  if (layout < -1 || layout > 1 || engine < -1 || engine > 1) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  g_pin_layout = layout;
+  g_pin_engine = engine;
+  g_tune.clear();   // choices made under other pins are dropped
+  g_tune_seen.clear();
+  g_tune_any = false;
   return TNMC_OK;
 }
 
@@ -924,7 +1037,12 @@ tnmc_status tnmc_slice_propose_static(tnmc_lattice* lat, int32_t chain, int32_t 
   // the descriptor is copied from this frame: wait for the copy before
   // returning (and before the kernels read it, which stream order gives)
   HIP_TRY(hipMemcpyAsync(dt, &t, sizeof(TaskDesc), hipMemcpyHostToDevice, s));
-  HIP_TRY(tnmc::launch_contract(dt, 1, d, cm, lat->precision, s));
+  {
+    tnmc::ContractCfg cfg;   // the pins, else the defaults (a single task is not tuned)
+    if (g_pin_layout >= 0) cfg.full = g_pin_layout;
+    if (g_pin_engine >= 0) cfg.mfma = g_pin_engine;
+    HIP_TRY(tnmc::launch_contract(dt, 1, d, cm, lat->precision, cfg, s));
+  }
   HIP_TRY(tnmc::launch_sample(dt, 1, d, cm, lat->precision, Lx, Ly, sweep, s));
   double rec[5];
   HIP_TRY(hipMemcpyAsync(s_new, t.s_new_out, plane, hipMemcpyDeviceToHost, s));
@@ -1420,7 +1538,7 @@ tnmc_status tnmc_nn_sweep(tnmc_lattice* const* lats, int32_t n_lats, tnmc_nn* nn
         if (g.key != p) continue;
         const TaskDesc* dt = g_ws.tasks + g.first;
         if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
-        HIP_TRY(tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, s));
+        HIP_TRY(tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, contract_cfg(g), s));
         if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
         if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
         HIP_TRY(tnmc::launch_sample(dt, g.count, g.d, g.chi_max, g.precision, g.lx_max, g.ly_max, sw, s));

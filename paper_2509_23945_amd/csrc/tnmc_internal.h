@@ -66,9 +66,26 @@ inline size_t rscr_doubles(int Lx, int d, int chi_max) {
   return (size_t)Lx * (size_t)(d * chi_max) * (d * chi_max);
 }
 
+// How the slice tasks of one (d, chi_max, precision) class are contracted:
+// the tile layout (full = 1 runs a class that has the compact two-per-CU
+// layout with the full one-per-CU layout instead) and the engine of the
+// products M, AT, C and Y (mfma = 1: matrix cores, FP64 or FP32 operands as
+// the environments are stored; 0: FP64 on the vector ALU).  Every choice is a
+// correct contraction; they agree within the FP64 parity bar (FP64 storage)
+// or the reduced-precision one (FP32 storage).
+struct ContractCfg {
+  int full = 0;
+  int mfma = 0;
+};
+
 // Kernel launchers (return hipError_t of the launch).
-hipError_t launch_contract(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int precision, hipStream_t s);
-hipError_t launch_contract_f32(const TaskDesc* tasks, int n_tasks, int d, int chi_max, hipStream_t s);
+hipError_t launch_contract(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int precision, ContractCfg cfg,
+                           hipStream_t s);
+hipError_t launch_contract_f64(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int full, hipStream_t s);
+hipError_t launch_contract_f64_mf(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int full, hipStream_t s);
+hipError_t launch_contract_f32(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int full, hipStream_t s);
+hipError_t launch_contract_f32_mf(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int full, hipStream_t s);
+bool contract_has_compact(int d, int chi_max);
 hipError_t launch_sample(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int precision, int Lx_max,
                          int Ly_max, uint64_t sweep, hipStream_t s);
 hipError_t launch_energy(const float* J, const int8_t* spins, int Lx, int Ly, int Lz, int d,

@@ -123,5 +123,12 @@ def test_direction_and_layout_arguments_checked_on_host(lib):
     assert lib.tnmc_layout_choice(2, 32, 0, None, None, None) == ARG
     # untuned class: -1
     assert lib.tnmc_layout_choice(2, 32, 1, ctypes.byref(lay), None, None) == 0 and lay.value == -1
+    eng = ctypes.c_int32()
+    assert lib.tnmc_autotune_choice(2, 32, 0, None, ctypes.byref(eng), None) == ARG
+    assert lib.tnmc_autotune_choice(5, 32, 0, ctypes.byref(lay), ctypes.byref(eng), None) == ARG
+    assert lib.tnmc_autotune_choice(2, 32, 1, ctypes.byref(lay), ctypes.byref(eng), None) == 0
+    assert lay.value == -1 and eng.value == -1
+    assert lib.tnmc_autotune_pin(2, 0) == ARG and lib.tnmc_autotune_pin(0, -2) == ARG
+    assert lib.tnmc_autotune_now(None, 1, None) == ARG
     assert lib.tnmc_sweep_direction(None, 1, 1, 1, 0, 0, 0, None, None) == ARG
     assert lib.tnmc_debug_set(3, 1) == ARG and lib.tnmc_debug_set(1, 2) == ARG

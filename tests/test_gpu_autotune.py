@@ -1,6 +1,7 @@
-"""The layout autotuner: on the first sweep of a class with a compact layout it
-times both layouts and keeps the faster one; the chain it then runs is the
-same, bit for bit, as with the default layout (autotuner off)."""
+"""The contraction autotuner: before a class's second sweep it times every
+candidate (product engine x tile layout) three times and keeps the smallest
+median; the chain it then runs equals, spin for spin, the chain with the
+defaults (autotuner off) on these seeds, and pinning fixes the choice."""
 import numpy as np
 import pytest
 
@@ -10,21 +11,46 @@ import paper_2509_23945_amd as tn
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("d,chi,kind,beta", [(2, 20, "gauss", 1.0), (3, 12, "ferro", 0.55)])
-def test_autotuned_layout_gives_the_same_chain(d, chi, kind, beta):
+@pytest.mark.parametrize("d,chi,kind,beta", [(2, 20, "gauss", 1.0), (3, 12, "ferro", 0.55), (2, 8, "pmj", 1.0)])
+def test_autotuned_contraction_gives_the_same_chain(d, chi, kind, beta):
     gh.announce(f"autotune d={d} chi={chi}")
     try:
         tn.tnmc_debug_set(1, 0)
         a, _, _, _ = gh.make_lattice(9, 8, 4, d, chi, kind=kind, beta=beta, seed=41, n_chains=2)
         tn.tnmc_sweep([a], 3)
-        assert tn.tnmc_layout_choice(d, chi)[0] == -1
+        assert tn.tnmc_autotune_choice(d, chi)[:2] == (-1, -1)
         tn.tnmc_debug_set(1, 1)
         b, _, _, _ = gh.make_lattice(9, 8, 4, d, chi, kind=kind, beta=beta, seed=41, n_chains=2)
         tn.tnmc_sweep([b], 3)
-        layout, ms_c, ms_f = tn.tnmc_layout_choice(d, chi)
-        assert layout in (0, 1) and ms_c > 0 and ms_f > 0
-        assert layout == (1 if ms_f < ms_c else 0)
+        layout, engine, ms = tn.tnmc_autotune_choice(d, chi)
+        assert engine in (0, 1) and layout in (0, 1)
+        tried = {(e, l): ms[2 * e + l] for e in (0, 1) for l in (0, 1) if ms[2 * e + l] >= 0}
+        assert len(tried) >= 2 and all(v > 0 for v in tried.values())
+        assert (engine, layout) == min(tried, key=tried.get)
         for c in range(2):
             assert np.array_equal(tn.tnmc_get_spins(a, c), tn.tnmc_get_spins(b, c))
     finally:
         tn.tnmc_debug_set(1, 1)
+
+
+def test_pinned_engine_is_not_tuned():
+    gh.announce("autotune pinned engine")
+    try:
+        tn.tnmc_autotune_pin(-1, 1)
+        a, _, _, _ = gh.make_lattice(9, 8, 4, 2, 20, kind="gauss", beta=1.0, seed=43, n_chains=2)
+        tn.tnmc_sweep([a], 3)
+        layout, engine, ms = tn.tnmc_autotune_choice(2, 20)
+        assert engine == 1 and ms[0] < 0 and ms[1] < 0 and ms[2] > 0 and ms[3] > 0
+    finally:
+        tn.tnmc_autotune_pin(-1, -1)
+
+
+def test_autotune_now_on_current_states():
+    gh.announce("autotune now")
+    a, _, _, _ = gh.make_lattice(9, 8, 4, 2, 20, kind="gauss", beta=1.0, seed=44, n_chains=2)
+    tn.tnmc_sweep([a], 2)
+    before = [tn.tnmc_get_spins(a, c) for c in range(2)]
+    tn.tnmc_autotune_now([a])
+    layout, engine, ms = tn.tnmc_autotune_choice(2, 20)
+    assert layout in (0, 1) and engine in (0, 1) and sum(m > 0 for m in ms) == 4
+    assert all(np.array_equal(before[c], tn.tnmc_get_spins(a, c)) for c in range(2))

@@ -33,10 +33,21 @@ from test_gpu_parity import CASES
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(params=[0, 1], ids=["valu", "mfma"])
+def engine(request):
+    """Products on the vector ALU (FP64 arithmetic on FP32-stored
+    environments) or on the matrix cores (FP32 operands and accumulation)."""
+    tn.tnmc_autotune_pin(-1, request.param)
+    try:
+        yield request.param
+    finally:
+        tn.tnmc_autotune_pin(-1, -1)
+
+
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:3])) + f"-d{c[3]}-{c[4]}-chi{c[6]}-z{c[7]}")
-def test_fp32_logq_of_own_proposals(case):
+def test_fp32_logq_of_own_proposals(case, engine):
     Lx, Ly, Lz, d, kind, beta, chi, z = case
-    gh.announce(f"fp32 propose case {case}")
+    gh.announce(f"fp32 propose case {case}, engine {engine}")
     lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, d, chi, kind=kind, beta=beta, seed=3, precision=tn.TNMC_FP32)
     lq_cur = ochain.slice_logq(J[0], spins[0], z, spins[0][z], beta, chi, d)
     for sweep in (0, 7):
@@ -45,7 +56,7 @@ def test_fp32_logq_of_own_proposals(case):
         assert gh.logq_close_reduced(lq_old, lq_cur), (lq_old, lq_cur)
         o_new, bad, worst, closest = gh.sitewise_draw_check(J[0], spins[0], z, s_new, beta, chi, d, seed=12345,
                                                             chain=0, sweep=sweep)
-        gh.record_margin("fp32 sitewise", case, sweep, bad, worst, closest)
+        gh.record_margin(f"fp32 sitewise engine {engine}", case, sweep, bad, worst, closest)
         assert bad == 0 or worst < gh.TIE_REDUCED, (bad, worst)
         assert gh.logq_close_reduced(lq_new, o_new), (lq_new, o_new)
         after = spins[0].copy()
@@ -55,9 +66,9 @@ def test_fp32_logq_of_own_proposals(case):
         assert abs(tn.tnmc_slice_logq(lat, 0, z, s_new) - lq_new) <= 1e-12 * max(1.0, abs(lq_new))
 
 
-def test_fp32_exact_regime_is_near_boltzmann():
+def test_fp32_exact_regime_is_near_boltzmann(engine):
     """Untruncated 3x3 layer: FP32 log q(s) = -beta E(s) - log Z within 1e-4 relative."""
-    gh.announce("fp32 exact regime 3x3")
+    gh.announce(f"fp32 exact regime 3x3, engine {engine}")
     lat, J, spins, _ = gh.make_lattice(3, 3, 3, 2, 4, kind="gauss", beta=1.1, seed=5, precision=tn.TNMC_FP32)
     cfgs, E = bf.layer_energies(J[0], spins[0], 1, 2)
     logz = bf.logsumexp(-1.1 * E)
@@ -67,12 +78,12 @@ def test_fp32_exact_regime_is_near_boltzmann():
         assert gh.logq_close_reduced(g, -1.1 * E[i] - logz)
 
 
-def test_fp32_chain_averages_match_enumeration():
+def test_fp32_chain_averages_match_enumeration(engine):
     """64 independent chains, each on its own 2x2x4 +-J instance, chi = 1
     (truncated, so proposals are rejected at times): the deviations of each
     chain's averages of E and M^2 over sweeps 50..399 from its exact
     enumeration average have mean zero within four standard errors."""
-    gh.announce("fp32 chain averages 2x2x4")
+    gh.announce(f"fp32 chain averages 2x2x4, engine {engine}")
     Lx, Ly, Lz, beta, n_chains, n_sweeps = 2, 2, 4, 1.0, 64, 400
     lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, 2, 1, kind="pmj", beta=beta, seed=3, n_chains=n_chains,
                                        record_capacity=n_sweeps, precision=tn.TNMC_FP32)
@@ -91,3 +102,35 @@ def test_fp32_chain_averages_match_enumeration():
     for devs in (np.array(devs_E), np.array(devs_M2)):
         err = devs.std(ddof=1) / math.sqrt(len(devs))
         assert abs(devs.mean()) < 4 * err + 1e-12, (devs.mean(), err)
+
+
+def test_reduced_mfma_form_reproduces_fp64_observables():
+    """Stationarity is unchanged by the reduced-precision proposal (main text
+    Eq. 1: MH is exact for any q with exact log q).  32 +-J instances x 2
+    replicas on 8^3 at beta = 1 and chi = 3 (truncated, so proposals are
+    rejected at times): the FP64 form (vector-ALU products) and the reduced
+    form (FP32 environments, FP32 MFMA products) each run 600 sweeps from the
+    same states; per instance the averages of E/N and of q^2 over sweeps
+    100..599 are compared, and the mean difference over instances must be
+    within four standard errors of zero."""
+    gh.announce("reduced (FP32 MFMA) vs FP64 observables, 8^3 beta=1 chi=3, 64 chains x 600 sweeps")
+    L, chi, beta, n_inst, n_sw = 8, 3, 1.0, 32, 600
+    pairs = np.array([[2 * i, 2 * i + 1] for i in range(n_inst)], dtype=np.int32)
+    res = {}
+    try:
+        for prec, eng in ((tn.TNMC_FP64, 0), (tn.TNMC_FP32, 1)):
+            tn.tnmc_autotune_pin(-1, eng)
+            lat, J, spins, _ = gh.make_lattice(L, L, L, 2, chi, kind="pmj", beta=beta, seed=70, n_chains=2 * n_inst,
+                                               pairs=pairs, record_capacity=n_sw, precision=prec)
+            st = tn.tnmc_sweep([lat], n_sw, record=True)
+            assert st["numeric_faults"] == 0 and st["accepted"] < st["proposed"]
+            E, _, q = tn.tnmc_timeseries(lat)
+            e_inst = (E[100:] / L ** 3).mean(axis=0).reshape(n_inst, 2).mean(axis=1)
+            q2_inst = (q[100:] ** 2).mean(axis=0)
+            res[prec] = (e_inst, q2_inst)
+    finally:
+        tn.tnmc_autotune_pin(-1, -1)
+    for k in range(2):
+        dlt = res[tn.TNMC_FP32][k] - res[tn.TNMC_FP64][k]
+        err = dlt.std(ddof=1) / math.sqrt(len(dlt))
+        assert abs(dlt.mean()) < 4 * err + 1e-12, (k, dlt.mean(), err)

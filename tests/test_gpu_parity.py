@@ -56,6 +56,30 @@ def test_propose_matches_oracle(case):
         assert not diff or diff.get("spins", ("",))[0] == "near-tie", diff
 
 
+@pytest.fixture
+def mfma_engine():
+    """Every contraction of the test runs its products on the matrix cores."""
+    tn.tnmc_autotune_pin(-1, 1)
+    try:
+        yield
+    finally:
+        tn.tnmc_autotune_pin(-1, -1)
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:3])) + f"-d{c[3]}-{c[4]}-chi{c[6]}-z{c[7]}")
+def test_propose_matches_oracle_mfma(case, mfma_engine):
+    """The same bar with the products M, AT, C, Y on FP64 MFMA."""
+    Lx, Ly, Lz, d, kind, beta, chi, z = case
+    gh.announce(f"propose case {case}, MFMA products")
+    lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, d, chi, kind=kind, beta=beta, seed=3)
+    for sweep in (0, 7):
+        gpu = tn.tnmc_slice_propose(lat, 0, z, sweep)
+        assert gpu[4] == 0
+        ref, margins = gh.oracle_propose(J[0], spins[0], z, beta, chi, d, seed=12345, chain=0, sweep=sweep)
+        diff = gh.compare_proposal(gpu, ref, margins, case=case)
+        assert not diff or diff.get("spins", ("",))[0] == "near-tie", diff
+
+
 # cases whose configuration uses the compact two-per-CU contraction layout
 COMPACT_CASES = [c for c in CASES if (c[3] == 2 and c[6] > 16) or (c[3] == 3 and 8 < c[6] <= 16)]
 
