@@ -146,7 +146,7 @@ def make_lattices(name: str, record_capacity: int = 0, precision: int = 0):
     return lats, groups
 
 
-def time_form(tn, lats, warmup: int, steps: int, stream):
+def time_form(tn, lats, warmup: int, steps: int, stream, graph: bool = False):
     """Warm up, tune the contraction on the warmed-up states (untimed), then
     time `steps` sweeps of every lattice; returns (seconds, stats)."""
     import torch
@@ -162,7 +162,11 @@ def time_form(tn, lats, warmup: int, steps: int, stream):
     done = 0
     while done < steps:
         k = min(500, steps - done)
-        part = tn.tnmc_sweep(lats, k, sweep_offset=warmup + done, record=True, time_kernels=True, stream=stream)
+        if graph:
+            # HIP-graph replays: no per-kernel events; the launch counts and flops come back, the durations stay 0
+            part = tn.tnmc_sweep_graph(lats, k, sweep_offset=warmup + done, record=True, stream=stream)
+        else:
+            part = tn.tnmc_sweep(lats, k, sweep_offset=warmup + done, record=True, time_kernels=True, stream=stream)
         st = part if st is None else {key: st[key] + part[key] for key in st}
         done += k
         if steps > 500:
@@ -439,6 +443,8 @@ def main():
                     help="sweeps per form of the tau_int leg (the same for every form; 0 skips the leg)")
     ap.add_argument("--tau-seconds", type=float, default=120.0,
                     help="wall-time cap per form of the tau_int leg")
+    ap.add_argument("--graph", action="store_true",
+                    help="time the FP64 sweeps as HIP-graph replays (tnmc_sweep_graph) instead of eager launches")
     ap.add_argument("--engine", choices=("auto", "valu", "mfma"), default="auto",
                     help="contraction products: chosen by the autotuner (default) or pinned")
     ap.add_argument("--copy-probe", action="store_true",
@@ -470,31 +476,37 @@ def main():
     print(f"[bench] workload {args.workload}: {n_chains} chains in {len(lats)} lattices, "
           f"{updates_per_sweep} slice updates per sweep, warmup {args.warmup}", file=sys.stderr, flush=True)
     print(f"[bench] timing {args.steps} sweeps", file=sys.stderr, flush=True)
-    secs, st = time_form(tn, lats, args.warmup, args.steps, stream)
+    secs, st = time_form(tn, lats, args.warmup, args.steps, stream, graph=args.graph)
     value = args.steps * updates_per_sweep / secs
 
     # algorithmic flops: textbook QR/SVD/GEMM counts at the bond dimensions each task used,
     # accumulated by the kernel; the fixed-chi model is reported beside it
     launches = max(1, st["contract_launches"])
     tasks_per_sweep = sum(len(g["inst"]) * g["L"] for g in groups)
-    avg_launch_s = st["contract_ms"] / 1e3 / launches
+    avg_launch_s = st["contract_ms"] / 1e3 / launches   # 0 for graph replays (no per-kernel events)
     flops_per_launch = st["contract_flops"] / launches
-    achieved = flops_per_launch / avg_launch_s / 1e12
+    achieved = flops_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else None
     kernels = sorted({(g.get("d", 2), g["chi"] if g["chi"] > 16 else 16) for g in groups})
     flops_model = sum(tn.tnmc_flop_model(g["L"], g["L"], g.get("d", 2), g["chi"])[0] * len(g["inst"]) * g["L"]
                       for g in groups) / tasks_per_sweep
-    # launches of different layer classes run concurrently on four streams: the
-    # per-launch rate (flops of a launch / its duration) is the roofline figure,
-    # the chip-level rate (all flops / wall time) is reported beside it
+    # the per-launch rate (counted flops of a launch / its HIP-event duration)
+    # is the roofline figure; the chip-level rate (all flops / wall time, the
+    # sampler included) is reported beside it, and so is the rate a fixed-chi
+    # implementation would need for the same launch time (the textbook model
+    # at full bond dimension, work the rank-revealing path does not do)
     achieved_chip = st["contract_flops"] / secs / 1e12
+    tasks_per_launch = args.steps * tasks_per_sweep / launches
+    model_rate = flops_model * tasks_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(args.workload),
+                "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": measured_traffic(args.workload),
                 "kernel": " + ".join(f"contract_kernel<{d},{c}>" for d, c in kernels),
                 "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
                 "achieved_chip": achieved_chip, "frac_chip": achieved_chip / FP64_PEAK_TFLOPS,
                 "flops_per_task": st["contract_flops"] / (args.steps * tasks_per_sweep),
                 "flops_per_task_fixed_chi": flops_model,
-                "tasks_per_launch": args.steps * tasks_per_sweep / launches}
+                "fixed_chi_model_rate": model_rate,
+                "fixed_chi_model_frac": model_rate / FP64_PEAK_TFLOPS if model_rate else None,
+                "tasks_per_launch": tasks_per_launch}
 
     next_sweep = args.warmup + args.steps   # sweep counters are never reused on a chain
     tau_fp64 = None

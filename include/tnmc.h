@@ -143,6 +143,19 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
                        uint64_t sweep_offset, int32_t record, int32_t time_kernels,
                        tnmc_stats* stats, void* hip_stream);
 
+/* As tnmc_sweep (without kernel timing), with one sweep captured once into a
+ * HIP graph (the contraction and sampler launches of both parities, the
+ * observables, and the advance of a device-resident sweep counter and record
+ * slots) and replayed n_sweeps times on hip_stream, so the host issues one
+ * graph launch per sweep instead of a launch per kernel.  The chains are the
+ * same, bit for bit, as those of tnmc_sweep with the same contraction choices:
+ * the replays use the autotuner's current choices or the pins and run no
+ * trials of their own.  Descriptors, counters and the sweep counter are set up
+ * on hip_stream before the replays (no memory set is recorded in the graph).
+ * stats (may be NULL) receives the counts; the call then synchronises. */
+tnmc_status tnmc_sweep_graph(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
+                             int32_t record, tnmc_stats* stats, void* hip_stream);
+
 /* As tnmc_sweep, with the slices taken perpendicular to axis `direction`
  * (0: z, identical to tnmc_sweep; 1: y; 2: x), so that chains can cycle the
  * slice direction between sweeps.  A y-slice is the layer of sites with one

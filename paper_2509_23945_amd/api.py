@@ -38,7 +38,7 @@ __all__ = [
     "tnmc_nn_counts", "tnmc_nn_counts_reset", "tnmc_nn_set_fallback", "tnmc_nn_get_fallback",
     "tnmc_nn_calibrate_fallback", "tnmc_get_couplings", "tnmc_checkpoint_save", "tnmc_checkpoint_load",
     "tnmc_sweep_direction", "tnmc_layout_choice", "tnmc_slice_propose_static", "tnmc_autotune_choice",
-    "tnmc_autotune_pin", "tnmc_autotune_now",
+    "tnmc_autotune_pin", "tnmc_autotune_now", "tnmc_sweep_graph",
 ]
 TNMC_NN_PARAMS = 38753
 
@@ -152,6 +152,7 @@ def load():
         "tnmc_autotune_choice": [i32, i32, i32, P(i32), P(i32), P(dbl)],
         "tnmc_autotune_pin": [i32, i32],
         "tnmc_autotune_now": [P(vp), i32, vp],
+        "tnmc_sweep_graph": [P(vp), i32, i32, u64, i32, P(_Stats), vp],
     }
     for name, sig in nn_sigs.items():
         getattr(lib, name).argtypes = sig
@@ -535,3 +536,12 @@ def tnmc_autotune_now(lats, stream=None) -> None:
     """Time the contraction candidates now on the chains' current states (replaces earlier choices)."""
     arr, n = _handles(lats)
     _check(load().tnmc_autotune_now(arr, n, stream), "tnmc_autotune_now")
+
+
+def tnmc_sweep_graph(lats, n_sweeps: int, sweep_offset: int = 0, record: bool = False, stream=None) -> dict:
+    """As tnmc_sweep, with one sweep captured into a HIP graph and replayed n_sweeps times."""
+    arr, n = _handles(lats)
+    st = _Stats()
+    _check(load().tnmc_sweep_graph(arr, n, n_sweeps, ctypes.c_uint64(sweep_offset), int(record), ctypes.byref(st),
+                                   stream), "tnmc_sweep_graph")
+    return st.as_dict()

@@ -99,6 +99,9 @@ struct Workspace {
   size_t nn_tasks_cap = 0;
   TaskDesc* tune_tasks = nullptr;   // descriptors of the layout trials
   size_t tune_tasks_cap = 0;
+  long long* graph_state = nullptr;   // graph replays: [0] sweep counter, [1 + l] record slot of lattice l
+  size_t graph_state_cap = 0;
+  hipStream_t capture = nullptr;      // private stream on which sweeps are captured (default priority)
   // Device-side end of the last call that used this workspace, on whatever
   // stream it ran: the next call's stream waits for it, so calls made on
   // different streams never overwrite descriptors or workspace that kernels
@@ -772,6 +775,84 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
     r = read_counters(n_tasks, stats);
     if (r != TNMC_OK) return r;
     r = finish_timer(tm, stats);
+    if (r != TNMC_OK) return r;
+  }
+  return TNMC_OK;
+}
+
+tnmc_status tnmc_sweep_graph(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
+                             int32_t record, tnmc_stats* stats, void* stream) {
+  if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0) return TNMC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  hipStream_t s = (hipStream_t)stream;
+  WsOrder order(s);
+  if (n_sweeps == 0) return TNMC_OK;
+  std::vector<Task> tasks;
+  for (int p : {0, 1})
+    for (Task t : half_sweep_tasks(lats, n_lats, p)) {
+      t.key = p;
+      tasks.push_back(t);
+    }
+  Plan plan;
+  tnmc_status r = make_plan(tasks, plan);
+  if (r != TNMC_OK) return r;
+  const size_t n_tasks = plan.desc.size();
+  if (grow(g_ws.counters, g_ws.counters_cap, tnmc::kCounterStride * n_tasks) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.tasks, g_ws.tasks_cap, n_tasks) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.graph_state, g_ws.graph_state_cap, (size_t)n_lats + 1) != TNMC_OK) return TNMC_ERR_OOM;
+  for (size_t k = 0; k < n_tasks; ++k) plan.desc[k].counters = g_ws.counters + tnmc::kCounterStride * k;
+  std::vector<long long> state(n_lats + 1);
+  state[0] = (long long)sweep_offset;
+  for (int l = 0; l < n_lats; ++l) state[1 + l] = lats[l]->n_recorded;
+  // everything the replays read is set up on the caller's stream, outside the graph
+  HIP_TRY(hipMemcpyAsync(g_ws.tasks, plan.desc.data(), n_tasks * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(g_ws.graph_state, state.data(), state.size() * sizeof(long long), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(g_ws.counters, 0, tnmc::kCounterStride * n_tasks * sizeof(long long), s));
+  HIP_TRY(hipStreamSynchronize(s));   // plan.desc and state are released on return
+  if (!g_ws.capture) HIP_TRY(hipStreamCreateWithFlags(&g_ws.capture, hipStreamNonBlocking));
+  // one sweep: the launch pairs of both parities, the observables, and the
+  // advance of the device-resident sweep counter and record slots
+  auto* sweep_dev = reinterpret_cast<unsigned long long*>(g_ws.graph_state);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  struct GraphGuard {
+    hipGraph_t& g;
+    hipGraphExec_t& e;
+    ~GraphGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } guard{graph, exec};
+  HIP_TRY(hipStreamBeginCapture(g_ws.capture, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (const auto& g : plan.groups) {
+    const TaskDesc* dt = g_ws.tasks + g.first;
+    if (e == hipSuccess) e = tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, contract_cfg(g), g_ws.capture);
+    if (e == hipSuccess)
+      e = tnmc::launch_sample(dt, g.count, g.d, g.chi_max, g.precision, g.lx_max, g.ly_max, 0, g_ws.capture, sweep_dev);
+  }
+  if (record) {
+    for (int l = 0; l < n_lats && e == hipSuccess; ++l) {
+      tnmc_lattice* L = lats[l];
+      e = tnmc::launch_observables(L->dJc, L->dSc, L->n_chains, L->dpa, L->dpb, L->n_pairs, L->Lx, L->Ly, L->Lz, L->d,
+                                   L->dErec, L->dMrec, L->dqrec, g_ws.capture, g_ws.graph_state + 1 + l,
+                                   L->record_capacity);
+    }
+  }
+  if (e == hipSuccess) e = tnmc::launch_graph_advance(sweep_dev, g_ws.graph_state + 1, n_lats, g_ws.capture);
+  const hipError_t e_end = hipStreamEndCapture(g_ws.capture, &graph);
+  HIP_TRY(e);
+  HIP_TRY(e_end);
+  HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  for (int t = 0; t < n_sweeps; ++t) HIP_TRY(hipGraphLaunch(exec, s));
+  if (record)
+    for (int l = 0; l < n_lats; ++l)
+      lats[l]->n_recorded = std::min<int64_t>(lats[l]->n_recorded + n_sweeps, lats[l]->record_capacity);
+  if (stats) {
+    stats->contract_launches += (int64_t)n_sweeps * (int64_t)plan.groups.size();
+    stats->sample_launches += (int64_t)n_sweeps * (int64_t)plan.groups.size();
+    HIP_TRY(hipStreamSynchronize(s));
+    r = read_counters(n_tasks, stats);
     if (r != TNMC_OK) return r;
   }
   return TNMC_OK;

@@ -144,7 +144,8 @@ __device__ __forceinline__ double recip(double v) { return (v > 1e-300) ? rcp_nr
 // current one is used, so each step waits on LDS only.  ET: storage type of
 // the environments (double or float); the walk itself is FP64.
 template <typename ET, int DP, int CHIM, bool SB>
-__global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict__ tasks, uint64_t sweep, int lx_max,
+__global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict__ tasks, uint64_t sweep,
+                                                     const unsigned long long* __restrict__ sweep_dev, int lx_max,
                                                      int ly_max) {
   __shared__ SampleShared<DP, CHIM> sh;
   extern __shared__ __align__(16) double dyn[];
@@ -166,6 +167,9 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
   const gptr<const int8_t> forced = (path == 1) ? gmem(static_cast<const int8_t*>(t.spins + (size_t)z * plane))
                                                 : gmem(t.force_new);
   acquire_device();
+  // a captured graph replays the same launch every sweep: the sweep counter
+  // then comes from device memory
+  if (sweep_dev) sweep = load_device(sweep_dev);
   const int contract_status = load_device(t.status);
   const bool contract_fault = contract_status != 0;
   double* Rp = dyn + (size_t)path * (lx_max + 1) * CHIM * DP;
@@ -457,7 +461,8 @@ size_t sample_total_bytes(int Lx_max, int Ly_max) {
 }
 
 template <typename ET, int DP, int CHIM, bool SB>
-hipError_t launch_sample_v(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep, hipStream_t s) {
+hipError_t launch_sample_v(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep,
+                           const unsigned long long* sweep_dev, hipStream_t s) {
   const size_t bytes = sample_dyn_bytes<DP, CHIM>(Lx_max, Ly_max, SB);
   static size_t attr_bytes = 0;
   if (bytes > 48 * 1024 && bytes > attr_bytes) {
@@ -466,18 +471,20 @@ hipError_t launch_sample_v(const TaskDesc* tasks, int n, int Lx_max, int Ly_max,
     if (e != hipSuccess) return e;
     attr_bytes = bytes;
   }
-  hipLaunchKernelGGL((sample_kernel<ET, DP, CHIM, SB>), dim3(n), dim3(NTS), bytes, s, tasks, sweep, Lx_max, Ly_max);
+  hipLaunchKernelGGL((sample_kernel<ET, DP, CHIM, SB>), dim3(n), dim3(NTS), bytes, s, tasks, sweep, sweep_dev, Lx_max,
+                     Ly_max);
   return hipGetLastError();
 }
 
 // Only Potts at chi_max = 32 on rows longer than 59 sites needs the single tile.
 template <typename ET, int DP, int CHIM>
-hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep, hipStream_t s) {
+hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep,
+                           const unsigned long long* sweep_dev, hipStream_t s) {
   if constexpr (DP == 3 && CHIM == 32) {
     if (sample_single<DP, CHIM>(Lx_max, Ly_max))
-      return launch_sample_v<ET, DP, CHIM, true>(tasks, n, Lx_max, Ly_max, sweep, s);
+      return launch_sample_v<ET, DP, CHIM, true>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
   }
-  return launch_sample_v<ET, DP, CHIM, false>(tasks, n, Lx_max, Ly_max, sweep, s);
+  return launch_sample_v<ET, DP, CHIM, false>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
 }
 
 // Full-lattice energy of one configuration, FP64: one workgroup of 256.
@@ -507,9 +514,18 @@ __global__ __launch_bounds__(256) void observables_kernel(const float* const* __
                                                           int8_t* const* __restrict__ spins, int n_chains,
                                                           const int* __restrict__ pa, const int* __restrict__ pb,
                                                           int Lx, int Ly, int Lz, double* E_out, double* M_out,
-                                                          double* q_out) {
+                                                          double* q_out, const long long* __restrict__ slot_dev,
+                                                          long long capacity, int n_pairs) {
   __shared__ double red[4];
   acquire_device();
+  if (slot_dev) {
+    // graph replays: the record slot comes from device memory; full records drop the sweep
+    const long long i = load_device(slot_dev);
+    if (i >= capacity) return;
+    E_out += i * n_chains;
+    M_out += i * n_chains;
+    q_out += i * (n_pairs > 0 ? n_pairs : 1);
+  }
   const size_t n = (size_t)Lx * Ly * Lz;
   const size_t plane = (size_t)Lx * Ly;
   const int b = blockIdx.x;
@@ -561,21 +577,22 @@ __global__ __launch_bounds__(256) void observables_kernel(const float* const* __
 
 template <typename ET>
 hipError_t launch_sample_et(const TaskDesc* tasks, int n, int d, int chi_max, int Lx_max, int Ly_max, uint64_t sweep,
+                            const unsigned long long* sweep_dev,
                             hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (d == 2) {
     switch (chi_max) {
-      case 4: return launch_sample_t<ET, 2, 4>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 8: return launch_sample_t<ET, 2, 8>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 16: return launch_sample_t<ET, 2, 16>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 32: return launch_sample_t<ET, 2, 32>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 4: return launch_sample_t<ET, 2, 4>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
+      case 8: return launch_sample_t<ET, 2, 8>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
+      case 16: return launch_sample_t<ET, 2, 16>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
+      case 32: return launch_sample_t<ET, 2, 32>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
     }
   } else if (d == 3) {
     switch (chi_max) {
-      case 4: return launch_sample_t<ET, 3, 4>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 8: return launch_sample_t<ET, 3, 8>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 16: return launch_sample_t<ET, 3, 16>(tasks, n, Lx_max, Ly_max, sweep, s);
-      case 32: return launch_sample_t<ET, 3, 32>(tasks, n, Lx_max, Ly_max, sweep, s);
+      case 4: return launch_sample_t<ET, 3, 4>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
+      case 8: return launch_sample_t<ET, 3, 8>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
+      case 16: return launch_sample_t<ET, 3, 16>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
+      case 32: return launch_sample_t<ET, 3, 32>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
     }
   }
   return hipErrorInvalidValue;
@@ -601,9 +618,9 @@ size_t sample_lds_bytes(int d, int chi_max, int Lx, int Ly) {
 }
 
 hipError_t launch_sample(const TaskDesc* tasks, int n, int d, int chi_max, int precision, int Lx_max, int Ly_max,
-                         uint64_t sweep, hipStream_t s) {
-  if (precision == kPrecF32) return launch_sample_et<float>(tasks, n, d, chi_max, Lx_max, Ly_max, sweep, s);
-  return launch_sample_et<double>(tasks, n, d, chi_max, Lx_max, Ly_max, sweep, s);
+                         uint64_t sweep, hipStream_t s, const unsigned long long* sweep_dev) {
+  if (precision == kPrecF32) return launch_sample_et<float>(tasks, n, d, chi_max, Lx_max, Ly_max, sweep, sweep_dev, s);
+  return launch_sample_et<double>(tasks, n, d, chi_max, Lx_max, Ly_max, sweep, sweep_dev, s);
 }
 
 hipError_t launch_energy(const float* J, const int8_t* spins, int Lx, int Ly, int Lz, int d, double* out,
@@ -647,15 +664,32 @@ hipError_t launch_permute_spins(int8_t* const* lat_spins, int8_t* const* view_sp
 
 hipError_t launch_observables(const float* const* Jc, int8_t* const* spins, int n_chains, const int* pair_a,
                               const int* pair_b, int n_pairs, int Lx, int Ly, int Lz, int d, double* E_out,
-                              double* M_out, double* q_out, hipStream_t s) {
+                              double* M_out, double* q_out, hipStream_t s, const long long* slot_dev,
+                              long long capacity) {
   const int nb = n_chains + n_pairs;
   if (nb <= 0) return hipSuccess;
   if (d == 2)
     hipLaunchKernelGGL(observables_kernel<2>, dim3(nb), dim3(256), 0, s, Jc, spins, n_chains, pair_a, pair_b, Lx,
-                       Ly, Lz, E_out, M_out, q_out);
+                       Ly, Lz, E_out, M_out, q_out, slot_dev, capacity, n_pairs);
   else
     hipLaunchKernelGGL(observables_kernel<3>, dim3(nb), dim3(256), 0, s, Jc, spins, n_chains, pair_a, pair_b, Lx,
-                       Ly, Lz, E_out, M_out, q_out);
+                       Ly, Lz, E_out, M_out, q_out, slot_dev, capacity, n_pairs);
+  return hipGetLastError();
+}
+
+// End of a replayed sweep: the next sweep counter, and every lattice's next
+// record slot.  One thread; vector stores.
+__global__ void graph_advance_kernel(unsigned long long* sweep, long long* slots, int n_slots) {
+  acquire_device();
+  if (threadIdx.x == 0) {
+    *sweep += 1ull;
+    for (int i = 0; i < n_slots; ++i) slots[i] += 1;
+  }
+  release_device();
+}
+
+hipError_t launch_graph_advance(unsigned long long* sweep, long long* slots, int n_slots, hipStream_t s) {
+  hipLaunchKernelGGL(graph_advance_kernel, dim3(1), dim3(64), 0, s, sweep, slots, n_slots);
   return hipGetLastError();
 }
 

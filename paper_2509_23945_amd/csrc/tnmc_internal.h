@@ -86,14 +86,19 @@ hipError_t launch_contract_f64_mf(const TaskDesc* tasks, int n_tasks, int d, int
 hipError_t launch_contract_f32(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int full, hipStream_t s);
 hipError_t launch_contract_f32_mf(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int full, hipStream_t s);
 bool contract_has_compact(int d, int chi_max);
+// sweep_dev (may be null): the sweep counter in device memory, read by the
+// kernel instead of sweep (graph replays).
 hipError_t launch_sample(const TaskDesc* tasks, int n_tasks, int d, int chi_max, int precision, int Lx_max,
-                         int Ly_max, uint64_t sweep, hipStream_t s);
+                         int Ly_max, uint64_t sweep, hipStream_t s, const unsigned long long* sweep_dev = nullptr);
 hipError_t launch_energy(const float* J, const int8_t* spins, int Lx, int Ly, int Lz, int d,
                          double* out, hipStream_t s);
 hipError_t launch_observables(const float* const* Jc, int8_t* const* spins, int n_chains,
                               const int* pair_a, const int* pair_b, int n_pairs, int Lx, int Ly,
                               int Lz, int d, double* E_out, double* M_out, double* q_out,
-                              hipStream_t s);
+                              hipStream_t s, const long long* slot_dev = nullptr, long long capacity = 0);
+// slot_dev (may be null): the record slot in device memory (graph replays); the
+// outputs are then E_out + slot * n_chains etc., and slots >= capacity are dropped.
+hipError_t launch_graph_advance(unsigned long long* sweep, long long* slots, int n_slots, hipStream_t s);
 bool contract_supported(int d, int chi_max);
 bool contract_uses_global(int d, int chi_max);   // tiles in the per-task global scratch (gscr)
 size_t contract_lds_bytes(int d, int chi_max);
