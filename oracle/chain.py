@@ -82,27 +82,65 @@ def slice_update(J, spins, z: int, beta: float, chi: int, d: int, *, seed: int,
     return rec
 
 
-def sweep(J, spins, beta: float, chi: int, d: int, *, seed: int, chain: int, sweep_index: int):
-    """Even layers, then odd layers (in place).  Returns the number of accepted updates."""
+def slice_update_multi(J, spins, z: int, beta: float, chi: int, d: int, n_candidates: int, *, seed: int,
+                       chain: int, sweep: int):
+    """Several candidates per environment (main text, "TNMCMC": a batch of
+    candidate samples is drawn from the same approximate distribution and one
+    is kept).  The environments of layer z are contracted once; then
+    n_candidates independence-MH steps with the same q are chained, each
+    against the layer's state left by the previous one (main text Eq. 1).
+    Candidate k draws its sites with Philox purpose 2k and its MH uniform
+    with purpose 2k + 1, so one candidate is slice_update.  Every step is an
+    exact MH kernel for the layer's conditional, so their product is too.
+    Updates spins in place; returns the number of accepted candidates, the
+    log q of the initial and final layer, and E(final) - E(initial)."""
+    F = model.slice_field(J, spins, z, d)
+    envs, _ = bmps.environments(J, F, z, beta, chi, d)
+    cur = model.to_states(spins[z], d)
+    _, lq_cur, f_cur = sampler.sample_layer(envs, J, F, z, beta, d, forced=cur)
+    e_cur = model.slice_energy(J, F, cur, z, d)
+    lq0, e0 = lq_cur, e_cur
+    n_acc = 0
+    for k in range(n_candidates):
+        new, lq_new, f_new = sampler.sample_layer(envs, J, F, z, beta, d, seed=seed, chain=chain, sweep=sweep,
+                                                  purpose=2 * k)
+        e_new = model.slice_energy(J, F, new, z, d)
+        u = uniform(seed, chain, sweep, z, 2 * k + 1, 0)
+        if not (f_new or f_cur) and mh_accept(lq_cur, lq_new, beta, e_new - e_cur, u):
+            cur, lq_cur, e_cur, f_cur = new, lq_new, e_new, f_new
+            n_acc += 1
+    spins[z] = model.from_states(cur, d)
+    return {"accepted": n_acc, "logq_initial": lq0, "logq_final": lq_cur, "dE": e_cur - e0}
+
+
+def sweep(J, spins, beta: float, chi: int, d: int, *, seed: int, chain: int, sweep_index: int,
+          n_candidates: int = 1):
+    """Even layers, then odd layers (in place), n_candidates chained candidates
+    per layer (one: slice_update).  Returns the number of accepted updates."""
     Lz = spins.shape[0]
     n_acc = 0
     for parity in (0, 1):
         for z in range(parity, Lz, 2):
-            rec = slice_update(J, spins, z, beta, chi, d, seed=seed, chain=chain,
-                               sweep=sweep_index)
-            n_acc += int(rec["accepted"])
+            if n_candidates == 1:
+                rec = slice_update(J, spins, z, beta, chi, d, seed=seed, chain=chain, sweep=sweep_index)
+                n_acc += int(rec["accepted"])
+            else:
+                rec = slice_update_multi(J, spins, z, beta, chi, d, n_candidates, seed=seed, chain=chain,
+                                         sweep=sweep_index)
+                n_acc += rec["accepted"]
     return n_acc
 
 
 def run_chain(J, spins, beta: float, chi: int, d: int, n_sweeps: int, *, seed: int,
-              chain: int = 0, sweep_offset: int = 0):
+              chain: int = 0, sweep_offset: int = 0, n_candidates: int = 1):
     """Run n_sweeps sweeps in place; returns per-sweep energies, magnetisations and
     the acceptance count."""
     E = np.zeros(n_sweeps)
     M = np.zeros(n_sweeps)
     acc = 0
     for t in range(n_sweeps):
-        acc += sweep(J, spins, beta, chi, d, seed=seed, chain=chain, sweep_index=sweep_offset + t)
+        acc += sweep(J, spins, beta, chi, d, seed=seed, chain=chain, sweep_index=sweep_offset + t,
+                     n_candidates=n_candidates)
         E[t] = model.energy(J, spins, d)
         M[t] = model.magnetisation(spins, d)
     return E, M, acc

@@ -13,7 +13,9 @@ Stream layout (our reading; the paper does not fix an RNG):
 
 * key     = (seed, chain)
 * counter = (draw, z, sweep, purpose); purpose 0 = site draw (draw = y*Lx + x),
-  purpose 1 = MH decision (draw = 0)
+  purpose 1 = MH decision (draw = 0); with several candidates per
+  environment, candidate k draws its sites with purpose 2k and its MH uniform
+  with purpose 2k + 1 (candidate 0 is the single-candidate update)
 * the uniform is taken from output word 0:  U = ((w >> 11) + 0.5) * 2^-53,
   so 0 < U < 1.
 """

@@ -57,7 +57,8 @@ def draw(p: np.ndarray, U: float) -> int:
 
 
 def sample_layer(envs, J, F, z: int, beta: float, d: int, *, forced=None,
-                 seed: int = 0, chain: int = 0, sweep: int = 0, margins=None, site_probs=None):
+                 seed: int = 0, chain: int = 0, sweep: int = 0, margins=None, site_probs=None,
+                 purpose: int = PURPOSE_SITE):
     """Draw a layer configuration (state indices [y, x]) and its log q.
 
     With ``forced`` given, the draws are replaced by the given states
@@ -66,7 +67,9 @@ def sample_layer(envs, J, F, z: int, beta: float, d: int, *, forced=None,
     threshold is appended to it (to recognise near-ties).  If ``site_probs``
     is a list, every site's final probabilities p(u) are appended to it in
     visiting order (drawn or forced), so a caller can check which state each
-    site's uniform selects under these conditionals.
+    site's uniform selects under these conditionals.  ``purpose`` selects the
+    Philox stream of the site uniforms (another candidate drawn from the same
+    environments uses another purpose).
     Returns (states, logq, fault)."""
     Ly, Lx, _ = F.shape
     sig = sig_table(d)
@@ -107,7 +110,7 @@ def sample_layer(envs, J, F, z: int, beta: float, d: int, *, forced=None,
             if forced is not None:
                 u = int(forced[y, x])
             else:
-                U = uniform(seed, chain, sweep, z, PURPOSE_SITE, y * Lx + x)
+                U = uniform(seed, chain, sweep, z, purpose, y * Lx + x)
                 u = draw(p, U)
                 if margins is not None:
                     margins.append(float(np.min(np.abs(U - np.cumsum(p)[:-1]))))

@@ -156,3 +156,51 @@ def test_direction_cycled_chain_matches_enumeration():
         devs.append(np.mean(Es) - float(np.sum(w * En)))
     devs = np.array(devs)
     assert abs(devs.mean()) < 4 * devs.std(ddof=1) / math.sqrt(len(devs)) + 1e-12
+
+
+def test_multi_candidate_update_is_the_chained_kernel():
+    """Several candidates per environment: the distribution of the final layer
+    after 3 chained candidates from a fixed state equals row `a` of K^3, K the
+    exact one-candidate MH kernel (2x2 layer of a 2x2x4 lattice, chi = 1, so
+    rejections happen).  Frequencies over 3000 independent sweep counters,
+    each within five binomial standard deviations.  A chain that compared
+    every candidate with the initial state instead of the current one, or
+    reused one uniform stream, has another law and fails."""
+    J = synth.couplings_pm_j(2, 2, 4, 3)
+    s = synth.spins_random(2, 2, 4, 91)
+    z, beta, chi, K = 1, 1.3, 1, 3
+    Kmat, pi = _kernel(J, s, z, beta, chi, 2)
+    cfgs = [tuple(map(tuple, np.array(a))) for a in bf.all_layer_configs(2, 2, 2)]
+    start = cfgs.index(tuple(map(tuple, model.to_states(s[z], 2))))
+    want = np.linalg.matrix_power(Kmat, K)[start]
+    n = 3000
+    counts = np.zeros(len(cfgs))
+    for sw in range(n):
+        t = s.copy()
+        chain.slice_update_multi(J, t, z, beta, chi, 2, K, seed=17, chain=0, sweep=sw)
+        counts[cfgs.index(tuple(map(tuple, model.to_states(t[z], 2))))] += 1
+    freq = counts / n
+    sd = np.sqrt(want * (1 - want) / n)
+    assert np.all(np.abs(freq - want) < 5 * sd + 1e-3), (freq, want)
+    # the one-candidate form is slice_update itself
+    a, b = s.copy(), s.copy()
+    r1 = chain.slice_update(J, a, z, beta, chi, 2, seed=17, chain=0, sweep=5)
+    r2 = chain.slice_update_multi(J, b, z, beta, chi, 2, 1, seed=17, chain=0, sweep=5)
+    assert np.array_equal(a, b) and int(r1["accepted"]) == r2["accepted"]
+
+
+def test_multi_candidate_chain_averages_match_enumeration():
+    Lx, Ly, Lz, beta, chi = 2, 2, 4, 1.0, 1
+    J = synth.couplings_pm_j(Lx, Ly, Lz, 3)
+    st, E = bf.lattice_states(J, Lx, Ly, Lz, 2)
+    w = np.exp(-beta * (E - E.min()))
+    w /= w.sum()
+    E_exact = float(np.sum(w * E))
+    s = synth.spins_random(Lx, Ly, Lz, 21)
+    n = 1500
+    Es, _, acc = chain.run_chain(J, s, beta, chi, 2, n, seed=21, chain=0, n_candidates=3)
+    Es = Es[50:]
+    tau, _ = autocorr.tau_int(Es)
+    err = math.sqrt(2 * max(tau, 0.5) * np.var(Es) / len(Es))
+    assert abs(Es.mean() - E_exact) < 4 * err + 1e-12
+    assert acc < 3 * 4 * n
