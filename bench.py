@@ -38,6 +38,9 @@ WORKLOADS = {
     "ea8": dict(L=8, chi=16, beta=0.5, n_inst=1, n_rep=1),
     # small layers where the learned proposal is accepted: 8^3 +-J, beta = 1.0, 32 instances x 2 replicas
     "ea8b": dict(L=8, chi=16, beta=1.0, n_inst=32, n_rep=2),
+    # a truncating proposal (chi = 4 on 16-wide layers), where MH rejects and several candidates per
+    # environment pay: 16^3 +-J, beta = 1.0, 64 instances x 2 replicas
+    "ea16t": dict(L=16, chi=4, beta=1.0, n_inst=64, n_rep=2),
     # heterogeneous batch: Gaussian couplings, chain k has L = Ls[k % 3],
     # chi = chis[(k // 3) % 3] and beta drawn uniformly in [0.5, 1.5]; chains of
     # the chi = 64 class are left out (that tile size is not built)
@@ -136,13 +139,14 @@ def make_lattice(name: str, record_capacity: int = 0):
     return lat, cfg, J, spins, inst, betas
 
 
-def make_lattices(name: str, record_capacity: int = 0, precision: int = 0):
+def make_lattices(name: str, record_capacity: int = 0, precision: int = 0, n_candidates: int = 1):
     import paper_2509_23945_amd as tn
     groups = build_groups(name)
     lats = [tn.tnmc_lattice_init(Lx=g["L"], Ly=g["L"], Lz=g["L"], d=g.get("d", 2), chi=g["chi"], J=g["J"],
                                  beta=g["betas"],
                                  spins=g["spins"], chain_instance=g["inst"], seed=PHILOX_SEED, pairs=g["pairs"],
-                                 record_capacity=record_capacity, precision=precision) for g in groups]
+                                 record_capacity=record_capacity, precision=precision,
+                                 n_candidates=n_candidates) for g in groups]
     return lats, groups
 
 
@@ -443,6 +447,8 @@ def main():
                     help="sweeps per form of the tau_int leg (the same for every form; 0 skips the leg)")
     ap.add_argument("--tau-seconds", type=float, default=120.0,
                     help="wall-time cap per form of the tau_int leg")
+    ap.add_argument("--candidates", type=int, default=1,
+                    help="candidates drawn per layer environment and chained by MH (every TN form)")
     ap.add_argument("--graph", action="store_true",
                     help="time the FP64 sweeps as HIP-graph replays (tnmc_sweep_graph) instead of eager launches")
     ap.add_argument("--engine", choices=("auto", "valu", "mfma"), default="auto",
@@ -468,7 +474,7 @@ def main():
         tn.tnmc_autotune_pin(-1, 1 if args.engine == "mfma" else 0)
     tau_on = args.tau_sweeps > 0
     cap = max(args.steps, args.tau_sweeps if tau_on else 0)
-    lats, groups = make_lattices(args.workload, record_capacity=cap)
+    lats, groups = make_lattices(args.workload, record_capacity=cap, n_candidates=args.candidates)
     tau_on = tau_on and len(lats) == 1 and groups[0]["pairs"] is not None
     cfg = WORKLOADS[args.workload]
     n_chains = sum(len(g["inst"]) for g in groups)
@@ -548,7 +554,7 @@ def main():
         "dtype": "f64",
         "data": data,
         "config": {"workload": desc, "chains": n_chains, "slice_updates_per_step": updates_per_sweep,
-                   "parallelism": "none (1 GPU)"},
+                   "candidates_per_environment": args.candidates, "parallelism": "none (1 GPU)"},
         "acceptance": st["accepted"] / max(1, st["proposed"]),
         "numeric_faults": st["numeric_faults"],
         "contract_retries": st["contract_retries"],
@@ -564,7 +570,8 @@ def main():
         # the reduced-precision form on the same inputs: FP32 environments, rank
         # cut-off at FP32 resolution, FP64 factorisations, log q and MH
         print(f"[bench] reduced-precision form: timing {args.steps} sweeps", file=sys.stderr, flush=True)
-        lats32, _ = make_lattices(args.workload, record_capacity=cap, precision=tn.TNMC_FP32)
+        lats32, _ = make_lattices(args.workload, record_capacity=cap, precision=tn.TNMC_FP32,
+                                  n_candidates=args.candidates)
         secs32, st32 = time_form(tn, lats32, args.warmup, args.steps, stream)
         v32 = args.steps * updates_per_sweep / secs32
         out["reduced_precision"] = {

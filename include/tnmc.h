@@ -73,6 +73,12 @@ typedef struct {
   int32_t n_pairs;              /* replica pairs for the overlap q, >= 0 */
   const int32_t* pairs;         /* [n_pairs][2] chain indices (same instance) */
   int32_t record_capacity;      /* sweeps of observables kept on the device */
+  int32_t n_candidates;         /* 0 or 1: one proposal per layer update; K in 2..64: sweeps draw K
+                                   candidates from each layer's environments and chain K
+                                   independence-MH steps (main text, "TNMCMC": a batch of candidates
+                                   from the same approximate distribution, one kept); candidate k
+                                   uses Philox purposes 2k (sites) and 2k + 1 (MH).  Single-task
+                                   calls (propose, logq) always draw one. */
 } tnmc_lattice_desc;
 
 /* Allocate the device state of a batch of chains (SM Alg. 2 inputs: L, {J},
@@ -173,7 +179,10 @@ tnmc_status tnmc_sweep_direction(tnmc_lattice* const* lats, int32_t n_lats, int3
 /* One half-sweep (parity 0: even layers, 1: odd layers) of every chain in
  * lats, as inside tnmc_sweep.  trace (DEVICE pointer or NULL) receives, for
  * task t in the order lattice-major, chain, layer z = parity, parity+2, ...:
- * trace[5t..5t+4] = {log q(new), log q(current), dE, accepted, fault}. */
+ * trace[5t..5t+4] = {log q(new), log q(current), dE, accepted, fault}; for a
+ * lattice with several candidates per environment: {log q of the final layer,
+ * log q of the initial one, E(final) - E(initial), candidates accepted,
+ * candidates rejected for a numeric fault}. */
 tnmc_status tnmc_half_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t parity,
                             uint64_t sweep, double* trace, tnmc_stats* stats, void* hip_stream);
 

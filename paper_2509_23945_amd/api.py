@@ -67,6 +67,7 @@ class _Desc(ctypes.Structure):
         ("n_pairs", ctypes.c_int32),
         ("pairs", ctypes.POINTER(ctypes.c_int32)),
         ("record_capacity", ctypes.c_int32),
+        ("n_candidates", ctypes.c_int32),
     ]
 
 
@@ -205,7 +206,7 @@ class Lattice:
 
 
 def tnmc_lattice_init(*, Lx, Ly, Lz, d, chi, J, beta, spins, chain_instance=None, seed=0, chain_key=None,
-                      pairs=None, record_capacity=0, precision=TNMC_FP64) -> Lattice:
+                      pairs=None, record_capacity=0, precision=TNMC_FP64, n_candidates=1) -> Lattice:
     lib = load()
     J = np.ascontiguousarray(J, dtype=np.float32)
     spins = np.ascontiguousarray(spins, dtype=np.int8)
@@ -224,7 +225,7 @@ def tnmc_lattice_init(*, Lx, Ly, Lz, d, chi, J, beta, spins, chain_instance=None
     desc = _Desc(Lx, Ly, Lz, d, chi, precision, n_chains, n_inst, _ptr(J, ctypes.c_float),
                  _ptr(ci, ctypes.c_int32), _ptr(beta, ctypes.c_double), _ptr(spins, ctypes.c_int8),
                  ctypes.c_uint64(seed), _ptr(ck, ctypes.c_uint64), pr.shape[0],
-                 _ptr(pr, ctypes.c_int32) if pr.shape[0] else None, record_capacity)
+                 _ptr(pr, ctypes.c_int32) if pr.shape[0] else None, record_capacity, n_candidates)
     h = ctypes.c_void_p()
     _check(lib.tnmc_lattice_init(ctypes.byref(desc), ctypes.byref(h)), "tnmc_lattice_init")
     lat = Lattice(h, Lx, Ly, Lz, d, chi, n_chains, pr.shape[0], record_capacity)

@@ -43,6 +43,7 @@ constexpr int kLyMax = 64;
 
 struct tnmc_lattice {
   int Lx = 0, Ly = 0, Lz = 0, d = 2, chi = 1, chi_max = 4, precision = TNMC_FP64;
+  int n_cand = 1;           // candidates per environment in sweeps
   int n_chains = 0, n_instances = 0, n_pairs = 0, record_capacity = 0;
   int64_t n_recorded = 0;
   uint64_t seed = 0;
@@ -229,6 +230,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.d = L->d;
     t.chi_max = L->chi_max;
     t.write_back = 1;
+    t.n_cand = L->n_cand;
     eo += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision));
     if (tnmc::contract_uses_global(L->d, L->chi_max))
       go += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
@@ -474,6 +476,7 @@ tnmc_status run_single(tnmc_lattice* lat, int chain, int z, uint64_t sweep, cons
   plan.desc[0].record = drec;
   plan.desc[0].counters = nullptr;
   plan.desc[0].write_back = 0;
+  plan.desc[0].n_cand = 1;   // a single proposal
   plan.desc[0].s_new_out = g_ws.bytes;
   if (force_host) {
     HIP_TRY(hipMemcpyAsync(g_ws.bytes + plane, force_host, plane, hipMemcpyHostToDevice, s));
@@ -534,6 +537,7 @@ tnmc_status tnmc_lattice_init(const tnmc_lattice_desc* ds, tnmc_lattice** out) {
     return TNMC_ERR_ARG;
   if (ds->n_pairs < 0 || (ds->n_pairs > 0 && !ds->pairs) || ds->record_capacity < 0) return TNMC_ERR_ARG;
   if (ds->precision != TNMC_FP64 && ds->precision != TNMC_FP32) return TNMC_ERR_UNSUPPORTED;
+  if (ds->n_candidates < 0 || ds->n_candidates > 64) return TNMC_ERR_ARG;
   const int cm = tnmc::chi_bucket(ds->chi);
   if (cm == 0 || !tnmc::contract_supported(ds->d, cm)) return TNMC_ERR_UNSUPPORTED;
   // the sampler keeps a row of right environments and two site tiles in LDS
@@ -558,6 +562,7 @@ tnmc_status tnmc_lattice_init(const tnmc_lattice_desc* ds, tnmc_lattice** out) {
   L->chi = ds->chi;
   L->chi_max = cm;
   L->precision = ds->precision;
+  L->n_cand = ds->n_candidates > 0 ? ds->n_candidates : 1;
   L->n_chains = ds->n_chains;
   L->n_instances = ds->n_instances;
   L->n_pairs = ds->n_pairs;
@@ -1922,6 +1927,7 @@ tnmc_status make_view(tnmc_lattice* L, int dir, tnmc_lattice** out) {
   V->chi = L->chi;
   V->chi_max = L->chi_max;
   V->precision = L->precision;
+  V->n_cand = L->n_cand;
   V->n_chains = L->n_chains;
   V->n_instances = L->n_instances;
   V->seed = L->seed;

@@ -32,7 +32,7 @@ template <int DP, int CHIM>
 struct SampleShared {
   double l[2][2][CHIM];               // left vector per path, two buffers alternating by site
   double et[2][LXMAX][DP][DP];        // exp(beta (F(x,u) + Jy sig(u, above)) + beta Jx(x-1) sig(t,u)) [path][x][t][u]
-  double uni[LXMAX];                  // the row's uniforms (drawn path)
+  double uni[2][LXMAX];               // the row's uniforms per drawing path
   double pch[2][LXMAX];               // probability of the state taken at each site of the row
   int bnd[2][LXMAX];                  // bond dimensions of E_y and E_{y+1}
   double lq[2];
@@ -164,8 +164,8 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
   const gptr<int8_t> spins = gmem(t.spins);
   const gptr<const int> bond = gmem(static_cast<const int*>(t.bond));
   const size_t plane = (size_t)Lx * Ly;
-  const gptr<const int8_t> forced = (path == 1) ? gmem(static_cast<const int8_t*>(t.spins + (size_t)z * plane))
-                                                : gmem(t.force_new);
+  const gptr<const int8_t> forced0 = (path == 1) ? gmem(static_cast<const int8_t*>(t.spins + (size_t)z * plane))
+                                                 : gmem(t.force_new);
   acquire_device();
   // a captured graph replays the same launch every sweep: the sweep counter
   // then comes from device memory
@@ -176,12 +176,31 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
   double* sAb = dyn + (size_t)2 * (lx_max + 1) * CHIM * DP;
   constexpr int NBUF = SB ? 1 : 2;              // site tiles in LDS (SB: one, reused after a barrier)
   int8_t* cfg = reinterpret_cast<int8_t*>(sAb + NBUF * SITEL);
+  // configuration tiles: 0 and 1, the layers walked by the two paths; 2, the
+  // layer's current state while several candidates are chained
+  int8_t* cur = cfg + (size_t)2 * ly_max * lx_max;
 #define RENV(x, al, u) Rp[((size_t)(x) * CHIM + (al)) * DP + (u)]
 #define CFG(p, y, x) cfg[((size_t)(p) * ly_max + (y)) * lx_max + (x)]
+  // Several candidates per environment (t.n_cand = K >= 1): pass 0 draws
+  // candidate 0 on path 0 and walks the current layer on path 1; pass j >= 1
+  // draws candidates 2j - 1 and 2j on the two paths.  Candidate c draws its
+  // sites with Philox purpose 2c and is accepted with the uniform of purpose
+  // 2c + 1 against the state the earlier candidates left; K = 1 is the
+  // single-candidate update.
+  const int n_cand = max(t.n_cand, 1);
+  const int n_pass = 1 + n_cand / 2;
+  double lq_cur = 0.0, lq_init = 0.0, e_rel = 0.0;   // path 0 keeps the chain's state
+  int f_cur = 0, n_acc = 0, faults = 0, acc0 = 0;
+  double lq_new0 = 0.0, dE0 = 0.0;
+  for (int pass = 0; pass < n_pass; ++pass) {
+  const int cand = (pass == 0) ? (path == 0 ? 0 : -1) : 2 * pass - 1 + path;   // -1: the current layer
+  const gptr<const int8_t> forced = (pass == 0) ? forced0 : nullptr;
+  const uint64_t purpose = (uint64_t)(2 * max(cand, 0));
 
   // the site tiles start at zero: entries outside a site's corner then hold
   // finite values only (zeros, or an earlier site's entries)
-  for (int i = tid; i < NBUF * SITEL; i += NTS) sAb[i] = 0.0;
+  if (pass == 0)
+    for (int i = tid; i < NBUF * SITEL; i += NTS) sAb[i] = 0.0;
   __syncthreads();
   double pf[PF];
   int buf = 0;
@@ -222,7 +241,7 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
       for (int tt = 0; tt < DP; ++tt)
 #pragma unroll
         for (int u = 0; u < DP; ++u) sh.et[path][x][tt][u] = exp(ftv[u] + jxv * sigma<DP>(tt, u));
-      if (path == 0) sh.uni[x] = philox_uniform((uint64_t)(y * Lx + x), (uint64_t)z, sweep, 0ull, t.key0, t.key1);
+      if (!forced) sh.uni[path][x] = philox_uniform((uint64_t)(y * Lx + x), (uint64_t)z, sweep, purpose, t.key0, t.key1);
     }
     if (lane < CHIM) {
 #pragma unroll
@@ -336,7 +355,7 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
       if (forced) {
         s = CFG(path, y, x);
       } else {
-        const double U = sh.uni[x];
+        const double U = sh.uni[path][x];
         s = DP - 1;
         double c = 0.0;
 #pragma unroll
@@ -393,51 +412,103 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
     sh.fault[path] = fault;
   }
   __syncthreads();
-  if (path != 0) return;
-
-  // energy change E(new) - E(current) of the layer: in-layer bonds and held-layer field
-  double dE = 0.0;
-  for (int i = lane; i < Ly * Lx; i += 64) {
-    const int y = i / Lx, x = i % Lx;
-    const int a = CFG(0, y, x), o = CFG(1, y, x);
-    double e = -(held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, a) - held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, o));
-    if (x + 1 < Lx) {
-      const double jx = (double)J[(size_t)z * plane + (size_t)y * Lx + x];
-      e -= jx * (sigma<DP>(a, CFG(0, y, x + 1)) - sigma<DP>(o, CFG(1, y, x + 1)));
+  if (path == 0) {
+    // energy change E(a) - E(o) of two configurations of the layer: in-layer
+    // bonds and held-layer field (exact dyadic sums)
+    auto delta_e = [&](const int8_t* A, const int8_t* O) {
+      double dE = 0.0;
+      for (int i = lane; i < Ly * Lx; i += 64) {
+        const int y = i / Lx, x = i % Lx;
+        const int a = A[(size_t)y * lx_max + x], o = O[(size_t)y * lx_max + x];
+        double e = -(held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, a) - held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, o));
+        if (x + 1 < Lx) {
+          const double jx = (double)J[(size_t)z * plane + (size_t)y * Lx + x];
+          e -= jx * (sigma<DP>(a, A[(size_t)y * lx_max + x + 1]) - sigma<DP>(o, O[(size_t)y * lx_max + x + 1]));
+        }
+        if (y + 1 < Ly) {
+          const double jy = (double)J[plane * Lz + (size_t)z * plane + (size_t)y * Lx + x];
+          e -= jy * (sigma<DP>(a, A[(size_t)(y + 1) * lx_max + x]) - sigma<DP>(o, O[(size_t)(y + 1) * lx_max + x]));
+        }
+        dE += e;
+      }
+      return wave_sum(dE);
+    };
+    auto keep = [&](const int8_t* A) {   // the current state becomes A
+      for (int i = lane; i < Ly * Lx; i += 64) {
+        const size_t o = (size_t)(i / Lx) * lx_max + i % Lx;
+        cur[o] = A[o];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    const int8_t* tile0 = &CFG(0, 0, 0);
+    const int8_t* tile1 = &CFG(1, 0, 0);
+    if (pass == 0) {
+      // candidate 0 against the current layer (walked on path 1)
+      dE0 = delta_e(tile0, tile1);
+      lq_new0 = sh.lq[0];
+      lq_init = sh.lq[1];
+      const int fault0 = (sh.fault[0] | sh.fault[1] | (contract_fault ? 1 : 0)) ? 1 : 0;
+      const double lr = lq_init - lq_new0 - beta * dE0;
+      const double Uacc = philox_uniform(0ull, (uint64_t)z, sweep, 1ull, t.key0, t.key1);
+      acc0 = (!fault0 && Uacc < exp(fmin(0.0, lr))) ? 1 : 0;
+      faults += fault0;
+      n_acc = acc0;
+      if (n_cand > 1) keep(acc0 ? tile0 : tile1);
+      lq_cur = acc0 ? lq_new0 : lq_init;
+      e_rel = acc0 ? dE0 : 0.0;
+      f_cur = acc0 ? sh.fault[0] : sh.fault[1];
+    } else {
+      for (int p2 = 0; p2 < 2; ++p2) {
+        const int c = 2 * pass - 1 + p2;
+        if (c >= n_cand) break;
+        const int8_t* tile = p2 ? tile1 : tile0;
+        const double dE = delta_e(tile, cur);
+        const int fc = (sh.fault[p2] | f_cur | (contract_fault ? 1 : 0)) ? 1 : 0;
+        const double lr = lq_cur - sh.lq[p2] - beta * dE;
+        const double Uacc = philox_uniform(0ull, (uint64_t)z, sweep, (uint64_t)(2 * c + 1), t.key0, t.key1);
+        const int acc = (!fc && Uacc < exp(fmin(0.0, lr))) ? 1 : 0;
+        faults += fc;
+        if (acc) {
+          keep(tile);
+          lq_cur = sh.lq[p2];
+          e_rel += dE;
+          f_cur = sh.fault[p2];
+          n_acc += 1;
+        }
+      }
     }
-    if (y + 1 < Ly) {
-      const double jy = (double)J[plane * Lz + (size_t)z * plane + (size_t)y * Lx + x];
-      e -= jy * (sigma<DP>(a, CFG(0, y + 1, x)) - sigma<DP>(o, CFG(1, y + 1, x)));
-    }
-    dE += e;
   }
-  dE = wave_sum(dE);
-  const double lq_new = sh.lq[0], lq_old = sh.lq[1];
-  const int any_fault = (sh.fault[0] | sh.fault[1] | (contract_fault ? 1 : 0)) ? 1 : 0;
-  const double lr = lq_old - lq_new - beta * dE;
-  const double Uacc = philox_uniform(0ull, (uint64_t)z, sweep, 1ull, t.key0, t.key1);
-  const int accepted = (!any_fault && Uacc < exp(fmin(0.0, lr))) ? 1 : 0;
+  __syncthreads();   // the next pass rewrites the configuration tiles
+  }   // passes
+  if (path != 0) return;
+  const int8_t* result = (n_cand > 1) ? cur : &CFG(0, 0, 0);   // the layer to write back if accepted
   if (t.s_new_out) {
     for (int i = lane; i < Ly * Lx; i += 64) t.s_new_out[i] = spin_of<DP>(CFG(0, i / Lx, i % Lx));
   }
-  if (t.write_back && accepted) {
-    for (int i = lane; i < Ly * Lx; i += 64) spins[(size_t)z * plane + i] = spin_of<DP>(CFG(0, i / Lx, i % Lx));
+  if (t.write_back && n_acc > 0) {
+    for (int i = lane; i < Ly * Lx; i += 64)
+      spins[(size_t)z * plane + i] = spin_of<DP>(result[(size_t)(i / Lx) * lx_max + i % Lx]);
   }
 #undef RENV
 #undef CFG
   if (lane == 0) {
     if (t.record) {
-      t.record[0] = lq_new;
-      t.record[1] = lq_old;
-      t.record[2] = dE;
-      t.record[3] = (double)accepted;
+      // one candidate: {log q(new), log q(current), dE, accepted, fault bits}; several: {log q of
+      // the final layer, log q of the initial one, E(final) - E(initial), candidates accepted, faults}
+      t.record[0] = (n_cand > 1) ? lq_cur : lq_new0;
+      t.record[1] = lq_init;
+      t.record[2] = (n_cand > 1) ? e_rel : dE0;
+      t.record[3] = (double)n_acc;
       // 0 = no fault; else bits 0-1: new path, bits 2-3: current path, bits 4-6: contraction
-      t.record[4] = (double)(sh.fault[0] | (sh.fault[1] << 2) | ((contract_status & 7) << 4));
+      t.record[4] = (n_cand > 1) ? (double)faults
+                                 : (double)(sh.fault[0] | (sh.fault[1] << 2) | ((contract_status & 7) << 4));
     }
     if (t.counters) {
-      add_device(t.counters + 0, 1);
-      add_device(t.counters + 1, accepted);
-      add_device(t.counters + 2, any_fault);
+      add_device(t.counters + 0, n_cand);
+      add_device(t.counters + 1, n_acc);
+      add_device(t.counters + 2, faults);
     }
   }
   release_device();
@@ -447,7 +518,7 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
 template <int DP, int CHIM>
 size_t sample_dyn_bytes(int Lx_max, int Ly_max, bool single) {
   return sizeof(double) * (2 * (size_t)(Lx_max + 1) * CHIM * DP + (single ? 1 : 2) * (size_t)site_lds<DP, CHIM>()) +
-         2 * (size_t)Lx_max * Ly_max;
+         3 * (size_t)Lx_max * Ly_max;
 }
 // The double-buffered layout when it fits a CU's LDS, else one site tile.
 template <int DP, int CHIM>

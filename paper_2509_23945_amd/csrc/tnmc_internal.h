@@ -53,7 +53,7 @@ struct TaskDesc {
   int Lx, Ly, Lz, z, chi, d;
   int chi_max;             // storage stride of the environment tensors
   int write_back;          // apply the MH decision to spins
-  int pad_;
+  int n_cand;              // candidates drawn from the environments and chained by MH (<= 1: one)
 };
 
 // Per-task workspace sizes (doubles / ints) for a (Lx, Ly, d, chi_max) task;

@@ -51,7 +51,7 @@ def announce(msg: str) -> None:
 
 
 def make_lattice(Lx, Ly, Lz, d, chi, *, kind="pmj", beta=1.0, seed=0, n_chains=1, init="random",
-                 pairs=None, record_capacity=0, philox_seed=12345, precision=tn.TNMC_FP64):
+                 pairs=None, record_capacity=0, philox_seed=12345, precision=tn.TNMC_FP64, n_candidates=1):
     """Couplings (one instance per chain pair) and initial spins from synth; returns
     (lattice handle, J[n_inst], spins[n_chains], betas)."""
     n_inst = max(1, (n_chains + 1) // 2) if pairs is not None else n_chains
@@ -75,7 +75,7 @@ def make_lattice(Lx, Ly, Lz, d, chi, *, kind="pmj", beta=1.0, seed=0, n_chains=1
     inst = np.array([c // 2 if pairs is not None else c for c in range(n_chains)], dtype=np.int32)
     lat = tn.tnmc_lattice_init(Lx=Lx, Ly=Ly, Lz=Lz, d=d, chi=chi, J=J, beta=betas, spins=spins,
                                chain_instance=inst, seed=philox_seed, pairs=pairs,
-                               record_capacity=record_capacity, precision=precision)
+                               record_capacity=record_capacity, precision=precision, n_candidates=n_candidates)
     return lat, J[inst], spins, betas
 
 
