@@ -38,16 +38,15 @@ WORKLOADS = {
     "ea8": dict(L=8, chi=16, beta=0.5, n_inst=1, n_rep=1),
     # small layers where the learned proposal is accepted: 8^3 +-J, beta = 1.0, 32 instances x 2 replicas
     "ea8b": dict(L=8, chi=16, beta=1.0, n_inst=32, n_rep=2),
-    # a truncating proposal (chi = 4 on 16-wide layers), where MH rejects and several candidates per
+    # a truncating proposal (chi = 2 on 16-wide layers), where MH rejects and several candidates per
     # environment pay: 16^3 +-J, beta = 1.0, 64 instances x 2 replicas
-    "ea16t": dict(L=16, chi=4, beta=1.0, n_inst=64, n_rep=2),
+    "ea16t": dict(L=16, chi=2, beta=1.0, n_inst=64, n_rep=2),
     # heterogeneous batch: Gaussian couplings, chain k has L = Ls[k % 3],
-    # chi = chis[(k // 3) % 3] and beta drawn uniformly in [0.5, 1.5]; chains of
-    # the chi = 64 class are left out (that tile size is not built)
+    # chi = chis[(k // 3) % 3] and beta drawn uniformly in [0.5, 1.5]
     # 3-state Potts, 64^3, uniform J = 1 at beta = 0.5505 (near the transition), chi = 32: 4 chains
     # started ordered (all state 0) and 4 from uniform random states
     "potts64": dict(potts=True, L=64, chi=32, beta=0.5505, n_ordered=4, n_random=4),
-    "c3": dict(mixed=True, n_chains=512, Ls=(16, 24, 32), chis=(16, 32, 64), built_chis=(16, 32),
+    "c3": dict(mixed=True, n_chains=512, Ls=(16, 24, 32), chis=(16, 32, 64), built_chis=(16, 32, 64),
                beta_range=(0.5, 1.5)),
 }
 PHILOX_SEED = 20250928
@@ -533,7 +532,7 @@ def main():
     elif cfg.get("mixed"):
         desc = (f"heterogeneous batch, Gaussian J (2^-20 grid), open BC: chain k of {cfg['n_chains']} has "
                 f"L={list(cfg['Ls'])}[k%3], chi={list(cfg['chis'])}[(k//3)%3], beta uniform in "
-                f"{list(cfg['beta_range'])}; the chi=64 class ({cfg['n_chains'] - n_chains} chains) left out")
+                f"{list(cfg['beta_range'])}" + (f"; {cfg['n_chains'] - n_chains} chains left out" if n_chains < cfg['n_chains'] else ""))
         data = "synthetic (seeded Gaussian couplings, seeded betas, random initial spins)"
     else:
         L = cfg["L"]

@@ -19,6 +19,7 @@ bool contract_has_compact(int d, int chi_max) {
       case 8: return layout_has_compact<2, 8>();
       case 16: return layout_has_compact<2, 16>();
       case 32: return layout_has_compact<2, 32>();
+      case 64: return layout_has_compact<2, 64>();
     }
   } else if (d == 3) {
     switch (chi_max) {
@@ -41,6 +42,7 @@ size_t contract_lds_bytes(int d, int chi_max) {
       case 8: return sizeof(double) * Layout<2, 8>::total;
       case 16: return sizeof(double) * Layout<2, 16>::total;
       case 32: return sizeof(double) * Layout<2, 32>::total;
+      case 64: return sizeof(double) * Layout<2, 64>::total;
     }
   } else if (d == 3) {
     switch (chi_max) {
@@ -64,6 +66,7 @@ int chi_bucket(int chi) {
   if (chi <= 8) return 8;
   if (chi <= 16) return 16;
   if (chi <= 32) return 32;
+  if (chi <= 64) return 64;
   return 0;
 }
 
@@ -73,6 +76,8 @@ hipError_t launch_contract_f64(const TaskDesc* tasks, int n, int d, int chi_max,
 
 hipError_t launch_contract(const TaskDesc* tasks, int n, int d, int chi_max, int precision, ContractCfg cfg,
                            hipStream_t s) {
+  // chi_max = 64 (tiles in global memory) is built with vector-ALU products only
+  if (chi_max == 64) cfg.mfma = 0;
   if (precision == kPrecF32)
     return cfg.mfma ? launch_contract_f32_mf(tasks, n, d, chi_max, cfg.full, s)
                     : launch_contract_f32(tasks, n, d, chi_max, cfg.full, s);

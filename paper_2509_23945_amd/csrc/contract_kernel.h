@@ -1673,6 +1673,9 @@ hipError_t launch_contract_et(const TaskDesc* tasks, int n, int d, int chi_max, 
       case 8: return launch_contract_t<ET, 2, 8, MF>(tasks, n, full, s);
       case 16: return launch_contract_t<ET, 2, 16, MF>(tasks, n, full, s);
       case 32: return launch_contract_t<ET, 2, 32, MF>(tasks, n, full, s);
+      case 64:
+        if constexpr (!MF) return launch_contract_t<ET, 2, 64, MF>(tasks, n, full, s);
+        break;
     }
   } else if (d == 3) {
     switch (chi_max) {

@@ -184,15 +184,28 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     if (la->precision != lb->precision) return la->precision < lb->precision;
     return task_cost(tasks[a]) > task_cost(tasks[b]);
   });
+  // Tasks of different keys (the two parities of a sweep) run in launches
+  // strictly in key order, and a task's workspace is dead once its sampler
+  // launch has run, so each key's tasks lay their workspace out from the
+  // start of the buffers again: the buffers hold the largest key's share.
   size_t env_need = 0, rscr_need = 0, int_need = 0, dbl_need = 0, gscr_need = 0;
-  for (int i : order) {
-    const auto* L = tasks[i].lat;
-    if (tnmc::contract_uses_global(L->d, L->chi_max))
-      gscr_need += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
-    env_need += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision));
-    rscr_need += tnmc::pad256_doubles(tnmc::rscr_doubles(L->Lx, L->d, L->chi_max));
-    int_need += tnmc::pad256_ints((size_t)L->Ly * L->Lx + 1);
-    dbl_need += tnmc::pad256_doubles((size_t)L->Ly);
+  {
+    size_t e = 0, r = 0, in = 0, db = 0, g = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+      const auto* L = tasks[order[k]].lat;
+      if (k > 0 && tasks[order[k]].key != tasks[order[k - 1]].key) e = r = in = db = g = 0;
+      if (tnmc::contract_uses_global(L->d, L->chi_max))
+        g += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
+      e += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision));
+      r += tnmc::pad256_doubles(tnmc::rscr_doubles(L->Lx, L->d, L->chi_max));
+      in += tnmc::pad256_ints((size_t)L->Ly * L->Lx + 1);
+      db += tnmc::pad256_doubles((size_t)L->Ly);
+      env_need = std::max(env_need, e);
+      rscr_need = std::max(rscr_need, r);
+      int_need = std::max(int_need, in);
+      dbl_need = std::max(dbl_need, db);
+      gscr_need = std::max(gscr_need, g);
+    }
   }
   if (grow(g_ws.env, g_ws.env_cap, env_need) != TNMC_OK) return TNMC_ERR_OOM;
   if (grow(g_ws.rscr, g_ws.rscr_cap, rscr_need) != TNMC_OK) return TNMC_ERR_OOM;
@@ -207,6 +220,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
   for (size_t k = 0; k < order.size(); ++k) {
     const Task& tk = tasks[order[k]];
     const auto* L = tk.lat;
+    if (k > 0 && tk.key != tasks[order[k - 1]].key) eo = ro = io = dof = go = 0;
     TaskDesc t;
     std::memset(&t, 0, sizeof(t));
     t.J = L->J_of(tk.chain);
@@ -717,12 +731,11 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
   std::lock_guard<std::mutex> lk(g_ws.mu);
   hipStream_t s = (hipStream_t)stream;
   WsOrder order(s);
-  // Every task of both parities with a workspace of its own; one launch pair
-  // (contraction, sampler) per (parity, d, chi_max), longest task first, all
-  // on the caller's stream.  Launches are kept strictly in order: launches of
-  // independent layer classes overlapped on several streams gave corrupted
-  // results now and then on this hardware, so no two
-  // kernels of a sweep run at the same time.
+  // Every task of a parity with a workspace of its own (the two parities
+  // share the buffers); one launch pair (contraction, sampler) per (parity,
+  // d, chi_max), longest task first, all on the caller's stream.  Launches
+  // are kept strictly in order (no two kernels of a sweep run at the same
+  // time), which the shared workspace relies on.
   std::vector<Task> tasks;
   for (int p : {0, 1})
     for (Task t : half_sweep_tasks(lats, n_lats, p)) {

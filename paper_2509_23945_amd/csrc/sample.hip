@@ -547,11 +547,12 @@ hipError_t launch_sample_v(const TaskDesc* tasks, int n, int Lx_max, int Ly_max,
   return hipGetLastError();
 }
 
-// Only Potts at chi_max = 32 on rows longer than 59 sites needs the single tile.
+// Potts at chi_max = 32 on rows longer than 59 sites, and chi_max = 64, need the
+// single tile where the double buffer exceeds a CU's LDS.
 template <typename ET, int DP, int CHIM>
 hipError_t launch_sample_t(const TaskDesc* tasks, int n, int Lx_max, int Ly_max, uint64_t sweep,
                            const unsigned long long* sweep_dev, hipStream_t s) {
-  if constexpr (DP == 3 && CHIM == 32) {
+  if constexpr ((DP == 3 && CHIM == 32) || CHIM == 64) {
     if (sample_single<DP, CHIM>(Lx_max, Ly_max))
       return launch_sample_v<ET, DP, CHIM, true>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
   }
@@ -657,6 +658,7 @@ hipError_t launch_sample_et(const TaskDesc* tasks, int n, int d, int chi_max, in
       case 8: return launch_sample_t<ET, 2, 8>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
       case 16: return launch_sample_t<ET, 2, 16>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
       case 32: return launch_sample_t<ET, 2, 32>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
+      case 64: return launch_sample_t<ET, 2, 64>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
     }
   } else if (d == 3) {
     switch (chi_max) {
@@ -676,6 +678,7 @@ size_t sample_lds_bytes(int d, int chi_max, int Lx, int Ly) {
       case 8: return sample_total_bytes<2, 8>(Lx, Ly);
       case 16: return sample_total_bytes<2, 16>(Lx, Ly);
       case 32: return sample_total_bytes<2, 32>(Lx, Ly);
+      case 64: return sample_total_bytes<2, 64>(Lx, Ly);
     }
   } else if (d == 3) {
     switch (chi_max) {

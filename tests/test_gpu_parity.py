@@ -40,6 +40,9 @@ CASES = [
     (7, 7, 3, 3, "ferro", 0.55, 24, 1),    # Potts, chi_max = 32, truncating
     (64, 6, 3, 3, "ferro", 0.55, 24, 1),   # Potts, chi_max = 32, 64-site rows: the sampler's single-tile layout
     (64, 5, 2, 3, "ferro", 0.55, 32, 0),   # the same with one held neighbour
+    (16, 16, 1, 2, "ferro", 0.44, 48, 0),  # chi_max = 64 (tiles in global memory), critical layer truncating at 48
+    (32, 32, 1, 2, "ferro", 0.40, 64, 0),  # chi_max = 64 on the largest layer, truncating at 64
+    (16, 16, 3, 2, "pmj", 1.0, 40, 1),     # chi_max = 64, +-J layer with held neighbours
 ]
 
 
