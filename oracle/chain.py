@@ -22,7 +22,7 @@ import math
 
 import numpy as np
 
-from . import bmps, model, sampler
+from . import bmps, layer, model, sampler
 from .philox import PURPOSE_MH, uniform
 
 
@@ -192,3 +192,45 @@ def sweep_direction(J, spins, beta: float, chi: int, d: int, direction: int, *, 
     n = sweep(Jp, sp, beta, chi, d, seed=seed, chain=chain, sweep_index=sweep_index + direction * DIRECTION_STRIDE)
     spins[...] = from_direction(sp, direction)
     return n
+
+
+# TNMCMC-2 (SM S2.B): composite layers (z0, z0 + 1) of superspins with d = 4.
+# A composite update draws from the sweep counter sweep + SUPERSPIN_STRIDE, so
+# its uniforms never coincide with those of TNMCMC-1 updates or of the other
+# slice directions; the layer index of the counter is z0.
+SUPERSPIN_STRIDE = 3 * 2 ** 56
+
+
+def superspin_update(J, spins, z0: int, beta: float, chi: int, *, seed: int, chain: int, sweep: int,
+                     margins=None):
+    """One TNMCMC-2 update of the composite layer (z0, z0 + 1) of an Ising
+    lattice, in place: contraction of its 2D network of superspins with the
+    blanket z0 - 1, z0 + 2 held, a drawn composite configuration with its log
+    q, log q of the current one, and the MH decision of main text Eq. 1."""
+    m = layer.composite_layer(J, spins, z0)
+    envs, _ = layer.environments(m, beta, chi)
+    sw = sweep + SUPERSPIN_STRIDE
+    new, lq_new, f_new = layer.sample_layer(envs, m, beta, seed=seed, chain=chain, sweep=sw, z_key=z0,
+                                            margins=margins)
+    cur = layer.composite_states(spins, z0)
+    _, lq_old, f_old = layer.sample_layer(envs, m, beta, forced=cur)
+    dE = layer.layer_energy(m, new) - layer.layer_energy(m, cur)
+    u = uniform(seed, chain, sw, z0, PURPOSE_MH, 0)
+    acc = (not (f_new or f_old)) and mh_accept(lq_old, lq_new, beta, dE, u)
+    if acc:
+        spins[z0], spins[z0 + 1] = layer.composite_spins(new)
+    return {"new": new, "logq_new": lq_new, "logq_old": lq_old, "dE": dE, "accepted": acc,
+            "fault": bool(f_new or f_old)}
+
+
+def superspin_sweep(J, spins, beta: float, chi: int, *, seed: int, chain: int, sweep_index: int):
+    """One TNMCMC-2 sweep (in place): every composite layer z0 = 0 .. Lz - 2,
+    in three phases z0 = 0, 3, 6, ..., then 1, 4, ..., then 2, 5, ... (composites
+    of one phase share no layer and no blanket layer they update, so their
+    updates commute).  Returns the number of accepted updates."""
+    Lz = spins.shape[0]
+    n_acc = 0
+    for phase in range(3):
+        for z0 in range(phase, Lz - 1, 3):
+            n_acc += int(superspin_update(J, spins, z0, beta, chi, seed=seed, chain=chain, sweep=sweep_index)["accepted"])
+    return n_acc
