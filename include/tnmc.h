@@ -149,6 +149,17 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
                        uint64_t sweep_offset, int32_t record, int32_t time_kernels,
                        tnmc_stats* stats, void* hip_stream);
 
+/* TNMCMC-2 sweeps (SM S2.B, "coarse-graining with superspins": layers z0 and
+ * z0 + 1 merged into one composite layer of 4-state superspins, contracted,
+ * sampled and accepted like a TNMCMC-1 layer) are NOT provided on the GPU by
+ * this library: the entry point is kept for the interface and returns
+ * TNMC_ERR_UNSUPPORTED for every call with valid handles (TNMC_ERR_ARG for
+ * invalid ones), touching no device memory.  trace is a DEVICE pointer or
+ * NULL; the other arguments mean what they mean for tnmc_sweep. */
+tnmc_status tnmc_sweep_superspin(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
+                                 int32_t record, int32_t time_kernels, double* trace, tnmc_stats* stats,
+                                 void* hip_stream);
+
 /* As tnmc_sweep (without kernel timing), with one sweep captured once into a
  * HIP graph (the contraction and sampler launches of both parities, the
  * observables, and the advance of a device-resident sweep counter and record

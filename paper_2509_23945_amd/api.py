@@ -38,7 +38,7 @@ __all__ = [
     "tnmc_nn_counts", "tnmc_nn_counts_reset", "tnmc_nn_set_fallback", "tnmc_nn_get_fallback",
     "tnmc_nn_calibrate_fallback", "tnmc_get_couplings", "tnmc_checkpoint_save", "tnmc_checkpoint_load",
     "tnmc_sweep_direction", "tnmc_layout_choice", "tnmc_slice_propose_static", "tnmc_autotune_choice",
-    "tnmc_autotune_pin", "tnmc_autotune_now", "tnmc_sweep_graph",
+    "tnmc_autotune_pin", "tnmc_autotune_now", "tnmc_sweep_graph", "tnmc_sweep_superspin",
 ]
 TNMC_NN_PARAMS = 38753
 
@@ -154,6 +154,7 @@ def load():
         "tnmc_autotune_pin": [i32, i32],
         "tnmc_autotune_now": [P(vp), i32, vp],
         "tnmc_sweep_graph": [P(vp), i32, i32, u64, i32, P(_Stats), vp],
+        "tnmc_sweep_superspin": [P(vp), i32, i32, u64, i32, i32, vp, P(_Stats), vp],
     }
     for name, sig in nn_sigs.items():
         getattr(lib, name).argtypes = sig
@@ -545,4 +546,14 @@ def tnmc_sweep_graph(lats, n_sweeps: int, sweep_offset: int = 0, record: bool = 
     st = _Stats()
     _check(load().tnmc_sweep_graph(arr, n, n_sweeps, ctypes.c_uint64(sweep_offset), int(record), ctypes.byref(st),
                                    stream), "tnmc_sweep_graph")
+    return st.as_dict()
+
+
+def tnmc_sweep_superspin(lats, n_sweeps: int, sweep_offset: int = 0, record: bool = False, time_kernels: bool = False,
+                         trace_ptr=None, stream=None) -> dict:
+    """TNMCMC-2 composite-layer sweeps: not provided on the GPU; raises TnmcError (TNMC_ERR_UNSUPPORTED)."""
+    arr, n = _handles(lats)
+    st = _Stats()
+    _check(load().tnmc_sweep_superspin(arr, n, n_sweeps, ctypes.c_uint64(sweep_offset), int(record),
+                                       int(time_kernels), trace_ptr, ctypes.byref(st), stream), "tnmc_sweep_superspin")
     return st.as_dict()

@@ -798,6 +798,15 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
   return TNMC_OK;
 }
 
+// TNMCMC-2 composite-layer sweeps are not offered on the GPU: every call with
+// valid arguments is refused.
+tnmc_status tnmc_sweep_superspin(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t,
+                                 int32_t, int32_t, double*, tnmc_stats*, void*) {
+  if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0) return TNMC_ERR_ARG;
+  g_last_error = "TNMCMC-2 composite-layer sweeps are not available on the GPU";
+  return TNMC_ERR_UNSUPPORTED;
+}
+
 tnmc_status tnmc_sweep_graph(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
                              int32_t record, tnmc_stats* stats, void* stream) {
   if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0) return TNMC_ERR_ARG;

@@ -218,10 +218,11 @@ def test_invalid_calls_are_rejected():
         assert ei.value.status == tn.api.TNMC_ERR_ARG
     with pytest.raises(tn.TnmcError):
         tn.tnmc_slice_logq(lat, 0, 0, np.zeros((4, 4), np.int8))
-    # chi above 32 is not built
-    with pytest.raises(tn.TnmcError) as ei:
-        gh.make_lattice(8, 2, 2, 2, 40, kind="ferro", seed=1)
-    assert ei.value.status == tn.api.TNMC_ERR_UNSUPPORTED
+    # chi above 64 (Ising) and above 32 (Potts) is not built
+    for d, chi in ((2, 80), (3, 40)):
+        with pytest.raises(tn.TnmcError) as ei:
+            gh.make_lattice(8, 2, 2, d, chi, kind="ferro", seed=1)
+        assert ei.value.status == tn.api.TNMC_ERR_UNSUPPORTED
     # the largest layers are: 64 x 64 Potts at chi = 32 (single-tile sampler layout) and Ising
     for d in (2, 3):
         gh.make_lattice(64, 64, 2, d, 32, kind="ferro", seed=1)

@@ -1,0 +1,82 @@
+"""TNMCMC-2 (SM S2.B) on the GPU against the oracle's composite-layer update.
+
+The library does not offer composite-layer (superspin) sweeps: the d = 4
+contraction that was built for them gave wrong truncations from run to run on
+identical inputs (the workgroup's wavefronts fell out of step in the right
+sweep), and one case (6x6x6, chi = 8) faulted the GPU; no cause was found, so
+the path was withdrawn and tnmc_sweep_superspin refuses every call.  The
+parity and chain-average tests below are kept, skipped, for the day a GPU path
+returns:
+
+* sweeps of superspin composites reproduce the oracle's chain spin for spin
+  (Gaussian and +-J couplings, chi = 2, 4 and 8, ragged shapes), with
+  identical acceptance counts;
+* 64 independent 2x2x4 chains at chi = 1 match exact enumeration of <E> and
+  <M^2>.
+
+What runs: the entry point refuses Ising, Potts and one-layer lattices alike."""
+import math
+
+import numpy as np
+import pytest
+
+import bruteforce as bf
+import gpu_helpers as gh
+import paper_2509_23945_amd as tn
+from oracle import chain as ochain
+
+pytestmark = pytest.mark.gpu
+
+WITHDRAWN = pytest.mark.skip(reason="composite-layer GPU path withdrawn: wrong truncations from run to run and a GPU "
+                                    "fault at 6x6x6 chi = 8, cause not found; tnmc_sweep_superspin refuses every call")
+
+
+@WITHDRAWN
+@pytest.mark.parametrize("Lx,Ly,Lz,kind,beta,chi", [(4, 3, 4, "gauss", 0.9, 2), (5, 4, 5, "pmj", 1.0, 4),
+                                                    (6, 6, 6, "pmj", 1.0, 8), (3, 5, 2, "gauss", 1.2, 4),
+                                                    (8, 8, 7, "pmj", 0.6, 8)])
+def test_superspin_sweeps_match_oracle(Lx, Ly, Lz, kind, beta, chi):
+    gh.announce(f"superspin sweeps {Lx}x{Ly}x{Lz} chi={chi}")
+    lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, 2, chi, kind=kind, beta=beta, seed=71, n_chains=2)
+    refs = [s.copy() for s in spins]
+    for t in range(3):
+        st = tn.tnmc_sweep_superspin([lat], 1, sweep_offset=t)
+        acc = sum(ochain.superspin_sweep(J[c], refs[c], beta, chi, seed=12345, chain=c, sweep_index=t)
+                  for c in range(2))
+        assert st["numeric_faults"] == 0 and st["proposed"] == 2 * (Lz - 1)
+        assert st["accepted"] == acc
+        for c in range(2):
+            assert np.array_equal(tn.tnmc_get_spins(lat, c), refs[c]), (t, c)
+
+
+@WITHDRAWN
+def test_superspin_chain_averages_match_enumeration():
+    gh.announce("superspin chain averages 2x2x4")
+    Lx, Ly, Lz, beta, n_chains, n_sweeps = 2, 2, 4, 1.0, 64, 300
+    lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, 2, 1, kind="pmj", beta=beta, seed=73, n_chains=n_chains,
+                                       record_capacity=n_sweeps)
+    st = tn.tnmc_sweep_superspin([lat], n_sweeps, record=True)
+    assert st["numeric_faults"] == 0 and st["accepted"] < st["proposed"]
+    E, M, _ = tn.tnmc_timeseries(lat)
+    devs_E, devs_M2 = [], []
+    for c in range(n_chains):
+        states, En = bf.lattice_states(J[c], Lx, Ly, Lz, 2)
+        w = np.exp(-beta * (En - En.min()))
+        w /= w.sum()
+        Mn = np.sum(1 - 2 * states, axis=(1, 2, 3)) / 16.0
+        devs_E.append(E[30:, c].mean() - float(np.sum(w * En)))
+        devs_M2.append((M[30:, c] ** 2).mean() - float(np.sum(w * Mn * Mn)))
+    for devs in (np.array(devs_E), np.array(devs_M2)):
+        err = devs.std(ddof=1) / math.sqrt(len(devs))
+        assert abs(devs.mean()) < 4 * err + 1e-12, (devs.mean(), err)
+
+
+def test_superspin_sweeps_are_refused():
+    gh.announce("superspin refusals")
+    ising = gh.make_lattice(4, 3, 4, 2, 2, kind="gauss", beta=0.9, seed=1)[0]
+    potts = gh.make_lattice(4, 4, 4, 3, 4, kind="ferro", beta=0.5, seed=1)[0]
+    flat = gh.make_lattice(4, 4, 1, 2, 4, kind="pmj", beta=0.5, seed=1)[0]
+    for lat in (ising, potts, flat):
+        with pytest.raises(tn.TnmcError) as e:
+            tn.tnmc_sweep_superspin([lat], 1)
+        assert e.value.status == -5
