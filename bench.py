@@ -438,6 +438,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduced", action="store_true", help="skip the FP32-environment form")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal form")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the FP64-storage run at the reduced form's rank cut-off")
     ap.add_argument("--learned-data-sweeps", type=int, default=98,
                     help="TN sweeps whose layers form the training set of the learned proposal")
     ap.add_argument("--learned-epochs", type=int, default=5)
@@ -574,7 +576,7 @@ def main():
         secs32, st32 = time_form(tn, lats32, args.warmup, args.steps, stream)
         v32 = args.steps * updates_per_sweep / secs32
         out["reduced_precision"] = {
-            "form": "environments stored in FP32, rank cut-off 1e-6; products M, AT, C, Y on the engine the autotuner "
+            "form": "environments stored in FP32, rank cut-off 1e-6 (the cut-off, not the storage, gives the speed-up: see ablation); products M, AT, C, Y on the engine the autotuner "
                     "picks (FP32 MFMA operands and accumulation, or FP64 VALU); factorisations, log q, dE, MH in FP64",
             "autotune": autotune_report(tn, groups, tn.TNMC_FP32),
             "value": v32, "unit": "slice updates/s", "ms_per_step": secs32 / args.steps * 1e3,
@@ -594,6 +596,29 @@ def main():
                 out["reduced_precision"]["indep_vs_fp64"] = leg["indep_samples_per_s"] / indep
         for lat in lats32:
             tn.tnmc_lattice_free(lat)
+        if not args.no_ablation:
+            # which half of the reduced form buys its speed: the same 1e-6 rank
+            # cut-off with FP64-stored environments (another q, MH still exact)
+            print(f"[bench] ablation: FP64 storage, rank cut-off 1e-6: timing {args.steps} sweeps", file=sys.stderr,
+                  flush=True)
+            tn.tnmc_debug_set(3, 6)
+            try:
+                lats_ab, _ = make_lattices(args.workload, record_capacity=cap, precision=tn.TNMC_FP64,
+                                           n_candidates=args.candidates)
+                secs_ab, st_ab = time_form(tn, lats_ab, args.warmup, args.steps, stream)
+            finally:
+                tn.tnmc_debug_set(3, 0)
+            v_ab = args.steps * updates_per_sweep / secs_ab
+            out["reduced_precision"]["ablation"] = {
+                "fp64_storage_cut_1e-6": {"value": v_ab, "ms_per_step": secs_ab / args.steps * 1e3,
+                                          "contract_ms_per_step": st_ab["contract_ms"] / args.steps,
+                                          "acceptance": st_ab["accepted"] / max(1, st_ab["proposed"]),
+                                          "numeric_faults": st_ab["numeric_faults"]},
+                "fp32_storage_cut_1e-6": {"value": v32, "ms_per_step": secs32 / args.steps * 1e3},
+                "fp64_storage_cut_1e-15": {"value": value, "ms_per_step": secs / args.steps * 1e3},
+                "speedup_from_cut": v_ab / value, "speedup_from_fp32_storage": v32 / v_ab}
+            for lat in lats_ab:
+                tn.tnmc_lattice_free(lat)
     if not args.no_learned and len(lats) == 1 and groups[0].get("d", 2) == 2:
         out["learned_proposal"] = learned_form(tn, lats[0], groups[0], args, stream, value, next_sweep,
                                                tau_on, indep)

@@ -247,8 +247,13 @@ tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes);
  * default; 0 = off, which also drops its choices).  what = 2: two
  * learned-proposal tasks per workgroup in tnmc_nn_sweep launches that allow
  * it (value 1 = on, the default; 0 = off).  Results agree within the parity
- * bar either way (what = 2: bit for bit).  Returns TNMC_ERR_ARG for an
- * unknown what. */
+ * bar either way (what = 2: bit for bit).  what = 3 (an ablation knob, not a
+ * test hook): value k in 1..15 sets the relative cut-off of the rank-revealing
+ * factorisations to 10^-k for every storage precision, for plans made after
+ * the call; 0 restores the defaults (1e-15 for FP64 environments, 1e-6 for
+ * FP32 ones).  A proposal made with another cut-off is another q: MH stays
+ * exact, but parity with the oracle holds only at the defaults.  Returns
+ * TNMC_ERR_ARG for an unknown what or a value out of range. */
 tnmc_status tnmc_debug_set(int32_t what, int32_t value);
 
 /* ------------------------------------------------------------------------

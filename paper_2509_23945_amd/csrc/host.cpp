@@ -140,6 +140,15 @@ tnmc_status grow(T*& p, size_t& cap, size_t need) {
   return TNMC_OK;
 }
 
+// Relative cut-off of the rank-revealing factorisations: 1e-15 for FP64
+// environments, 1e-6 for FP32 ones, or 10^-g_rank_cut_exp for both when that is
+// set (an ablation knob, tnmc_debug_set(3, k)).
+int g_rank_cut_exp = 0;
+double rank_tol_for(int precision) {
+  if (g_rank_cut_exp > 0) return std::pow(10.0, -(double)g_rank_cut_exp);
+  return (precision == TNMC_FP32) ? tnmc::kRankTolF32 : tnmc::kRankTolF64;
+}
+
 struct Task {
   tnmc_lattice* lat;
   int chain;
@@ -233,7 +242,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.logscale = g_ws.dbl + dof;
     t.counters = g_ws.counters + tnmc::kCounterStride * k;
     t.beta = L->beta[tk.chain];
-    t.rank_tol = (L->precision == TNMC_FP32) ? tnmc::kRankTolF32 : tnmc::kRankTolF64;
+    t.rank_tol = rank_tol_for(L->precision);
     t.key0 = L->seed;
     t.key1 = L->chain_key[tk.chain];
     t.Lx = L->Lx;
@@ -903,9 +912,12 @@ tnmc_status tnmc_autotune_now(tnmc_lattice* const* lats, int32_t n_lats, void* s
 }
 
 tnmc_status tnmc_debug_set(int32_t what, int32_t value) {
-  if (what < 0 || what > 2 || (value != 0 && value != 1)) return TNMC_ERR_ARG;
+  if (what < 0 || what > 3) return TNMC_ERR_ARG;
+  if (what == 3 ? (value < 0 || value > 15) : (value != 0 && value != 1)) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
-  if (what == 0) {
+  if (what == 3) {
+    g_rank_cut_exp = value;
+  } else if (what == 0) {
     tnmc::set_force_retry(value);
   } else if (what == 2) {
     g_nn_pairing = value != 0;
@@ -1129,7 +1141,7 @@ tnmc_status tnmc_slice_propose_static(tnmc_lattice* lat, int32_t chain, int32_t 
   t.counters = nullptr;
   t.force_new = nullptr;
   t.beta = lat->beta[chain];
-  t.rank_tol = (lat->precision == TNMC_FP32) ? tnmc::kRankTolF32 : tnmc::kRankTolF64;
+  t.rank_tol = rank_tol_for(lat->precision);
   t.key0 = lat->seed;
   t.key1 = lat->chain_key[chain];
   t.Lx = Lx;
