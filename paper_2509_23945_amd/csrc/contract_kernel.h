@@ -1228,6 +1228,10 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         if (!in_regs) __syncthreads();   // the register path's barrier above already orders sR and sA
       }
     }
+    // thread 0 wrote the last left rank after the last step's barriers: every
+    // wavefront must see it before the right sweep reads it (a stale rank there
+    // sends wavefronts down different branches, with different barrier counts)
+    __syncthreads();
 
     // ---- right-to-left SVD sweep ----
     {
@@ -1256,7 +1260,9 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         const double* Gx = sG + x * DP * DP;
         const double* Hx = sH + x * DP * DP;
         // R_{x-1} is read from global memory while AT is formed
-        const int rR = (x > 0) ? sRr[x - 1] : 0;
+        // clamped into [0, RROWS] like the bond dimensions: no extent derived
+        // from LDS can leave a tile
+        const int rR = (x > 0) ? min(max(sRr[x - 1], 0), Lay::RROWS) : 0;
         const int nri = rR * cl;
         const float inv_cl = 1.0f / (float)cl;
         const gptr<const double> gR = rscr + (size_t)((x > 0) ? x - 1 : 0) * D * D;
@@ -1635,6 +1641,10 @@ constexpr size_t kCuLds = 160 * 1024;
 
 template <int DP, int CHIM>
 constexpr bool layout_has_compact() {
+  // Potts at chi_max = 16 runs the full layout only: a compact task whose
+  // left rank outgrew its tiles partway through a layer, resumed with the full
+  // layout from that row, faulted the GPU once and the cause is not known
+  if constexpr (DP == 3 && CHIM == 16) return false;
   return sizeof(double) * Layout<DP, CHIM, false>::total > kHalfLds &&
          sizeof(double) * Layout<DP, CHIM, true>::total <= kHalfLds;
 }

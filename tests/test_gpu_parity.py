@@ -84,7 +84,7 @@ def test_propose_matches_oracle_mfma(case, mfma_engine):
 
 
 # cases whose configuration uses the compact two-per-CU contraction layout
-COMPACT_CASES = [c for c in CASES if (c[3] == 2 and c[6] > 16) or (c[3] == 3 and 8 < c[6] <= 16)]
+COMPACT_CASES = [c for c in CASES if c[3] == 2 and 16 < c[6] <= 32]
 
 
 @pytest.mark.parametrize("case", COMPACT_CASES, ids=lambda c: "x".join(map(str, c[:3])) + f"-d{c[3]}-chi{c[6]}")
