@@ -149,13 +149,26 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
                        uint64_t sweep_offset, int32_t record, int32_t time_kernels,
                        tnmc_stats* stats, void* hip_stream);
 
-/* TNMCMC-2 sweeps (SM S2.B, "coarse-graining with superspins": layers z0 and
- * z0 + 1 merged into one composite layer of 4-state superspins, contracted,
- * sampled and accepted like a TNMCMC-1 layer) are NOT provided on the GPU by
- * this library: the entry point is kept for the interface and returns
- * TNMC_ERR_UNSUPPORTED for every call with valid handles (TNMC_ERR_ARG for
- * invalid ones), touching no device memory.  trace is a DEVICE pointer or
- * NULL; the other arguments mean what they mean for tnmc_sweep. */
+/* TNMCMC-2 sweeps (SM S2.B, coarse-graining with superspins): layers z0 and
+ * z0 + 1 of an Ising lattice (d = 2) are merged into one composite layer of
+ * 4-state superspins u = u_a + 2 u_b (u_a, u_b the 0/1 states of layers z0 and
+ * z0 + 1).  The composite's 2D network carries both sublayers' in-plane bonds,
+ * and its on-site term holds the bond between the two layers and the fields of
+ * the held layers z0 - 1 and z0 + 2; it is contracted, sampled and accepted
+ * like a TNMCMC-1 layer (main text, Methods: boundary-MPS contraction, exact
+ * sampling of the approximate distribution, Metropolis-Hastings with its log q).
+ * One sweep updates the composites z0 = 0 .. Lz - 2 in three phases (z0 mod 3),
+ * a launch pair per phase, each phase's composites sharing no layer they update
+ * or hold.  Philox counters use the sweep index sweep_offset + t + 3 * 2^56,
+ * so they never meet those of tnmc_sweep.  Requires d = 2, Lz >= 2,
+ * chi_max <= 8 (4 or 8 after rounding up) and a sampler footprint within a
+ * CU's LDS; anything else returns TNMC_ERR_UNSUPPORTED without touching device
+ * memory (TNMC_ERR_ARG for invalid handles or n_sweeps < 0).  trace is a
+ * DEVICE pointer or NULL: 5 doubles per composite task (log q of the
+ * proposal, log q of the current composite, dE, accepted, numeric fault), tasks
+ * ordered by phase, then lattice, chain and z0, rewritten by every sweep; record, time_kernels, stats and hip_stream mean what
+ * they mean for tnmc_sweep.  The composite contraction uses the vector-ALU
+ * engine and the full tile layout only. */
 tnmc_status tnmc_sweep_superspin(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
                                  int32_t record, int32_t time_kernels, double* trace, tnmc_stats* stats,
                                  void* hip_stream);

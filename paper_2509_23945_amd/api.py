@@ -552,7 +552,7 @@ def tnmc_sweep_graph(lats, n_sweeps: int, sweep_offset: int = 0, record: bool = 
 
 def tnmc_sweep_superspin(lats, n_sweeps: int, sweep_offset: int = 0, record: bool = False, time_kernels: bool = False,
                          trace_ptr=None, stream=None) -> dict:
-    """TNMCMC-2 composite-layer sweeps: not provided on the GPU; raises TnmcError (TNMC_ERR_UNSUPPORTED)."""
+    """TNMCMC-2 composite-layer (superspin) sweeps of Ising lattices, chi_max <= 8; TnmcError otherwise."""
     arr, n = _handles(lats)
     st = _Stats()
     _check(load().tnmc_sweep_superspin(arr, n, n_sweeps, ctypes.c_uint64(sweep_offset), int(record),

@@ -28,6 +28,11 @@ bool contract_has_compact(int d, int chi_max) {
       case 16: return layout_has_compact<3, 16>();
       case 32: return layout_has_compact<3, 32>();
     }
+  } else if (d == 4) {
+    switch (chi_max) {
+      case 4: return layout_has_compact<4, 4>();
+      case 8: return layout_has_compact<4, 8>();
+    }
   }
   return false;
 }
@@ -50,6 +55,11 @@ size_t contract_lds_bytes(int d, int chi_max) {
       case 8: return sizeof(double) * Layout<3, 8>::total;
       case 16: return sizeof(double) * Layout<3, 16>::total;
       case 32: return sizeof(double) * Layout<3, 32>::total;
+    }
+  } else if (d == 4) {   // TNMCMC-2 composite layers (superspins), chi <= 8
+    switch (chi_max) {
+      case 4: return sizeof(double) * Layout<4, 4>::total;
+      case 8: return sizeof(double) * Layout<4, 8>::total;
     }
   }
   return 0;
@@ -76,8 +86,9 @@ hipError_t launch_contract_f64(const TaskDesc* tasks, int n, int d, int chi_max,
 
 hipError_t launch_contract(const TaskDesc* tasks, int n, int d, int chi_max, int precision, ContractCfg cfg,
                            hipStream_t s) {
-  // chi_max = 64 (tiles in global memory) is built with vector-ALU products only
-  if (chi_max == 64) cfg.mfma = 0;
+  // chi_max = 64 (tiles in global memory) and the superspin layers are built
+  // with vector-ALU products only
+  if (chi_max == 64 || d == 4) cfg.mfma = 0;
   if (precision == kPrecF32)
     return cfg.mfma ? launch_contract_f32_mf(tasks, n, d, chi_max, cfg.full, s)
                     : launch_contract_f32(tasks, n, d, chi_max, cfg.full, s);

@@ -1023,7 +1023,6 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
   const double rtol = t.rank_tol;   // relative cut-off of the rank-revealing factorisations
   const gptr<double> rscr = gmem(t.rscr);
   const gptr<int> bond = gmem(t.bond);
-  const size_t plane = (size_t)Lx * Ly;
   int fault = retry ? ((st0 >> 4) & 7) : 0;
   double flops = 0.0;   // accumulated by thread 0 only
 
@@ -1043,11 +1042,10 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
     // ---- local weights of row y ----
     for (int i = tid; i < Lx * DP * DP; i += NTK) {
       const int x = i / (DP * DP), r = (i / DP) % DP, b = i % DP;
-      const double jy = (double)J[plane * Lz + (size_t)z * plane + (size_t)(y - 1) * Lx + x];
-      const double f = held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, b);
-      sG[i] = exp(beta * (jy * sigma<DP>(r, b) + f));
-      const double jx = (x > 0) ? (double)J[(size_t)z * plane + (size_t)y * Lx + (x - 1)] : 0.0;
-      sH[i] = (x > 0) ? exp(beta * jx * sigma<DP>(r, b)) : 1.0;   // here r plays the role of a
+      const double f = site_term<DP>(J, spins, Lx, Ly, Lz, z, y, x, b);
+      sG[i] = exp(beta * (bond_y<DP>(J, Lx, Ly, Lz, z, y - 1, x, r, b) + f));
+      // here r plays the role of a, the state of site x - 1
+      sH[i] = (x > 0) ? exp(beta * bond_x<DP>(J, Lx, Ly, Lz, z, y, x - 1, r, b)) : 1.0;
     }
     // bond dimensions come back from memory: clamped into [1, CHIM], so that
     // no extent derived from them can leave a tile whatever memory holds
@@ -1645,6 +1643,8 @@ constexpr bool layout_has_compact() {
   // left rank outgrew its tiles partway through a layer, resumed with the full
   // layout from that row, faulted the GPU once and the cause is not known
   if constexpr (DP == 3 && CHIM == 16) return false;
+  // composite layers (d = 4) likewise run the full layout only
+  if constexpr (DP == 4) return false;
   return sizeof(double) * Layout<DP, CHIM, false>::total > kHalfLds &&
          sizeof(double) * Layout<DP, CHIM, true>::total <= kHalfLds;
 }
@@ -1693,6 +1693,13 @@ hipError_t launch_contract_et(const TaskDesc* tasks, int n, int d, int chi_max, 
       case 8: return launch_contract_t<ET, 3, 8, MF>(tasks, n, full, s);
       case 16: return launch_contract_t<ET, 3, 16, MF>(tasks, n, full, s);
       case 32: return launch_contract_t<ET, 3, 32, MF>(tasks, n, full, s);
+    }
+  } else if (d == 4) {   // TNMCMC-2 composite layers
+    if constexpr (!MF) {
+      switch (chi_max) {
+        case 4: return launch_contract_t<ET, 4, 4, MF>(tasks, n, full, s);
+        case 8: return launch_contract_t<ET, 4, 8, MF>(tasks, n, full, s);
+      }
     }
   }
   return hipErrorInvalidValue;

@@ -303,4 +303,62 @@ __device__ inline double held_field(JP J, SP spins, int Lx, int Ly, int Lz, int 
   return f;
 }
 
+// Local terms of a layer's 2D network, in units of beta (Boltzmann factor
+// exp(beta * term)).  DP = 2 (Ising) and 3 (Potts): a slice task's layer z
+// with couplings J x sig and the held-layer field.  DP = 4: the composite
+// layer of layers z and z + 1 of an Ising lattice (TNMCMC-2 superspins, state
+// u = ua + 2 ub, bit k the state of layer z + k, 0 = spin +1), whose bonds
+// couple each sublayer with its own couplings, and whose on-site term holds the
+// bond between the two layers and the field of layers z - 1 and z + 2.
+__device__ __forceinline__ double sub_spin(int u, int k) { return ((u >> k) & 1) ? -1.0 : 1.0; }
+
+// Bond between site (x, y) in state a and (x + 1, y) in state b.
+template <int DP, typename JP>
+__device__ inline double bond_x(JP J, int Lx, int Ly, int Lz, int z, int y, int x, int a, int b) {
+  const size_t plane = (size_t)Lx * Ly;
+  const size_t site = (size_t)y * Lx + x;
+  if constexpr (DP == 4) {
+    return (double)J[(size_t)z * plane + site] * (sub_spin(a, 0) * sub_spin(b, 0)) +
+           (double)J[(size_t)(z + 1) * plane + site] * (sub_spin(a, 1) * sub_spin(b, 1));
+  } else {
+    return (double)J[(size_t)z * plane + site] * sigma<DP>(a, b);
+  }
+}
+// Bond between site (x, y) in state r and (x, y + 1) in state b.
+template <int DP, typename JP>
+__device__ inline double bond_y(JP J, int Lx, int Ly, int Lz, int z, int y, int x, int r, int b) {
+  const size_t plane = (size_t)Lx * Ly;
+  const size_t site = (size_t)y * Lx + x;
+  if constexpr (DP == 4) {
+    return (double)J[plane * Lz + (size_t)z * plane + site] * (sub_spin(r, 0) * sub_spin(b, 0)) +
+           (double)J[plane * Lz + (size_t)(z + 1) * plane + site] * (sub_spin(r, 1) * sub_spin(b, 1));
+  } else {
+    return (double)J[plane * Lz + (size_t)z * plane + site] * sigma<DP>(r, b);
+  }
+}
+// On-site term of state u at (x, y).
+template <int DP, typename JP, typename SP>
+__device__ inline double site_term(JP J, SP spins, int Lx, int Ly, int Lz, int z, int y, int x, int u) {
+  if constexpr (DP == 4) {
+    const size_t plane = (size_t)Lx * Ly;
+    const size_t site = (size_t)y * Lx + x;
+    const double sa = sub_spin(u, 0), sb = sub_spin(u, 1);
+    double f = (double)J[2 * plane * Lz + (size_t)z * plane + site] * (sa * sb);
+    if (z > 0)
+      f += (double)J[2 * plane * Lz + (size_t)(z - 1) * plane + site] * (double)spins[(size_t)(z - 1) * plane + site] * sa;
+    if (z + 2 < Lz)
+      f += (double)J[2 * plane * Lz + (size_t)(z + 1) * plane + site] * (double)spins[(size_t)(z + 2) * plane + site] * sb;
+    return f;
+  } else {
+    return held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, u);
+  }
+}
+// State of site i of the task's layer (DP = 4: of the composite, from the
+// planes of layers z and z + 1; p points at layer z's plane).
+template <int DP, typename SP>
+__device__ __forceinline__ int layer_state(SP p, size_t plane, size_t i) {
+  if constexpr (DP == 4) return state_of<2>(p[i]) + 2 * state_of<2>(p[plane + i]);
+  else return state_of<DP>(p[i]);
+}
+
 }  // namespace tnmc

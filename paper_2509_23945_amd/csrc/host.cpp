@@ -38,6 +38,9 @@ thread_local std::string g_last_error;
 
 constexpr int kLxMax = 64;
 constexpr int kLyMax = 64;
+// Philox sweep counters of TNMCMC-2 sweeps: sweep + 3 * 2^56 (slice directions
+// use + 1 and + 2 times 2^56), so no uniform is shared with other updates.
+constexpr uint64_t kSuperspinStride = 3ull << 56;
 
 }  // namespace
 
@@ -153,8 +156,12 @@ struct Task {
   tnmc_lattice* lat;
   int chain;
   int z;
-  int key = 0;   // launch class: tasks of different keys never share a launch; lower keys first
+  int key = 0;     // launch class: tasks of different keys never share a launch; lower keys first
+  int super = 0;   // 1: TNMCMC-2 composite layer (z, z + 1) of superspins, d = 4
 };
+
+// States per site of a task's layer.
+int task_d(const Task& t) { return t.super ? 4 : t.lat->d; }
 
 // Builds the device descriptors of `tasks` at descriptor slot `slot0`, laid out
 // in the shared workspace, grouped by kernel instantiation.
@@ -173,7 +180,7 @@ struct Plan {
 // states need larger bonds (about twice the work).
 double task_cost(const Task& t) {
   const auto* L = t.lat;
-  const double dc = (double)L->d * L->chi;
+  const double dc = (double)task_d(t) * L->chi;
   const bool edge = (L->Lz > 1) && (t.z == 0 || t.z == L->Lz - 1);
   return (double)L->Lx * L->Ly * dc * dc * dc * (edge ? 2.0 : 1.0);
 }
@@ -188,7 +195,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     const auto* la = tasks[a].lat;
     const auto* lb = tasks[b].lat;
     if (tasks[a].key != tasks[b].key) return tasks[a].key < tasks[b].key;
-    if (la->d != lb->d) return la->d < lb->d;
+    if (task_d(tasks[a]) != task_d(tasks[b])) return task_d(tasks[a]) < task_d(tasks[b]);
     if (la->chi_max != lb->chi_max) return la->chi_max < lb->chi_max;
     if (la->precision != lb->precision) return la->precision < lb->precision;
     return task_cost(tasks[a]) > task_cost(tasks[b]);
@@ -202,11 +209,12 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     size_t e = 0, r = 0, in = 0, db = 0, g = 0;
     for (size_t k = 0; k < order.size(); ++k) {
       const auto* L = tasks[order[k]].lat;
+      const int d = task_d(tasks[order[k]]);
       if (k > 0 && tasks[order[k]].key != tasks[order[k - 1]].key) e = r = in = db = g = 0;
-      if (tnmc::contract_uses_global(L->d, L->chi_max))
-        g += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
-      e += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision));
-      r += tnmc::pad256_doubles(tnmc::rscr_doubles(L->Lx, L->d, L->chi_max));
+      if (tnmc::contract_uses_global(d, L->chi_max))
+        g += tnmc::pad256_doubles(tnmc::contract_lds_bytes(d, L->chi_max) / sizeof(double));
+      e += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, d, L->chi_max, L->precision));
+      r += tnmc::pad256_doubles(tnmc::rscr_doubles(L->Lx, d, L->chi_max));
       in += tnmc::pad256_ints((size_t)L->Ly * L->Lx + 1);
       db += tnmc::pad256_doubles((size_t)L->Ly);
       env_need = std::max(env_need, e);
@@ -229,6 +237,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
   for (size_t k = 0; k < order.size(); ++k) {
     const Task& tk = tasks[order[k]];
     const auto* L = tk.lat;
+    const int d = task_d(tk);
     if (k > 0 && tk.key != tasks[order[k - 1]].key) eo = ro = io = dof = go = 0;
     TaskDesc t;
     std::memset(&t, 0, sizeof(t));
@@ -236,7 +245,7 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.spins = L->spins_of(tk.chain);
     t.env = g_ws.env + eo;
     t.rscr = g_ws.rscr + ro;
-    t.gscr = tnmc::contract_uses_global(L->d, L->chi_max) ? g_ws.gscr + go : nullptr;
+    t.gscr = tnmc::contract_uses_global(d, L->chi_max) ? g_ws.gscr + go : nullptr;
     t.bond = g_ws.ints + io;
     t.status = g_ws.ints + io + (size_t)L->Ly * L->Lx;
     t.logscale = g_ws.dbl + dof;
@@ -250,19 +259,19 @@ tnmc_status make_plan(const std::vector<Task>& tasks, Plan& plan) {
     t.Lz = L->Lz;
     t.z = tk.z;
     t.chi = L->chi;
-    t.d = L->d;
+    t.d = d;
     t.chi_max = L->chi_max;
     t.write_back = 1;
     t.n_cand = L->n_cand;
-    eo += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, L->d, L->chi_max, L->precision));
-    if (tnmc::contract_uses_global(L->d, L->chi_max))
-      go += tnmc::pad256_doubles(tnmc::contract_lds_bytes(L->d, L->chi_max) / sizeof(double));
-    ro += tnmc::pad256_doubles(tnmc::rscr_doubles(L->Lx, L->d, L->chi_max));
+    eo += tnmc::pad256_doubles(tnmc::env_doubles(L->Lx, L->Ly, d, L->chi_max, L->precision));
+    if (tnmc::contract_uses_global(d, L->chi_max))
+      go += tnmc::pad256_doubles(tnmc::contract_lds_bytes(d, L->chi_max) / sizeof(double));
+    ro += tnmc::pad256_doubles(tnmc::rscr_doubles(L->Lx, d, L->chi_max));
     io += tnmc::pad256_ints((size_t)L->Ly * L->Lx + 1);
     dof += tnmc::pad256_doubles((size_t)L->Ly);
-    if (plan.groups.empty() || plan.groups.back().d != L->d || plan.groups.back().chi_max != L->chi_max ||
+    if (plan.groups.empty() || plan.groups.back().d != d || plan.groups.back().chi_max != L->chi_max ||
         plan.groups.back().key != tk.key || plan.groups.back().precision != L->precision) {
-      plan.groups.push_back({L->d, L->chi_max, (int)k, 0, 0, 0, tk.key, L->precision});
+      plan.groups.push_back({d, L->chi_max, (int)k, 0, 0, 0, tk.key, L->precision});
     }
     plan.groups.back().count += 1;
     plan.groups.back().lx_max = std::max(plan.groups.back().lx_max, L->Lx);
@@ -807,13 +816,82 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
   return TNMC_OK;
 }
 
-// TNMCMC-2 composite-layer sweeps are not offered on the GPU: every call with
-// valid arguments is refused.
-tnmc_status tnmc_sweep_superspin(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t,
-                                 int32_t, int32_t, double*, tnmc_stats*, void*) {
+tnmc_status tnmc_sweep_superspin(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
+                                 int32_t record, int32_t time_kernels, double* trace, tnmc_stats* stats,
+                                 void* stream) {
   if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0) return TNMC_ERR_ARG;
-  g_last_error = "TNMCMC-2 composite-layer sweeps are not available on the GPU";
-  return TNMC_ERR_UNSUPPORTED;
+  for (int l = 0; l < n_lats; ++l) {
+    const tnmc_lattice* L = lats[l];
+    if (L->d != 2 || L->Lz < 2 || L->chi_max > 8 || !tnmc::contract_supported(4, L->chi_max) ||
+        tnmc::sample_lds_bytes(4, L->chi_max, L->Lx, L->Ly) > 160 * 1024)
+      return TNMC_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_ws.mu);
+  hipStream_t s = (hipStream_t)stream;
+  WsOrder order(s);
+  // composite layers z0 = 0 .. Lz - 2 in three phases (z0 mod 3): the
+  // composites of a phase share no layer they update nor one they hold, so
+  // each phase is one launch pair per (precision, chi_max), strictly in order
+  std::vector<Task> tasks;
+  for (int p = 0; p < 3; ++p)
+    for (int l = 0; l < n_lats; ++l)
+      for (int c = 0; c < lats[l]->n_chains; ++c)
+        for (int z0 = p; z0 + 1 < lats[l]->Lz; z0 += 3) {
+          Task t{lats[l], c, z0};
+          t.key = p;
+          t.super = 1;
+          tasks.push_back(t);
+        }
+  Plan plan;
+  tnmc_status r = make_plan(tasks, plan);
+  if (r != TNMC_OK) return r;
+  const size_t n_tasks = plan.desc.size();
+  if (grow(g_ws.counters, g_ws.counters_cap, tnmc::kCounterStride * n_tasks) != TNMC_OK) return TNMC_ERR_OOM;
+  if (grow(g_ws.tasks, g_ws.tasks_cap, n_tasks) != TNMC_OK) return TNMC_ERR_OOM;
+  for (size_t k = 0; k < n_tasks; ++k) {
+    plan.desc[k].counters = g_ws.counters + tnmc::kCounterStride * k;
+    plan.desc[k].n_cand = 1;   // one candidate per composite update
+    plan.desc[k].record = trace ? trace + 5 * (size_t)plan.order[k] : nullptr;
+  }
+  HIP_TRY(hipMemcpyAsync(g_ws.tasks, plan.desc.data(), n_tasks * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemsetAsync(g_ws.counters, 0, tnmc::kCounterStride * n_tasks * sizeof(long long), s));
+  Timer tm;
+  tm.on = (time_kernels != 0 && stats != nullptr);
+  for (int t = 0; t < n_sweeps; ++t) {
+    const uint64_t sw = sweep_offset + (uint64_t)t + kSuperspinStride;
+    for (const auto& g : plan.groups) {
+      const TaskDesc* dt = g_ws.tasks + g.first;
+      if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+      HIP_TRY(tnmc::launch_contract(dt, g.count, g.d, g.chi_max, g.precision, contract_cfg(g), s));
+      if (tm.on && tm.mark(tm.c_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+      if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+      HIP_TRY(tnmc::launch_sample(dt, g.count, g.d, g.chi_max, g.precision, g.lx_max, g.ly_max, sw, s));
+      if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
+      if (stats) {
+        stats->contract_launches += 1;
+        stats->sample_launches += 1;
+      }
+    }
+    if (record) {
+      for (int l = 0; l < n_lats; ++l) {
+        tnmc_lattice* L = lats[l];
+        if (L->n_recorded >= L->record_capacity) continue;
+        const int64_t i = L->n_recorded++;
+        HIP_TRY(tnmc::launch_observables(L->dJc, L->dSc, L->n_chains, L->dpa, L->dpb, L->n_pairs, L->Lx, L->Ly,
+                                         L->Lz, L->d, L->dErec + i * L->n_chains, L->dMrec + i * L->n_chains,
+                                         L->dqrec + i * std::max(1, L->n_pairs), s));
+      }
+    }
+  }
+  if (stats) {
+    HIP_TRY(hipStreamSynchronize(s));
+    r = read_counters(n_tasks, stats);
+    if (r != TNMC_OK) return r;
+    r = finish_timer(tm, stats);
+    if (r != TNMC_OK) return r;
+  }
+  return TNMC_OK;
 }
 
 tnmc_status tnmc_sweep_graph(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,

@@ -226,21 +226,20 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
         if (y == 0) sh.bnd[0][x] = min(max(bond[x], 1), CHIM);
         if (y + 1 < Ly) sh.bnd[(y + 1) & 1][x] = min(max(bond[(size_t)(y + 1) * Lx + x], 1), CHIM);
       }
-      if (forced) CFG(path, y, x) = (int8_t)state_of<DP>(forced[(size_t)y * Lx + x]);
-      const double jy = (y > 0) ? (double)J[plane * Lz + (size_t)z * plane + (size_t)(y - 1) * Lx + x] : 0.0;
+      if (forced) CFG(path, y, x) = (int8_t)layer_state<DP>(forced, plane, (size_t)y * Lx + x);
       const int above = (y > 0) ? CFG(path, y - 1, x) : 0;
       double ftv[DP];
 #pragma unroll
       for (int u = 0; u < DP; ++u) {
-        double f = held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, u);
-        if (y > 0) f += jy * sigma<DP>(u, above);
+        double f = site_term<DP>(J, spins, Lx, Ly, Lz, z, y, x, u);
+        if (y > 0) f += bond_y<DP>(J, Lx, Ly, Lz, z, y - 1, x, above, u);
         ftv[u] = beta * f;
       }
-      const double jxv = (x > 0) ? beta * (double)J[(size_t)z * plane + (size_t)y * Lx + (x - 1)] : 0.0;
 #pragma unroll
       for (int tt = 0; tt < DP; ++tt)
 #pragma unroll
-        for (int u = 0; u < DP; ++u) sh.et[path][x][tt][u] = exp(ftv[u] + jxv * sigma<DP>(tt, u));
+        for (int u = 0; u < DP; ++u)
+          sh.et[path][x][tt][u] = exp(ftv[u] + ((x > 0) ? beta * bond_x<DP>(J, Lx, Ly, Lz, z, y, x - 1, tt, u) : 0.0));
       if (!forced) sh.uni[path][x] = philox_uniform((uint64_t)(y * Lx + x), (uint64_t)z, sweep, purpose, t.key0, t.key1);
     }
     if (lane < CHIM) {
@@ -420,15 +419,13 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
       for (int i = lane; i < Ly * Lx; i += 64) {
         const int y = i / Lx, x = i % Lx;
         const int a = A[(size_t)y * lx_max + x], o = O[(size_t)y * lx_max + x];
-        double e = -(held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, a) - held_field<DP>(J, spins, Lx, Ly, Lz, z, y, x, o));
-        if (x + 1 < Lx) {
-          const double jx = (double)J[(size_t)z * plane + (size_t)y * Lx + x];
-          e -= jx * (sigma<DP>(a, A[(size_t)y * lx_max + x + 1]) - sigma<DP>(o, O[(size_t)y * lx_max + x + 1]));
-        }
-        if (y + 1 < Ly) {
-          const double jy = (double)J[plane * Lz + (size_t)z * plane + (size_t)y * Lx + x];
-          e -= jy * (sigma<DP>(a, A[(size_t)(y + 1) * lx_max + x]) - sigma<DP>(o, O[(size_t)(y + 1) * lx_max + x]));
-        }
+        double e = -(site_term<DP>(J, spins, Lx, Ly, Lz, z, y, x, a) - site_term<DP>(J, spins, Lx, Ly, Lz, z, y, x, o));
+        if (x + 1 < Lx)
+          e -= bond_x<DP>(J, Lx, Ly, Lz, z, y, x, a, A[(size_t)y * lx_max + x + 1]) -
+               bond_x<DP>(J, Lx, Ly, Lz, z, y, x, o, O[(size_t)y * lx_max + x + 1]);
+        if (y + 1 < Ly)
+          e -= bond_y<DP>(J, Lx, Ly, Lz, z, y, x, a, A[(size_t)(y + 1) * lx_max + x]) -
+               bond_y<DP>(J, Lx, Ly, Lz, z, y, x, o, O[(size_t)(y + 1) * lx_max + x]);
         dE += e;
       }
       return wave_sum(dE);
@@ -485,11 +482,19 @@ __global__ __launch_bounds__(NTS) void sample_kernel(const TaskDesc* __restrict_
   if (path != 0) return;
   const int8_t* result = (n_cand > 1) ? cur : &CFG(0, 0, 0);   // the layer to write back if accepted
   if (t.s_new_out) {
-    for (int i = lane; i < Ly * Lx; i += 64) t.s_new_out[i] = spin_of<DP>(CFG(0, i / Lx, i % Lx));
+    if constexpr (DP != 4)   // superspin tasks run in sweeps only
+      for (int i = lane; i < Ly * Lx; i += 64) t.s_new_out[i] = spin_of<DP>(CFG(0, i / Lx, i % Lx));
   }
   if (t.write_back && n_acc > 0) {
-    for (int i = lane; i < Ly * Lx; i += 64)
-      spins[(size_t)z * plane + i] = spin_of<DP>(result[(size_t)(i / Lx) * lx_max + i % Lx]);
+    for (int i = lane; i < Ly * Lx; i += 64) {
+      const int u = result[(size_t)(i / Lx) * lx_max + i % Lx];
+      if constexpr (DP == 4) {   // both layers of the composite
+        spins[(size_t)z * plane + i] = spin_of<2>(u & 1);
+        spins[(size_t)(z + 1) * plane + i] = spin_of<2>(u >> 1);
+      } else {
+        spins[(size_t)z * plane + i] = spin_of<DP>(u);
+      }
+    }
   }
 #undef RENV
 #undef CFG
@@ -667,6 +672,11 @@ hipError_t launch_sample_et(const TaskDesc* tasks, int n, int d, int chi_max, in
       case 16: return launch_sample_t<ET, 3, 16>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
       case 32: return launch_sample_t<ET, 3, 32>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
     }
+  } else if (d == 4) {   // TNMCMC-2 composite layers
+    switch (chi_max) {
+      case 4: return launch_sample_t<ET, 4, 4>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
+      case 8: return launch_sample_t<ET, 4, 8>(tasks, n, Lx_max, Ly_max, sweep, sweep_dev, s);
+    }
   }
   return hipErrorInvalidValue;
 }
@@ -686,6 +696,12 @@ size_t sample_lds_bytes(int d, int chi_max, int Lx, int Ly) {
       case 8: return sample_total_bytes<3, 8>(Lx, Ly);
       case 16: return sample_total_bytes<3, 16>(Lx, Ly);
       case 32: return sample_total_bytes<3, 32>(Lx, Ly);
+    }
+  }
+  if (d == 4) {
+    switch (chi_max) {
+      case 4: return sample_total_bytes<4, 4>(Lx, Ly);
+      case 8: return sample_total_bytes<4, 8>(Lx, Ly);
     }
   }
   return 0;

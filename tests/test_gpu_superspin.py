@@ -1,20 +1,18 @@
 """TNMCMC-2 (SM S2.B) on the GPU against the oracle's composite-layer update.
 
-The library does not offer composite-layer (superspin) sweeps: the d = 4
-contraction that was built for them gave wrong truncations from run to run on
-identical inputs (the workgroup's wavefronts fell out of step in the right
-sweep), and one case (6x6x6, chi = 8) faulted the GPU; no cause was found, so
-the path was withdrawn and tnmc_sweep_superspin refuses every call.  The
-parity and chain-average tests below are kept, skipped, for the day a GPU path
-returns:
-
 * sweeps of superspin composites reproduce the oracle's chain spin for spin
   (Gaussian and +-J couplings, chi = 2, 4 and 8, ragged shapes), with
   identical acceptance counts;
 * 64 independent 2x2x4 chains at chi = 1 match exact enumeration of <E> and
-  <M^2>.
+  <M^2>;
+* the entry point refuses Potts lattices, chi_max above 8 and one-layer
+  lattices.
 
-What runs: the entry point refuses Ising, Potts and one-layer lattices alike."""
+An earlier build of this path gave wrong truncations from run to run and
+faulted the GPU once (6x6x6, chi = 8): the right sweep of a row read the last
+left rank from LDS before every wavefront could see thread 0's write of it, so
+wavefronts took different branches (with different barrier counts) and
+extents.  That read is now ordered by a barrier and clamped into the tiles."""
 import math
 
 import numpy as np
@@ -27,11 +25,7 @@ from oracle import chain as ochain
 
 pytestmark = pytest.mark.gpu
 
-WITHDRAWN = pytest.mark.skip(reason="composite-layer GPU path withdrawn: wrong truncations from run to run and a GPU "
-                                    "fault at 6x6x6 chi = 8, cause not found; tnmc_sweep_superspin refuses every call")
 
-
-@WITHDRAWN
 @pytest.mark.parametrize("Lx,Ly,Lz,kind,beta,chi", [(4, 3, 4, "gauss", 0.9, 2), (5, 4, 5, "pmj", 1.0, 4),
                                                     (6, 6, 6, "pmj", 1.0, 8), (3, 5, 2, "gauss", 1.2, 4),
                                                     (8, 8, 7, "pmj", 0.6, 8)])
@@ -49,7 +43,6 @@ def test_superspin_sweeps_match_oracle(Lx, Ly, Lz, kind, beta, chi):
             assert np.array_equal(tn.tnmc_get_spins(lat, c), refs[c]), (t, c)
 
 
-@WITHDRAWN
 def test_superspin_chain_averages_match_enumeration():
     gh.announce("superspin chain averages 2x2x4")
     Lx, Ly, Lz, beta, n_chains, n_sweeps = 2, 2, 4, 1.0, 64, 300
@@ -73,10 +66,10 @@ def test_superspin_chain_averages_match_enumeration():
 
 def test_superspin_sweeps_are_refused():
     gh.announce("superspin refusals")
-    ising = gh.make_lattice(4, 3, 4, 2, 2, kind="gauss", beta=0.9, seed=1)[0]
+    wide = gh.make_lattice(4, 3, 4, 2, 16, kind="gauss", beta=0.9, seed=1)[0]
     potts = gh.make_lattice(4, 4, 4, 3, 4, kind="ferro", beta=0.5, seed=1)[0]
     flat = gh.make_lattice(4, 4, 1, 2, 4, kind="pmj", beta=0.5, seed=1)[0]
-    for lat in (ising, potts, flat):
+    for lat in (wide, potts, flat):
         with pytest.raises(tn.TnmcError) as e:
             tn.tnmc_sweep_superspin([lat], 1)
         assert e.value.status == -5
