@@ -396,7 +396,7 @@ def copy_probe() -> None:
     print("copied", a.numel() * 8, "bytes x 3", flush=True)
 
 
-def tau_leg(tn, lat, run, label: str, budget_s: float, max_sweeps: int, chunk: int = 100):
+def tau_leg(tn, lat, run, label: str, budget_s: float, max_sweeps: int, chunk: int = 100, every: int = 500):
     """Runs the form's own sweeps (run(k, offset) does k recorded sweeps) for
     about budget_s seconds (at most max_sweeps), then estimates tau_int of the
     replica overlap q (SM S3; Sokal window) from the recorded series and the
@@ -414,7 +414,7 @@ def tau_leg(tn, lat, run, label: str, budget_s: float, max_sweeps: int, chunk: i
         done += k
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        if done % 500 == 0 or el > budget_s:
+        if done % every == 0 or el > budget_s:
             print(f"[bench] tau leg ({label}): {done} sweeps, {el:.0f} s", file=sys.stderr, flush=True)
         if el > budget_s:
             break
@@ -426,6 +426,94 @@ def tau_leg(tn, lat, run, label: str, budget_s: float, max_sweeps: int, chunk: i
         tau, W = analysis.tau_int(q.T)
         out.update(tau_int_q=tau, window=W, sweeps_per_tau=q.shape[0] / tau, tau_converged=q.shape[0] >= 50 * tau,
                    indep_samples_per_s=q.shape[1] / (tau * secs / done))
+    return out
+
+
+def superspin_leg(tn, args, stream, chi: int = 8):
+    """TNMCMC-2 (SM S2.B: layers z0, z0 + 1 merged into 4-state superspins,
+    updated in three phases z0 mod 3) on the single-lattice workload's
+    couplings, betas and initial spins at bond dimension chi (the composite
+    path's largest), with TNMCMC-1 at the same chi on the same inputs beside it:
+    updates/s, acceptance, and the composite contraction's flops per launch
+    over its HIP-event duration.  A composite task costs several times a
+    TNMCMC-1 task (left ranks near d * chi), so the leg times a few sweeps, one
+    call per sweep with a progress line after each; tau_int of the overlap is
+    estimated only when asked for (--tnmcmc2-tau-seconds)."""
+    import torch
+    cfg, J, spins, inst, pairs, betas = build_inputs(args.workload)
+    L = cfg["L"]
+    n_chains = len(inst)
+    steps, warm = args.tnmcmc2_steps, 1
+    budget = args.tnmcmc2_tau_seconds
+    tau_sweeps = args.tau_sweeps if budget > 0 else 0
+    cap = warm + steps + tau_sweeps
+
+    def lattice():
+        return tn.tnmc_lattice_init(Lx=L, Ly=L, Lz=L, d=2, chi=chi, J=J, beta=betas, spins=spins,
+                                    chain_instance=inst, seed=PHILOX_SEED, pairs=pairs, record_capacity=cap)
+
+    out = {"chi": chi, "workload": f"{args.workload} inputs at chi={chi}"}
+    # TNMCMC-2: each composite update proposes two layers at once
+    print(f"[bench] TNMCMC-2 (superspins, chi={chi}): {warm} warm-up sweep, timing {steps} sweeps", file=sys.stderr,
+          flush=True)
+    lat = lattice()
+    t0 = time.perf_counter()
+    tn.tnmc_sweep_superspin([lat], warm, stream=stream)
+    torch.cuda.synchronize()
+    print(f"[bench] TNMCMC-2 warm-up sweep: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    tn.tnmc_timeseries_reset(lat)
+    st = None
+    t0 = time.perf_counter()
+    for k in range(steps):
+        part = tn.tnmc_sweep_superspin([lat], 1, sweep_offset=warm + k, record=True, time_kernels=True, stream=stream)
+        st = part if st is None else {key: st[key] + part[key] for key in st}
+        print(f"[bench] TNMCMC-2 sweep {k + 1}/{steps}: {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    per_sweep = n_chains * (L - 1)
+    launches = max(1, st["contract_launches"])
+    avg_s = st["contract_ms"] / 1e3 / launches
+    achieved = st["contract_flops"] / launches / avg_s / 1e12 if avg_s > 0 else None
+    out["tnmcmc2"] = {
+        "value": steps * per_sweep / secs, "unit": "composite updates/s",
+        "layer_updates_per_s": 2 * steps * per_sweep / secs, "steps": steps,
+        "composite_updates_per_sweep": per_sweep, "ms_per_sweep": secs / steps * 1e3,
+        "acceptance": st["accepted"] / max(1, st["proposed"]), "numeric_faults": st["numeric_faults"],
+        "contract_ms_per_sweep": st["contract_ms"] / steps, "sample_ms_per_sweep": st["sample_ms"] / steps,
+        "roofline": {"bound": "alu", "kernel": f"contract_kernel<4,{chi}>", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS if achieved else None,
+                     "avg_launch_ms": avg_s * 1e3, "launches": launches,
+                     "tasks_per_launch": steps * per_sweep / launches,
+                     "flops_per_task": st["contract_flops"] / (steps * per_sweep)}}
+    if tau_sweeps:
+        base = warm + steps
+        out["tnmcmc2"]["tau_leg"] = tau_leg(
+            tn, lat, lambda k, off: tn.tnmc_sweep_superspin([lat], k, sweep_offset=base + off, record=True,
+                                                            stream=stream),
+            "TNMCMC-2", budget, tau_sweeps, chunk=1, every=10)
+    tn.tnmc_lattice_free(lat)
+    # TNMCMC-1 at the same chi
+    print(f"[bench] TNMCMC-1 at chi={chi}: timing {args.steps} sweeps", file=sys.stderr, flush=True)
+    lat1 = lattice()
+    secs1, st1 = time_form(tn, [lat1], args.warmup, args.steps, stream)
+    out["tnmcmc1_same_chi"] = {
+        "value": args.steps * n_chains * L / secs1, "unit": "slice updates/s", "ms_per_sweep": secs1 / args.steps * 1e3,
+        "acceptance": st1["accepted"] / max(1, st1["proposed"]), "numeric_faults": st1["numeric_faults"],
+        "contract_ms_per_sweep": st1["contract_ms"] / args.steps,
+        "flops_per_task": st1["contract_flops"] / (args.steps * n_chains * L)}
+    out["layer_updates_ratio_tnmcmc2_over_tnmcmc1"] = (out["tnmcmc2"]["layer_updates_per_s"] /
+                                                       out["tnmcmc1_same_chi"]["value"])
+    if tau_sweeps:
+        base = args.warmup + args.steps
+        out["tnmcmc1_same_chi"]["tau_leg"] = tau_leg(
+            tn, lat1, lambda k, off: tn.tnmc_sweep([lat1], k, sweep_offset=base + off, record=True, stream=stream),
+            "TNMCMC-1 same chi", budget, tau_sweeps)
+        a = out["tnmcmc2"]["tau_leg"]["indep_samples_per_s"]
+        b = out["tnmcmc1_same_chi"]["tau_leg"]["indep_samples_per_s"]
+        out["indep_ratio_tnmcmc2_over_tnmcmc1"] = a / b if a and b else None
+    tn.tnmc_lattice_free(lat1)
     return out
 
 
@@ -454,6 +542,12 @@ def main():
                     help="time the FP64 sweeps as HIP-graph replays (tnmc_sweep_graph) instead of eager launches")
     ap.add_argument("--engine", choices=("auto", "valu", "mfma"), default="auto",
                     help="contraction products: chosen by the autotuner (default) or pinned")
+    ap.add_argument("--no-tnmcmc2", action="store_true",
+                    help="skip the TNMCMC-2 (superspin) leg and its TNMCMC-1 comparison at the same chi")
+    ap.add_argument("--tnmcmc2-steps", type=int, default=3,
+                    help="timed sweeps of the TNMCMC-2 leg (one warm-up sweep before them)")
+    ap.add_argument("--tnmcmc2-tau-seconds", type=float, default=0.0,
+                    help="wall-time cap of each tau_int run of the TNMCMC-2 leg (0, the default, skips them)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 64 MiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -622,6 +716,8 @@ def main():
     if not args.no_learned and len(lats) == 1 and groups[0].get("d", 2) == 2:
         out["learned_proposal"] = learned_form(tn, lats[0], groups[0], args, stream, value, next_sweep,
                                                tau_on, indep)
+    if not args.no_tnmcmc2 and not cfg.get("potts") and not cfg.get("mixed"):
+        out["superspin"] = superspin_leg(tn, args, stream)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, per_worker=1 if cfg.get("potts") else 6)
