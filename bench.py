@@ -38,6 +38,8 @@ WORKLOADS = {
     "ea8": dict(L=8, chi=16, beta=0.5, n_inst=1, n_rep=1),
     # small layers where the learned proposal is accepted: 8^3 +-J, beta = 1.0, 32 instances x 2 replicas
     "ea8b": dict(L=8, chi=16, beta=1.0, n_inst=32, n_rep=2),
+    # the same at beta = 1.5, the low temperature of the paper's main scaling figure
+    "ea8h": dict(L=8, chi=16, beta=1.5, n_inst=32, n_rep=2),
     # a truncating proposal (chi = 2 on 16-wide layers), where MH rejects and several candidates per
     # environment pay: 16^3 +-J, beta = 1.0, 64 instances x 2 replicas
     "ea16t": dict(L=16, chi=2, beta=1.0, n_inst=64, n_rep=2),
