@@ -625,14 +625,25 @@ __device__ __attribute__((always_inline)) int qr_pivoted_lpc(const double* M, in
   return rank;
 }
 
-// Register QR for an m x n tile with m <= MMW and n <= 64: the window is the
-// smallest of 16, 32, 48, 64 rows that holds m, and a column gets 4, 2 or 1
-// lanes as n allows.
+// Register QR for an m x n tile with m <= MMW and n <= 64 (n <= 32 when
+// m > 64): the window is the smallest of 16, 32, 48, 64, 96, 128 rows that
+// holds m, and a column gets 4, 2 or 1 lanes as n allows.  A lane holds at
+// most 64 rows in every case, so the exchange rows never exceed 66 doubles.
 template <int MMW, bool MODE_Q, bool GM = false>
 __device__ __attribute__((always_inline)) int qr_pivoted_reg(const double* M, int ld, int m, int n, int kcap,
                                                              double rel_tol, double* Wc, double* W, double* Wt,
                                                              double* Out, int ldo, gptr<double> Rglob, int gld,
                                                              double* rmax) {
+  if constexpr (MMW >= 128) {
+    if (m > 96) {
+      if (n <= 16) return qr_pivoted_lpc<128, 4, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      return qr_pivoted_lpc<128, 2, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+    }
+    if (m > 64) {
+      if (n <= 16) return qr_pivoted_lpc<96, 4, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+      return qr_pivoted_lpc<96, 2, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
+    }
+  }
   if constexpr (MMW >= 64) {
     if (m > 48) {
       if (n <= 16) return qr_pivoted_lpc<64, 4, MODE_Q, GM>(M, ld, m, n, kcap, rel_tol, Wc, W, Wt, Out, ldo, Rglob, gld, rmax);
@@ -931,10 +942,14 @@ struct Layout {
   static constexpr int oBnd = oIdx + D;                          // [2][LXMAX] ints: bonds of E_y, left ranks
   // largest register-QR windows (rows held per lane): the left QR has up to
   // DP * RCAP rows, the LQ of C^T at most D
+  // composite layers (DP = 4, full layout): M reaches DP * D = 128 rows with
+  // n <= D = 32 columns, held two lanes per column
   static constexpr int MMW = CMP ? ((DP * RCAP >= 32) ? 64 : ((DP * RCAP > 16) ? 32 : 16))
-                                : ((D >= 32) ? 64 : ((DP * D > 16) ? 32 : 16));
+                                : (DP == 4) ? ((DP * D >= 128) ? 128 : 64)
+                                            : ((D >= 32) ? 64 : ((DP * D > 16) ? 32 : 16));
+  static constexpr int MRMAX = (MMW > 64) ? 64 : MMW;                // rows per lane at most
   static constexpr int MMQ = (D >= 64) ? 64 : ((D >= 32) ? 32 : 16);
-  static constexpr int WC = 64 * (MMW + 2);                      // register-QR column exchange
+  static constexpr int WC = 64 * (MRMAX + 2);                    // register-QR column exchange
   static constexpr int WCQ = 64 * (MMQ / (CMP ? 2 : 1) + 2);     // compact: the LQ has n <= RCAP <= 32 columns
   // LQ reflectors: at most chi of them are kept (step chi + 1 only detects truncation)
   static constexpr int WQ = CHIM * MMQ;
@@ -944,7 +959,7 @@ struct Layout {
   static constexpr int oA1 = oWork;                              // [DP][CHIM][CHIM]
   static constexpr int oR1 = oA1 + DP * CHIM * CHIM;             // [RROWS][LD]
   static constexpr int oM1 = oR1 + RSZ;                          // [DP*RCAP][LD]
-  static constexpr int oWcL = CMP ? oM1 : oM1 + MT;              // [64][MMW+2]
+  static constexpr int oWcL = CMP ? oM1 : oM1 + MT;              // [64][MRMAX+2]
   static constexpr int end1 = CMP ? oM1 + ((WC > MT) ? WC : MT) : oWcL + WC;
   // right sweep
   static constexpr int oA2 = oWork;                              // full layout only
@@ -1152,7 +1167,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         int* sPerm = sIdx;
         int rx;
         const gptr<double> gR = rscr + (size_t)x * D * D;
-        const bool in_regs = (m <= Lay::MMW && n <= 64);
+        const bool in_regs = (m <= Lay::MMW && n <= ((m > 64) ? 32 : 64));
         // site tensor of x + 1 (for the right sweep's first step when x + 1 = Lx - 1)
         const int ncl = cr, ncr = bondY[x + 1];
         const gptr<const ET> gAn = envY + (size_t)(x + 1) * SITE;
