@@ -983,6 +983,14 @@ struct Layout {
   static constexpr bool WQ_IN_T = WQ <= D * CHIM;                // small tiles: after the exchange
   static constexpr int oWq = WQ_IN_T ? oT2 : endWc;
   static constexpr int end2 = WQ_IN_T ? endWc : endWc + WQ;
+  // truncating SVD on the full layout: a register QR of C (rR <= D rows,
+  // nC <= D columns) with column pivoting first, its rows of R Pi^T going to
+  // R_{x-1}'s tile, its column exchange to the LQ's; only where that exchange
+  // holds the QR's (MRS rows per lane at most), and for D <= 32 (at D = 64 the
+  // extra register QR makes the kernel spill)
+  static constexpr int MMS = (D > 16) ? 32 : 16;
+  static constexpr int MRS = MMS / 2;   // n <= D <= 32: two or four lanes per column
+  static constexpr bool PRECOND = !CMP && D <= 32 && 64 * (MRS + 2) <= endWc - oWcR;
   static constexpr int total = (end1 > end2) ? end1 : end2;
   static_assert(oWcL % 2 == 0 && oWcR % 2 == 0 && oWq % 2 == 0, "16-byte aligned register-QR buffers");
   static_assert(!CMP || RCAP * D <= D * CHIM, "compact: C fits T's tile");
@@ -1472,7 +1480,35 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
         }
         if (need_svd) {
           int mrows = rR;
-          if (rR > nC) {
+          bool pre = false;
+          if constexpr (Lay::PRECOND && !GM) {
+            // one-sided Jacobi needs about half the sweeps on the rows of the R
+            // factor of a column-pivoted QR of C (graded, nearly orthogonal
+            // rows; the same row space, singular values and right singular
+            // vectors as C): R Pi^T, scaled by 1 / max|R|, goes to R_{x-1}'s
+            // tile, which C no longer needs (Y reuses it only after V is read)
+            if (tid < 64) {
+              double rmax = 0.0;
+              const int r0 = qr_pivoted_reg<Lay::MMS, false, GM>(sC, LDC, rR, nC, rR, rtol, smem + Lay::oWcR, nullptr,
+                                                                 nullptr, sR, LD, nullptr, 0, &rmax);
+              if (tid == 0) {
+                sIdx[D] = (r0 > 0 && rmax > 0.0 && isfinite(rmax)) ? r0 : 0;
+              }
+            }
+            __syncthreads();
+            mrows = min(max(sIdx[D], 0), rR);
+            if (mrows == 0) {
+              // C vanished or is not finite: one zero row (kx = 1, T = 0), flagged
+              fault |= 1;
+              for (int c = tid; c < nC; c += NTK) sR[c] = 0.0;
+              mrows = 1;
+            }
+            __syncthreads();
+            vsrc = sR;
+            vld = LD;
+            pre = true;
+          }
+          if (!pre && rR > nC) {
             qr_r_inplace<NTK>(sC, LDC, rR, nC, sScal);
             for (int w = tid; w < nC * nC; w += NTK) {
               const int i = w / nC, j = w % nC;
@@ -1481,25 +1517,27 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
             __syncthreads();
             mrows = nC;
           }
+          double* sJ = pre ? sR : sC;   // the rows the Jacobi rotates, leading dim ldj
+          const int ldj = pre ? LD : LDC;
           {
             double fro = 0.0;
             for (int w = tid; w < mrows * nC; w += NTK) {
-              const double v = sC[(w / nC) * LDC + (w % nC)];
+              const double v = sJ[(w / nC) * ldj + (w % nC)];
               fro += v * v;
             }
             fro = block_sum<NTK>(fro, sRed);
             const double floor = rtol * rtol * fro;   // |a_ij| below this: negligible at the cut-off
             if (((mrows + 1) >> 1) <= 8) {
-              if (tid < 64) jacobi_rows<(D + 7) / 8, true, NTK, GM>(sC, LDC, mrows, nC, floor);
+              if (tid < 64) jacobi_rows<(D + 7) / 8, true, NTK, GM>(sJ, ldj, mrows, nC, floor);
               __syncthreads();
             } else {
-              jacobi_rows<(D + 7) / 8, false, NTK, GM>(sC, LDC, mrows, nC, floor);
+              jacobi_rows<(D + 7) / 8, false, NTK, GM>(sJ, ldj, mrows, nC, floor);
             }
           }
           double nmax = 0.0;
           for (int i = tid; i < mrows; i += NTK) {
             double s = 0.0;
-            for (int c = 0; c < nC; ++c) s += sC[i * LDC + c] * sC[i * LDC + c];
+            for (int c = 0; c < nC; ++c) s += sJ[i * ldj + c] * sJ[i * ldj + c];
             // a non-finite row ranks as a zero one (the ranking below is then
             // a permutation whatever the values; T then carries the fault)
             if (!isfinite(s)) s = 0.0;
@@ -1512,7 +1550,8 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
           nkeep = block_sum<NTK>(nkeep, sRed);
           const int rs = (nkeep >= 1.0) ? (int)nkeep : 1;
           kx = (chi < rs) ? chi : rs;
-          if (tid == 0) flops += ((rR > nC) ? qr_count(rR, nC, nC) : 0.0) + svd_count(mrows, nC);
+          if (tid == 0) flops += (pre ? qr_count(rR, nC, mrows) : ((rR > nC) ? qr_count(rR, nC, nC) : 0.0)) +
+                                 svd_count(mrows, nC);
           for (int i = tid; i < mrows; i += NTK) {
             const double ni = sNrm[i];
             int rank = 0;
