@@ -5,6 +5,8 @@
   identical acceptance counts;
 * 64 independent 2x2x4 chains at chi = 1 match exact enumeration of <E> and
   <M^2>;
+* 40 seeded random shapes, couplings, temperatures and bond dimensions
+  (one sweep each) reproduce the oracle's chain spin for spin;
 * the entry point refuses Potts lattices, chi_max above 8 and one-layer
   lattices.
 
@@ -41,6 +43,37 @@ def test_superspin_sweeps_match_oracle(Lx, Ly, Lz, kind, beta, chi):
         assert st["accepted"] == acc
         for c in range(2):
             assert np.array_equal(tn.tnmc_get_spins(lat, c), refs[c]), (t, c)
+
+
+@pytest.mark.parametrize("block", range(2))
+def test_random_composites_match_oracle(block):
+    """Seeded draws of shape (Lx, Ly in 2..7, Lz in 2..6), couplings (+-J,
+    Gaussian, uniform ferromagnetic), beta in [0.2, 1.6] and chi in {1, 2, 3,
+    4, 6, 8}, two chains each: one sweep of composites from a random sweep
+    index, spins and acceptance counts equal to the oracle's.  The draws reach
+    exact and truncating composites, both Jacobi variants and composites whose
+    left ranks pass 64 rows (the 96- and 128-row register QR windows)."""
+    rng = np.random.default_rng(4242 + block)
+    for k in range(20):
+        Lx, Ly, Lz = int(rng.integers(2, 8)), int(rng.integers(2, 8)), int(rng.integers(2, 7))
+        kind = str(rng.choice(["pmj", "gauss", "ferro"]))
+        beta = float(rng.uniform(0.2, 1.6))
+        chi = int(rng.choice([1, 2, 3, 4, 6, 8]))
+        sweep = int(rng.integers(0, 1000))
+        label = f"random composites block {block} draw {k}: {Lx}x{Ly}x{Lz} {kind} beta={beta:.4f} chi={chi} sweep {sweep}"
+        gh.announce(label)
+        lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, 2, chi, kind=kind, beta=beta, seed=900 + 41 * block + k,
+                                           n_chains=2)
+        refs = [s.copy() for s in spins]
+        st = tn.tnmc_sweep_superspin([lat], 1, sweep_offset=sweep)
+        acc = sum(ochain.superspin_sweep(J[c], refs[c], beta, chi, seed=12345, chain=c, sweep_index=sweep)
+                  for c in range(2))
+        after = [tn.tnmc_get_spins(lat, c) for c in range(2)]
+        tn.tnmc_lattice_free(lat)
+        assert st["numeric_faults"] == 0 and st["proposed"] == 2 * (Lz - 1), label
+        assert st["accepted"] == acc, label
+        for c in range(2):
+            assert np.array_equal(after[c], refs[c]), (label, c)
 
 
 def test_superspin_chain_averages_match_enumeration():
