@@ -213,6 +213,7 @@ __device__ int jacobi_rows(double* C, int ld, int m, int n, double floor) {
   const int np = mm >> 1;
   const int nq = (n + 7) >> 3;          // column blocks in use (<= NPL)
   const double tol = 4.0 * 2.220446049250313e-16 * sqrt((double)n);
+  const double tol2 = tol * tol;
   for (int sw = 0; sw < JACOBI_MAX_SWEEPS; ++sw) {
     int rotated = 0;
     // pairing of slot pp in round r: (r + pp, r - pp) mod (mm - 1), slot 0 pairs r with mm - 1;
@@ -255,13 +256,17 @@ __device__ int jacobi_rows(double* C, int ld, int m, int n, double floor) {
           aii = group8_sum(aii);
           ajj = group8_sum(ajj);
           aij = group8_sum(aij);
-          if (fabs(aij) > floor && fabs(aij) > tol * sqrt(aii * ajj)) {
+          // |a_ij| > tol sqrt(a_ii a_jj), squared (no square root on the path)
+          if (fabs(aij) > floor && aij * aij > tol2 * (aii * ajj)) {
             // tangent of the rotation angle that zeroes the off-diagonal Gram entry:
-            // t = 2 a_ij / (d + sign(d) sqrt(d^2 + 4 a_ij^2)), d = a_jj - a_ii
+            // t = 2 a_ij / (d + sign(d) sqrt(d^2 + 4 a_ij^2)), d = a_jj - a_ii; the
+            // square roots and the quotient from refined hardware estimates (a few
+            // ulp; q, |den| and 1 + t^2 are positive normals since |a_ij| > floor)
             const double dd = ajj - aii, b2 = 2.0 * aij;
-            const double den = dd + copysign(sqrt(dd * dd + b2 * b2), dd);
-            const double t = b2 / den;
-            const double cs = 1.0 / sqrt(1.0 + t * t);
+            const double q = fma(dd, dd, b2 * b2);
+            const double den = dd + copysign(q * rsqrt_nr(q), dd);
+            const double t = b2 * rcp_nr(den);
+            const double cs = rsqrt_nr(fma(t, t, 1.0));
             const double sn = cs * t;
 #pragma unroll
             for (int q = 0; q < NPL; ++q) {
