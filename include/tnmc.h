@@ -284,10 +284,14 @@ tnmc_status tnmc_debug_set(int32_t what, int32_t value);
  *    next four read the previous layer masked to earlier sites and the
  *    centre), and a 3x3 output channel masked the same way: the logit l of
  *    P(s = +1), clipped to [-30, 30]; zero padding at the open edges;
- *  - parameters: TNMC_NN_PARAMS FP32 numbers, per layer W[c_out][c_in][3][3]
+ *  - parameters: TNMC_NN_PARAMS numbers, per layer W[c_out][c_in][3][3]
  *    then b[c_out] (c_in, c_out = (5,32), (32,32) x4, (32,1)); masked weights
- *    are stored but unused.
- * Convolutions run in FP32; probabilities, log q, dE and the MH test in FP64.
+ *    are stored but unused.  The handle keeps FP32 master values (what the
+ *    get / set calls exchange and Adam updates) and evaluates the network with
+ *    their BF16 roundings (nearest, ties to even), refreshed whenever the
+ *    masters change; gradients are taken at the BF16 parameters.
+ * Convolutions run in FP32 arithmetic with FP32 accumulation; probabilities,
+ * log q, dE and the MH test in FP64.
  * Site j of a drawn layer takes +1 when its uniform (Philox counter
  * (y*Lx+x, z, sweep, 0), as for the TN sampler) is below P(s_j = +1).
  * Ising lattices (d = 2) only.  The batched calls take layers up to 64 sites
@@ -316,8 +320,9 @@ tnmc_status tnmc_nn_logq(tnmc_nn* nn, const float* cond, const int8_t* s, int32_
  * it is active. */
 tnmc_status tnmc_nn_loss_grad(tnmc_nn* nn, const float* cond, const int8_t* s, int32_t n, int32_t Lx, int32_t Ly,
                               double* loss, float* grad, void* hip_stream);
-/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
- * DEVICE gradient grad and learning rate lr. */
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * FP32 masters with the DEVICE gradient grad and learning rate lr; the BF16
+ * parameters are refreshed from the result. */
 tnmc_status tnmc_nn_adam_step(tnmc_nn* nn, const float* grad, double lr, void* hip_stream);
 /* epochs passes of minibatch Adam over the n pairs in their given order
  * (minibatches of `batch` consecutive pairs, the last one possibly shorter);

@@ -24,6 +24,12 @@ is the one the build fixes:
 
 Parameters are one flat vector: for each layer W[c_out][c_in][3][3] then
 b[c_out] (38 753 numbers).  Masked weights are stored but multiply nothing.
+The network is evaluated with BF16 parameters: training keeps FP32 master
+values, and weights_bf16 rounds them to the BF16 numbers the network uses.
+forward, logq, sample, loss_and_grad, propose and slice_update take the
+parameters they evaluate with (already rounded); train takes and returns the
+masters, takes each gradient at their rounding and applies Adam to the
+masters (a straight-through step).
 
 Sampling draws the sites in order; site j takes spin +1 when its uniform is
 below P(s_j = +1 | s_<j, cond) (state 0 first, as in the tensor-network
@@ -208,6 +214,20 @@ def loss_and_grad(theta, conds, spins):
     return total / B, pack(grads)
 
 
+def weights_bf16(theta) -> np.ndarray:
+    """The BF16 parameters of FP32 master values: BF16 keeps the upper 16 bits
+    of an IEEE binary32 (sign, 8 exponent bits, 7 mantissa bits); a binary32
+    rounds to it to nearest, ties to even.  Masters given in float64 are taken
+    to FP32 first (they are FP32 values).  Finite inputs; returns float64."""
+    x = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).astype(np.float32))
+    u = x.view(np.uint32).astype(np.uint64)
+    low = u & 0xFFFF                      # the 16 bits dropped
+    keep = u >> 16
+    up = (low > 0x8000) | ((low == 0x8000) & ((keep & 1) == 1))
+    r = (keep + up.astype(np.uint64)) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def adam_step(theta, m, v, grad, t: int, lr: float):
     """One Adam step (Kingma and Ba; t counts from 1).  Returns new (theta, m, v)."""
     m = ADAM_B1 * m + (1.0 - ADAM_B1) * grad
@@ -219,8 +239,9 @@ def adam_step(theta, m, v, grad, t: int, lr: float):
 
 def train(theta, conds, spins, epochs: int, batch: int, lr: float):
     """Plain minibatch Adam over the pairs in their given order (minibatches of
-    `batch` consecutive pairs, the last one possibly shorter).  Returns the
-    parameters and the loss of the last minibatch before its step."""
+    `batch` consecutive pairs, the last one possibly shorter), on the master
+    parameters theta, each gradient taken at their BF16 rounding.  Returns the
+    masters and the loss of the last minibatch before its step."""
     theta = np.asarray(theta, dtype=np.float64).copy()
     m = np.zeros_like(theta)
     v = np.zeros_like(theta)
@@ -229,7 +250,7 @@ def train(theta, conds, spins, epochs: int, batch: int, lr: float):
     n = len(spins)
     for _ in range(epochs):
         for i in range(0, n, batch):
-            loss, g = loss_and_grad(theta, conds[i:i + batch], spins[i:i + batch])
+            loss, g = loss_and_grad(weights_bf16(theta), conds[i:i + batch], spins[i:i + batch])
             t += 1
             theta, m, v = adam_step(theta, m, v, g, t, lr)
     return theta, loss

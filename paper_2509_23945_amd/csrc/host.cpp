@@ -1321,7 +1321,8 @@ tnmc_status tnmc_flop_model(int32_t Lx, int32_t Ly, int32_t d, int32_t chi, doub
 // ------------------------------------------------------------ learned proposal
 
 struct tnmc_nn {
-  float* theta = nullptr;   // parameters, the flat layout of include/tnmc.h
+  float* theta = nullptr;   // FP32 master parameters, the flat layout of include/tnmc.h
+  uint16_t* wbf = nullptr;  // their BF16 roundings, which every evaluation of the network uses
   float* m = nullptr;       // Adam moments
   float* v = nullptr;
   float* grad = nullptr;
@@ -1451,7 +1452,7 @@ tnmc_status nn_single(tnmc_lattice* lat, tnmc_nn* nn, int chain, int z, uint64_t
   }
   HIP_TRY(hipMemcpyAsync(g_ws.nn_tasks, &t, sizeof(TaskDesc), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));   // the host copies above are released on return
-  HIP_TRY(tnmc::launch_nn_sample(g_ws.nn_tasks, 1, nn->theta, lat->Lx, lat->Ly, sweep, s));
+  HIP_TRY(tnmc::launch_nn_sample(g_ws.nn_tasks, 1, nn->wbf, lat->Lx, lat->Ly, sweep, s));
   if (s_new_host) HIP_TRY(hipMemcpyAsync(s_new_host, g_ws.bytes, plane, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(rec_host, g_ws.dbl, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1494,8 +1495,13 @@ tnmc_status tnmc_nn_create(const float* params, uint64_t seed, tnmc_nn** out) {
     e = hipMemset(*b, 0, bytes);
     if (e != hipSuccess) return fail(e, "hipMemset");
   }
-  hipError_t e = hipMemcpy(nn->theta, h.data(), bytes, hipMemcpyHostToDevice);
+  hipError_t e = hipMalloc((void**)&nn->wbf, tnmc::kNnParams * sizeof(uint16_t));
+  if (e != hipSuccess) return fail(e, "hipMalloc");
+  e = hipMemcpy(nn->theta, h.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(e, "hipMemcpy");
+  e = tnmc::nn_round_bf16(nn->theta, nn->wbf, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail(e, "BF16 parameters");
   *out = nn;
   return TNMC_OK;
 }
@@ -1503,7 +1509,7 @@ tnmc_status tnmc_nn_create(const float* params, uint64_t seed, tnmc_nn** out) {
 tnmc_status tnmc_nn_free(tnmc_nn* nn) {
   if (!nn) return TNMC_ERR_ARG;
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {nn->theta, nn->m, nn->v, nn->grad, nn->act, nn->gbuf, nn->logit, nn->glogit, nn->logq, nn->part};
+  void* ptrs[] = {nn->theta, nn->wbf, nn->m, nn->v, nn->grad, nn->act, nn->gbuf, nn->logit, nn->glogit, nn->logq, nn->part};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete nn;
@@ -1523,6 +1529,8 @@ tnmc_status tnmc_nn_set_params(tnmc_nn* nn, const float* in) {
     if (!std::isfinite(in[i])) return TNMC_ERR_ARG;
   HIP_TRY(hipDeviceSynchronize());
   HIP_TRY(hipMemcpy(nn->theta, in, tnmc::kNnParams * sizeof(float), hipMemcpyHostToDevice));
+  HIP_TRY(tnmc::nn_round_bf16(nn->theta, nn->wbf, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
   HIP_TRY(hipMemset(nn->m, 0, tnmc::kNnParams * sizeof(float)));
   HIP_TRY(hipMemset(nn->v, 0, tnmc::kNnParams * sizeof(float)));
   nn->step = 0;
@@ -1536,7 +1544,7 @@ tnmc_status tnmc_nn_logq(tnmc_nn* nn, const float* cond, const int8_t* s, int32_
   tnmc::NnBatch B;
   tnmc_status r = nn_batch(nn, cond, s, n, Lx, Ly, B);
   if (r != TNMC_OK) return r;
-  HIP_TRY(tnmc::nn_forward(B, nn->theta, st));
+  HIP_TRY(tnmc::nn_forward(B, nn->wbf, st));
   HIP_TRY(hipMemcpyAsync(logq, B.logq, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
   return TNMC_OK;
 }
@@ -1548,8 +1556,8 @@ tnmc_status tnmc_nn_loss_grad(tnmc_nn* nn, const float* cond, const int8_t* s, i
   tnmc::NnBatch B;
   tnmc_status r = nn_batch(nn, cond, s, n, Lx, Ly, B);
   if (r != TNMC_OK) return r;
-  HIP_TRY(tnmc::nn_forward(B, nn->theta, st));
-  HIP_TRY(tnmc::nn_backward(B, nn->theta, nn->grad, st));
+  HIP_TRY(tnmc::nn_forward(B, nn->wbf, st));
+  HIP_TRY(tnmc::nn_backward(B, nn->wbf, nn->grad, st));
   if (grad) HIP_TRY(hipMemcpyAsync(grad, nn->grad, tnmc::kNnParams * sizeof(float), hipMemcpyDeviceToDevice, st));
   std::vector<double> lq(n);
   HIP_TRY(hipMemcpyAsync(lq.data(), B.logq, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1563,7 +1571,7 @@ tnmc_status tnmc_nn_loss_grad(tnmc_nn* nn, const float* cond, const int8_t* s, i
 tnmc_status tnmc_nn_adam_step(tnmc_nn* nn, const float* grad, double lr, void* stream) {
   if (!nn || !grad || !(lr > 0.0) || !std::isfinite(lr)) return TNMC_ERR_ARG;
   nn->step += 1;
-  HIP_TRY(tnmc::nn_adam(nn->theta, nn->m, nn->v, grad, nn->step, lr, (hipStream_t)stream));
+  HIP_TRY(tnmc::nn_adam(nn->theta, nn->wbf, nn->m, nn->v, grad, nn->step, lr, (hipStream_t)stream));
   return TNMC_OK;
 }
 
@@ -1580,10 +1588,10 @@ tnmc_status tnmc_nn_train(tnmc_nn* nn, const float* cond, const int8_t* s, int64
       const int bn = (int)std::min<int64_t>(batch, n - i);
       tnmc_status r = nn_batch(nn, cond + (size_t)i * tnmc::kNnCond * plane, s + (size_t)i * plane, bn, Lx, Ly, B);
       if (r != TNMC_OK) return r;
-      HIP_TRY(tnmc::nn_forward(B, nn->theta, st));
-      HIP_TRY(tnmc::nn_backward(B, nn->theta, nn->grad, st));
+      HIP_TRY(tnmc::nn_forward(B, nn->wbf, st));
+      HIP_TRY(tnmc::nn_backward(B, nn->wbf, nn->grad, st));
       nn->step += 1;
-      HIP_TRY(tnmc::nn_adam(nn->theta, nn->m, nn->v, nn->grad, nn->step, lr, st));
+      HIP_TRY(tnmc::nn_adam(nn->theta, nn->wbf, nn->m, nn->v, nn->grad, nn->step, lr, st));
       last_n = bn;
     }
   }
@@ -1727,7 +1735,7 @@ tnmc_status tnmc_nn_sweep(tnmc_lattice* const* lats, int32_t n_lats, tnmc_nn* nn
     for (int p : {0, 1}) {
       if (!nd[p].empty()) {
         if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
-        HIP_TRY(tnmc::launch_nn_sample(g_ws.nn_tasks + (p ? nd[0].size() : 0), (int)nd[p].size(), nn->theta, lxm[p],
+        HIP_TRY(tnmc::launch_nn_sample(g_ws.nn_tasks + (p ? nd[0].size() : 0), (int)nd[p].size(), nn->wbf, lxm[p],
                                        lym[p], sw, s, paired[p]));
         if (tm.on && tm.mark(tm.s_ev, s) != TNMC_OK) return TNMC_ERR_DEVICE;
         if (stats) stats->sample_launches += 1;

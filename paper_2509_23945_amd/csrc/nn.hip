@@ -11,9 +11,12 @@
 // hides the centre and later sites; five 3x3 layers of 32 channels with ReLU
 // (the last four masked to earlier sites and the centre); a 3x3 masked output
 // channel, the logit of P(s = +1), clipped to [-30, 30].  Zero padding at the
-// open edges.  Parameters: one flat FP32 vector, per layer W[c_out][c_in][3][3]
-// then b[c_out].  Arithmetic in FP32; probabilities, log q, dE and the MH test
-// in FP64.
+// open edges.  Parameters: one flat vector, per layer W[c_out][c_in][3][3]
+// then b[c_out], held as FP32 master values (which Adam updates) and used as
+// their BF16 roundings (nearest, ties to even): every kernel that evaluates
+// the network reads the BF16 copy, which is refreshed whenever the masters
+// change, so the gradient is taken at the BF16 weights.  Arithmetic and
+// accumulation in FP32; probabilities, log q, dE and the MH test in FP64.
 //
 // Kernels:
 //  * nn_sample_kernel - one slice task per workgroup of two wavefronts:
@@ -38,6 +41,16 @@
 namespace tnmc {
 
 namespace {
+
+// BF16 is the upper half of an IEEE binary32: its value is those 16 bits with
+// 16 zero bits below, and a binary32 rounds to it to nearest, ties to even
+// (NaN stays NaN).
+__device__ __forceinline__ float bf16_value(uint16_t u) { return __uint_as_float((uint32_t)u << 16); }
+__device__ __forceinline__ uint16_t bf16_round(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
 
 constexpr int C = kNnChannels;   // hidden channels
 constexpr int NCOND = kNnCond;   // condition channels
@@ -171,7 +184,7 @@ __device__ __forceinline__ float dot16(const float* a, const float* b) {
 
 template <int NSLOT>
 __global__ __launch_bounds__(NTS * NSLOT) void nn_sample_kernel(const TaskDesc* __restrict__ tasks,
-                                                                const float* __restrict__ theta_in, uint64_t sweep,
+                                                                const uint16_t* __restrict__ wbf_in, uint64_t sweep,
                                                                 int lx_max, int ly_max) {
   extern __shared__ __align__(16) float lds[];
   __shared__ double lq_sh[NSLOT][2];
@@ -193,7 +206,8 @@ __global__ __launch_bounds__(NTS * NSLOT) void nn_sample_kernel(const TaskDesc* 
   const double beta = t.beta;
   const gptr<const float> J = gmem(t.J);
   const gptr<int8_t> spins = gmem(t.spins);
-  const gptr<const float> theta = gmem(theta_in);
+  const gptr<const uint16_t> wbf = gmem(wbf_in);
+  auto theta = [&](int i) { return bf16_value(wbf[i]); };   // the network's BF16 parameters
   const size_t plane = (size_t)Lx * Ly;
   const gptr<const int8_t> forced = (path == 1) ? gmem(static_cast<const int8_t*>(t.spins + (size_t)z * plane))
                                                 : gmem(t.force_new);
@@ -219,18 +233,18 @@ __global__ __launch_bounds__(NTS * NSLOT) void nn_sample_kernel(const TaskDesc* 
   constexpr int NT = NTS * NSLOT;
   for (int i = gtid; i < C * NCOND * 9; i += NT) {
     const int co = i / (NCOND * 9), r = i % (NCOND * 9);
-    wc0[i] = theta[OFF_W0 + co * (NCOND + 1) * 9 + r];
+    wc0[i] = theta(OFF_W0 + co * (NCOND + 1) * 9 + r);
   }
-  for (int i = gtid; i < C * 4; i += NT) ws0[i] = theta[OFF_W0 + ((i >> 2) * (NCOND + 1) + NCOND) * 9 + (i & 3)];
-  for (int i = gtid; i < C; i += NT) b0[i] = theta[OFF_B0 + i];
+  for (int i = gtid; i < C * 4; i += NT) ws0[i] = theta(OFF_W0 + ((i >> 2) * (NCOND + 1) + NCOND) * 9 + (i & 3));
+  for (int i = gtid; i < C; i += NT) b0[i] = theta(OFF_B0 + i);
   for (int i = gtid; i < NHID * C * 5 * C; i += NT) {
     const int l = i / (C * 5 * C), r = i % (C * 5 * C);
     const int co = r / (5 * C), k = (r / C) % 5, ci = r % C;
-    wh[(l * C + co) * WCO + k * C + ci] = theta[OFF_H + l * HID + (co * C + ci) * 9 + k];
+    wh[(l * C + co) * WCO + k * C + ci] = theta(OFF_H + l * HID + (co * C + ci) * 9 + k);
   }
-  for (int i = gtid; i < NHID * C; i += NT) bh[i] = theta[OFF_H + (i / C) * HID + C * C * 9 + (i % C)];
-  for (int i = gtid; i < 5 * C; i += NT) w5[i] = theta[OFF_W5 + (i % C) * 9 + i / C];
-  if (gtid == 0) lds[L.b5] = theta[OFF_B5];
+  for (int i = gtid; i < NHID * C; i += NT) bh[i] = theta(OFF_H + (i / C) * HID + C * C * 9 + (i % C));
+  for (int i = gtid; i < 5 * C; i += NT) w5[i] = theta(OFF_W5 + (i % C) * 9 + i / C);
+  if (gtid == 0) lds[L.b5] = theta(OFF_B5);
   for (int i = tid; i < 2 * (NHID + 1) * (lx_max + 2) * C; i += NTS) sl[L.ring + i] = 0.0f;
   // configuration tiles: the forced layers ahead of the walk
   const bool have_forced = (path == 1) || (t.force_new != nullptr);
@@ -434,7 +448,7 @@ __device__ __forceinline__ float layer_input(const float* act_prev, const float*
 // out[b][co][y][x] = act(b_co + sum masked W x); ReLU for layers 0..4, the raw
 // logit for layer 5.  One workgroup per (sample, row).
 template <int LAYER>
-__global__ __launch_bounds__(NTT) void nn_fwd_kernel(const float* __restrict__ theta, const float* __restrict__ act_prev,
+__global__ __launch_bounds__(NTT) void nn_fwd_kernel(const uint16_t* __restrict__ wbf, const float* __restrict__ act_prev,
                                                      const float* __restrict__ cond, const int8_t* __restrict__ s,
                                                      float* __restrict__ out, int Lx, int Ly) {
   using S = LayerShape<LAYER>;
@@ -445,9 +459,9 @@ __global__ __launch_bounds__(NTT) void nn_fwd_kernel(const float* __restrict__ t
   const int XS = Lx + 2;
   for (int i = threadIdx.x; i < S::NW; i += NTT) {
     const int ci = (i / 9) % S::CIN, k = i % 9;
-    wm[i] = tap_kept(LAYER, ci, k) ? theta[S::OFF + i] : 0.0f;
+    wm[i] = tap_kept(LAYER, ci, k) ? bf16_value(wbf[S::OFF + i]) : 0.0f;
   }
-  for (int i = threadIdx.x; i < S::COUT; i += NTT) bs[i] = theta[S::OFF + S::NW + i];
+  for (int i = threadIdx.x; i < S::COUT; i += NTT) bs[i] = bf16_value(wbf[S::OFF + S::NW + i]);
   for (int i = threadIdx.x; i < S::CIN * 3 * XS; i += NTT) {
     const int ci = i / (3 * XS), rr = (i / XS) % 3, xx = i % XS;
     xs[i] = layer_input<LAYER>(act_prev, cond, s, b, ci, y + rr - 1, xx - 1, Lx, Ly);
@@ -485,7 +499,7 @@ constexpr int WA = 5 * 16 * 64;   // weights in operand order: [tap][channel pai
 __host__ __device__ inline size_t conv32_lds_floats(int Lx) { return (size_t)WA + (size_t)C * (MROWS + 2) * (Lx + 2); }
 
 template <bool BWD>
-__global__ __launch_bounds__(256) void nn_conv32_kernel(const float* __restrict__ theta, int off,
+__global__ __launch_bounds__(256) void nn_conv32_kernel(const uint16_t* __restrict__ wbf, int off,
                                                         const float* __restrict__ in,
                                                         const float* __restrict__ mask_src, float* __restrict__ out,
                                                         int n_groups, int Lx, int Ly) {
@@ -499,7 +513,7 @@ __global__ __launch_bounds__(256) void nn_conv32_kernel(const float* __restrict_
   for (int i = tid; i < WA; i += 256) {
     const int ks = i >> 6, l = i & 63, tt = ks >> 4, kk = ks & 15;
     const int m = l & 31, c = 2 * kk + (l >> 5);
-    wa[i] = BWD ? theta[off + (c * C + m) * 9 + (4 - tt)] : theta[off + (m * C + c) * 9 + tt];
+    wa[i] = bf16_value(BWD ? wbf[off + (c * C + m) * 9 + (4 - tt)] : wbf[off + (m * C + c) * 9 + tt]);
   }
   // flat over all threads; the quotient by the row length through an exact float reciprocal
   const float inv_xs = 1.0f / (float)XS;
@@ -533,7 +547,7 @@ __global__ __launch_bounds__(256) void nn_conv32_kernel(const float* __restrict_
         for (int r = 0; r < 16; ++r) {
           const int m = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
           const size_t o = ((size_t)b * C + m) * plane + (size_t)y * Lx + xl;
-          out[o] = BWD ? (mask_src[o] > 0.0f ? acc[r] : 0.0f) : fmaxf(acc[r] + theta[off + C * C * 9 + m], 0.0f);
+          out[o] = BWD ? (mask_src[o] > 0.0f ? acc[r] : 0.0f) : fmaxf(acc[r] + bf16_value(wbf[off + C * C * 9 + m]), 0.0f);
         }
       }
     }
@@ -541,7 +555,7 @@ __global__ __launch_bounds__(256) void nn_conv32_kernel(const float* __restrict_
 }
 
 template <bool BWD>
-hipError_t conv32(const float* theta, int layer, const float* in, const float* mask_src, float* out, int n, int Lx,
+hipError_t conv32(const uint16_t* wbf, int layer, const float* in, const float* mask_src, float* out, int n, int Lx,
                   int Ly, hipStream_t s) {
   const size_t bytes = conv32_lds_floats(Lx) * sizeof(float);
   static size_t attr_bytes = 0;
@@ -552,7 +566,7 @@ hipError_t conv32(const float* theta, int layer, const float* in, const float* m
     attr_bytes = bytes;
   }
   const int n_groups = n * ((Ly + MROWS - 1) / MROWS);
-  hipLaunchKernelGGL(nn_conv32_kernel<BWD>, dim3(std::min(n_groups, 1024)), dim3(256), bytes, s, theta,
+  hipLaunchKernelGGL(nn_conv32_kernel<BWD>, dim3(std::min(n_groups, 1024)), dim3(256), bytes, s, wbf,
                      OFF_H + (layer - 1) * HID, in, mask_src, out, n_groups, Lx, Ly);
   return hipGetLastError();
 }
@@ -651,7 +665,7 @@ __global__ __launch_bounds__(NTT) void nn_loss_kernel(const float* __restrict__ 
 // gin[b][ci][y][x] = [act_prev > 0] sum_co sum_k Wm[co][ci][k] g[b][co][y - dy_k][x - dx_k]
 // (layers 1..5; act_prev is the layer's input, the previous layer's output).
 template <int LAYER>
-__global__ __launch_bounds__(NTT) void nn_bwd_data_kernel(const float* __restrict__ theta, const float* __restrict__ g,
+__global__ __launch_bounds__(NTT) void nn_bwd_data_kernel(const uint16_t* __restrict__ wbf, const float* __restrict__ g,
                                                           const float* __restrict__ act_prev,
                                                           float* __restrict__ gin, int Lx, int Ly) {
   using S = LayerShape<LAYER>;
@@ -661,7 +675,7 @@ __global__ __launch_bounds__(NTT) void nn_bwd_data_kernel(const float* __restric
   const int b = blockIdx.x / Ly, y = blockIdx.x % Ly;
   const int XS = Lx + 2;
   const size_t plane = (size_t)Lx * Ly;
-  for (int i = threadIdx.x; i < S::NW; i += NTT) wm[i] = tap_kept(LAYER, (i / 9) % S::CIN, i % 9) ? theta[S::OFF + i] : 0.0f;
+  for (int i = threadIdx.x; i < S::NW; i += NTT) wm[i] = tap_kept(LAYER, (i / 9) % S::CIN, i % 9) ? bf16_value(wbf[S::OFF + i]) : 0.0f;
   // rows y+1, y, y-1 of g (row rr holds y + 1 - rr), zero padded
   for (int i = threadIdx.x; i < S::COUT * 3 * XS; i += NTT) {
     const int co = i / (3 * XS), rr = (i / XS) % 3, xx = i % XS;
@@ -771,8 +785,9 @@ __global__ __launch_bounds__(NTT) void nn_grad_reduce_kernel(const float* __rest
   }
 }
 
-__global__ __launch_bounds__(NTT) void nn_adam_kernel(float* __restrict__ theta, float* __restrict__ m,
-                                                      float* __restrict__ v, const float* __restrict__ grad, int n,
+__global__ __launch_bounds__(NTT) void nn_adam_kernel(float* __restrict__ theta, uint16_t* __restrict__ wbf,
+                                                      float* __restrict__ m, float* __restrict__ v,
+                                                      const float* __restrict__ grad, int n,
                                                       float lr, float b1, float b2, float c1, float c2, float eps) {
   const int i = blockIdx.x * NTT + threadIdx.x;
   if (i >= n) return;
@@ -781,7 +796,15 @@ __global__ __launch_bounds__(NTT) void nn_adam_kernel(float* __restrict__ theta,
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  const float ti = theta[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+  theta[i] = ti;
+  wbf[i] = bf16_round(ti);
+}
+
+// BF16 copy of the FP32 master parameters.
+__global__ __launch_bounds__(NTT) void nn_round_kernel(const float* __restrict__ theta, uint16_t* __restrict__ wbf, int n) {
+  const int i = blockIdx.x * NTT + threadIdx.x;
+  if (i < n) wbf[i] = bf16_round(theta[i]);
 }
 
 template <int LAYER>
@@ -845,7 +868,7 @@ size_t nn_sample_lds_bytes(int lx_max, int ly_max, int nslot) {
 }
 
 template <int NSLOT>
-hipError_t launch_nn_sample_t(const TaskDesc* tasks, int n_groups, const float* theta, int lx_max, int ly_max,
+hipError_t launch_nn_sample_t(const TaskDesc* tasks, int n_groups, const uint16_t* wbf, int lx_max, int ly_max,
                               uint64_t sweep, hipStream_t s) {
   const size_t bytes = nn_sample_lds_bytes(lx_max, ly_max, NSLOT);
   static size_t attr_bytes = 0;
@@ -855,54 +878,60 @@ hipError_t launch_nn_sample_t(const TaskDesc* tasks, int n_groups, const float* 
     if (e != hipSuccess) return e;
     attr_bytes = bytes;
   }
-  hipLaunchKernelGGL(nn_sample_kernel<NSLOT>, dim3(n_groups), dim3(NTS * NSLOT), bytes, s, tasks, theta, sweep, lx_max,
+  hipLaunchKernelGGL(nn_sample_kernel<NSLOT>, dim3(n_groups), dim3(NTS * NSLOT), bytes, s, tasks, wbf, sweep, lx_max,
                      ly_max);
   return hipGetLastError();
 }
 
 // paired: n is even and consecutive tasks 2k, 2k + 1 share one layer shape.
-hipError_t launch_nn_sample(const TaskDesc* tasks, int n, const float* theta, int lx_max, int ly_max, uint64_t sweep,
+hipError_t launch_nn_sample(const TaskDesc* tasks, int n, const uint16_t* wbf, int lx_max, int ly_max, uint64_t sweep,
                             hipStream_t s, bool paired) {
-  if (paired) return launch_nn_sample_t<2>(tasks, n / 2, theta, lx_max, ly_max, sweep, s);
-  return launch_nn_sample_t<1>(tasks, n, theta, lx_max, ly_max, sweep, s);
+  if (paired) return launch_nn_sample_t<2>(tasks, n / 2, wbf, lx_max, ly_max, sweep, s);
+  return launch_nn_sample_t<1>(tasks, n, wbf, lx_max, ly_max, sweep, s);
 }
 
-hipError_t nn_forward(const NnBatch& B, const float* theta, hipStream_t s) {
+hipError_t nn_forward(const NnBatch& B, const uint16_t* wbf, hipStream_t s) {
   const dim3 grid(B.n * B.Ly), blk(NTT);
-  hipLaunchKernelGGL(nn_fwd_kernel<0>, grid, blk, 0, s, theta, nullptr, B.cond, B.s, B.act[0], B.Lx, B.Ly);
+  hipLaunchKernelGGL(nn_fwd_kernel<0>, grid, blk, 0, s, wbf, nullptr, B.cond, B.s, B.act[0], B.Lx, B.Ly);
   for (int l = 1; l <= 4; ++l) {
-    hipError_t e = conv32<false>(theta, l, B.act[l - 1], nullptr, B.act[l], B.n, B.Lx, B.Ly, s);
+    hipError_t e = conv32<false>(wbf, l, B.act[l - 1], nullptr, B.act[l], B.n, B.Lx, B.Ly, s);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(nn_fwd_kernel<5>, grid, blk, 0, s, theta, B.act[4], nullptr, nullptr, B.logit, B.Lx, B.Ly);
+  hipLaunchKernelGGL(nn_fwd_kernel<5>, grid, blk, 0, s, wbf, B.act[4], nullptr, nullptr, B.logit, B.Lx, B.Ly);
   hipLaunchKernelGGL(nn_loss_kernel, dim3(B.n), blk, 0, s, B.logit, B.s, B.logq, B.glogit, B.Lx * B.Ly,
                      1.0 / (double)B.n);
   return hipGetLastError();
 }
 
-hipError_t nn_backward(const NnBatch& B, const float* theta, float* grad, hipStream_t s) {
+hipError_t nn_backward(const NnBatch& B, const uint16_t* wbf, float* grad, hipStream_t s) {
   const dim3 grid(B.n * B.Ly), blk(NTT);
   hipError_t e;
   // layer 5: g = dlogit; input act[4]
   if ((e = bwd_weight<5>(B, B.glogit, B.act[4], grad, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(nn_bwd_data_kernel<5>, grid, blk, 0, s, theta, B.glogit, B.act[4], B.g[0], B.Lx, B.Ly);
+  hipLaunchKernelGGL(nn_bwd_data_kernel<5>, grid, blk, 0, s, wbf, B.glogit, B.act[4], B.g[0], B.Lx, B.Ly);
   if ((e = bwd_weight<4>(B, B.g[0], B.act[3], grad, s)) != hipSuccess) return e;
-  if ((e = conv32<true>(theta, 4, B.g[0], B.act[3], B.g[1], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
+  if ((e = conv32<true>(wbf, 4, B.g[0], B.act[3], B.g[1], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
   if ((e = bwd_weight<3>(B, B.g[1], B.act[2], grad, s)) != hipSuccess) return e;
-  if ((e = conv32<true>(theta, 3, B.g[1], B.act[2], B.g[0], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
+  if ((e = conv32<true>(wbf, 3, B.g[1], B.act[2], B.g[0], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
   if ((e = bwd_weight<2>(B, B.g[0], B.act[1], grad, s)) != hipSuccess) return e;
-  if ((e = conv32<true>(theta, 2, B.g[0], B.act[1], B.g[1], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
+  if ((e = conv32<true>(wbf, 2, B.g[0], B.act[1], B.g[1], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
   if ((e = bwd_weight<1>(B, B.g[1], B.act[0], grad, s)) != hipSuccess) return e;
-  if ((e = conv32<true>(theta, 1, B.g[1], B.act[0], B.g[0], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
+  if ((e = conv32<true>(wbf, 1, B.g[1], B.act[0], B.g[0], B.n, B.Lx, B.Ly, s)) != hipSuccess) return e;
   if ((e = bwd_weight<0>(B, B.g[0], nullptr, grad, s)) != hipSuccess) return e;
   return hipGetLastError();
 }
 
-hipError_t nn_adam(float* theta, float* m, float* v, const float* grad, int64_t step, double lr, hipStream_t s) {
+hipError_t nn_adam(float* theta, uint16_t* wbf, float* m, float* v, const float* grad, int64_t step, double lr,
+                   hipStream_t s) {
   const double c1 = 1.0 / (1.0 - std::pow(kNnAdamB1, (double)step));
   const double c2 = 1.0 / (1.0 - std::pow(kNnAdamB2, (double)step));
-  hipLaunchKernelGGL(nn_adam_kernel, dim3((kNnParams + NTT - 1) / NTT), dim3(NTT), 0, s, theta, m, v, grad, kNnParams,
+  hipLaunchKernelGGL(nn_adam_kernel, dim3((kNnParams + NTT - 1) / NTT), dim3(NTT), 0, s, theta, wbf, m, v, grad, kNnParams,
                      (float)lr, (float)kNnAdamB1, (float)kNnAdamB2, (float)c1, (float)c2, (float)kNnAdamEps);
+  return hipGetLastError();
+}
+
+hipError_t nn_round_bf16(const float* theta, uint16_t* wbf, hipStream_t s) {
+  hipLaunchKernelGGL(nn_round_kernel, dim3((kNnParams + NTT - 1) / NTT), dim3(NTT), 0, s, theta, wbf, kNnParams);
   return hipGetLastError();
 }
 

@@ -1,8 +1,10 @@
 """The learned proposal's HIP kernels against the FP64 oracle (oracle.nn).
 
-The network runs in FP32 on the GPU and in FP64 in the oracle, so values are
-compared within tolerances derived from FP32 rounding (log q and logits 1e-4
-relative, the gradient 1e-4 of its largest entry); decisions taken by floating
+The network is evaluated with BF16 parameters (the FP32 masters rounded to
+nearest even, on the GPU and in the oracle alike), in FP32 arithmetic on the
+GPU and in FP64 in the oracle, so values are compared within tolerances
+derived from FP32 rounding (log q and logits 1e-4 relative, the gradient 1e-4
+of its largest entry); decisions taken by floating
 point (a site's spin) are checked for consistency with the oracle's
 probability at that site, except within 1e-5 of a tie.  dE is exact."""
 import math
@@ -67,8 +69,16 @@ def test_nn_logq_batch(Lx, Ly, n, scale):
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     for i in range(n):
-        ref = onn.logq(th.astype(np.float64), cond[i], s[i])
+        ref = onn.logq(onn.weights_bf16(th), cond[i], s[i])
         assert close(got[i], ref), (i, got[i], ref)
+    # the kernels use the BF16 parameters: where the FP32 masters' own log q is
+    # clearly different (BF16 rounding moves log q by 1e-5 to 1e-3 relative
+    # here), the GPU's value is much nearer the BF16 network's
+    for i in range(n):
+        ref = onn.logq(onn.weights_bf16(th), cond[i], s[i])
+        alt = onn.logq(th.astype(np.float64), cond[i], s[i])
+        if abs(ref - alt) > 2e-5 * max(1.0, abs(ref)):
+            assert abs(got[i] - ref) < 0.5 * abs(ref - alt), (i, got[i], ref, alt)
 
 
 @pytest.mark.parametrize("Lx,Ly,Lz,z,scale", [(6, 5, 4, 1, 1.0), (9, 7, 3, 0, 2.0), (5, 6, 3, 2, 1.0),
@@ -79,7 +89,7 @@ def test_nn_slice_propose(Lx, Ly, Lz, z, scale):
     th = params(2, scale)
     lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, 2, 4, kind="pmj", beta=1.0, seed=4)
     net = tn.tnmc_nn_create(th)
-    th64 = th.astype(np.float64)
+    th64 = onn.weights_bf16(th)   # the BF16 parameters the GPU evaluates with
     cond = onn.cond_channels(J[0], spins[0], z)
     for sweep in (0, 5):
         s_new, lq_new, lq_old, dE, st = tn.tnmc_nn_slice_propose(lat, net, 0, z, sweep)
@@ -107,7 +117,7 @@ def test_nn_slice_propose_matches_oracle_draws():
     th = params(3, 2.0)
     lat, J, spins, _ = gh.make_lattice(5, 4, 3, 2, 4, kind="gauss", beta=0.7, seed=6)
     net = tn.tnmc_nn_create(th)
-    th64 = th.astype(np.float64)
+    th64 = onn.weights_bf16(th)   # the BF16 parameters the GPU evaluates with
     for z in range(3):
         rec = onn.propose(th64, J[0], spins[0], z, seed=12345, chain_key=0, sweep=3)
         s_new, lq_new, lq_old, dE, st = tn.tnmc_nn_slice_propose(lat, net, 0, z, 3)
@@ -146,7 +156,7 @@ def test_nn_gradient(Lx, Ly, n):
     g = torch.zeros(tn.TNMC_NN_PARAMS, dtype=torch.float32, device="cuda")
     loss = tn.tnmc_nn_loss_grad(net, dc.data_ptr(), ds.data_ptr(), n, Lx, Ly, g.data_ptr())
     torch.cuda.synchronize()
-    ref_loss, ref_g = onn.loss_and_grad(th.astype(np.float64), cond, s)
+    ref_loss, ref_g = onn.loss_and_grad(onn.weights_bf16(th), cond, s)
     assert close(loss, ref_loss, 1e-5), (loss, ref_loss)
     got = g.cpu().numpy().astype(np.float64)
     scale = np.abs(ref_g).max()
@@ -160,7 +170,7 @@ def test_nn_adam_and_train():
     Lx, Ly = 6, 5
     th = params(5, 1.0)
     cond, s = make_pairs(Lx, Ly, 3, 4, 13)
-    th64 = th.astype(np.float64)
+    th64 = th.astype(np.float64)   # FP32 masters: Adam and train() step them (gradients at their BF16 rounding)
     dc, ds = to_dev(cond), to_dev(s)
     # one explicit step: Adam on the GPU's gradient against the oracle's Adam on the same gradient
     net = tn.tnmc_nn_create(th)
@@ -233,7 +243,7 @@ def test_nn_sweep_step_matches_oracle_update():
     th = params(7, 1.0)
     lat, J, spins, _ = gh.make_lattice(5, 4, 2, 2, 4, kind="pmj", beta=0.5, seed=9, n_chains=2)
     net = tn.tnmc_nn_create(th)
-    th64 = th.astype(np.float64)
+    th64 = onn.weights_bf16(th)   # the BF16 parameters the GPU evaluates with
     tn.tnmc_nn_sweep([lat], net, 1, sweep_offset=4)
     for c in range(2):
         ref = spins[c].copy()
@@ -320,7 +330,7 @@ def test_nn_sweep_over_lattices_of_different_shapes():
     layer) equals the oracle's slice updates of each lattice."""
     gh.announce("nn sweep two lattices")
     th = params(9, 1.5)
-    th64 = th.astype(np.float64)
+    th64 = onn.weights_bf16(th)   # the BF16 parameters the GPU evaluates with
     net = tn.tnmc_nn_create(th)
     a, Ja, sa, _ = gh.make_lattice(6, 5, 4, 2, 4, kind="gauss", beta=0.7, seed=12, n_chains=2)
     b, Jb, sb, _ = gh.make_lattice(3, 8, 3, 2, 4, kind="pmj", beta=1.2, seed=13, n_chains=1)

@@ -11,6 +11,10 @@ than the oracle itself:
 * the gradient of the loss matches central finite differences;
 * Adam: the first step, and every step under a constant gradient, moves each
   parameter by lr g / (|g| + eps) (closed form);
+* BF16 parameters: the rounding equals torch's float32 -> bfloat16 cast (round
+  to nearest even) across magnitudes, keeps BF16 values, breaks ties to the
+  even neighbour, stays within half a BF16 ulp (2^-8 relative), and train()
+  steps the masters by Adam on the gradient taken at their rounding;
 * the Metropolis-Hastings kernel with the learned proposal leaves the exact
   conditional Boltzmann distribution of a layer invariant (exact stationarity
   on a 2x2x3 lattice)."""
@@ -175,6 +179,33 @@ def test_adam_closed_forms():
         nxt, m, v = nn.adam_step(cur, m, v, g, t, lr)
         assert np.allclose(nxt, cur - lr * g / (np.abs(g) + nn.ADAM_EPS), rtol=0, atol=1e-14)
         cur = nxt
+
+
+def test_bf16_rounding_matches_torch_and_the_format():
+    import torch
+    rng = np.random.default_rng(12)
+    x = (rng.standard_normal(20000) * np.exp2(rng.integers(-100, 100, 20000))).astype(np.float32)
+    r = nn.weights_bf16(x)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).double().numpy()
+    assert np.array_equal(r, ref)
+    assert np.array_equal(nn.weights_bf16(r), r)                      # BF16 values are kept
+    assert np.all(np.abs(r - x) <= np.abs(x.astype(np.float64)) * 2.0 ** -8)   # unit roundoff, 8-bit significand
+    # ties go to the even neighbour (spacing 2^-7 on [1, 2))
+    for v, want in [(1 + 2.0 ** -8, 1.0), (1 + 3 * 2.0 ** -8, 1 + 2.0 ** -6), (1 + 2.0 ** -8 + 2.0 ** -20, 1 + 2.0 ** -7),
+                    (-(1 + 3 * 2.0 ** -8), -(1 + 2.0 ** -6)), (2.0 ** -130, 2.0 ** -130), (0.0, 0.0)]:
+        assert nn.weights_bf16([v])[0] == want, (v, want)
+
+
+def test_train_steps_masters_at_bf16_weights():
+    rng = np.random.default_rng(13)
+    th = params(9, 1.0) + rng.standard_normal(nn.n_params()) * 1e-4   # masters off the BF16 grid
+    conds = np.stack([rand_cond(rng, 3, 4) for _ in range(2)])
+    spins = rng.choice([-1, 1], size=(2, 3, 4)).astype(np.int8)
+    got, loss = nn.train(th, conds, spins, 1, 2, 1e-3)
+    ref_loss, g = nn.loss_and_grad(nn.weights_bf16(th), conds, spins)
+    want, _, _ = nn.adam_step(th, np.zeros_like(th), np.zeros_like(th), g, 1, 1e-3)
+    assert loss == ref_loss and np.array_equal(got, want)
+    assert not np.array_equal(nn.weights_bf16(th), th)
 
 
 def test_mh_with_learned_proposal_is_exactly_stationary():
