@@ -345,7 +345,8 @@ def learned_form(tn, lat, group, args, stream, fp64_value, sweep0, tau_on, fp64_
                       "learned", args.tau_seconds, args.tau_sweeps)
         indep = (leg["indep_samples_per_s"], leg["tau_int_q"])
     return {
-        "form": "masked-conv autoregressive proposal (6 layers, 32 channels, FP32) with exact log q, "
+        "form": "masked-conv autoregressive proposal (6 layers, 32 channels, BF16 weights from FP32 masters, FP32 "
+                "arithmetic and accumulation) with exact log q, "
                 "MH per main text Eq. 1, TN fallback frozen after a calibration window (the learned-only sweeps; acceptance < 5%)",
         "value": value, "unit": "slice updates/s", "ms_per_step": secs / args.steps * 1e3,
         "vs_fp64": value / fp64_value,
