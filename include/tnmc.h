@@ -90,8 +90,9 @@ tnmc_status tnmc_lattice_free(tnmc_lattice* lat);
  * builds the layer network from the held layers z-1, z+1, contracts it by
  * boundary MPS to chi, draws a new layer with the site uniforms of counter
  * (., z, sweep, 0), and evaluates q of the current layer by teacher forcing.
- * The state is not changed.  Outputs are HOST pointers: s_new [Ly][Lx] int8,
- * and natural-log q of the new and current layer and dE = E(new) - E(current).
+ * The state is not changed.  Outputs: s_new [Ly][Lx] int8, a HOST or DEVICE
+ * pointer (the copy takes its direction from unified addressing), and, at HOST
+ * pointers, natural-log q of the new and current layer and dE = E(new) - E(current).
  * Returns TNMC_ERR_NUMERIC if either path hit a non-positive or non-finite
  * total site weight (the outputs are still written). */
 tnmc_status tnmc_slice_propose(tnmc_lattice* lat, int32_t chain, int32_t z, uint64_t sweep,
@@ -108,13 +109,13 @@ tnmc_status tnmc_slice_propose(tnmc_lattice* lat, int32_t chain, int32_t z, uint
  * up to 32x32 at chi <= 32 fit).  Results equal tnmc_slice_propose's.  Every
  * call on one GPU shares that GPU's array: calls that overlap on one GPU
  * (other host threads, or other streams before this call has returned) race
- * and must not be made.  Outputs are HOST pointers as for tnmc_slice_propose;
- * the call synchronises hip_stream. */
+ * and must not be made.  Outputs as for tnmc_slice_propose; the call
+ * synchronises hip_stream. */
 tnmc_status tnmc_slice_propose_static(tnmc_lattice* lat, int32_t chain, int32_t z, uint64_t sweep,
                                       int8_t* s_new, double* logq_new, double* logq_old, double* dE,
                                       void* hip_stream);
 
-/* log q of an arbitrary configuration s [Ly][Lx] (HOST) of layer z given the
+/* log q of an arbitrary configuration s [Ly][Lx] (HOST or DEVICE) of layer z given the
  * current held layers (SM S1.C: product of the conditionals along the
  * sampling order, with the spins projected on their states). */
 tnmc_status tnmc_slice_logq(tnmc_lattice* lat, int32_t chain, int32_t z, const int8_t* s,
@@ -135,6 +136,9 @@ typedef struct {
   int64_t contract_launches, sample_launches;
   int64_t contract_retries;     /* slice tasks whose left-sweep rank outgrew the compact LDS layout
                                    (two workgroups per CU) and were contracted again with the full one */
+  double seconds;               /* host wall time of the call, entry to return (a call given stats
+                                   synchronises hip_stream before it returns) */
+  int64_t nn_fallbacks;         /* tnmc_nn_sweep: layer updates proposed by the tensor-network fallback */
 } tnmc_stats;
 
 /* n_sweeps sweeps of every chain of every lattice in lats[0..n_lats-1]

@@ -76,7 +76,7 @@ class _Stats(ctypes.Structure):
         ("proposed", ctypes.c_int64), ("accepted", ctypes.c_int64), ("numeric_faults", ctypes.c_int64),
         ("contract_ms", ctypes.c_double), ("sample_ms", ctypes.c_double), ("contract_flops", ctypes.c_double),
         ("contract_launches", ctypes.c_int64), ("sample_launches", ctypes.c_int64),
-        ("contract_retries", ctypes.c_int64),
+        ("contract_retries", ctypes.c_int64), ("seconds", ctypes.c_double), ("nn_fallbacks", ctypes.c_int64),
     ]
 
     def as_dict(self):

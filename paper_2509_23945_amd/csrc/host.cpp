@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -24,6 +25,18 @@ using tnmc::TaskDesc;
 
 
 namespace {
+
+// Host wall time of an entry point that reports statistics, from entry to
+// return (such calls synchronise before they return).
+struct CallClock {
+  tnmc_stats* st;
+  std::chrono::steady_clock::time_point t0;
+  explicit CallClock(tnmc_stats* s) : st(s), t0(std::chrono::steady_clock::now()) {}
+  ~CallClock() {
+    if (st) st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+};
+
 
 thread_local std::string g_last_error;
 
@@ -490,8 +503,8 @@ tnmc_status autotune_groups(const Plan& plan, hipStream_t s, bool force = false)
 }
 
 // One task run with optional forced layer; used by propose / logq.
-tnmc_status run_single(tnmc_lattice* lat, int chain, int z, uint64_t sweep, const int8_t* force_host,
-                       int8_t* s_new_host, double* rec_host, hipStream_t s) {
+tnmc_status run_single(tnmc_lattice* lat, int chain, int z, uint64_t sweep, const int8_t* force_in,
+                       int8_t* s_new_out, double* rec_host, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_ws.mu);
   WsOrder order(s);
   g_last_error.clear();
@@ -510,15 +523,15 @@ tnmc_status run_single(tnmc_lattice* lat, int chain, int z, uint64_t sweep, cons
   plan.desc[0].write_back = 0;
   plan.desc[0].n_cand = 1;   // a single proposal
   plan.desc[0].s_new_out = g_ws.bytes;
-  if (force_host) {
-    HIP_TRY(hipMemcpyAsync(g_ws.bytes + plane, force_host, plane, hipMemcpyHostToDevice, s));
+  if (force_in) {
+    HIP_TRY(hipMemcpyAsync(g_ws.bytes + plane, force_in, plane, hipMemcpyDefault, s));   // host or device
     plan.desc[0].force_new = g_ws.bytes + plane;
   }
   HIP_TRY(hipMemcpyAsync(g_ws.tasks, plan.desc.data(), sizeof(TaskDesc), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));   // host buffers above are released on return
   r = launch_plan(plan, g_ws.tasks, sweep, s, nullptr, nullptr);
   if (r != TNMC_OK) return r;
-  if (s_new_host) HIP_TRY(hipMemcpyAsync(s_new_host, g_ws.bytes, plane, hipMemcpyDeviceToHost, s));
+  if (s_new_out) HIP_TRY(hipMemcpyAsync(s_new_out, g_ws.bytes, plane, hipMemcpyDefault, s));   // host or device
   HIP_TRY(hipMemcpyAsync(rec_host, drec, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return TNMC_OK;
@@ -710,6 +723,7 @@ tnmc_status tnmc_slice_logq(tnmc_lattice* lat, int32_t chain, int32_t z, const i
 
 tnmc_status tnmc_half_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t parity, uint64_t sweep,
                             double* trace, tnmc_stats* stats, void* stream) {
+  CallClock clock(stats);
   if (check_lats(lats, n_lats) != TNMC_OK || (parity != 0 && parity != 1)) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
   hipStream_t s = (hipStream_t)stream;
@@ -745,6 +759,7 @@ tnmc_status tnmc_half_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t p
 // created on first use).
 tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
                        int32_t record, int32_t time_kernels, tnmc_stats* stats, void* stream) {
+  CallClock clock(stats);
   if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
   hipStream_t s = (hipStream_t)stream;
@@ -819,6 +834,7 @@ tnmc_status tnmc_sweep(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_swee
 tnmc_status tnmc_sweep_superspin(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
                                  int32_t record, int32_t time_kernels, double* trace, tnmc_stats* stats,
                                  void* stream) {
+  CallClock clock(stats);
   if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0) return TNMC_ERR_ARG;
   for (int l = 0; l < n_lats; ++l) {
     const tnmc_lattice* L = lats[l];
@@ -896,6 +912,7 @@ tnmc_status tnmc_sweep_superspin(tnmc_lattice* const* lats, int32_t n_lats, int3
 
 tnmc_status tnmc_sweep_graph(tnmc_lattice* const* lats, int32_t n_lats, int32_t n_sweeps, uint64_t sweep_offset,
                              int32_t record, tnmc_stats* stats, void* stream) {
+  CallClock clock(stats);
   if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
   hipStream_t s = (hipStream_t)stream;
@@ -1243,7 +1260,7 @@ tnmc_status tnmc_slice_propose_static(tnmc_lattice* lat, int32_t chain, int32_t 
   }
   HIP_TRY(tnmc::launch_sample(dt, 1, d, cm, lat->precision, Lx, Ly, sweep, s));
   double rec[5];
-  HIP_TRY(hipMemcpyAsync(s_new, t.s_new_out, plane, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(s_new, t.s_new_out, plane, hipMemcpyDefault, s));   // host or device
   HIP_TRY(hipMemcpyAsync(rec, t.record, sizeof(rec), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   *logq_new = rec[0];
@@ -1433,8 +1450,8 @@ TaskDesc nn_task(tnmc_lattice* L, int chain, int z) {
   return t;
 }
 
-tnmc_status nn_single(tnmc_lattice* lat, tnmc_nn* nn, int chain, int z, uint64_t sweep, const int8_t* force_host,
-                      int8_t* s_new_host, double* rec_host, hipStream_t s) {
+tnmc_status nn_single(tnmc_lattice* lat, tnmc_nn* nn, int chain, int z, uint64_t sweep, const int8_t* force_in,
+                      int8_t* s_new_out, double* rec_host, hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_ws.mu);
   WsOrder order(s);
   g_last_error.clear();
@@ -1446,14 +1463,14 @@ tnmc_status nn_single(tnmc_lattice* lat, tnmc_nn* nn, int chain, int z, uint64_t
   t.record = g_ws.dbl;
   t.write_back = 0;
   t.s_new_out = g_ws.bytes;
-  if (force_host) {
-    HIP_TRY(hipMemcpyAsync(g_ws.bytes + plane, force_host, plane, hipMemcpyHostToDevice, s));
+  if (force_in) {
+    HIP_TRY(hipMemcpyAsync(g_ws.bytes + plane, force_in, plane, hipMemcpyDefault, s));   // host or device
     t.force_new = g_ws.bytes + plane;
   }
   HIP_TRY(hipMemcpyAsync(g_ws.nn_tasks, &t, sizeof(TaskDesc), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));   // the host copies above are released on return
   HIP_TRY(tnmc::launch_nn_sample(g_ws.nn_tasks, 1, nn->wbf, lat->Lx, lat->Ly, sweep, s));
-  if (s_new_host) HIP_TRY(hipMemcpyAsync(s_new_host, g_ws.bytes, plane, hipMemcpyDeviceToHost, s));
+  if (s_new_out) HIP_TRY(hipMemcpyAsync(s_new_out, g_ws.bytes, plane, hipMemcpyDefault, s));   // host or device
   HIP_TRY(hipMemcpyAsync(rec_host, g_ws.dbl, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   return TNMC_OK;
@@ -1656,6 +1673,7 @@ tnmc_status tnmc_nn_slice_logq(tnmc_lattice* lat, tnmc_nn* nn, int32_t chain, in
 tnmc_status tnmc_nn_sweep(tnmc_lattice* const* lats, int32_t n_lats, tnmc_nn* nn, int32_t n_sweeps,
                           uint64_t sweep_offset, int32_t record, int32_t time_kernels, tnmc_stats* stats,
                           void* stream) {
+  CallClock clock(stats);
   if (check_lats(lats, n_lats) != TNMC_OK || !nn || n_sweeps < 0) return TNMC_ERR_ARG;
   for (int l = 0; l < n_lats; ++l) {
     tnmc_status r = nn_lattice_ok(lats[l]);
@@ -1766,6 +1784,7 @@ tnmc_status tnmc_nn_sweep(tnmc_lattice* const* lats, int32_t n_lats, tnmc_nn* nn
       }
     }
   }
+  if (stats) stats->nn_fallbacks += (int64_t)tn_tasks.size() * n_sweeps;
   if (stats) {
     HIP_TRY(hipStreamSynchronize(s));
     for (int l = 0; l < n_lats; ++l) {
@@ -2085,6 +2104,7 @@ tnmc_status tnmc_sweep_direction(tnmc_lattice* const* lats, int32_t n_lats, int3
                                  uint64_t sweep_offset, int32_t record, int32_t time_kernels, tnmc_stats* stats,
                                  void* stream) {
   if (direction == 0) return tnmc_sweep(lats, n_lats, n_sweeps, sweep_offset, record, time_kernels, stats, stream);
+  CallClock clock(stats);
   if (check_lats(lats, n_lats) != TNMC_OK || n_sweeps < 0 || direction < 0 || direction > 2) return TNMC_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
   std::vector<tnmc_lattice*> views(n_lats);
