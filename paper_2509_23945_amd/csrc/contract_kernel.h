@@ -1523,7 +1523,18 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
             mrows = nC;
           }
           double* sJ = pre ? sR : sC;   // the rows the Jacobi rotates, leading dim ldj
-          const int ldj = pre ? LD : LDC;
+          int ldj = pre ? LD : LDC;
+          if constexpr (GM) {
+            // tiles in global memory: the rows are rotated in an LDS copy (the
+            // kernel's dynamic LDS holds D rows of D + 1 doubles, free otherwise)
+            for (int w = tid; w < mrows * nC; w += NTK) {
+              const int i = w / nC, c = w - i * nC;
+              lds[i * (D + 1) + c] = sC[i * LDC + c];
+            }
+            __syncthreads();
+            sJ = lds;
+            ldj = D + 1;
+          }
           {
             double fro = 0.0;
             for (int w = tid; w < mrows * nC; w += NTK) {
@@ -1532,13 +1543,16 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
             }
             fro = block_sum<NTK>(fro, sRed);
             const double floor = rtol * rtol * fro;   // |a_ij| below this: negligible at the cut-off
+            // sJ is in LDS in every layout
             if (((mrows + 1) >> 1) <= 8) {
-              if (tid < 64) jacobi_rows<(D + 7) / 8, true, NTK, GM>(sJ, ldj, mrows, nC, floor);
+              if (tid < 64) jacobi_rows<(D + 7) / 8, true, NTK, false>(sJ, ldj, mrows, nC, floor);
               __syncthreads();
             } else {
-              jacobi_rows<(D + 7) / 8, false, NTK, GM>(sJ, ldj, mrows, nC, floor);
+              jacobi_rows<(D + 7) / 8, false, NTK, false>(sJ, ldj, mrows, nC, floor);
             }
           }
+          vsrc = sJ;
+          vld = ldj;
           double nmax = 0.0;
           for (int i = tid; i < mrows; i += NTK) {
             double s = 0.0;
@@ -1680,7 +1694,9 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
 template <typename ET, int DP, int CHIM, bool CMP, bool GM, bool MF>
 hipError_t launch_contract_k(const TaskDesc* tasks, int n, int retry, hipStream_t s) {
   using Lay = Layout<DP, CHIM, CMP>;
-  const size_t bytes = GM ? 0 : sizeof(double) * Lay::total;
+  // global-memory tiles: LDS holds the truncating SVD's rows only
+  static_assert(!GM || sizeof(double) * Lay::D * (Lay::D + 1) <= 160 * 1024, "the SVD rows fit a CU's LDS");
+  const size_t bytes = sizeof(double) * (GM ? (size_t)Lay::D * (Lay::D + 1) : (size_t)Lay::total);
   static bool attr_set = false;
   if (!attr_set && bytes > 48 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)contract_kernel<ET, DP, CHIM, CMP, GM, MF>,
