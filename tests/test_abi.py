@@ -135,3 +135,39 @@ def test_direction_and_layout_arguments_checked_on_host(lib):
     # the rank cut-off knob takes exponents 0..15 (0 restores the defaults)
     assert lib.tnmc_debug_set(3, 16) == ARG and lib.tnmc_debug_set(3, -1) == ARG
     assert lib.tnmc_debug_set(3, 6) == 0 and lib.tnmc_debug_set(3, 0) == 0
+
+
+def test_binding_structs_match_the_header():
+    """The ctypes mirrors of the header's by-value structs list the same fields,
+    in the same order, with the same types (a field added on one side only
+    would shift every later one)."""
+    import ctypes
+    import re
+    hdr = open(os.path.join(os.path.dirname(tn.api.__file__), "..", "include", "tnmc.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", " ", hdr, flags=re.S)
+
+    def fields_of(name):
+        end = hdr.index("} " + name + ";")
+        body = hdr[hdr.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+        out = []
+        for decl in body.split(";"):
+            words = decl.replace(",", " , ").replace("*", " * ").split()
+            if not words:
+                continue
+            i = 0
+            while words[i] == "const":
+                i += 1
+            ctype, rest = words[i], words[i + 1:]
+            ptr = "*" in rest
+            out += [(n, ctype + ("*" if ptr else "")) for n in rest if n not in (",", "*")]
+        return out
+
+    P = ctypes.POINTER
+    kind = {"int64_t": ctypes.c_int64, "double": ctypes.c_double, "int32_t": ctypes.c_int32, "uint64_t": ctypes.c_uint64,
+            "float*": P(ctypes.c_float), "int32_t*": P(ctypes.c_int32), "double*": P(ctypes.c_double),
+            "int8_t*": P(ctypes.c_int8), "uint64_t*": P(ctypes.c_uint64)}
+    for name, mirror in (("tnmc_stats", tn.api._Stats), ("tnmc_lattice_desc", tn.api._Desc)):
+        fields = fields_of(name)
+        assert [n for n, _ in fields] == [n for n, _ in mirror._fields_], name
+        for (n, c), (_, t) in zip(fields, mirror._fields_):
+            assert kind[c] == t, (name, n, c, t)
