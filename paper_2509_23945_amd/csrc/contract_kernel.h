@@ -932,7 +932,10 @@ __device__ __attribute__((always_inline)) void form_c_mfma(const double* sR, con
 
 template <int DP, int CHIM, bool CMP = false>
 struct Layout {
-  static constexpr int NTH = CMP ? 128 : 256;   // threads per workgroup
+  // composite layers (DP = 4) run the full tiles with two wavefronts per task
+  // and the register QR's exchange over M, so that two tasks share a CU
+  static constexpr bool NARROW = !CMP && DP == 4;
+  static constexpr int NTH = (CMP || NARROW) ? 128 : 256;   // threads per workgroup
   static constexpr int D = DP * CHIM;   // largest bond after the MPO
   static constexpr int LD = D + 1;      // padded row stride of the square tiles
   static constexpr int RCAP = CMP ? CHIM : D;                    // largest left-sweep rank
@@ -964,8 +967,8 @@ struct Layout {
   static constexpr int oA1 = oWork;                              // [DP][CHIM][CHIM]
   static constexpr int oR1 = oA1 + DP * CHIM * CHIM;             // [RROWS][LD]
   static constexpr int oM1 = oR1 + RSZ;                          // [DP*RCAP][LD]
-  static constexpr int oWcL = CMP ? oM1 : oM1 + MT;              // [64][MRMAX+2]
-  static constexpr int end1 = CMP ? oM1 + ((WC > MT) ? WC : MT) : oWcL + WC;
+  static constexpr int oWcL = (CMP || NARROW) ? oM1 : oM1 + MT;   // [64][MRMAX+2]
+  static constexpr int end1 = (CMP || NARROW) ? oM1 + ((WC > MT) ? WC : MT) : oWcL + WC;
   // right sweep
   static constexpr int oA2 = oWork;                              // full layout only
   static constexpr int oT2 = CMP ? oWork : oA2 + DP * CHIM * CHIM;   // [D][CHIM]
