@@ -269,8 +269,13 @@ tnmc_status tnmc_debug_workspace(int32_t what, void* out, int64_t bytes);
  * factorisations to 10^-k for every storage precision, for plans made after
  * the call; 0 restores the defaults (1e-15 for FP64 environments, 1e-6 for
  * FP32 ones).  A proposal made with another cut-off is another q: MH stays
- * exact, but parity with the oracle holds only at the defaults.  Returns
- * TNMC_ERR_ARG for an unknown what or a value out of range. */
+ * exact, but parity with the oracle holds only at the defaults.  what = 4: a
+ * contraction class that runs the full tile layout launches its narrow variant
+ * (two wavefronts per task, two tasks per CU; otherwise used only when a
+ * launch has more tasks than the device has CUs) at any size, so that path
+ * can be checked against the oracle on small cases; value 1 = on, 0 = off
+ * (default).  Returns TNMC_ERR_ARG for an unknown what or a value out of
+ * range. */
 tnmc_status tnmc_debug_set(int32_t what, int32_t value);
 
 /* ------------------------------------------------------------------------

@@ -351,7 +351,8 @@ def tnmc_debug_workspace(what: int, nbytes: int) -> bytes:
 
 def tnmc_debug_set(what: int, value: int) -> None:
     """Test hooks and knobs (see include/tnmc.h): what = 0 forces the compact layout's overflow path,
-    1 the autotuner, 2 learned-task pairing, 3 the rank cut-off 10^-value (0 = defaults)."""
+    1 the autotuner, 2 learned-task pairing, 3 the rank cut-off 10^-value (0 = defaults), 4 forces the
+    narrow (two tasks per CU) variant of full-layout launches."""
     _check(load().tnmc_debug_set(what, value), "tnmc_debug_set")
 
 

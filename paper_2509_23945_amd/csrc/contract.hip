@@ -10,7 +10,10 @@ namespace tnmc {
 
 int g_force_retry = 0;
 
+int g_force_narrow = 0;
+
 void set_force_retry(int on) { g_force_retry = on; }
+void set_force_narrow(int on) { g_force_narrow = on; }
 
 bool contract_has_compact(int d, int chi_max) {
   if (d == 2) {

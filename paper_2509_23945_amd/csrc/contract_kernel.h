@@ -29,6 +29,7 @@
 namespace tnmc {
 
 extern int g_force_retry;   // test hook: every compact-layout task takes the retry path
+extern int g_force_narrow;  // test hook: full-layout launches take the narrow variant whatever their size
 
 namespace {
 
@@ -930,11 +931,12 @@ __device__ __attribute__((always_inline)) void form_c_mfma(const double* sR, con
   }
 }
 
-template <int DP, int CHIM, bool CMP = false>
+template <int DP, int CHIM, bool CMP = false, bool NAR = false>
 struct Layout {
-  // composite layers (DP = 4) run the full tiles with two wavefronts per task
-  // and the register QR's exchange over M, so that two tasks share a CU
-  static constexpr bool NARROW = !CMP && DP == 4;
+  // narrow: the full tiles with two wavefronts per task and the register QR's
+  // exchange over M, so that two tasks share a CU (composite layers, DP = 4,
+  // always; other full layouts on request, for launches of more tasks than CUs)
+  static constexpr bool NARROW = !CMP && (NAR || DP == 4);
   static constexpr int NTH = (CMP || NARROW) ? 128 : 256;   // threads per workgroup
   static constexpr int D = DP * CHIM;   // largest bond after the MPO
   static constexpr int LD = D + 1;      // padded row stride of the square tiles
@@ -1014,10 +1016,10 @@ struct Layout {
 // C and Y run on the vector ALU in FP64 (MF = false) or on the matrix cores
 // (MF = true) in FP64 (ET = double) or with FP32 operands and accumulation
 // (ET = float).
-template <typename ET, int DP, int CHIM, bool CMP, bool GM = false, bool MF = false>
-__global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(const TaskDesc* __restrict__ tasks,
-                                                                            int retry) {
-  using Lay = Layout<DP, CHIM, CMP>;
+template <typename ET, int DP, int CHIM, bool CMP, bool GM = false, bool MF = false, bool NAR = false>
+__global__ __launch_bounds__((Layout<DP, CHIM, CMP, NAR>::NTH)) void contract_kernel(const TaskDesc* __restrict__ tasks,
+                                                                                 int retry) {
+  using Lay = Layout<DP, CHIM, CMP, NAR>;
   constexpr int NTK = Lay::NTH;
   constexpr int D = Lay::D;
   constexpr int LD = Lay::LD;
@@ -1694,25 +1696,37 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP>::NTH)) void contract_kernel(
 }
 
 
-template <typename ET, int DP, int CHIM, bool CMP, bool GM, bool MF>
+template <typename ET, int DP, int CHIM, bool CMP, bool GM, bool MF, bool NAR = false>
 hipError_t launch_contract_k(const TaskDesc* tasks, int n, int retry, hipStream_t s) {
-  using Lay = Layout<DP, CHIM, CMP>;
+  using Lay = Layout<DP, CHIM, CMP, NAR>;
   // global-memory tiles: LDS holds the truncating SVD's rows only
   static_assert(!GM || sizeof(double) * Lay::D * (Lay::D + 1) <= 160 * 1024, "the SVD rows fit a CU's LDS");
   const size_t bytes = sizeof(double) * (GM ? (size_t)Lay::D * (Lay::D + 1) : (size_t)Lay::total);
   static bool attr_set = false;
   if (!attr_set && bytes > 48 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)contract_kernel<ET, DP, CHIM, CMP, GM, MF>,
+    hipError_t e = hipFuncSetAttribute((const void*)contract_kernel<ET, DP, CHIM, CMP, GM, MF, NAR>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL((contract_kernel<ET, DP, CHIM, CMP, GM, MF>), dim3(n), dim3(Lay::NTH), bytes, s, tasks, retry);
+  hipLaunchKernelGGL((contract_kernel<ET, DP, CHIM, CMP, GM, MF, NAR>), dim3(n), dim3(Lay::NTH), bytes, s, tasks, retry);
   return hipGetLastError();
 }
 
 // Two workgroups per CU need at most half of the 160 KB of LDS each.
 constexpr size_t kHalfLds = 80 * 1024;
+
+// Compute units of the current device (queried once; 256 on MI355X).
+inline int device_cus() {
+  static int cus = 0;
+  if (cus <= 0) {
+    int dev = 0, c = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      cus = c;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
 constexpr size_t kCuLds = 160 * 1024;
 
 template <int DP, int CHIM>
@@ -1746,6 +1760,13 @@ hipError_t launch_contract_t(const TaskDesc* tasks, int n, int full, hipStream_t
     if (e != hipSuccess) return e;
     return launch_contract_k<ET, DP, CHIM, false, false, MF>(tasks, n, 1, s);
   } else {
+    // more tasks than CUs: two narrow tasks per CU (where their tiles fit half
+    // a CU's LDS) take half the rounds of one wide task per CU
+    constexpr bool narrow_ok = DP != 4 && sizeof(double) * Layout<DP, CHIM, false, true>::total <= kHalfLds;
+    if constexpr (narrow_ok) {
+      if (g_force_narrow || n > device_cus())
+        return launch_contract_k<ET, DP, CHIM, false, false, MF, true>(tasks, n, 0, s);
+    }
     return launch_contract_k<ET, DP, CHIM, false, false, MF>(tasks, n, 0, s);
   }
 }

@@ -1007,13 +1007,15 @@ tnmc_status tnmc_autotune_now(tnmc_lattice* const* lats, int32_t n_lats, void* s
 }
 
 tnmc_status tnmc_debug_set(int32_t what, int32_t value) {
-  if (what < 0 || what > 3) return TNMC_ERR_ARG;
+  if (what < 0 || what > 4) return TNMC_ERR_ARG;
   if (what == 3 ? (value < 0 || value > 15) : (value != 0 && value != 1)) return TNMC_ERR_ARG;
   std::lock_guard<std::mutex> lk(g_ws.mu);
   if (what == 3) {
     g_rank_cut_exp = value;
   } else if (what == 0) {
     tnmc::set_force_retry(value);
+  } else if (what == 4) {
+    tnmc::set_force_narrow(value);
   } else if (what == 2) {
     g_nn_pairing = value != 0;
   } else {

@@ -104,6 +104,7 @@ bool contract_uses_global(int d, int chi_max);   // tiles in the per-task global
 size_t contract_lds_bytes(int d, int chi_max);
 size_t sample_lds_bytes(int d, int chi_max, int Lx, int Ly);   // static + dynamic LDS of a sampler workgroup
 void set_force_retry(int on);   // test hook: every compact-layout task takes the retry path
+void set_force_narrow(int on);  // test hook: full-layout launches take the narrow (two per CU) variant at any size
 int chi_bucket(int chi);   // storage chi_max used for a requested chi (0 if unsupported)
 
 }  // namespace tnmc

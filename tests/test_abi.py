@@ -131,7 +131,9 @@ def test_direction_and_layout_arguments_checked_on_host(lib):
     assert lib.tnmc_autotune_pin(2, 0) == ARG and lib.tnmc_autotune_pin(0, -2) == ARG
     assert lib.tnmc_autotune_now(None, 1, None) == ARG
     assert lib.tnmc_sweep_direction(None, 1, 1, 1, 0, 0, 0, None, None) == ARG
-    assert lib.tnmc_debug_set(4, 1) == ARG and lib.tnmc_debug_set(1, 2) == ARG
+    assert lib.tnmc_debug_set(5, 1) == ARG and lib.tnmc_debug_set(1, 2) == ARG
+    assert lib.tnmc_debug_set(4, 2) == ARG
+    assert lib.tnmc_debug_set(4, 1) == 0 and lib.tnmc_debug_set(4, 0) == 0
     # the rank cut-off knob takes exponents 0..15 (0 restores the defaults)
     assert lib.tnmc_debug_set(3, 16) == ARG and lib.tnmc_debug_set(3, -1) == ARG
     assert lib.tnmc_debug_set(3, 6) == 0 and lib.tnmc_debug_set(3, 0) == 0

@@ -6,7 +6,8 @@ ferromagnetic), beta in [0.2, 1.6] and chi in 1..16 (so that some layers are
 contracted exactly and others truncate hard), with two chains, and runs one
 half-sweep of a random parity through tnmc_half_sweep, with the contraction's
 products pinned to the vector ALU for half of the draws and to the matrix
-cores for the other half.  For every slice task the oracle, on the same
+cores for the other half, and the full tile layout in its wide (one task per
+CU) variant for half and its narrow (two per CU) one for the other half.  For every slice task the oracle, on the same
 seeded inputs and Philox counters, gives the current layer's log q, the
 proposal, its log q and dE, and the MH decision on the shared uniform; the GPU's trace must agree (log q to the FP64 bar, dE and
 spins exactly, ties on a cumulative threshold allowed as elsewhere).  The
@@ -46,23 +47,34 @@ def engine_pin(request):
     tn.tnmc_autotune_pin(-1, -1)
 
 
+@pytest.fixture
+def narrow(request):
+    tn.tnmc_debug_set(4, request.param)
+    yield request.param
+    tn.tnmc_debug_set(4, 0)
+
+
 @pytest.mark.parametrize("engine_pin", [0, 1], indirect=True, ids=["valu", "mfma"])
+@pytest.mark.parametrize("narrow", [0, 1], indirect=True, ids=["wide", "narrow"])
 @pytest.mark.parametrize("block", range(2))
-def test_random_configurations_match_oracle(block, engine_pin):
+def test_random_configurations_match_oracle(block, narrow, engine_pin):
+    """Two blocks of 40 draws per engine in each variant of the full layouts:
+    wide (one task per CU) and narrow (two per CU, otherwise taken only by
+    launches of more tasks than CUs), forced here whatever the launch size."""
     import torch
 
     block = 2 * block + engine_pin
-    rng = np.random.default_rng(2026 + block)
+    rng = np.random.default_rng(2026 + block + 100 * narrow)
     checked = ties = 0
-    for k in range(N_DRAWS // 4):
+    for k in range(N_DRAWS // 8):
         case = draw_case(rng)
         Lx, Ly, Lz, d, chi, beta = case["Lx"], case["Ly"], case["Lz"], case["d"], case["chi"], case["beta"]
         parity = int(rng.integers(0, 2))
         sweep = int(rng.integers(0, 1000))
-        label = f"random block {block} draw {k}: {case} parity {parity} sweep {sweep}"
+        label = f"random block {block} {'narrow' if narrow else 'wide'} draw {k}: {case} parity {parity} sweep {sweep}"
         gh.announce(label)
-        lat, J, spins, betas = gh.make_lattice(Lx, Ly, Lz, d, chi, kind=case["kind"], beta=beta, seed=500 + 37 * block + k,
-                                               n_chains=2, philox_seed=SEED)
+        lat, J, spins, betas = gh.make_lattice(Lx, Ly, Lz, d, chi, kind=case["kind"], beta=beta,
+                                               seed=500 + 37 * block + 1000 * narrow + k, n_chains=2, philox_seed=SEED)
         tasks = [(c, z) for c in range(2) for z in range(parity, Lz, 2)]
         trace = torch.zeros(5 * len(tasks), dtype=torch.float64, device="cuda")
         st = tn.tnmc_half_sweep([lat], parity, sweep, trace_ptr=trace.data_ptr())
