@@ -1735,7 +1735,8 @@ constexpr bool layout_has_compact() {
   // left rank outgrew its tiles partway through a layer, resumed with the full
   // layout from that row, faulted the GPU once and the cause is not known
   if constexpr (DP == 3 && CHIM == 16) return false;
-  // composite layers (d = 4) likewise run the full layout only
+  // composite layers (d = 4) run the full tiles only (in the narrow variant),
+  // never the compact ones
   if constexpr (DP == 4) return false;
   return sizeof(double) * Layout<DP, CHIM, false>::total > kHalfLds &&
          sizeof(double) * Layout<DP, CHIM, true>::total <= kHalfLds;
