@@ -14,6 +14,8 @@ oracle's draws.  What is checked, on the GPU's own proposals:
   ancestral sampling defines q, so MH is exact only if s is drawn from the q
   whose log q is reported);
 * dE exact (a full-lattice energy difference of the oracle's model);
+* the same for the narrow variant of the full tile layout (two tasks per CU,
+  taken by launches of more tasks than CUs), forced on the cases it serves;
 * the Markov chain stays exact: with a truncated (chi = 1) proposal on a
   2x2x4 lattice, chain averages of E and M^2 over independent GPU chains match
   exact enumeration within statistical error.
@@ -44,8 +46,30 @@ def engine(request):
         tn.tnmc_autotune_pin(-1, -1)
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:3])) + f"-d{c[3]}-{c[4]}-chi{c[6]}-z{c[7]}")
+def case_id(c):
+    return "x".join(map(str, c[:3])) + f"-d{c[3]}-{c[4]}-chi{c[6]}-z{c[7]}"
+
+
+@pytest.mark.parametrize("case", CASES, ids=case_id)
 def test_fp32_logq_of_own_proposals(case, engine):
+    check_fp32_proposals(case, engine)
+
+
+# the cases whose class runs the full tile layout, which has a narrow variant
+# (two tasks per CU) for launches of more tasks than CUs
+NARROW_CASES = [c for c in CASES if (c[3] == 2 and c[6] <= 16) or (c[3] == 3 and c[6] <= 8)]
+
+
+@pytest.mark.parametrize("case", NARROW_CASES, ids=case_id)
+def test_fp32_logq_of_own_proposals_narrow_layout(case, engine):
+    tn.tnmc_debug_set(4, 1)
+    try:
+        check_fp32_proposals(case, engine)
+    finally:
+        tn.tnmc_debug_set(4, 0)
+
+
+def check_fp32_proposals(case, engine):
     Lx, Ly, Lz, d, kind, beta, chi, z = case
     gh.announce(f"fp32 propose case {case}, engine {engine}")
     lat, J, spins, _ = gh.make_lattice(Lx, Ly, Lz, d, chi, kind=kind, beta=beta, seed=3, precision=tn.TNMC_FP32)
