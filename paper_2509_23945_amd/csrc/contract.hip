@@ -15,6 +15,17 @@ int g_force_narrow = 0;
 void set_force_retry(int on) { g_force_retry = on; }
 void set_force_narrow(int on) { g_force_narrow = on; }
 
+int device_cus() {
+  static int cus = 0;
+  if (cus <= 0) {
+    int dev = 0, c = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      cus = c;
+    if (cus <= 0) cus = 256;
+  }
+  return cus;
+}
+
 bool contract_has_compact(int d, int chi_max) {
   if (d == 2) {
     switch (chi_max) {

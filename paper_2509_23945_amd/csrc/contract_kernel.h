@@ -1716,17 +1716,6 @@ hipError_t launch_contract_k(const TaskDesc* tasks, int n, int retry, hipStream_
 // Two workgroups per CU need at most half of the 160 KB of LDS each.
 constexpr size_t kHalfLds = 80 * 1024;
 
-// Compute units of the current device (queried once; 256 on MI355X).
-inline int device_cus() {
-  static int cus = 0;
-  if (cus <= 0) {
-    int dev = 0, c = 0;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-      cus = c;
-    if (cus <= 0) cus = 256;
-  }
-  return cus;
-}
 constexpr size_t kCuLds = 160 * 1024;
 
 template <int DP, int CHIM>

@@ -639,6 +639,7 @@ tnmc_status tnmc_lattice_init(const tnmc_lattice_desc* ds, tnmc_lattice** out) {
     for (size_t i = 0; i < (size_t)ds->n_instances * 3 * n * sizeof(float); ++i) h = (h ^ p[i]) * 1099511628211ull;
     L->J_hash = h;
   }
+  (void)tnmc::device_cus();   // the one device query of the launch rules, made here, outside any capture
   INIT_TRY(hipMalloc((void**)&L->dJ, (size_t)ds->n_instances * 3 * n * sizeof(float)));
   INIT_TRY(hipMemcpy(L->dJ, ds->J, (size_t)ds->n_instances * 3 * n * sizeof(float), hipMemcpyHostToDevice));
   INIT_TRY(hipMalloc((void**)&L->dspins, (size_t)ds->n_chains * n));

@@ -105,6 +105,10 @@ size_t contract_lds_bytes(int d, int chi_max);
 size_t sample_lds_bytes(int d, int chi_max, int Lx, int Ly);   // static + dynamic LDS of a sampler workgroup
 void set_force_retry(int on);   // test hook: every compact-layout task takes the retry path
 void set_force_narrow(int on);  // test hook: full-layout launches take the narrow (two per CU) variant at any size
+// Compute units of the current device (queried on the first call, 256 on
+// MI355X); lattice creation makes that call, so no later launch queries the
+// device, not even under graph capture.
+int device_cus();
 int chi_bucket(int chi);   // storage chi_max used for a requested chi (0 if unsupported)
 
 }  // namespace tnmc
