@@ -1001,6 +1001,10 @@ struct Layout {
   static constexpr int MMS = (D > 16) ? 32 : 16;
   static constexpr int MRS = MMS / 2;   // n <= D <= 32: two or four lanes per column
   static constexpr bool PRECOND = !CMP && D <= 32 && 64 * (MRS + 2) <= endWc - oWcR;
+  // tiles in global memory: the dynamic LDS (150 KB, in doubles) holds a
+  // site's M tile and the register QR's exchange where they fit, and the
+  // truncating SVD's rows
+  static constexpr int GM_LDS = (D * (D + 1) > 19200) ? D * (D + 1) : 19200;
   static constexpr int total = (end1 > end2) ? end1 : end2;
   static_assert(oWcL % 2 == 0 && oWcR % 2 == 0 && oWq % 2 == 0, "16-byte aligned register-QR buffers");
   static_assert(!CMP || RCAP * D <= D * CHIM, "compact: C fits T's tile");
@@ -1105,6 +1109,18 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP, NAR>::NTH)) void contract_ke
         // R~[i][al*d+b] = sum_a R[i][al*na+a] H[a][b]  (H folded in)
         const double* Hx = sH + x * DP * DP;
         const double* Gx = sG + x * DP * DP;
+        // tiles in global memory: M (rR * DP rows) and the register QR's
+        // exchange go to LDS whenever they fit there (rR is the same in every
+        // thread, so is the choice)
+        double* sMx = sM;
+        double* sWcx = smem + Lay::oWcL;
+        if constexpr (GM) {
+          const int wc_off = (rR * DP * LD + 1) & ~1;
+          if (wc_off + Lay::WC <= Lay::GM_LDS) {
+            sMx = lds;
+            sWcx = lds + wc_off;
+          }
+        }
         {
           if constexpr (MF) {
             // matrix cores: for each b, the rR x cr product of R (rows i, columns
@@ -1138,7 +1154,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP, NAR>::NTH)) void contract_ke
 #pragma unroll
                   for (int r = 0; r < DP; ++r)
 #pragma unroll
-                    for (int b = 0; b < DP; ++b) sM[(row * DP + r) * LD + be * DP + b] = Gx[r * DP + b] * (double)acc[b][q];
+                    for (int b = 0; b < DP; ++b) sMx[(row * DP + r) * LD + be * DP + b] = Gx[r * DP + b] * (double)acc[b][q];
                 }
               }
             }
@@ -1176,7 +1192,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP, NAR>::NTH)) void contract_ke
                 }
               }
 #pragma unroll
-              for (int r = 0; r < DP; ++r) sM[(i * DP + r) * LD + be * DP + b] = Gx[r * DP + b] * s;
+              for (int r = 0; r < DP; ++r) sMx[(i * DP + r) * LD + be * DP + b] = Gx[r * DP + b] * s;
             }
           }
         }
@@ -1193,8 +1209,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP, NAR>::NTH)) void contract_ke
           // R Pi^T straight from registers to sR and gR, already scaled
           if (tid < 64) {
             double rmax = 0.0;
-            double* sWc = smem + Lay::oWcL;
-            const int r0 = qr_pivoted_reg<Lay::MMW, false, GM>(sM, LD, m, n, CMP ? Lay::RCAP + 1 : m, rtol, sWc, nullptr,
+            const int r0 = qr_pivoted_reg<Lay::MMW, false, GM>(sMx, LD, m, n, CMP ? Lay::RCAP + 1 : m, rtol, sWcx, nullptr,
                                                           nullptr, sR, LD, gR, D, &rmax);
             if (tid == 0) {
               sIdx[D] = r0;
@@ -1222,7 +1237,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP, NAR>::NTH)) void contract_ke
           }
         } else if (n <= 64 && m <= 64) {
           if (tid < 64) {
-            const int r0 = qr_pivoted_wave<GM>(sM, LD, m, n, sPerm, rtol);
+            const int r0 = qr_pivoted_wave<GM>(sMx, LD, m, n, sPerm, rtol);
             if (tid == 0) sIdx[D] = r0;   // pass the rank to the other waves
           } else {
             stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid - 64, NTK - 64);
@@ -1231,7 +1246,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP, NAR>::NTH)) void contract_ke
           rx = sIdx[D];
           __syncthreads();
         } else {
-          rx = qr_pivoted<NTK>(sM, LD, m, n, sPerm, sNrm, sScal, rtol);
+          rx = qr_pivoted<NTK>(sMx, LD, m, n, sPerm, sNrm, sScal, rtol);
           stage_site<DP, CHIM>(sA, gAn, ncl, ncr, tid, NTK);
         }
         if (rx == 0) fault |= 1;
@@ -1240,7 +1255,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP, NAR>::NTH)) void contract_ke
           double mx = 0.0;
           for (int w = tid; w < rx * n; w += NTK) {
             const int i = w / n, j = w % n;
-            if (j >= i) mx = fmax(mx, fabs(sM[i * LD + j]));
+            if (j >= i) mx = fmax(mx, fabs(sMx[i * LD + j]));
           }
           mx = block_max<NTK>(mx, sRed);
           const double inv = (mx > 0.0 && isfinite(mx)) ? 1.0 / mx : 1.0;
@@ -1248,7 +1263,7 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP, NAR>::NTH)) void contract_ke
           // R_x = R Pi^T: any factor with R_x^T R_x = M^T M serves as the metric of the left part
           for (int w = tid; w < rx * n; w += NTK) {
             const int i = w / n, j = w % n;
-            const double v = (j >= i) ? sM[i * LD + j] * inv : 0.0;
+            const double v = (j >= i) ? sMx[i * LD + j] * inv : 0.0;
             const int oj = sPerm[j];
             sR[i * LD + oj] = v;
             gR[(size_t)i * D + oj] = v;
@@ -1699,9 +1714,9 @@ __global__ __launch_bounds__((Layout<DP, CHIM, CMP, NAR>::NTH)) void contract_ke
 template <typename ET, int DP, int CHIM, bool CMP, bool GM, bool MF, bool NAR = false>
 hipError_t launch_contract_k(const TaskDesc* tasks, int n, int retry, hipStream_t s) {
   using Lay = Layout<DP, CHIM, CMP, NAR>;
-  // global-memory tiles: LDS holds the truncating SVD's rows only
-  static_assert(!GM || sizeof(double) * Lay::D * (Lay::D + 1) <= 160 * 1024, "the SVD rows fit a CU's LDS");
-  const size_t bytes = sizeof(double) * (GM ? (size_t)Lay::D * (Lay::D + 1) : (size_t)Lay::total);
+  // global-memory tiles: LDS holds M where it fits and the truncating SVD's rows
+  static_assert(!GM || sizeof(double) * Lay::GM_LDS <= 160 * 1024, "the staging area fits a CU's LDS");
+  const size_t bytes = sizeof(double) * (GM ? (size_t)Lay::GM_LDS : (size_t)Lay::total);
   static bool attr_set = false;
   if (!attr_set && bytes > 48 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)contract_kernel<ET, DP, CHIM, CMP, GM, MF, NAR>,
