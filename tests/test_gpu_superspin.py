@@ -5,7 +5,7 @@
   identical acceptance counts;
 * 64 independent 2x2x4 chains at chi = 1 match exact enumeration of <E> and
   <M^2>;
-* 40 seeded random shapes, couplings, temperatures and bond dimensions
+* 120 seeded random shapes, couplings, temperatures and bond dimensions
   (one sweep each) reproduce the oracle's chain spin for spin;
 * the entry point refuses Potts lattices, chi_max above 8 and one-layer
   lattices.
@@ -45,7 +45,7 @@ def test_superspin_sweeps_match_oracle(Lx, Ly, Lz, kind, beta, chi):
             assert np.array_equal(tn.tnmc_get_spins(lat, c), refs[c]), (t, c)
 
 
-@pytest.mark.parametrize("block", range(2))
+@pytest.mark.parametrize("block", range(6))
 def test_random_composites_match_oracle(block):
     """Seeded draws of shape (Lx, Ly in 2..7, Lz in 2..6), couplings (+-J,
     Gaussian, uniform ferromagnetic), beta in [0.2, 1.6] and chi in {1, 2, 3,
