@@ -139,6 +139,24 @@ def test_direction_and_layout_arguments_checked_on_host(lib):
     assert lib.tnmc_debug_set(3, 6) == 0 and lib.tnmc_debug_set(3, 0) == 0
 
 
+def test_sweep_entry_points_reject_empty_lattice_lists(lib):
+    """An empty or NULL lattice list and a negative sweep count are argument
+    errors, returned before any device work."""
+    import ctypes
+    ARG = tn.api.TNMC_ERR_ARG
+    empty = (ctypes.c_void_p * 1)()
+    for lats in (None, empty):
+        assert lib.tnmc_sweep(lats, 0, 1, 0, 0, 0, None, None) == ARG
+        assert lib.tnmc_half_sweep(lats, 0, 0, 0, None, None, None) == ARG
+        assert lib.tnmc_sweep_graph(lats, 0, 1, 0, 0, None, None) == ARG
+        assert lib.tnmc_sweep_superspin(lats, 0, 1, 0, 0, 0, None, None, None) == ARG
+        assert lib.tnmc_sweep_direction(lats, 0, 2, 1, 0, 0, 0, None, None) == ARG
+        assert lib.tnmc_nn_sweep(lats, 0, None, 1, 0, 0, 0, None, None) == ARG
+    # a list holding a NULL handle
+    assert lib.tnmc_sweep(empty, 1, 1, 0, 0, 0, None, None) == ARG
+    assert lib.tnmc_sweep(None, 1, -1, 0, 0, 0, None, None) == ARG
+
+
 def test_binding_structs_match_the_header():
     """The ctypes mirrors of the header's by-value structs list the same fields,
     in the same order, with the same types (a field added on one side only

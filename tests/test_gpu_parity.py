@@ -29,6 +29,8 @@ CASES = [
     (7, 6, 2, 2, "pmj", 1.2, 5, 1),        # one held neighbour
     (1, 6, 3, 2, "gauss", 0.9, 1, 1),      # single column
     (6, 1, 3, 2, "pmj", 1.0, 2, 1),        # single row
+    (1, 1, 3, 2, "gauss", 0.9, 2, 1),      # one-site layer
+    (1, 1, 3, 3, "ferro", 0.55, 2, 1),     # one-site Potts layer
     (4, 3, 3, 3, "ferro", 0.55, 9, 1),     # Potts, exact
     (6, 5, 3, 3, "ferro", 0.55, 4, 1),     # Potts, truncated
     (16, 16, 16, 2, "pmj", 1.0, 32, 5),    # 16^3 layer at chi=32
@@ -226,6 +228,21 @@ def test_invalid_calls_are_rejected():
     # the largest layers are: 64 x 64 Potts at chi = 32 (single-tile sampler layout) and Ising
     for d in (2, 3):
         gh.make_lattice(64, 64, 2, d, 32, kind="ferro", seed=1)
+
+
+def test_zero_sweeps_change_nothing():
+    """n_sweeps = 0 is a valid call: no launch, zero counts, no record, the
+    spins as they were."""
+    gh.announce("zero sweeps")
+    lat, J, spins, _ = gh.make_lattice(5, 4, 4, 2, 4, seed=2, n_chains=2, record_capacity=4)
+    st = tn.tnmc_sweep([lat], 0, record=True)
+    assert st["proposed"] == 0 and st["accepted"] == 0 and st["numeric_faults"] == 0
+    assert st["contract_launches"] == 0 and st["sample_launches"] == 0
+    for c in range(2):
+        assert np.array_equal(tn.tnmc_get_spins(lat, c), spins[c])
+    E, _, _ = tn.tnmc_timeseries(lat)
+    assert E.shape[0] == 0
+    tn.tnmc_lattice_free(lat)
 
 
 def test_heterogeneous_batch_like_c3():
