@@ -35,6 +35,8 @@ CASES = [
     (6, 5, 3, 3, "ferro", 0.55, 4, 1),     # Potts, truncated
     (16, 16, 16, 2, "pmj", 1.0, 32, 5),    # 16^3 layer at chi=32
     (32, 32, 3, 2, "pmj", 1.0, 32, 1),     # 32x32 layer at chi=32 (largest shape)
+    (64, 4, 3, 2, "pmj", 1.0, 32, 1),      # widest rows (64 sites), chi=32
+    (4, 64, 2, 2, "gauss", 0.9, 8, 0),     # most rows (64), one held neighbour
     (16, 16, 3, 2, "pmj", 1.0, 20, 1),     # compact layout, truncating (rank > chi)
     (7, 6, 3, 3, "ferro", 0.55, 10, 1),    # Potts, compact layout, truncating
     (8, 6, 3, 3, "ferro", 0.55, 14, 1),    # Potts, compact, truncating after an LQ of more than 32 rows
