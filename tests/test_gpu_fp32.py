@@ -128,17 +128,20 @@ def test_fp32_chain_averages_match_enumeration(engine):
         assert abs(devs.mean()) < 4 * err + 1e-12, (devs.mean(), err)
 
 
-def test_reduced_mfma_form_reproduces_fp64_observables():
+@pytest.mark.parametrize("L,beta,n_sw", [(8, 1.0, 600), (16, 0.7, 400)], ids=["8cubed-beta1", "16cubed-beta0.7"])
+def test_reduced_mfma_form_reproduces_fp64_observables(L, beta, n_sw):
     """Stationarity is unchanged by the reduced-precision proposal (main text
     Eq. 1: MH is exact for any q with exact log q).  32 +-J instances x 2
-    replicas on 8^3 at beta = 1 and chi = 3 (truncated, so proposals are
-    rejected at times): the FP64 form (vector-ALU products) and the reduced
-    form (FP32 environments, FP32 MFMA products) each run 600 sweeps from the
-    same states; per instance the averages of E/N and of q^2 over sweeps
-    100..599 are compared, and the mean difference over instances must be
-    within four standard errors of zero."""
-    gh.announce("reduced (FP32 MFMA) vs FP64 observables, 8^3 beta=1 chi=3, 64 chains x 600 sweeps")
-    L, chi, beta, n_inst, n_sw = 8, 3, 1.0, 32, 600
+    replicas at chi = 3 (truncated, so proposals are rejected at times), on
+    8^3 at beta = 1 and on 16^3 at beta = 0.7 (above the glass transition, so
+    that 16^3 chains equilibrate within the discarded sweeps): the FP64 form
+    (vector-ALU products) and the reduced form (FP32 environments, FP32 MFMA
+    products) each run n_sw sweeps from the same states; per instance the
+    averages of E/N and of q^2 over sweeps 100..n_sw-1 are compared, and the
+    mean difference over instances must be within four standard errors of
+    zero."""
+    gh.announce(f"reduced (FP32 MFMA) vs FP64 observables, {L}^3 beta={beta} chi=3, 64 chains x {n_sw} sweeps")
+    chi, n_inst = 3, 32
     pairs = np.array([[2 * i, 2 * i + 1] for i in range(n_inst)], dtype=np.int32)
     res = {}
     try:
@@ -149,6 +152,7 @@ def test_reduced_mfma_form_reproduces_fp64_observables():
             st = tn.tnmc_sweep([lat], n_sw, record=True)
             assert st["numeric_faults"] == 0 and st["accepted"] < st["proposed"]
             E, _, q = tn.tnmc_timeseries(lat)
+            tn.tnmc_lattice_free(lat)
             e_inst = (E[100:] / L ** 3).mean(axis=0).reshape(n_inst, 2).mean(axis=1)
             q2_inst = (q[100:] ** 2).mean(axis=0)
             res[prec] = (e_inst, q2_inst)
