@@ -324,6 +324,65 @@ def test_training_gains_acceptance():
     assert a0 < 0.01 and a1 > 0.15 and st1["numeric_faults"] == 0
 
 
+def test_trained_learned_chain_reproduces_tn_observables():
+    """Stationarity with the learned proposal at a size where it is accepted
+    (main text Eq. 1: MH is exact for any q whose log q is exact).  32 +-J
+    instances x 2 replicas on 8^3 at beta = 0.7 (above the glass transition,
+    so chains decorrelate within a few sweeps): the FP64 TN chain (chi = 16)
+    and a learned-only chain (network trained for 10 epochs on 20 480 TN
+    (condition, layer) pairs of the same instances, no TN fallback) each run
+    600 recorded sweeps; per instance the averages of E/N and of q^2 over
+    sweeps 100..599 are compared, and the mean difference over instances must
+    be within four standard errors of zero."""
+    torch = torch_dev()
+    gh.announce("learned vs TN observables 8^3 beta=0.7, 64 chains x 600 sweeps")
+    L, beta, chi, n_inst, n_sw, K = 8, 0.7, 16, 32, 600, 40
+    n_chains = 2 * n_inst
+    pairs = np.array([[2 * i, 2 * i + 1] for i in range(n_inst)], dtype=np.int32)
+
+    def lattice():
+        return gh.make_lattice(L, L, L, 2, chi, kind="pmj", beta=beta, seed=80, n_chains=n_chains, pairs=pairs,
+                               record_capacity=n_sw)[0]
+
+    ref = lattice()
+    st = tn.tnmc_sweep([ref], n_sw, record=True)
+    assert st["numeric_faults"] == 0
+    E_ref, _, q_ref = tn.tnmc_timeseries(ref)
+    tn.tnmc_lattice_free(ref)
+
+    lat = lattice()
+    per = n_chains * L
+    cond = torch.empty((K * per, 4, L, L), dtype=torch.float32, device="cuda")
+    s_data = torch.empty((K * per, L, L), dtype=torch.int8, device="cuda")
+    for k in range(K):
+        # Philox counters of their own, so the data sweeps do not replay the reference chain
+        tn.tnmc_sweep([lat], 1, sweep_offset=50_000 + k)
+        tn.tnmc_nn_dataset(lat, cond.data_ptr() + k * per * 4 * L * L * 4, s_data.data_ptr() + k * per * L * L)
+    torch.cuda.synchronize()
+    perm = torch.from_numpy(np.random.Generator(np.random.PCG64(7)).permutation(K * per)).cuda()
+    cond, s_data = cond[perm].contiguous(), s_data[perm].contiguous()
+    net = tn.tnmc_nn_create(None, seed=3)
+    tn.tnmc_nn_train(net, cond.data_ptr(), s_data.data_ptr(), K * per, L, L, 10, 256, 2e-3)
+    del cond, s_data
+    tn.tnmc_timeseries_reset(lat)
+    st = tn.tnmc_nn_sweep([lat], net, n_sw, sweep_offset=100_000, record=True)
+    acc = st["accepted"] / st["proposed"]
+    print(f"learned-only acceptance at 8^3 beta={beta}: {acc:.3f}")
+    assert st["numeric_faults"] == 0 and st["nn_fallbacks"] == 0 and acc > 0.15
+    E_nn, _, q_nn = tn.tnmc_timeseries(lat)
+    tn.tnmc_lattice_free(lat)
+    assert E_nn.shape == (n_sw, n_chains) and E_ref.shape == (n_sw, n_chains)
+
+    def per_instance(E, q):
+        return ((E[100:] / L ** 3).mean(axis=0).reshape(n_inst, 2).mean(axis=1), (q[100:] ** 2).mean(axis=0))
+
+    for name, a, b in zip(("E/N", "q^2"), per_instance(E_nn, q_nn), per_instance(E_ref, q_ref)):
+        dlt = a - b
+        err = dlt.std(ddof=1) / math.sqrt(len(dlt))
+        print(f"learned minus TN, {name}: {dlt.mean():.3e} +- {err:.3e}")
+        assert abs(dlt.mean()) < 4 * err + 1e-12, (name, dlt.mean(), err)
+
+
 def test_nn_sweep_over_lattices_of_different_shapes():
     """One learned-proposal sweep over two lattices of different (Lx, Ly, Lz) in
     one call (each parity is one launch sized for the widest and tallest
