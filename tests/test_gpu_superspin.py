@@ -7,6 +7,8 @@
   <M^2>;
 * 120 seeded random shapes, couplings, temperatures and bond dimensions
   (one sweep each) reproduce the oracle's chain spin for spin;
+* on 8^3 at beta = 0.7, TNMCMC-2 chains reproduce the TNMCMC-1 chains'
+  averages of E/N and q^2 per instance within statistical error;
 * the entry point refuses Potts lattices, chi_max above 8 and one-layer
   lattices.
 
@@ -95,6 +97,34 @@ def test_superspin_chain_averages_match_enumeration():
     for devs in (np.array(devs_E), np.array(devs_M2)):
         err = devs.std(ddof=1) / math.sqrt(len(devs))
         assert abs(devs.mean()) < 4 * err + 1e-12, (devs.mean(), err)
+
+
+def test_superspin_chain_reproduces_tnmcmc1_observables():
+    """Stationarity of the composite-layer kernel on a lattice too large to
+    enumerate: 32 +-J instances x 2 replicas on 8^3 at beta = 0.7 (above the
+    glass transition, so chains decorrelate within a few sweeps), TNMCMC-2 at
+    chi = 4 against TNMCMC-1 at chi = 8, 400 recorded sweeps each from the
+    same states; per instance the averages of E/N and of q^2 over sweeps
+    100..399 are compared, and the mean difference over instances must be
+    within four standard errors of zero."""
+    gh.announce("superspin vs TNMCMC-1 observables 8^3 beta=0.7, 64 chains x 400 sweeps")
+    L, beta, n_inst, n_sw = 8, 0.7, 32, 400
+    pairs = np.array([[2 * i, 2 * i + 1] for i in range(n_inst)], dtype=np.int32)
+    res = []
+    for chi, sweep in ((8, tn.tnmc_sweep), (4, tn.tnmc_sweep_superspin)):
+        lat = gh.make_lattice(L, L, L, 2, chi, kind="pmj", beta=beta, seed=90, n_chains=2 * n_inst, pairs=pairs,
+                              record_capacity=n_sw)[0]
+        st = sweep([lat], n_sw, record=True)
+        assert st["numeric_faults"] == 0
+        E, _, q = tn.tnmc_timeseries(lat)
+        tn.tnmc_lattice_free(lat)
+        assert E.shape == (n_sw, 2 * n_inst)
+        res.append(((E[100:] / L ** 3).mean(axis=0).reshape(n_inst, 2).mean(axis=1), (q[100:] ** 2).mean(axis=0)))
+    for name, a, b in zip(("E/N", "q^2"), res[1], res[0]):
+        dlt = a - b
+        err = dlt.std(ddof=1) / math.sqrt(len(dlt))
+        print(f"TNMCMC-2 minus TNMCMC-1, {name}: {dlt.mean():.3e} +- {err:.3e}")
+        assert abs(dlt.mean()) < 4 * err + 1e-12, (name, dlt.mean(), err)
 
 
 def test_superspin_sweeps_are_refused():
