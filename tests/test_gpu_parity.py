@@ -247,6 +247,32 @@ def test_zero_sweeps_change_nothing():
     tn.tnmc_lattice_free(lat)
 
 
+def test_potts_chain_averages_match_enumeration():
+    """64 independent 3-state Potts chains on one 2x2x3 ferromagnet at beta =
+    0.55, chi = 1 (truncated, so proposals are rejected at times): each
+    chain's averages of E and of the recorded magnetisation
+    M = (3 max_k n_k / N - 1) / 2 over sweeps 30..299 deviate from the exact
+    Boltzmann averages (all 3^12 states enumerated) by amounts whose mean is
+    zero within four standard errors."""
+    gh.announce("potts chain averages 2x2x3")
+    Lx, Ly, Lz, beta, n_chains, n_sweeps = 2, 2, 3, 0.55, 64, 300
+    lat, J, _, _ = gh.make_lattice(Lx, Ly, Lz, 3, 1, kind="ferro", beta=beta, seed=5, n_chains=n_chains,
+                                   record_capacity=n_sweeps)
+    st = tn.tnmc_sweep([lat], n_sweeps, record=True)
+    assert st["numeric_faults"] == 0 and st["accepted"] < st["proposed"]
+    E, M, _ = tn.tnmc_timeseries(lat)
+    tn.tnmc_lattice_free(lat)
+    states, En = bf.lattice_states(J[0], Lx, Ly, Lz, 3)
+    counts = np.stack([(states == k).sum(axis=(1, 2, 3)) for k in range(3)])
+    Mn = (3.0 * counts.max(axis=0) / (Lx * Ly * Lz) - 1.0) / 2.0
+    w = np.exp(-beta * (En - En.min()))
+    w /= w.sum()
+    for series, exact in ((E, float(np.sum(w * En))), (M, float(np.sum(w * Mn)))):
+        devs = series[30:].mean(axis=0) - exact
+        err = devs.std(ddof=1) / math.sqrt(len(devs))
+        assert abs(devs.mean()) < 4 * err + 1e-12, (devs.mean(), err)
+
+
 def test_heterogeneous_batch_like_c3():
     """The mixed batch of the c3 workload at small sizes: three lattice sizes x two
     bond dimensions (one truncating), Gaussian couplings and a spread of beta, all in
