@@ -72,17 +72,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, choice=None, path: str = TRAFFIC_FILE):
     """Bytes per launch from the committed counter summary, or None when it is
-    missing, for another workload, or taken on different kernel sources."""
+    missing, for another workload, taken on different kernel sources, or (with
+    choice, the autotuner's [{"engine", "layout"}] for the workload's one
+    class) taken on another product engine or tile layout than this run's."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             kv = dict(line.split(":", 1) for line in fh if line.startswith("- ") and ":" in line)
     except OSError:
         return None
     kv = {k[2:].strip(): v.strip().strip("`") for k, v in kv.items()}
     if kv.get("workload") != workload or kv.get("kernel_source_sha256") != kernel_source_hash():
         return None
+    if choice is not None:
+        if len(choice) != 1 or any(kv.get(k) != choice[0].get(k) for k in ("engine", "layout")):
+            return None
     try:
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -601,8 +606,10 @@ def main():
     achieved_chip = st["contract_flops"] / secs / 1e12
     tasks_per_launch = args.steps * tasks_per_sweep / launches
     model_rate = flops_model * tasks_per_launch / avg_launch_s / 1e12 if avg_launch_s > 0 else None
+    tune = autotune_report(tn, groups, tn.TNMC_FP64)
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS if achieved else None, "traffic": measured_traffic(args.workload),
+                "frac": achieved / FP64_PEAK_TFLOPS if achieved else None,
+                "traffic": measured_traffic(args.workload, tune),
                 "kernel": " + ".join(f"contract_kernel<{d},{c}>" for d, c in kernels),
                 "avg_launch_ms": avg_launch_s * 1e3, "launches": launches,
                 "achieved_chip": achieved_chip, "frac_chip": achieved_chip / FP64_PEAK_TFLOPS,
@@ -663,7 +670,7 @@ def main():
         "tau_leg": tau_fp64,
         "roofline": roofline,
     }
-    out["autotune"] = autotune_report(tn, groups, tn.TNMC_FP64)
+    out["autotune"] = tune
     if not args.no_reduced:
         # the reduced-precision form on the same inputs: FP32 environments, rank
         # cut-off at FP32 resolution, FP64 factorisations, log q and MH
