@@ -58,8 +58,12 @@ typedef struct {
   int32_t precision;            /* TNMC_FP64, or TNMC_FP32: the reduced-precision form.  The
                                    environments are stored in FP32 and the rank-revealing
                                    factorisations cut at 1e-6 relative (FP32 resolution) instead
-                                   of 1e-15; all arithmetic, log q, dE and the MH test stay FP64.
-                                   The proposal q changes (log q by ~1e-6 relative), the chain's
+                                   of 1e-15; the factorisations, log q, dE and the MH test stay
+                                   FP64, the products run in FP64 on the vector ALU or with FP32
+                                   operands on the matrix cores (the autotuner's choice).  The
+                                   proposal q changes (log q typically by ~1e-6 relative, more
+                                   where the dropped directions carry a layer's weight, as for
+                                   near-ordered layers of an ordered ferromagnet); the chain's
                                    stationary law does not: q(old) and q(new) come from the same
                                    environments (SM S2.A, MH of main text Eq. 1). */
   int32_t n_chains;             /* >= 1 */
